@@ -1,0 +1,213 @@
+/*
+ * fbst.h -- C ABI of the MI355X (gfx950) fast broadband beamspace
+ * transformation (FBST) library, libfbst.so.
+ *
+ * What it computes (Singh, DeLude, Davenport, Romberg, "A Fast Broadband
+ * Beamspace Transformation"): from N snapshots of an M-sensor array it forms
+ * N uniform samples of each of B broadband beams (problem statement of
+ * Sec. III-A).  For beam b the samples are
+ *
+ *     beams_b = F_u (F_b^H F_b + delta I)^{-1} F_b^H y          (eqs. betahatls, bhatls)
+ *
+ * with F_b the MN x L Fourier-extension matrix of eq. (FthetaH),
+ * [F_b]_{(m,n),l} = exp(-j 2 pi f_c tau_{b,m}) exp(j omega_l (t_n - tau_{b,m})),
+ * omega_l = 2 pi eps (l - L/2) / (L T_s), l = 1..L (eq. stfourierapprox),
+ * t_n = n T_s (n = 0..N-1) and [F_u]_{n,l} = exp(j omega_l t_n).
+ * The library never forms these matrices: stage 1 evaluates all F_b^H y at
+ * once as two chirp-z transforms (Sec. IV, eq. DFT_1; App. B for a grid),
+ * stage 2 applies (F_b^H F_b + delta I)^{-1}, a Hermitian Toeplitz inverse,
+ * through its Gohberg-Semencul form by circulant-embedded FFTs, then F_u as a
+ * chirp-z transform (Sec. V of the paper, "Fast Inverse").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Complex data are interleaved (re, im) pairs: complex64 = two float32,
+ *   complex128 = two float64, i.e. a contiguous torch.complex64 / complex128.
+ *   The I/O element type is complex128 when the plan's precision is
+ *   FBST_PREC_FP64 and complex64 otherwise.
+ * - x (input block) is device memory [M][N], row-major, sensor-major: sample
+ *   n of element m at x[m*N + n].  For a grid, m = k*my + k2 (k indexes the x
+ *   axis).  A batch of nb blocks is [nb][M][N].
+ * - beams (output) is device memory [B][N]: sample n of beam b at
+ *   beams[b*N + n]; for a grid b = a*bv + c (a indexes u).  A batch is
+ *   [nb][B][N].  beams[b] estimates s(t_n) for a source from beam direction b,
+ *   referenced to the coordinate origin of the geometry.
+ * - All device pointers must be 16-byte aligned; x and beams must not alias.
+ * - Asynchrony: execute calls only enqueue kernels on the given hipStream_t
+ *   (NULL = the default stream) and never synchronise the host.
+ * - Ownership: a plan owns its device tables (allocated in plan_create, freed
+ *   in fbst_destroy).  The caller owns x, beams and any workspace.
+ * - Errors: every call returns a status and never throws across the ABI;
+ *   fbst_last_error() gives a thread-local message for the last failure.
+ * - Thread safety: a plan is immutable after creation; executes of one plan
+ *   on several streams at once are safe when each uses its own workspace.
+ */
+#ifndef FBST_H
+#define FBST_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FBST_OK = 0,
+  FBST_E_INVALID = -1,     /* an argument is null, out of range or inconsistent  */
+  FBST_E_UNSUPPORTED = -2, /* valid, but outside what this build implements      */
+  FBST_E_NOMEM = -3,       /* host or device allocation failed                    */
+  FBST_E_DEVICE = -4       /* HIP runtime error (no device, launch or copy error) */
+} fbst_status;
+
+typedef enum { FBST_LINE = 0, FBST_GRID = 1 } fbst_geom_kind;
+
+typedef enum {
+  FBST_PREC_FP32 = 0,        /* every stage in float32                                  */
+  FBST_PREC_FP64_STAGE2 = 1, /* stage 1 float32; Toeplitz solve + F_u in float64          */
+  FBST_PREC_FP64 = 2,        /* every stage in float64; complex128 input and output       */
+  FBST_PREC_BF16_SPLIT = 3,  /* stage 1a as a blocked DFT on MFMA, bfloat16 hi/lo split   */
+  FBST_PREC_FP16_SPLIT = 4   /* stage 1a as a blocked DFT on MFMA, float16 hi/lo split    */
+} fbst_precision;
+
+/* Array geometry (Sec. III: tau_{theta,m} = p_m^T theta).  Element (k, k2)
+ * sits at delay coordinates px = (x0 + k) dx and py = (y0 + k2) dy, in seconds
+ * per unit direction cosine, so a beam with direction cosines (u, v) has
+ * delays tau = u px + v py relative to the origin (the reference point).
+ * LINE: mx = M, my = 1.  GRID: mx * my = M.  dx (dy) = 0 selects
+ * half-wavelength spacing at the top band edge, 1 / (2 (f_c + Omega)) (Sec. IV). */
+typedef struct {
+  fbst_geom_kind kind;
+  int mx, my;
+  double dx, dy;
+  double x0, y0;
+} fbst_geometry;
+
+/* Band (Sec. III): carrier f_c (Hz), baseband half-bandwidth Omega (Hz) and
+ * sample period T_s (s); requires 0 < T_s <= 1 / (2 Omega). */
+typedef struct {
+  double fc, omega, ts;
+} fbst_band;
+
+/* Beam grid, uniform in direction cosine on each axis: u_a = u0 + a du
+ * (a = 0..bu-1), v_c = v0 + c dv (c = 0..bv-1).  du = 0 (dv = 0) selects the
+ * grid of eq. (thetab): sin(theta) = (2b - B - 1)/(B - 1) for odd counts and
+ * (2b - B - 1)/B for even counts (b = 1..B).  LINE: bu = B, bv = 1. */
+typedef struct {
+  int bu, bv;
+  double u0, du;
+  double v0, dv;
+} fbst_grid;
+
+/* Plan flags. */
+#define FBST_FLAG_HOST_ONLY 1u        /* build the FP64 host tables only; no device memory,
+                                         execute calls fail (introspection and CPU tests) */
+#define FBST_FLAG_KEEP_HOST_TABLES 2u /* keep FP64 host copies for fbst_plan_table()      */
+
+/* Basis and solver options.  eps: band expansion epsilon > 0 (0 selects 1.01).
+ * L: number of basis frequencies, even and >= 2 (0 selects 2N, i.e.
+ * gamma = 2; Sec. III-A).  delta: ridge of eq. (betahatls), > 0, absolute.
+ * The condition number of F^H F + delta I is about 2MN/delta, so float32
+ * stage 2 needs delta of the order of the noise level (e.g. sigma^2 L); the
+ * paper's delta = 1e-5 needs FBST_PREC_FP64.  A NULL options pointer selects
+ * eps = 1.01, L = 2N, delta = 1e-5, FBST_PREC_FP32, flags 0. */
+typedef struct {
+  double eps;
+  int L;
+  double delta;
+  fbst_precision precision;
+  unsigned flags;
+} fbst_options;
+
+/* Read-only plan summary (fbst_plan_info). */
+typedef struct {
+  int M, N, B, L;
+  int mx, my, bu, bv;
+  int p1;            /* FFT size of the stage-1a (time) chirp-z               */
+  int p2x, p2y;      /* FFT sizes of the stage-1b (space) chirp-z, per axis   */
+  int p3;            /* FFT size of the Toeplitz apply and the F_u chirp-z      */
+  fbst_precision precision;
+  size_t io_elem_bytes;      /* 8 (complex64) or 16 (complex128)                */
+  size_t device_bytes;       /* device tables owned by the plan                  */
+  size_t workspace_per_block;/* bytes of workspace one block needs               */
+} fbst_info;
+
+typedef struct fbst_plan fbst_plan;
+
+/* Create a plan: validates, builds every table in float64 on the host
+ * (chirps, chirp-kernel spectra, the Toeplitz generator c_b(d) of Sec. V in
+ * closed form, x_b = A_b^{-1} e_0 by Levinson recursion and the spectra of the
+ * Gohberg-Semencul factors), uploads them in the stage precisions and
+ * allocates a one-block workspace.  geometry NULL: a line of M elements,
+ * lambda/2 at f_c + Omega, reference at element 0.  grid NULL: B beams on the
+ * eq. (thetab) grid.  band must not be NULL.  On failure *out is NULL. */
+fbst_status fbst_plan_create(int M, int N, int B, const fbst_geometry* geometry,
+                             const fbst_band* band, const fbst_grid* grid,
+                             const fbst_options* options, fbst_plan** out);
+
+/* Beams of one block: x [M][N] -> beams [B][N] on hip_stream.  workspace:
+ * device memory of at least fbst_workspace_bytes(plan, 1) bytes, or NULL to
+ * use the plan's own one-block workspace (then calls on one plan must not
+ * overlap in time).  Fails with FBST_E_INVALID on null x/beams or a
+ * host-only plan. */
+fbst_status fbst_execute(const fbst_plan* plan, const void* x, void* beams,
+                         void* workspace, void* hip_stream);
+
+/* nblocks independent blocks of one plan in one set of launches:
+ * x [nblocks][M][N] -> beams [nblocks][B][N].  workspace: at least
+ * fbst_workspace_bytes(plan, chunk) bytes where chunk = min(nblocks,
+ * max_chunk) (max_chunk <= 0: all blocks at once; the blocks are then
+ * processed chunk blocks per launch), or NULL when chunk == 1. */
+fbst_status fbst_execute_batched(const fbst_plan* plan, int nblocks, int max_chunk,
+                                 const void* x, void* beams, void* workspace,
+                                 void* hip_stream);
+
+/* One stage, for per-stage parity and timing.  Element types are the plan's
+ * stage types (complex64, or complex128 for FBST_PREC_FP64; stage 2 input is
+ * the stage-1 type).
+ *   stage 0 (time chirp-z, Sec. IV):   in x [nb][M][N]  -> out Yhat [nb][M][L],
+ *            Yhat[m][l-1] = sum_n x[m][n] exp(-j omega_l t_n);
+ *   stage 1 (space chirp-z, eq. DFT_1 / App. B): in Yhat -> out W [nb][B][L],
+ *            W[b][l-1] = [F_b^H x]_l; a grid needs workspace of
+ *            fbst_workspace_bytes(plan, nb) bytes (else may be NULL);
+ *   stage 2 (Sec. V):                  in W -> out beams [nb][B][N].          */
+fbst_status fbst_execute_stage(const fbst_plan* plan, int stage, int nblocks,
+                               const void* in, void* out, void* workspace,
+                               void* hip_stream);
+
+/* Workspace bytes for nblocks blocks processed in one launch (0 on NULL plan). */
+size_t fbst_workspace_bytes(const fbst_plan* plan, int nblocks);
+
+/* Device bytes owned by the plan (tables + its one-block workspace). */
+size_t fbst_plan_device_bytes(const fbst_plan* plan);
+
+/* Fill *info; FBST_E_INVALID on NULL arguments. */
+fbst_status fbst_plan_info(const fbst_plan* plan, fbst_info* info);
+
+/* FP64 host tables kept by plans created with FBST_FLAG_HOST_ONLY or
+ * FBST_FLAG_KEEP_HOST_TABLES, copied to host memory dst (bytes available):
+ *   FBST_TABLE_BEAM_U, FBST_TABLE_BEAM_V: double [B], direction cosines;
+ *   FBST_TABLE_GRAM:      complex128 [B][L], first column of A_b = F_b^H F_b
+ *                         + delta I, i.e. c_b(d) + delta [d == 0];
+ *   FBST_TABLE_GENERATOR: complex128 [B][L], x_b = A_b^{-1} e_0.
+ * FBST_E_INVALID if the table is absent or bytes is too small. */
+#define FBST_TABLE_BEAM_U 0
+#define FBST_TABLE_BEAM_V 1
+#define FBST_TABLE_GRAM 2
+#define FBST_TABLE_GENERATOR 3
+fbst_status fbst_plan_table(const fbst_plan* plan, int table, void* dst, size_t bytes);
+
+/* Free the plan and its device tables (after work using it has finished).
+ * NULL is a no-op. */
+void fbst_destroy(fbst_plan* plan);
+
+/* Thread-local text of the last failure ("" if none). */
+const char* fbst_last_error(void);
+
+/* Library version string. */
+const char* fbst_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FBST_H */

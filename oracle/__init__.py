@@ -13,10 +13,10 @@ direct
     beta = (F^H F + delta I)^{-1} F^H y  (eq. betahatls, with F from
     eq. FthetaH) and b = F_u beta (eq. bhatls), in float64, with the
     projection F^H y evaluated as the double sum of eq. (sum_1), the Gram
-    matrix from the entry formula of Sec. IV and a dense Cholesky solve.
+    matrix from the entry formula of Sec. V and a dense Cholesky solve.
     Also the explicit-matrix form for tiny sizes.
 analysis
-    The bias and variance expressions of Sec. VI (discrete-time reading) used
+    The bias and variance expressions of Sec. VII (discrete-time reading) used
     by the Monte-Carlo pins.
 
 Pins (tests/test_oracle_*.py, run with ``-m "not gpu"``)
@@ -28,8 +28,8 @@ Pins (tests/test_oracle_*.py, run with ``-m "not gpu"``)
 * the narrowband limit (FB -> 0): beams become a spatial DFT (numpy FFT);
 * a noise-free on-grid plane wave is recovered to the bias level and peaks
   in its own beam;
-* Monte-Carlo noise vs the variance formula of Sec. VI, and Monte-Carlo
-  band-limited Gaussian sources vs the bias formula of Sec. VI;
+* Monte-Carlo noise vs the variance formula of Sec. VII, and Monte-Carlo
+  band-limited Gaussian sources vs the bias formula of Sec. VII;
 * invariances: time origin, linearity, and the pure phase/delay effect of a
   moved reference point.
 

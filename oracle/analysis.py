@@ -1,4 +1,4 @@
-"""Bias and variance of the FBST beam (Sec. VI), test oracle only.
+"""Bias and variance of the FBST beam (Sec. VII), test oracle only.
 
 The paper states both on the continuous interval [0, T].  The pins use two
 forms:
@@ -8,7 +8,7 @@ forms:
 * the same quantities at the N output times t_n (reading: the beam is only
   ever evaluated there), variance sigma^2 tr(F_u Q F_u^H) and, for a source
   that is a zero-mean band-limited Gaussian process with covariance
-  P sinc(2 Omega tau) (the flat-spectrum process of Sec. VI), the mean squared
+  P sinc(2 Omega tau) (the flat-spectrum process of Sec. VII), the mean squared
   bias tr(K C_yy K^H) - 2 Re tr(K C_ys) + tr(C_ss) with K = F_u A^{-1} F^H.
 """
 from __future__ import annotations
@@ -22,7 +22,7 @@ __all__ = ["Q_matrix", "variance_discrete", "variance_continuous", "bias_discret
 
 
 def Q_matrix(p: Problem, b: int) -> np.ndarray:
-    """Q = (F^H F + delta I)^{-1} F^H F (F^H F + delta I)^{-1} (Sec. VI)."""
+    """Q = (F^H F + delta I)^{-1} F^H F (F^H F + delta I)^{-1} (Sec. VII)."""
     F = F_matrix(p, b)
     T = F.conj().T @ F
     A = T + p.delta * np.eye(p.L)

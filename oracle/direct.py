@@ -127,7 +127,7 @@ def project(y: np.ndarray, p: Problem, beam_idx=None, yhat=None) -> np.ndarray:
 
 
 def gram_column(p: Problem, b: int) -> np.ndarray:
-    """c_b(d) = [F_b^H F_b]_{l+d, l}, d = 0..L-1 (Sec. IV).
+    """c_b(d) = [F_b^H F_b]_{l+d, l}, d = 0..L-1 (Sec. V, Fast Inverse).
 
     The entry is sum_{m,n} exp(-j (omega_l - omega_k)(t_n - tau_{b,m})) with
     l - k = d, i.e. a function of d alone (Toeplitz); the exponent splits into
@@ -141,7 +141,7 @@ def gram_column(p: Problem, b: int) -> np.ndarray:
 
 
 def toeplitz_system(p: Problem, b: int) -> np.ndarray:
-    """A_b = F_b^H F_b + delta I (Sec. IV), Hermitian Toeplitz, L x L."""
+    """A_b = F_b^H F_b + delta I (Sec. V), Hermitian Toeplitz, L x L."""
     c = gram_column(p, b)
     A = sla.toeplitz(c, np.conj(c))
     A[np.diag_indices(p.L)] += p.delta
@@ -157,7 +157,7 @@ def solve(A: np.ndarray, w: np.ndarray) -> np.ndarray:
 
 def generator(p: Problem, b: int) -> np.ndarray:
     """First column of A_b^{-1} (the generating vector x of the
-    Gohberg-Semencul representation in Sec. IV)."""
+    Gohberg-Semencul representation in Sec. V)."""
     e0 = np.zeros(p.L, dtype=np.complex128)
     e0[0] = 1.0
     return solve(toeplitz_system(p, b), e0)

@@ -1,0 +1,375 @@
+// C ABI of libfbst.so (declared in include/fbst.h).
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "fft_lds.h"
+#include "kernels.h"
+#include "plan.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+fbst_status fail(fbst_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+fbst_status hip_fail(hipError_t e, const char* what) {
+  return fail(FBST_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+bool stage1_double(const fbst::Params& p) { return p.prec == FBST_PREC_FP64; }
+bool stage2_double(const fbst::Params& p) {
+  return p.prec == FBST_PREC_FP64 || p.prec == FBST_PREC_FP64_STAGE2;
+}
+size_t s1_elem(const fbst::Params& p) { return stage1_double(p) ? 16 : 8; }
+size_t s2_elem(const fbst::Params& p) { return stage2_double(p) ? 16 : 8; }
+
+size_t ws_per_block(const fbst::Params& p) {
+  size_t elems = (static_cast<size_t>(p.M) + p.B) * p.L;
+  if (p.kind == FBST_GRID) elems += static_cast<size_t>(p.bu) * p.my * p.L;
+  return elems * s1_elem(p);
+}
+
+size_t align_up(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
+
+// Staging of host tables into one device allocation.
+struct Upload {
+  std::vector<unsigned char> blob;
+  size_t add(const std::vector<fbst::zd>& v, bool as_double) {
+    const size_t off = align_up(blob.size());
+    const size_t bytes = v.size() * (as_double ? 16 : 8);
+    blob.resize(off + bytes);
+    if (as_double) {
+      std::memcpy(blob.data() + off, v.data(), bytes);
+    } else {
+      float* f = reinterpret_cast<float*>(blob.data() + off);
+      for (size_t i = 0; i < v.size(); ++i) {
+        f[2 * i] = static_cast<float>(v[i].real());
+        f[2 * i + 1] = static_cast<float>(v[i].imag());
+      }
+    }
+    return off;
+  }
+};
+
+std::vector<fbst::zd> twiddles() {
+  std::vector<fbst::zd> tw(fbst::PMAX);
+  const double pi = 3.141592653589793238462643383279502884;
+  for (int i = 0; i < fbst::PMAX; ++i) {
+    // exp(-2 pi j i / PMAX) from the symmetric octant to keep every entry correctly rounded
+    const double a = 2.0 * pi * i / fbst::PMAX;
+    tw[i] = fbst::zd(std::cos(a), -std::sin(a));
+  }
+  return tw;
+}
+
+fbst_status upload(fbst_plan* pl) {
+  const fbst::Params& p = pl->p;
+  const bool d1 = stage1_double(p), d2 = stage2_double(p);
+  fbst::HostTables& h = pl->host;
+  Upload up;
+  const std::vector<fbst::zd> tw = twiddles();
+  const size_t o_tw1 = up.add(tw, d1);
+  const size_t o_tw2 = (d1 == d2) ? o_tw1 : up.add(tw, d2);
+  const size_t o_pre1 = up.add(h.pre1, d1), o_H1 = up.add(h.H1, d1), o_post1 = up.add(h.post1, d1);
+  const size_t o_axp = up.add(h.ax.pre, d1), o_axH = up.add(h.ax.H, d1), o_axq = up.add(h.ax.post, d1);
+  size_t o_ayp = 0, o_ayH = 0, o_ayq = 0;
+  if (p.kind == FBST_GRID) {
+    o_ayp = up.add(h.ay.pre, d1);
+    o_ayH = up.add(h.ay.H, d1);
+    o_ayq = up.add(h.ay.post, d1);
+  }
+  const size_t o_G1 = up.add(h.G1, d2), o_G2 = up.add(h.G2, d2);
+  const size_t o_pre3 = up.add(h.pre3, d2), o_H3 = up.add(h.H3, d2), o_post3 = up.add(h.post3, d2);
+  const size_t tables = align_up(up.blob.size());
+  const size_t total = tables + align_up(pl->ws_bytes_per_block);
+
+  hipError_t e = hipGetDevice(&pl->device);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  void* dev = nullptr;
+  e = hipMalloc(&dev, total);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(FBST_E_NOMEM, "hipMalloc of " + std::to_string(total) + " bytes of plan tables failed");
+  }
+  e = hipMemcpy(dev, up.blob.data(), up.blob.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(dev);
+    return hip_fail(e, "hipMemcpy of plan tables");
+  }
+  unsigned char* b = static_cast<unsigned char*>(dev);
+  pl->dev = dev;
+  pl->dev_bytes = total;
+  pl->tw1 = b + o_tw1;
+  pl->tw2 = b + o_tw2;
+  pl->pre1 = b + o_pre1;
+  pl->H1 = b + o_H1;
+  pl->post1 = b + o_post1;
+  pl->axp = b + o_axp;
+  pl->axH = b + o_axH;
+  pl->axq = b + o_axq;
+  if (p.kind == FBST_GRID) {
+    pl->ayp = b + o_ayp;
+    pl->ayH = b + o_ayH;
+    pl->ayq = b + o_ayq;
+  }
+  pl->G1 = b + o_G1;
+  pl->G2 = b + o_G2;
+  pl->pre3 = b + o_pre3;
+  pl->H3 = b + o_H3;
+  pl->post3 = b + o_post3;
+  pl->own_ws = b + tables;
+  return FBST_OK;
+}
+
+template <typename T1>
+hipError_t run_stage0(const fbst_plan* pl, int nb, const void* x, void* yhat, hipStream_t st) {
+  const fbst::Params& p = pl->p;
+  return fbst::launch_time_czt<T1>(p.p1, x, yhat, pl->pre1, pl->H1, pl->post1, pl->tw1, p.N, p.L,
+                                   nb * p.M, st);
+}
+
+template <typename T1>
+hipError_t run_stage1(const fbst_plan* pl, int nb, const void* yhat, void* w, void* z,
+                      hipStream_t st) {
+  const fbst::Params& p = pl->p;
+  if (p.kind == FBST_LINE) {
+    return fbst::launch_axis_czt<T1>(p.p2x, yhat, w, pl->axp, pl->axH, pl->axq, pl->tw1, p.M, p.B,
+                                     1, 1, p.L, nb, st);
+  }
+  // grid: x axis on [nb][1][mx][my][L] -> z [nb][1][bu][my][L], then the
+  // y axis on [nb][bu][my][1][L] -> w [nb][bu][bv][1][L]
+  hipError_t e = fbst::launch_axis_czt<T1>(p.p2x, yhat, z, pl->axp, pl->axH, pl->axq, pl->tw1,
+                                           p.mx, p.bu, 1, p.my, p.L, nb, st);
+  if (e != hipSuccess) return e;
+  return fbst::launch_axis_czt<T1>(p.p2y, z, w, pl->ayp, pl->ayH, pl->ayq, pl->tw1, p.my, p.bv,
+                                   p.bu, 1, p.L, nb, st);
+}
+
+hipError_t run_stage2(const fbst_plan* pl, int nb, const void* w, void* beams, hipStream_t st) {
+  const fbst::Params& p = pl->p;
+  const int rows = nb * p.B;
+  switch (p.prec) {
+    case FBST_PREC_FP64:
+      return fbst::launch_toeplitz_fu<double, double, double>(p.p3, w, beams, pl->G1, pl->G2,
+                                                              pl->pre3, pl->H3, pl->post3, pl->tw2,
+                                                              p.B, p.L, p.N, rows, st);
+    case FBST_PREC_FP64_STAGE2:
+      return fbst::launch_toeplitz_fu<double, float, float>(p.p3, w, beams, pl->G1, pl->G2,
+                                                            pl->pre3, pl->H3, pl->post3, pl->tw2,
+                                                            p.B, p.L, p.N, rows, st);
+    default:
+      return fbst::launch_toeplitz_fu<float, float, float>(p.p3, w, beams, pl->G1, pl->G2,
+                                                           pl->pre3, pl->H3, pl->post3, pl->tw2,
+                                                           p.B, p.L, p.N, rows, st);
+  }
+}
+
+hipError_t run_stage(const fbst_plan* pl, int stage, int nb, const void* in, void* out, void* z,
+                     hipStream_t st) {
+  const bool d1 = stage1_double(pl->p);
+  if (stage == 0) return d1 ? run_stage0<double>(pl, nb, in, out, st) : run_stage0<float>(pl, nb, in, out, st);
+  if (stage == 1)
+    return d1 ? run_stage1<double>(pl, nb, in, out, z, st) : run_stage1<float>(pl, nb, in, out, z, st);
+  return run_stage2(pl, nb, in, out, st);
+}
+
+// Whole path for nb blocks with the given workspace [yhat | w | z].
+hipError_t run_all(const fbst_plan* pl, int nb, const void* x, void* beams, void* ws, hipStream_t st) {
+  const fbst::Params& p = pl->p;
+  const size_t e1 = s1_elem(p);
+  unsigned char* base = static_cast<unsigned char*>(ws);
+  void* yhat = base;
+  void* w = base + static_cast<size_t>(nb) * p.M * p.L * e1;
+  void* z = static_cast<unsigned char*>(w) + static_cast<size_t>(nb) * p.B * p.L * e1;
+  hipError_t e = run_stage(pl, 0, nb, x, yhat, nullptr, st);
+  if (e != hipSuccess) return e;
+  e = run_stage(pl, 1, nb, yhat, w, z, st);
+  if (e != hipSuccess) return e;
+  return run_stage(pl, 2, nb, w, beams, nullptr, st);
+}
+
+fbst_status check_exec(const fbst_plan* plan) {
+  if (!plan) return fail(FBST_E_INVALID, "plan is NULL");
+  if (plan->host_only) return fail(FBST_E_INVALID, "plan was created host-only");
+  return FBST_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fbst_status fbst_plan_create(int M, int N, int B, const fbst_geometry* geometry,
+                             const fbst_band* band, const fbst_grid* grid,
+                             const fbst_options* options, fbst_plan** out) {
+  if (!out) return fail(FBST_E_INVALID, "out is NULL");
+  *out = nullptr;
+  std::string msg;
+  fbst::Params p;
+  fbst_status st = fbst::resolve_params(M, N, B, geometry, band, grid, options, &p, &msg);
+  if (st != FBST_OK) return fail(st, msg);
+  fbst_plan* pl = new (std::nothrow) fbst_plan();
+  if (!pl) return fail(FBST_E_NOMEM, "host allocation of the plan failed");
+  pl->p = p;
+  pl->host_only = (p.flags & FBST_FLAG_HOST_ONLY) != 0;
+  pl->kept = pl->host_only || (p.flags & FBST_FLAG_KEEP_HOST_TABLES) != 0;
+  pl->ws_bytes_per_block = ws_per_block(p);
+  try {
+    st = fbst::build_tables(p, pl->kept, &pl->host, &msg);
+  } catch (const std::bad_alloc&) {
+    st = FBST_E_NOMEM;
+    msg = "host allocation of the plan tables failed";
+  }
+  if (st != FBST_OK) {
+    delete pl;
+    return fail(st, msg);
+  }
+  if (!pl->host_only) {
+    st = upload(pl);
+    if (st != FBST_OK) {
+      delete pl;
+      return st;
+    }
+    // device copies are the working set; keep only what was asked for on the host
+    if (!pl->kept) pl->host = fbst::HostTables();
+  }
+  *out = pl;
+  return FBST_OK;
+}
+
+fbst_status fbst_execute(const fbst_plan* plan, const void* x, void* beams, void* workspace,
+                         void* hip_stream) {
+  fbst_status s = check_exec(plan);
+  if (s != FBST_OK) return s;
+  if (!x || !beams) return fail(FBST_E_INVALID, "x and beams must not be NULL");
+  void* ws = workspace ? workspace : plan->own_ws;
+  hipError_t e = run_all(plan, 1, x, beams, ws, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return hip_fail(e, "fbst_execute launch");
+  return FBST_OK;
+}
+
+fbst_status fbst_execute_batched(const fbst_plan* plan, int nblocks, int max_chunk, const void* x,
+                                 void* beams, void* workspace, void* hip_stream) {
+  fbst_status s = check_exec(plan);
+  if (s != FBST_OK) return s;
+  if (nblocks < 0) return fail(FBST_E_INVALID, "nblocks must be >= 0");
+  if (nblocks == 0) return FBST_OK;
+  if (!x || !beams) return fail(FBST_E_INVALID, "x and beams must not be NULL");
+  const int chunk = (max_chunk <= 0 || max_chunk > nblocks) ? nblocks : max_chunk;
+  void* ws = workspace;
+  if (!ws) {
+    if (chunk != 1) return fail(FBST_E_INVALID, "workspace is NULL but chunk > 1");
+    ws = plan->own_ws;
+  }
+  const fbst::Params& p = plan->p;
+  const size_t io = (p.prec == FBST_PREC_FP64) ? 16 : 8;
+  const size_t in_blk = static_cast<size_t>(p.M) * p.N * io;
+  const size_t out_blk = static_cast<size_t>(p.B) * p.N * io;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  for (int b0 = 0; b0 < nblocks; b0 += chunk) {
+    const int nb = (nblocks - b0 < chunk) ? nblocks - b0 : chunk;
+    hipError_t e = run_all(plan, nb, static_cast<const unsigned char*>(x) + b0 * in_blk,
+                           static_cast<unsigned char*>(beams) + b0 * out_blk, ws, st);
+    if (e != hipSuccess) return hip_fail(e, "fbst_execute_batched launch");
+  }
+  return FBST_OK;
+}
+
+fbst_status fbst_execute_stage(const fbst_plan* plan, int stage, int nblocks, const void* in,
+                               void* out, void* workspace, void* hip_stream) {
+  fbst_status s = check_exec(plan);
+  if (s != FBST_OK) return s;
+  if (stage < 0 || stage > 2) return fail(FBST_E_INVALID, "stage must be 0, 1 or 2");
+  if (nblocks < 1) return fail(FBST_E_INVALID, "nblocks must be >= 1");
+  if (!in || !out) return fail(FBST_E_INVALID, "in and out must not be NULL");
+  void* z = nullptr;
+  if (stage == 1 && plan->p.kind == FBST_GRID) {
+    if (!workspace) {
+      if (nblocks != 1) return fail(FBST_E_INVALID, "a grid stage 1 over several blocks needs a workspace");
+      workspace = plan->own_ws;
+    }
+    z = workspace;
+  }
+  hipError_t e = run_stage(plan, stage, nblocks, in, out, z, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return hip_fail(e, "fbst_execute_stage launch");
+  return FBST_OK;
+}
+
+size_t fbst_workspace_bytes(const fbst_plan* plan, int nblocks) {
+  if (!plan || nblocks < 1) return 0;
+  return plan->ws_bytes_per_block * static_cast<size_t>(nblocks);
+}
+
+size_t fbst_plan_device_bytes(const fbst_plan* plan) { return plan ? plan->dev_bytes : 0; }
+
+fbst_status fbst_plan_info(const fbst_plan* plan, fbst_info* info) {
+  if (!plan || !info) return fail(FBST_E_INVALID, "plan and info must not be NULL");
+  const fbst::Params& p = plan->p;
+  info->M = p.M;
+  info->N = p.N;
+  info->B = p.B;
+  info->L = p.L;
+  info->mx = p.mx;
+  info->my = p.my;
+  info->bu = p.bu;
+  info->bv = p.bv;
+  info->p1 = p.p1;
+  info->p2x = p.p2x;
+  info->p2y = p.p2y;
+  info->p3 = p.p3;
+  info->precision = p.prec;
+  info->io_elem_bytes = (p.prec == FBST_PREC_FP64) ? 16 : 8;
+  info->device_bytes = plan->dev_bytes;
+  info->workspace_per_block = plan->ws_bytes_per_block;
+  return FBST_OK;
+}
+
+fbst_status fbst_plan_table(const fbst_plan* plan, int table, void* dst, size_t bytes) {
+  if (!plan || !dst) return fail(FBST_E_INVALID, "plan and dst must not be NULL");
+  if (!plan->kept) return fail(FBST_E_INVALID, "host tables were not kept for this plan");
+  const fbst::HostTables& h = plan->host;
+  const void* src = nullptr;
+  size_t need = 0;
+  switch (table) {
+    case FBST_TABLE_BEAM_U:
+      src = h.u.data();
+      need = h.u.size() * sizeof(double);
+      break;
+    case FBST_TABLE_BEAM_V:
+      src = h.v.data();
+      need = h.v.size() * sizeof(double);
+      break;
+    case FBST_TABLE_GRAM:
+      src = h.gram.data();
+      need = h.gram.size() * sizeof(fbst::zd);
+      break;
+    case FBST_TABLE_GENERATOR:
+      src = h.gen.data();
+      need = h.gen.size() * sizeof(fbst::zd);
+      break;
+    default:
+      return fail(FBST_E_INVALID, "unknown table id");
+  }
+  if (need == 0) return fail(FBST_E_INVALID, "table is empty");
+  if (bytes < need) return fail(FBST_E_INVALID, "destination too small");
+  std::memcpy(dst, src, need);
+  return FBST_OK;
+}
+
+void fbst_destroy(fbst_plan* plan) {
+  if (!plan) return;
+  if (plan->dev) (void)hipFree(plan->dev);
+  delete plan;
+}
+
+const char* fbst_last_error(void) { return g_last_error.c_str(); }
+
+const char* fbst_version(void) { return "fbst-gfx950 0.1"; }
+
+}  // extern "C"

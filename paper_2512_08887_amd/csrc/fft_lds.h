@@ -1,0 +1,219 @@
+// Workgroup-cooperative power-of-two FFTs in LDS for gfx950.
+//
+// One transform of P points is owned by TT = P / E threads; thread t holds
+// E elements in registers, v[s] = x[t + s * TT] (s = 0..E-1), both on entry
+// and on exit, so a forward transform, a pointwise product and an inverse
+// transform chain without any reordering, and global loads/stores of
+// consecutive elements by consecutive threads stay coalesced.
+//
+// Algorithm: self-sorting Stockham passes of radix R (R = E, then one smaller
+// remainder pass).  A pass with span NS performs, for butterfly j
+// (j = t + q TT, q = 0..E/R-1), k = j mod NS:
+//     a[r] = x[j + r P/R] * w_{NS R}^{r k}     (r = 0..R-1)
+//     A = DFT_R(a)
+//     y[(j - k) R + k + r NS] = A[r]
+// The first pass takes its operands from the registers (j + r P/R is the
+// register v[q + r E/R]), the last pass leaves its results in the registers,
+// and every pass in between exchanges through LDS, so a transform of
+// k passes costs k - 1 LDS round trips.
+//
+// LDS addresses are padded, i -> i + (i >> 4), which keeps the radix-16 and
+// remainder-pass writes and reads free of bank conflicts for complex64.
+//
+// Twiddles come from one table tw[i] = exp(-2 pi j i / PMAX) (computed in
+// float64 on the host, rounded once), indexed with stride PMAX / (NS R).
+#pragma once
+
+#include "cx.h"
+
+namespace fbst {
+
+constexpr int PMAX = 16384;      // largest supported transform size
+
+__host__ __device__ constexpr int lds_pad(int i) { return i + (i >> 4); }
+// per-transform LDS stride in elements (padding + 2 keeps sub-groups apart in banks)
+__host__ __device__ constexpr int lds_stride(int P) { return P + P / 16 + 2; }
+
+// ---------------------------------------------------------------------------
+// Small DFTs in registers, natural order in and out.  DIR = -1: forward
+// (exp(-j ...)); DIR = +1: inverse without scaling.
+// ---------------------------------------------------------------------------
+namespace detail {
+constexpr double kC1 = 0.92387953251128675613;   // cos(pi/8)
+constexpr double kS1 = 0.38268343236508977173;   // sin(pi/8)
+constexpr double kR2 = 0.70710678118654752440;   // sqrt(2)/2
+}  // namespace detail
+
+// a * exp(DIR * j * 2 pi * e / 16)
+template <int e, int DIR, typename T>
+__device__ __forceinline__ cx<T> tw16(cx<T> a) {
+  constexpr int m = ((e % 16) + 16) % 16;
+  if constexpr (m == 0) {
+    return a;
+  } else if constexpr (m == 4) {
+    return rot90<DIR>(a);
+  } else if constexpr (m == 8) {
+    return cx<T>{-a.re, -a.im};
+  } else if constexpr (m == 12) {
+    return rot90<-DIR>(a);
+  } else if constexpr (m % 2 == 0) {
+    // odd multiples of pi/4: (+-1 +- j) sqrt(2)/2
+    constexpr T r = static_cast<T>(detail::kR2);
+    constexpr int c_sign = (m == 2 || m == 14) ? 1 : -1;      // sign of cos
+    constexpr int s_sign = (m == 2 || m == 6) ? 1 : -1;       // sign of sin
+    constexpr int s = s_sign * DIR;                           // sign of imaginary part of factor
+    // factor = r * (c_sign + j s)
+    T re, im;
+    if constexpr (c_sign > 0) {
+      if constexpr (s > 0) { re = a.re - a.im; im = a.re + a.im; }
+      else { re = a.re + a.im; im = a.im - a.re; }
+    } else {
+      if constexpr (s > 0) { re = -a.re - a.im; im = a.re - a.im; }
+      else { re = a.im - a.re; im = -a.re - a.im; }
+    }
+    return cx<T>{re * r, im * r};
+  } else {
+    constexpr double cs[16] = {1.0, detail::kC1, detail::kR2, detail::kS1, 0.0, -detail::kS1,
+                               -detail::kR2, -detail::kC1, -1.0, -detail::kC1, -detail::kR2,
+                               -detail::kS1, 0.0, detail::kS1, detail::kR2, detail::kC1};
+    constexpr double sn[16] = {0.0, detail::kS1, detail::kR2, detail::kC1, 1.0, detail::kC1,
+                               detail::kR2, detail::kS1, 0.0, -detail::kS1, -detail::kR2,
+                               -detail::kC1, -1.0, -detail::kC1, -detail::kR2, -detail::kS1};
+    constexpr T c = static_cast<T>(cs[m]);
+    constexpr T s = static_cast<T>(DIR * sn[m]);
+    return cx<T>{a.re * c - a.im * s, a.re * s + a.im * c};
+  }
+}
+
+template <int DIR, typename T>
+__device__ __forceinline__ void dft4(cx<T>& a0, cx<T>& a1, cx<T>& a2, cx<T>& a3) {
+  const cx<T> t0 = a0 + a2, t1 = a0 - a2, t2 = a1 + a3, t3 = rot90<DIR>(a1 - a3);
+  a0 = t0 + t2;
+  a2 = t0 - t2;
+  a1 = t1 + t3;
+  a3 = t1 - t3;
+}
+
+template <int R, int DIR, typename T>
+__device__ __forceinline__ void dft(cx<T> (&v)[R]) {
+  if constexpr (R == 1) {
+  } else if constexpr (R == 2) {
+    const cx<T> a = v[0];
+    v[0] = a + v[1];
+    v[1] = a - v[1];
+  } else if constexpr (R == 4) {
+    dft4<DIR>(v[0], v[1], v[2], v[3]);
+  } else if constexpr (R == 8) {
+    // n = 2 n1 + n2, k = k1 + 4 k2
+    dft4<DIR>(v[0], v[2], v[4], v[6]);
+    dft4<DIR>(v[1], v[3], v[5], v[7]);
+    v[3] = tw16<2, DIR>(v[3]);
+    v[5] = tw16<4, DIR>(v[5]);
+    v[7] = tw16<6, DIR>(v[7]);
+    cx<T> o[8];
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+      o[k1] = v[2 * k1] + v[2 * k1 + 1];
+      o[k1 + 4] = v[2 * k1] - v[2 * k1 + 1];
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = o[i];
+  } else if constexpr (R == 16) {
+    // n = 4 n1 + n2, k = k1 + 4 k2
+    dft4<DIR>(v[0], v[4], v[8], v[12]);
+    dft4<DIR>(v[1], v[5], v[9], v[13]);
+    dft4<DIR>(v[2], v[6], v[10], v[14]);
+    dft4<DIR>(v[3], v[7], v[11], v[15]);
+    // Y[n2][k1] sits in v[4 k1 + n2]; multiply by w16^(n2 k1)
+    v[5] = tw16<1, DIR>(v[5]);
+    v[6] = tw16<2, DIR>(v[6]);
+    v[7] = tw16<3, DIR>(v[7]);
+    v[9] = tw16<2, DIR>(v[9]);
+    v[10] = tw16<4, DIR>(v[10]);
+    v[11] = tw16<6, DIR>(v[11]);
+    v[13] = tw16<3, DIR>(v[13]);
+    v[14] = tw16<6, DIR>(v[14]);
+    v[15] = tw16<9, DIR>(v[15]);
+    dft4<DIR>(v[0], v[1], v[2], v[3]);
+    dft4<DIR>(v[4], v[5], v[6], v[7]);
+    dft4<DIR>(v[8], v[9], v[10], v[11]);
+    dft4<DIR>(v[12], v[13], v[14], v[15]);
+    // X[k1 + 4 k2] sits in v[4 k1 + k2]: transpose 4 x 4
+    cx<T> o[16];
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1)
+#pragma unroll
+      for (int k2 = 0; k2 < 4; ++k2) o[k1 + 4 * k2] = v[4 * k1 + k2];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = o[i];
+  } else {
+    static_assert(R == 16, "unsupported radix");
+  }
+}
+
+// ---------------------------------------------------------------------------
+// One Stockham pass.
+// ---------------------------------------------------------------------------
+template <typename T, int P, int E, int R, int NS, int DIR, bool FIRST, bool LAST>
+__device__ __forceinline__ void stockham_pass(cx<T> (&v)[E], cx<T>* __restrict__ buf,
+                                              const cx<T>* __restrict__ tw, int t) {
+  constexpr int TT = P / E;
+  constexpr int NB = E / R;
+  static_assert(E % R == 0, "radix must divide the per-thread element count");
+  cx<T> b[NB][R];
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    const int j = t + q * TT;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if constexpr (FIRST) b[q][r] = v[q + r * NB];
+      else b[q][r] = buf[lds_pad(j + r * (P / R))];
+    }
+    if constexpr (NS > 1) {
+      const int k = j & (NS - 1);
+      constexpr int STRIDE = PMAX / (NS * R);
+#pragma unroll
+      for (int r = 1; r < R; ++r) b[q][r] = cmul_dir<DIR>(b[q][r], tw[r * k * STRIDE]);
+    }
+    dft<R, DIR>(b[q]);
+  }
+  if constexpr (LAST) {
+#pragma unroll
+    for (int q = 0; q < NB; ++q)
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[q + r * NB] = b[q][r];
+  } else {
+    __syncthreads();   // every thread has finished reading the previous contents
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int j = t + q * TT;
+      const int k = j & (NS - 1);
+      const int base = (j - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[lds_pad(base + r * NS)] = b[q][r];
+    }
+    __syncthreads();   // the new contents are visible to every thread
+  }
+}
+
+template <typename T, int P, int E, int DIR, int NS>
+__device__ __forceinline__ void fft_passes(cx<T> (&v)[E], cx<T>* buf, const cx<T>* tw, int t) {
+  constexpr int REM = P / NS;
+  constexpr int R = (REM >= E) ? E : REM;
+  constexpr bool FIRST = (NS == 1);
+  constexpr bool LAST = (REM == R);
+  stockham_pass<T, P, E, R, NS, DIR, FIRST, LAST>(v, buf, tw, t);
+  if constexpr (!LAST) fft_passes<T, P, E, DIR, NS * R>(v, buf, tw, t);
+}
+
+// In-register P-point DFT (DIR = -1) or unscaled inverse (DIR = +1) of the
+// transform held by the TT = P / E threads t = 0..TT-1 sharing buf (at least
+// lds_stride(P) elements).  Must be reached by every thread of the workgroup
+// (it contains workgroup barriers).
+template <typename T, int P, int E, int DIR>
+__device__ __forceinline__ void fft(cx<T> (&v)[E], cx<T>* buf, const cx<T>* tw, int t) {
+  static_assert((P & (P - 1)) == 0 && P >= E && P <= PMAX, "P must be a power of two in [E, PMAX]");
+  fft_passes<T, P, E, DIR, 1>(v, buf, tw, t);
+}
+
+}  // namespace fbst

@@ -1,0 +1,29 @@
+// Host-side launchers of the FBST kernels (kernels.hip).  Pointers are device
+// pointers to interleaved complex arrays of the template element type; P is
+// the FFT size of the launch (power of two, 32..16384; 8192 at most for
+// double).  All return the HIP error of the launch.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace fbst {
+
+// Stage 1a: yhat[row][i] = sum_n x[row][n] exp(-j omega_{i+1} t_n), rows = nb * M.
+template <typename T>
+hipError_t launch_time_czt(int P, const void* x, void* yhat, const void* pre, const void* H,
+                           const void* post, const void* tw, int N, int L, int rows,
+                           hipStream_t st);
+
+// Stage 1b, one axis: layout [nb][pre_n][A][post_n][L], A = a_in -> a_out.
+template <typename T>
+hipError_t launch_axis_czt(int P, const void* in, void* out, const void* pre, const void* H,
+                           const void* post, const void* tw, int a_in, int a_out, int pre_n,
+                           int post_n, int L, int nblocks, hipStream_t st);
+
+// Stage 2: beams[row][n], rows = nb * B, from w[row][0..L-1].
+template <typename T, typename TIN, typename TOUT>
+hipError_t launch_toeplitz_fu(int P, const void* w, void* beams, const void* G1, const void* G2,
+                              const void* pre3, const void* H3, const void* post3, const void* tw,
+                              int B, int L, int N, int rows, hipStream_t st);
+
+}  // namespace fbst

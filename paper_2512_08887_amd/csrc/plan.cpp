@@ -1,0 +1,480 @@
+// FP64 host plan builder: validation, chirp tables, chirp-kernel spectra,
+// Toeplitz generators and Gohberg-Semencul spectra.
+#include "plan.h"
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <mutex>
+#include <thread>
+
+#include "fft_lds.h"
+
+namespace fbst {
+
+namespace {
+
+constexpr double kPi = 3.141592653589793238462643383279502884;
+
+zd cis(double ph) { return zd(std::cos(ph), std::sin(ph)); }
+
+// exp(j pi x), with x reduced modulo 2 exactly before the trigonometric call
+zd cispi(double x) {
+  const double r = std::fmod(x, 2.0);
+  return zd(std::cos(kPi * r), std::sin(kPi * r));
+}
+
+int next_pow2(long long n) {
+  long long p = 1;
+  while (p < n) p <<= 1;
+  return static_cast<int>(std::min<long long>(p, 1LL << 30));
+}
+
+// sum_{n=0}^{K-1} exp(j (phi0 + n phi))
+zd geometric_sum(int K, double phi0, double phi) {
+  const double s = std::sin(0.5 * phi);
+  if (s == 0.0) {
+    // phi is a multiple of 2 pi (to the last bit): every term equals exp(j phi0)
+    return cis(phi0) * static_cast<double>(K);
+  }
+  const double ratio = std::sin(0.5 * K * phi) / s;
+  return cis(phi0 + 0.5 * (K - 1) * phi) * ratio;
+}
+
+// Default grid of eq. (thetab): odd count (2b - B - 1)/(B - 1), even count
+// (2b - B - 1)/B, b = 1..B; one beam at broadside.
+void default_grid(int B, double* u0, double* du) {
+  if (B <= 1) {
+    *u0 = 0.0;
+    *du = 0.0;
+  } else if (B % 2 == 1) {
+    *u0 = -1.0;
+    *du = 2.0 / (B - 1);
+  } else {
+    *u0 = (1.0 - B) / B;
+    *du = 2.0 / B;
+  }
+}
+
+// Circularly placed chirp kernel exp(j * coef * (k + shift)^2) for
+// k in [kmin, kmax], put at index k mod P; returns its scaled spectrum FFT/P.
+// phase/pi = coef_pi * (k + shift)^2 evaluated with an exact integer square.
+std::vector<zd> kernel_spectrum_int(int P, long long kmin, long long kmax, long long shift,
+                                    double coef_pi) {
+  std::vector<zd> h(P, zd(0.0, 0.0));
+  for (long long k = kmin; k <= kmax; ++k) {
+    const long long q = k + shift;
+    const double q2 = static_cast<double>(q * q);
+    const long long idx = ((k % P) + P) % P;
+    h[idx] = cispi(coef_pi * q2);
+  }
+  fft64(h.data(), P, -1);
+  const double s = 1.0 / P;
+  for (auto& z : h) z *= s;
+  return h;
+}
+
+void build_axis(const Params& p, int a_in, int a_out, double pos0, double d_samples, double u0,
+                double du, int P, AxisTables* ax) {
+  const int L = p.L;
+  ax->a_in = a_in;
+  ax->a_out = a_out;
+  ax->P = P;
+  ax->pre.assign(static_cast<size_t>(a_in) * L, zd());
+  ax->H.assign(static_cast<size_t>(P) * L, zd());
+  ax->post.assign(static_cast<size_t>(a_out) * L, zd());
+  const double lp0 = 1.0 - 0.5 * L;
+  std::vector<zd> h(P);
+  for (int l = 0; l < L; ++l) {
+    const double lp = l + lp0;
+    const double rho = 2.0 * kPi * (p.fc * p.ts + p.eps * lp / L);   // rad per (sample of delay)
+    const double theta = rho * d_samples * du;
+    for (int i = 0; i < a_in; ++i) {
+      const double di = i;
+      ax->pre[static_cast<size_t>(i) * L + l] = cis(rho * d_samples * u0 * di + 0.5 * theta * di * di);
+    }
+    std::fill(h.begin(), h.end(), zd());
+    for (int k = -(a_in - 1); k <= a_out - 1; ++k) {
+      const double dk = k;
+      h[((k % P) + P) % P] = cis(-0.5 * theta * dk * dk);
+    }
+    fft64(h.data(), P, -1);
+    for (int i = 0; i < P; ++i) ax->H[static_cast<size_t>(i) * L + l] = h[i] / static_cast<double>(P);
+    for (int a = 0; a < a_out; ++a) {
+      const double da = a;
+      ax->post[static_cast<size_t>(a) * L + l] =
+          cis(rho * d_samples * pos0 * (u0 + da * du) + 0.5 * theta * da * da);
+    }
+  }
+}
+
+// beta = A^{-1} r through the Gohberg-Semencul form with generator x
+// (x0 = x[0] real), circulant-embedded in P >= 2L - 1 points; float64.
+void gs_apply(const std::vector<zd>& x, const std::vector<zd>& r, int L, int P, std::vector<zd>* out) {
+  std::vector<zd> g1(P), g2(P), v(P), a(P), b(P);
+  std::copy(x.begin(), x.end(), g1.begin());
+  for (int i = 1; i < L; ++i) g2[i] = std::conj(x[L - i]);
+  std::copy(r.begin(), r.end(), v.begin());
+  fft64(g1.data(), P, -1);
+  fft64(g2.data(), P, -1);
+  fft64(v.data(), P, -1);
+  for (int i = 0; i < P; ++i) {
+    a[i] = std::conj(g1[i]) * v[i];
+    b[i] = std::conj(g2[i]) * v[i];
+  }
+  fft64(a.data(), P, +1);
+  fft64(b.data(), P, +1);
+  for (int i = 0; i < P; ++i) {
+    const bool keep = i < L;
+    a[i] = keep ? a[i] / static_cast<double>(P) : zd();
+    b[i] = keep ? b[i] / static_cast<double>(P) : zd();
+  }
+  fft64(a.data(), P, -1);
+  fft64(b.data(), P, -1);
+  for (int i = 0; i < P; ++i) v[i] = g1[i] * a[i] - g2[i] * b[i];
+  fft64(v.data(), P, +1);
+  out->resize(L);
+  const double s = 1.0 / (static_cast<double>(P) * x[0].real());
+  for (int i = 0; i < L; ++i) (*out)[i] = v[i] * s;
+}
+
+// One step of iterative refinement of x ~ A^{-1} e_0: the residual
+// e_0 - A x is formed exactly enough in long double (O(L^2)), and the
+// correction solves A dx = r with the Gohberg-Semencul form of x itself.
+// Levinson's forward error grows like cond(A) u; the refined generator is
+// accurate to a few u even when cond(A) ~ 1e9 (delta of 1e-5).
+void refine_generator(const zd* col, int L, int P, std::vector<zd>* x) {
+  using ld = long double;
+  std::vector<zd> r(L);
+  for (int i = 0; i < L; ++i) {
+    ld re = (i == 0) ? 1.0L : 0.0L, im = 0.0L;
+    for (int k = 0; k < L; ++k) {
+      // A[i][k] = col[i-k] for i >= k, conj(col[k-i]) otherwise
+      const zd a = (i >= k) ? col[i - k] : std::conj(col[k - i]);
+      const ld ar = a.real(), ai = a.imag(), xr = (*x)[k].real(), xi = (*x)[k].imag();
+      re -= ar * xr - ai * xi;
+      im -= ar * xi + ai * xr;
+    }
+    r[i] = zd(static_cast<double>(re), static_cast<double>(im));
+  }
+  std::vector<zd> dx;
+  gs_apply(*x, r, L, P, &dx);
+  for (int i = 0; i < L; ++i) (*x)[i] += dx[i];
+  (*x)[0] = zd((*x)[0].real(), 0.0);
+}
+
+}  // namespace
+
+void fft64(zd* a, int n, int sign) {
+  // iterative radix-2, bit-reversed input order, twiddles from direct cos/sin
+  for (int i = 1, j = 0; i < n; ++i) {
+    int bit = n >> 1;
+    for (; j & bit; bit >>= 1) j ^= bit;
+    j ^= bit;
+    if (i < j) std::swap(a[i], a[j]);
+  }
+  std::vector<zd> w(n / 2 > 0 ? n / 2 : 1);
+  for (int k = 0; k < n / 2; ++k) w[k] = cis(sign * 2.0 * kPi * k / n);
+  for (int len = 2; len <= n; len <<= 1) {
+    const int half = len >> 1;
+    const int step = n / len;
+    for (int i = 0; i < n; i += len) {
+      for (int k = 0; k < half; ++k) {
+        const zd u = a[i + k];
+        const zd v = a[i + k + half] * w[k * step];
+        a[i + k] = u + v;
+        a[i + k + half] = u - v;
+      }
+    }
+  }
+}
+
+bool levinson_first_column(const zd* col, int L, zd* x) {
+  // T a_k = e_0 * err_k for the leading (k+1) x (k+1) block, a_k[0] = 1;
+  // a_{k+1} = [a_k; 0] - g [0; J conj(a_k)], g = eta / err,
+  // eta = sum_i col[k+1-i] a_k[i], err_{k+1} = err_k - g conj(eta).
+  std::vector<zd> a(L, zd());
+  a[0] = 1.0;
+  double err = col[0].real();
+  if (!(err > 0.0)) return false;
+  for (int k = 0; k + 1 < L; ++k) {
+    zd eta = 0.0;
+    for (int i = 0; i <= k; ++i) eta += col[k + 1 - i] * a[i];
+    const zd g = eta / err;
+    // pairwise in-place update of a[i] and a[k+1-i]
+    for (int i = 0, j = k + 1; i <= j; ++i, --j) {
+      const zd ai = a[i], aj = a[j];
+      if (i == j) {
+        a[i] = ai - g * std::conj(aj);
+      } else {
+        a[i] = ai - g * std::conj(aj);
+        a[j] = aj - g * std::conj(ai);
+      }
+    }
+    err -= (g * std::conj(eta)).real();
+    if (!(err > 0.0)) return false;
+  }
+  for (int i = 0; i < L; ++i) x[i] = a[i] / err;
+  return true;
+}
+
+fbst_status resolve_params(int M, int N, int B, const fbst_geometry* geom, const fbst_band* band,
+                           const fbst_grid* grid, const fbst_options* opt, Params* out,
+                           std::string* msg) {
+  Params p;
+  if (M < 1 || N < 1 || B < 1) {
+    *msg = "M, N and B must be >= 1";
+    return FBST_E_INVALID;
+  }
+  if (!band) {
+    *msg = "band must not be NULL";
+    return FBST_E_INVALID;
+  }
+  if (!(band->fc >= 0.0) || !(band->omega > 0.0) || !(band->ts > 0.0) ||
+      band->ts > 1.0 / (2.0 * band->omega) * (1.0 + 1e-12) || !std::isfinite(band->fc)) {
+    *msg = "band needs fc >= 0, omega > 0 and 0 < ts <= 1/(2 omega)";
+    return FBST_E_INVALID;
+  }
+  p.M = M;
+  p.N = N;
+  p.B = B;
+  p.fc = band->fc;
+  p.omega = band->omega;
+  p.ts = band->ts;
+  p.eps = 1.01;
+  p.L = 2 * N;
+  p.delta = 1e-5;
+  p.prec = FBST_PREC_FP32;
+  if (opt) {
+    if (opt->eps != 0.0) p.eps = opt->eps;
+    if (opt->L != 0) p.L = opt->L;
+    p.delta = opt->delta;
+    p.prec = opt->precision;
+    p.flags = opt->flags;
+  }
+  if (!(p.eps > 0.0) || !std::isfinite(p.eps)) {
+    *msg = "eps must be > 0";
+    return FBST_E_INVALID;
+  }
+  if (p.L < 2 || (p.L % 2) != 0) {
+    *msg = "L must be even and >= 2";
+    return FBST_E_INVALID;
+  }
+  if (!(p.delta > 0.0) || !std::isfinite(p.delta)) {
+    *msg = "delta must be > 0";
+    return FBST_E_INVALID;
+  }
+  if (p.prec < FBST_PREC_FP32 || p.prec > FBST_PREC_FP16_SPLIT) {
+    *msg = "unknown precision";
+    return FBST_E_INVALID;
+  }
+  const double dflt = 1.0 / (2.0 * (p.fc + p.omega));
+  if (!geom) {
+    p.kind = FBST_LINE;
+    p.mx = M;
+    p.my = 1;
+    p.dx = dflt;
+  } else {
+    p.kind = geom->kind;
+    p.mx = geom->mx;
+    p.my = geom->my;
+    p.dx = geom->dx != 0.0 ? geom->dx : dflt;
+    p.dy = geom->dy != 0.0 ? geom->dy : dflt;
+    p.x0 = geom->x0;
+    p.y0 = geom->y0;
+    if (p.kind != FBST_LINE && p.kind != FBST_GRID) {
+      *msg = "unknown geometry kind";
+      return FBST_E_INVALID;
+    }
+    if (p.kind == FBST_LINE) {
+      if (p.mx != M || p.my != 1) {
+        *msg = "a line needs mx == M and my == 1";
+        return FBST_E_INVALID;
+      }
+      p.dy = 0.0;
+      p.y0 = 0.0;
+    } else if (p.mx < 1 || p.my < 1 || 1LL * p.mx * p.my != M) {
+      *msg = "a grid needs mx * my == M";
+      return FBST_E_INVALID;
+    }
+    if (!std::isfinite(p.dx) || !std::isfinite(p.dy) || !std::isfinite(p.x0) || !std::isfinite(p.y0)) {
+      *msg = "geometry values must be finite";
+      return FBST_E_INVALID;
+    }
+  }
+  if (!grid) {
+    if (p.kind == FBST_GRID) {
+      *msg = "a grid geometry needs an explicit beam grid (bu x bv)";
+      return FBST_E_INVALID;
+    }
+    p.bu = B;
+    p.bv = 1;
+    default_grid(B, &p.u0, &p.du);
+  } else {
+    p.bu = grid->bu;
+    p.bv = grid->bv;
+    if (p.bu < 1 || p.bv < 1 || 1LL * p.bu * p.bv != B) {
+      *msg = "grid needs bu * bv == B";
+      return FBST_E_INVALID;
+    }
+    if (p.kind == FBST_LINE && p.bv != 1) {
+      *msg = "a line needs bv == 1";
+      return FBST_E_INVALID;
+    }
+    if (grid->du == 0.0) default_grid(p.bu, &p.u0, &p.du);
+    else { p.u0 = grid->u0; p.du = grid->du; }
+    if (p.kind == FBST_GRID) {
+      if (grid->dv == 0.0) default_grid(p.bv, &p.v0, &p.dv);
+      else { p.v0 = grid->v0; p.dv = grid->dv; }
+    }
+    if (!std::isfinite(p.u0) || !std::isfinite(p.du) || !std::isfinite(p.v0) || !std::isfinite(p.dv)) {
+      *msg = "grid values must be finite";
+      return FBST_E_INVALID;
+    }
+  }
+  p.p1 = next_pow2(static_cast<long long>(p.N) + p.L - 1);
+  p.p2x = next_pow2(static_cast<long long>(p.mx) + p.bu - 1);
+  p.p2y = p.kind == FBST_GRID ? next_pow2(static_cast<long long>(p.my) + p.bv - 1) : 0;
+  p.p3 = next_pow2(std::max(2LL * p.L - 1, static_cast<long long>(p.L) + p.N - 1));
+  p.p2x = std::max(p.p2x, 32);
+  if (p.kind == FBST_GRID) p.p2y = std::max(p.p2y, 32);
+  p.p1 = std::max(p.p1, 32);
+  p.p3 = std::max(p.p3, 32);
+  if (p.prec == FBST_PREC_BF16_SPLIT || p.prec == FBST_PREC_FP16_SPLIT) {
+    *msg = "the bf16/fp16 split-precision stage 1a is not available in this build";
+    return FBST_E_UNSUPPORTED;
+  }
+  const int lim1 = (p.prec == FBST_PREC_FP64) ? 8192 : PMAX;
+  const int lim2 = (p.prec == FBST_PREC_FP32) ? PMAX : 8192;
+  if (p.p1 > lim1 || p.p2x > lim1 || p.p2y > lim1 || p.p3 > lim2) {
+    *msg = "an FFT size exceeds what one workgroup holds in LDS for this precision";
+    return FBST_E_UNSUPPORTED;
+  }
+  *out = p;
+  return FBST_OK;
+}
+
+fbst_status build_tables(const Params& p, bool keep_gram_gen, HostTables* t, std::string* msg) {
+  const int N = p.N, L = p.L, B = p.B;
+  const double lp0 = 1.0 - 0.5 * L;             // l' of the first basis frequency
+  // kappa = 2 pi eps / L rad per sample and per unit of l'; phases of the
+  // chirps are (kappa/2) k^2 = pi * (eps / L) * k^2.
+  const double c_pi = p.eps / L;
+
+  // --- stage 1a: Yhat[i] = post1[i] sum_n (x[n] pre1[n]) h1[i - n] -------------
+  t->pre1.resize(N);
+  for (int n = 0; n < N; ++n) t->pre1[n] = cispi(-c_pi * static_cast<double>(1LL * n * n));
+  // h1[s] = exp(+j (kappa/2) (s + lp0)^2) for s in [-(N-1), L-1]
+  t->H1 = kernel_spectrum_int(p.p1, -(N - 1), L - 1, static_cast<long long>(lp0), c_pi);
+  t->post1.resize(L);
+  for (int i = 0; i < L; ++i) {
+    const long long q = static_cast<long long>(i + lp0);
+    t->post1[i] = cispi(-c_pi * static_cast<double>(q * q));
+  }
+
+  // --- stage 1b: spatial chirp-z per axis ------------------------------------
+  build_axis(p, p.mx, p.bu, p.x0, p.dx / p.ts, p.u0, p.du, p.p2x, &t->ax);
+  if (p.kind == FBST_GRID) build_axis(p, p.my, p.bv, p.y0, p.dy / p.ts, p.v0, p.dv, p.p2y, &t->ay);
+
+  // --- beams ---------------------------------------------------------------
+  t->u.resize(B);
+  t->v.resize(B);
+  for (int a = 0; a < p.bu; ++a)
+    for (int c = 0; c < p.bv; ++c) {
+      t->u[a * p.bv + c] = p.u0 + a * p.du;
+      t->v[a * p.bv + c] = (p.kind == FBST_GRID) ? p.v0 + c * p.dv : 0.0;
+    }
+
+  // --- stage 2 F_u chirp-z: b[n] = post3[n] sum_i (beta[i] pre3[i]) h3[n - i] -----
+  t->pre3.resize(L);
+  for (int i = 0; i < L; ++i) {
+    const long long q = static_cast<long long>(i + lp0);
+    t->pre3[i] = cispi(c_pi * static_cast<double>(q * q));
+  }
+  // h3[s] = exp(-j (kappa/2) (s - lp0)^2) for s in [-(L-1), N-1]
+  t->H3 = kernel_spectrum_int(p.p3, -(L - 1), N - 1, -static_cast<long long>(lp0), -c_pi);
+  t->post3.resize(N);
+  for (int n = 0; n < N; ++n) t->post3[n] = cispi(c_pi * static_cast<double>(1LL * n * n));
+
+  // --- stage 2 Toeplitz generators (Sec. V) -----------------------------------
+  // c_b(d) = [sum_n e^{-j kd n}] [sum_k e^{j kd u px_k}] [sum_k2 e^{j kd v py_k2}],
+  // kd = 2 pi eps d / L (per sample), px, py in samples; A_b = toeplitz(c_b) + delta I.
+  const int P3 = p.p3;
+  t->G1.assign(static_cast<size_t>(B) * P3, zd());
+  t->G2.assign(static_cast<size_t>(B) * P3, zd());
+  if (keep_gram_gen) {
+    t->gram.assign(static_cast<size_t>(B) * L, zd());
+    t->gen.assign(static_cast<size_t>(B) * L, zd());
+  } else {
+    t->gram.clear();
+    t->gen.clear();
+  }
+  std::vector<zd> time_sum(L);
+  for (int d = 0; d < L; ++d) {
+    const double kd = 2.0 * kPi * p.eps * d / L;
+    time_sum[d] = geometric_sum(N, 0.0, -kd);
+  }
+  const double dxs = p.dx / p.ts, dys = p.dy / p.ts;
+  std::atomic<bool> ok{true};
+  std::mutex fail_mu;
+  std::string fail;
+  // refine the Levinson generators when cond(A) ~ 2MN/delta makes their
+  // float64 forward error visible (above ~1e6)
+  const bool refine = 2.0 * p.M * p.N / p.delta > 1e6;
+  auto work = [&](int b0, int b1) {
+    std::vector<zd> col(L), x(L), buf(P3);
+    for (int b = b0; b < b1; ++b) {
+      const double ub = t->u[b], vb = t->v[b];
+      for (int d = 0; d < L; ++d) {
+        const double kd = 2.0 * kPi * p.eps * d / L;
+        zd sx = geometric_sum(p.mx, kd * ub * p.x0 * dxs, kd * ub * dxs);
+        zd sy = (p.kind == FBST_GRID) ? geometric_sum(p.my, kd * vb * p.y0 * dys, kd * vb * dys)
+                                      : zd(1.0, 0.0);
+        col[d] = time_sum[d] * sx * sy;
+      }
+      col[0] = zd(col[0].real() + p.delta, 0.0);
+      if (keep_gram_gen) std::copy(col.begin(), col.end(), t->gram.begin() + static_cast<size_t>(b) * L);
+      if (!ok.load()) return;
+      if (!levinson_first_column(col.data(), L, x.data())) {
+        std::lock_guard<std::mutex> lk(fail_mu);
+        ok = false;
+        fail = "Toeplitz system not positive definite in float64 (delta too small?)";
+        return;
+      }
+      if (refine) refine_generator(col.data(), L, P3, &x);
+      if (keep_gram_gen) std::copy(x.begin(), x.end(), t->gen.begin() + static_cast<size_t>(b) * L);
+      const double x0r = x[0].real();
+      const double scale = 1.0 / (P3 * std::sqrt(x0r));
+      // G1 = FFT(x zero-padded)
+      std::fill(buf.begin(), buf.end(), zd());
+      std::copy(x.begin(), x.end(), buf.begin());
+      fft64(buf.data(), P3, -1);
+      for (int i = 0; i < P3; ++i) t->G1[static_cast<size_t>(b) * P3 + i] = buf[i] * scale;
+      // G2 = FFT(y~ zero-padded), y~ = (0, conj x_{L-1}, ..., conj x_1)
+      std::fill(buf.begin(), buf.end(), zd());
+      for (int i = 1; i < L; ++i) buf[i] = std::conj(x[L - i]);
+      fft64(buf.data(), P3, -1);
+      for (int i = 0; i < P3; ++i) t->G2[static_cast<size_t>(b) * P3 + i] = buf[i] * scale;
+    }
+  };
+  const int nt = std::max(1, std::min<int>(static_cast<int>(std::thread::hardware_concurrency()), B));
+  const int nthreads = std::min(nt, 64);
+  if (nthreads <= 1 || 1LL * B * L * L < 4'000'000LL) {
+    work(0, B);
+  } else {
+    std::vector<std::thread> th;
+    const int per = (B + nthreads - 1) / nthreads;
+    for (int i = 0; i < nthreads; ++i) {
+      const int b0 = i * per, b1 = std::min(B, b0 + per);
+      if (b0 < b1) th.emplace_back(work, b0, b1);
+    }
+    for (auto& x : th) x.join();
+  }
+  if (!ok) {
+    *msg = fail;
+    return FBST_E_INVALID;
+  }
+  return FBST_OK;
+}
+
+}  // namespace fbst

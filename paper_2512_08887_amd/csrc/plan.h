@@ -1,0 +1,82 @@
+// Plan object and FP64 host table builder of the FBST library.
+#pragma once
+
+#include <complex>
+#include <cstddef>
+#include <string>
+#include <vector>
+
+#include "../../include/fbst.h"
+
+namespace fbst {
+
+using zd = std::complex<double>;
+
+// One axis of the stage-1b spatial chirp-z (Sec. IV; App. B per axis):
+// out[a] = sum_i in[i] exp(j rho_l u_a pos_i), pos_i = (o + i) d samples,
+// u_a = u0 + a du.  Tables are l-fastest: pre [a_in][L], H [P][L], post [a_out][L].
+struct AxisTables {
+  int a_in = 0, a_out = 0, P = 0;
+  std::vector<zd> pre, H, post;
+};
+
+struct HostTables {
+  std::vector<zd> pre1, H1, post1;        // stage 1a: [N], [P1], [L]
+  AxisTables ax, ay;                      // stage 1b (ay unused for a line)
+  std::vector<zd> G1, G2;                 // stage 2: [B][P3] spectra of x_b and y~_b
+  std::vector<zd> pre3, H3, post3;        // F_u chirp-z: [L], [P3], [N]
+  std::vector<double> u, v;               // beam direction cosines [B]
+  std::vector<zd> gram, gen;              // [B][L] (kept on request)
+};
+
+struct Params {
+  int M = 0, N = 0, B = 0, L = 0;
+  fbst_geom_kind kind = FBST_LINE;
+  int mx = 0, my = 0, bu = 0, bv = 0;
+  double dx = 0, dy = 0, x0 = 0, y0 = 0;  // seconds per unit direction cosine; element offsets
+  double fc = 0, omega = 0, ts = 0;
+  double u0 = 0, du = 0, v0 = 0, dv = 0;
+  double eps = 0, delta = 0;
+  fbst_precision prec = FBST_PREC_FP32;
+  unsigned flags = 0;
+  int p1 = 0, p2x = 0, p2y = 0, p3 = 0;
+};
+
+// Validate and complete the user parameters (defaults, FFT sizes).  Returns
+// FBST_OK or an error with *msg set.
+fbst_status resolve_params(int M, int N, int B, const fbst_geometry* geom, const fbst_band* band,
+                           const fbst_grid* grid, const fbst_options* opt, Params* out,
+                           std::string* msg);
+
+// Build every table in float64.  keep_gram_gen: also fill gram/gen.
+fbst_status build_tables(const Params& p, bool keep_gram_gen, HostTables* t, std::string* msg);
+
+// Levinson recursion for a Hermitian positive definite Toeplitz matrix with
+// first column col: returns x = A^{-1} e_0.  false if a pivot is not positive.
+bool levinson_first_column(const zd* col, int L, zd* x);
+
+// In-place power-of-two DFT in float64, sign = -1 (forward) or +1 (unscaled inverse).
+void fft64(zd* a, int n, int sign);
+
+}  // namespace fbst
+
+// The plan: parameters, optional FP64 host tables and device tables.
+struct fbst_plan {
+  fbst::Params p;
+  bool host_only = false;
+  fbst::HostTables host;           // emptied after upload unless tables are kept
+  bool kept = false;
+  // device memory: one allocation holding every table and the own workspace
+  void* dev = nullptr;
+  size_t dev_bytes = 0;
+  size_t ws_bytes_per_block = 0;
+  void* own_ws = nullptr;
+  // device table pointers (element type per stage precision)
+  const void* tw1 = nullptr;       // twiddles in the stage-1 type
+  const void* tw2 = nullptr;       // twiddles in the stage-2 type
+  const void *pre1 = nullptr, *H1 = nullptr, *post1 = nullptr;
+  const void *axp = nullptr, *axH = nullptr, *axq = nullptr;
+  const void *ayp = nullptr, *ayH = nullptr, *ayq = nullptr;
+  const void *G1 = nullptr, *G2 = nullptr, *pre3 = nullptr, *H3 = nullptr, *post3 = nullptr;
+  int device = 0;
+};

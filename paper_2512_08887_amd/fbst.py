@@ -1,0 +1,291 @@
+"""Python binding of libfbst.so (include/fbst.h): argument marshalling only.
+
+The functions keep the C names; they take device pointers as Python ints.
+``Plan`` is a small convenience around them that takes torch tensors and the
+current torch stream (PyTorch provides device memory and streams; every step
+of the transformation runs in the library's HIP kernels).
+
+The library must be built (``python -m paper_2512_08887_amd.build``); there is
+no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from ctypes import POINTER, byref, c_char_p, c_double, c_int, c_size_t, c_uint, c_void_p
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libfbst.so")
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "fbst.h")
+
+FBST_OK, FBST_E_INVALID, FBST_E_UNSUPPORTED, FBST_E_NOMEM, FBST_E_DEVICE = 0, -1, -2, -3, -4
+FBST_LINE, FBST_GRID = 0, 1
+FBST_PREC_FP32, FBST_PREC_FP64_STAGE2, FBST_PREC_FP64, FBST_PREC_BF16_SPLIT, FBST_PREC_FP16_SPLIT = range(5)
+FBST_FLAG_HOST_ONLY, FBST_FLAG_KEEP_HOST_TABLES = 1, 2
+FBST_TABLE_BEAM_U, FBST_TABLE_BEAM_V, FBST_TABLE_GRAM, FBST_TABLE_GENERATOR = 0, 1, 2, 3
+
+PRECISIONS = {"fp32": FBST_PREC_FP32, "fp64_stage2": FBST_PREC_FP64_STAGE2, "fp64": FBST_PREC_FP64,
+              "bf16_split": FBST_PREC_BF16_SPLIT, "fp16_split": FBST_PREC_FP16_SPLIT}
+
+
+class fbst_geometry(ctypes.Structure):
+    _fields_ = [("kind", c_int), ("mx", c_int), ("my", c_int), ("dx", c_double), ("dy", c_double),
+                ("x0", c_double), ("y0", c_double)]
+
+
+class fbst_band(ctypes.Structure):
+    _fields_ = [("fc", c_double), ("omega", c_double), ("ts", c_double)]
+
+
+class fbst_grid(ctypes.Structure):
+    _fields_ = [("bu", c_int), ("bv", c_int), ("u0", c_double), ("du", c_double), ("v0", c_double),
+                ("dv", c_double)]
+
+
+class fbst_options(ctypes.Structure):
+    _fields_ = [("eps", c_double), ("L", c_int), ("delta", c_double), ("precision", c_int),
+                ("flags", c_uint)]
+
+
+class fbst_info(ctypes.Structure):
+    _fields_ = [("M", c_int), ("N", c_int), ("B", c_int), ("L", c_int), ("mx", c_int), ("my", c_int),
+                ("bu", c_int), ("bv", c_int), ("p1", c_int), ("p2x", c_int), ("p2y", c_int),
+                ("p3", c_int), ("precision", c_int), ("io_elem_bytes", c_size_t),
+                ("device_bytes", c_size_t), ("workspace_per_block", c_size_t)]
+
+
+class FbstError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"fbst status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load libfbst.so once (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2512_08887_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        L.fbst_plan_create.argtypes = [c_int, c_int, c_int, POINTER(fbst_geometry), POINTER(fbst_band),
+                                       POINTER(fbst_grid), POINTER(fbst_options), POINTER(c_void_p)]
+        L.fbst_plan_create.restype = c_int
+        L.fbst_execute.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
+        L.fbst_execute.restype = c_int
+        L.fbst_execute_batched.argtypes = [c_void_p, c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p]
+        L.fbst_execute_batched.restype = c_int
+        L.fbst_execute_stage.argtypes = [c_void_p, c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p]
+        L.fbst_execute_stage.restype = c_int
+        L.fbst_workspace_bytes.argtypes = [c_void_p, c_int]
+        L.fbst_workspace_bytes.restype = c_size_t
+        L.fbst_plan_device_bytes.argtypes = [c_void_p]
+        L.fbst_plan_device_bytes.restype = c_size_t
+        L.fbst_plan_info.argtypes = [c_void_p, POINTER(fbst_info)]
+        L.fbst_plan_info.restype = c_int
+        L.fbst_plan_table.argtypes = [c_void_p, c_int, c_void_p, c_size_t]
+        L.fbst_plan_table.restype = c_int
+        L.fbst_destroy.argtypes = [c_void_p]
+        L.fbst_destroy.restype = None
+        L.fbst_last_error.argtypes = []
+        L.fbst_last_error.restype = c_char_p
+        L.fbst_version.argtypes = []
+        L.fbst_version.restype = c_char_p
+        _lib = L
+    return _lib
+
+
+def header_functions() -> list[str]:
+    """Names of the functions include/fbst.h declares."""
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(fbst_[a-z_]+)\s*\(", txt)))
+
+
+def _check(st: int):
+    if st != FBST_OK:
+        raise FbstError(st, lib().fbst_last_error().decode())
+
+
+def fbst_last_error() -> str:
+    return lib().fbst_last_error().decode()
+
+
+def fbst_version() -> str:
+    return lib().fbst_version().decode()
+
+
+def fbst_plan_create(M, N, B, geometry=None, band=None, grid=None, options=None) -> int:
+    h = c_void_p()
+    g = byref(geometry) if geometry is not None else None
+    b = byref(band) if band is not None else None
+    gr = byref(grid) if grid is not None else None
+    o = byref(options) if options is not None else None
+    _check(lib().fbst_plan_create(M, N, B, g, b, gr, o, byref(h)))
+    return h.value
+
+
+def fbst_plan_create_status(M, N, B, geometry=None, band=None, grid=None, options=None):
+    """Like fbst_plan_create but returns (status, handle or None) without raising."""
+    h = c_void_p()
+    g = byref(geometry) if geometry is not None else None
+    b = byref(band) if band is not None else None
+    gr = byref(grid) if grid is not None else None
+    o = byref(options) if options is not None else None
+    st = lib().fbst_plan_create(M, N, B, g, b, gr, o, byref(h))
+    return st, h.value
+
+
+def fbst_execute(plan, x, beams, workspace=0, stream=0):
+    _check(lib().fbst_execute(plan, x, beams, workspace or None, stream or None))
+
+
+def fbst_execute_batched(plan, nblocks, max_chunk, x, beams, workspace=0, stream=0):
+    _check(lib().fbst_execute_batched(plan, nblocks, max_chunk, x, beams, workspace or None,
+                                      stream or None))
+
+
+def fbst_execute_stage(plan, stage, nblocks, inp, out, workspace=0, stream=0):
+    _check(lib().fbst_execute_stage(plan, stage, nblocks, inp, out, workspace or None, stream or None))
+
+
+def fbst_workspace_bytes(plan, nblocks) -> int:
+    return int(lib().fbst_workspace_bytes(plan, nblocks))
+
+
+def fbst_plan_device_bytes(plan) -> int:
+    return int(lib().fbst_plan_device_bytes(plan))
+
+
+def fbst_plan_info(plan) -> fbst_info:
+    info = fbst_info()
+    _check(lib().fbst_plan_info(plan, byref(info)))
+    return info
+
+
+def fbst_plan_table(plan, table, out_array):
+    """Copy a kept FP64 host table into a numpy array (float64 or complex128)."""
+    _check(lib().fbst_plan_table(plan, table, out_array.ctypes.data, out_array.nbytes))
+    return out_array
+
+
+def fbst_destroy(plan):
+    lib().fbst_destroy(plan)
+
+
+# ---------------------------------------------------------------------------
+# Convenience layer over torch tensors.
+# ---------------------------------------------------------------------------
+
+def make_band(fc, omega, ts=1.0):
+    return fbst_band(fc, omega, ts)
+
+
+def make_line(M, dx=0.0, x0=0.0):
+    return fbst_geometry(FBST_LINE, M, 1, dx, 0.0, x0, 0.0)
+
+
+def make_grid_geometry(mx, my, dx=0.0, dy=0.0, x0=0.0, y0=0.0):
+    return fbst_geometry(FBST_GRID, mx, my, dx, dy, x0, y0)
+
+
+def make_beam_grid(bu, bv=1, u0=0.0, du=0.0, v0=0.0, dv=0.0):
+    return fbst_grid(bu, bv, u0, du, v0, dv)
+
+
+def make_options(delta, eps=1.01, L=0, precision="fp32", flags=0):
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    return fbst_options(eps, L, delta, prec, flags)
+
+
+class Plan:
+    """Owns one fbst plan; executes on torch tensors on the current stream."""
+
+    def __init__(self, M, N, B, *, band, geometry=None, grid=None, options=None):
+        self.handle = fbst_plan_create(M, N, B, geometry, band, grid, options)
+        self.info = fbst_plan_info(self.handle)
+        self.M, self.N, self.B, self.L = M, N, B, self.info.L
+
+    @property
+    def complex_dtype(self):
+        import torch
+        return torch.complex128 if self.info.io_elem_bytes == 16 else torch.complex64
+
+    @property
+    def stage1_dtype(self):
+        import torch
+        return torch.complex128 if self.info.precision == FBST_PREC_FP64 else torch.complex64
+
+    def workspace(self, nblocks=1):
+        import torch
+        nbytes = fbst_workspace_bytes(self.handle, nblocks)
+        return torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+
+    @staticmethod
+    def _stream():
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+
+    def _check_in(self, x, shape):
+        if not x.is_cuda or not x.is_contiguous() or x.dtype != self.complex_dtype or tuple(x.shape[-2:]) != shape:
+            raise ValueError(f"expected a contiguous {self.complex_dtype} CUDA tensor of shape [..., {shape[0]}, {shape[1]}]")
+
+    def execute(self, x, beams=None, workspace=None):
+        import torch
+        self._check_in(x, (self.M, self.N))
+        if beams is None:
+            beams = torch.empty((self.B, self.N), dtype=self.complex_dtype, device=x.device)
+        fbst_execute(self.handle, x.data_ptr(), beams.data_ptr(),
+                     workspace.data_ptr() if workspace is not None else 0, self._stream())
+        return beams
+
+    def execute_batched(self, x, beams=None, workspace=None, max_chunk=0):
+        import torch
+        self._check_in(x, (self.M, self.N))
+        nb = x.shape[0]
+        chunk = nb if max_chunk <= 0 else min(max_chunk, nb)
+        if beams is None:
+            beams = torch.empty((nb, self.B, self.N), dtype=self.complex_dtype, device=x.device)
+        if workspace is None and chunk > 1:
+            workspace = self.workspace(chunk)
+        fbst_execute_batched(self.handle, nb, chunk, x.data_ptr(), beams.data_ptr(),
+                             workspace.data_ptr() if workspace is not None else 0, self._stream())
+        return beams
+
+    def stage(self, stage, inp, nblocks=1, out=None, workspace=None):
+        import torch
+        shapes = {0: (self.M, self.L), 1: (self.B, self.L), 2: (self.B, self.N)}
+        odt = self.complex_dtype if stage == 2 else self.stage1_dtype
+        if out is None:
+            out = torch.empty((nblocks,) + shapes[stage], dtype=odt, device=inp.device)
+        if workspace is None and stage == 1 and self.info.bv > 1:
+            workspace = self.workspace(nblocks)
+        fbst_execute_stage(self.handle, stage, nblocks, inp.data_ptr(), out.data_ptr(),
+                           workspace.data_ptr() if workspace is not None else 0, self._stream())
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            fbst_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def plan_for_config(cfg, *, delta=None, precision="fp32", eps=None, flags=0):
+    """Plan for a named synthetic workload (synth.Config)."""
+    band = make_band(cfg.band.fc, cfg.band.omega, cfg.band.ts)
+    d = cfg.delta_noise if delta is None else delta
+    opts = make_options(d, eps=cfg.eps if eps is None else eps, L=cfg.L, precision=precision, flags=flags)
+    if cfg.kind == "ura":
+        geom = make_grid_geometry(cfg.mx, cfg.my)
+        grid = make_beam_grid(cfg.bu, cfg.bv)
+        return Plan(cfg.M, cfg.N, cfg.B, band=band, geometry=geom, grid=grid, options=opts)
+    return Plan(cfg.M, cfg.N, cfg.B, band=band, geometry=make_line(cfg.M), options=opts)

@@ -11,13 +11,13 @@ code the CPU oracle and the GPU library both see.
 
 Units: everything is expressed with the sample period T_s = 1 and the baseband
 half-bandwidth Omega = 1/2 (critical sampling, as in the experiments of
-Sec. V), so a fractional bandwidth FB = 2 Omega / f_c gives f_c = 1 / FB.
+Sec. VI), so a fractional bandwidth FB = 2 Omega / f_c gives f_c = 1 / FB.
 
 Source waveforms follow the sum-of-sinusoids model the paper uses for its
-experiments (Sec. V, footnote on the source model): s(t) = sum_i a_i
+experiments (Sec. VI, footnote on the source model): s(t) = sum_i a_i
 exp(j 2 pi f_i t) with f_i uniform on [-Omega, Omega] and a_i circular complex
 Gaussian with total power P.  Its covariance is exactly P sinc(2 Omega tau)
-for any number of terms, so it is the band-limited Gaussian process of Sec. VI
+for any number of terms, so it is the band-limited Gaussian process of Sec. VII
 in expectation, and it can be evaluated exactly at fractional delays.
 
 Random draws: numpy PCG64.  A scene draws, per source and in this order, its
@@ -192,7 +192,7 @@ class Scene:
 
 
 # ---------------------------------------------------------------------------
-# Named workloads, shaped like the experiments of Sec. V (critical sampling,
+# Named workloads, shaped like the experiments of Sec. VI (critical sampling,
 # f_c / f_s = 2 at fractional bandwidth 0.5, lambda/2 spacing at f_c + Omega,
 # N at least twice the aperture in samples), epsilon = 1.01 and gamma = 2.
 # ---------------------------------------------------------------------------

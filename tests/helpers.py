@@ -1,0 +1,37 @@
+"""Shared helpers of the test-suite (inputs, oracle problems, error measures)."""
+import numpy as np
+
+from oracle import direct as od
+import synth
+
+
+def rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def crandn(rng, *shape):
+    return (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)) / np.sqrt(2.0)
+
+
+def oracle_problem(cfg, delta, eps=None):
+    """The oracle's Problem for a synth.Config (its own geometry and grid code)."""
+    band = cfg.band
+    e = cfg.eps if eps is None else eps
+    if cfg.kind == "ura":
+        return od.grid_problem(cfg.mx, cfg.my, cfg.bu, cfg.bv, cfg.N, fc=band.fc, omega=band.omega,
+                               ts=band.ts, eps=e, gamma=cfg.gamma, delta=delta)
+    return od.line_problem(cfg.M, cfg.N, cfg.B, fc=band.fc, omega=band.omega, ts=band.ts, eps=e,
+                           gamma=cfg.gamma, delta=delta)
+
+
+def line_cfg(M, N, B, fb=0.5, sigma2=0.1, n_sources=2, index=90):
+    return synth.Config(f"line{M}x{N}x{B}", "ula", M=M, N=N, B=B, fb=fb, n_sources=n_sources,
+                        power_db_range=0.0, sigma2=sigma2, index=index)
+
+
+def grid_cfg(mx, my, bu, bv, N, fb=0.4, sigma2=0.1, n_sources=2, index=91):
+    return synth.Config(f"grid{mx}x{my}", "ura", M=mx * my, N=N, B=bu * bv, fb=fb,
+                        n_sources=n_sources, power_db_range=0.0, sigma2=sigma2, mx=mx, my=my,
+                        bu=bu, bv=bv, index=index)

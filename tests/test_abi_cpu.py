@@ -1,0 +1,168 @@
+"""CPU tests of the C ABI: the library loads, exports every declared symbol,
+validates its arguments, and its FP64 host plan tables (beam grid, Toeplitz
+generator c_b(d) + delta, Levinson generator x_b = A_b^{-1} e_0) agree with the
+oracle.  No GPU call is made: plans are created host-only."""
+import ctypes
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+from paper_2512_08887_amd import fbst as F
+from oracle import direct as od
+
+
+def test_library_exports_every_declared_symbol():
+    lib = F.lib()
+    names = F.header_functions()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(lib, n), n
+    assert F.fbst_version().startswith("fbst")
+
+
+def host_plan(M, N, B, *, fc=2.0, omega=0.5, delta=1e-3, eps=1.01, L=0, geometry=None, grid=None):
+    band = F.make_band(fc, omega, 1.0)
+    opts = F.make_options(delta, eps=eps, L=L, flags=F.FBST_FLAG_HOST_ONLY)
+    return F.fbst_plan_create(M, N, B, geometry, band, grid, opts)
+
+
+@pytest.mark.parametrize("M,N,B", [(8, 32, 8), (7, 20, 5), (16, 64, 12)])
+def test_host_tables_match_oracle_line(M, N, B):
+    h = host_plan(M, N, B, delta=1e-3)
+    try:
+        info = F.fbst_plan_info(h)
+        L = info.L
+        assert L == 2 * N
+        u = F.fbst_plan_table(h, F.FBST_TABLE_BEAM_U, np.zeros(B))
+        p = od.line_problem(M, N, B, fc=2.0, omega=0.5, delta=1e-3)
+        assert np.allclose(u, p.u, atol=1e-15)
+        gram = F.fbst_plan_table(h, F.FBST_TABLE_GRAM, np.zeros((B, L), complex))
+        gen = F.fbst_plan_table(h, F.FBST_TABLE_GENERATOR, np.zeros((B, L), complex))
+        for b in range(B):
+            A = od.toeplitz_system(p, b)
+            assert np.allclose(gram[b], A[:, 0], rtol=0, atol=1e-12 * np.abs(A[0, 0]))
+            x = od.generator(p, b)
+            assert np.linalg.norm(gen[b] - x) < 1e-8 * np.linalg.norm(x)
+    finally:
+        F.fbst_destroy(h)
+
+
+def test_host_tables_match_oracle_grid():
+    geom = F.make_grid_geometry(3, 4)
+    grid = F.make_beam_grid(3, 2)
+    h = host_plan(12, 16, 6, fc=2.5, geometry=geom, grid=grid)
+    try:
+        L = F.fbst_plan_info(h).L
+        p = od.grid_problem(3, 4, 3, 2, 16, fc=2.5, delta=1e-3)
+        u = F.fbst_plan_table(h, F.FBST_TABLE_BEAM_U, np.zeros(6))
+        v = F.fbst_plan_table(h, F.FBST_TABLE_BEAM_V, np.zeros(6))
+        assert np.allclose(u, p.u) and np.allclose(v, p.v)
+        gen = F.fbst_plan_table(h, F.FBST_TABLE_GENERATOR, np.zeros((6, L), complex))
+        for b in range(6):
+            x = od.generator(p, b)
+            assert np.linalg.norm(gen[b] - x) < 1e-8 * np.linalg.norm(x)
+    finally:
+        F.fbst_destroy(h)
+
+
+def test_gohberg_semencul_from_plan_generator():
+    """The plan's generator reproduces A^{-1} w through the Gohberg-Semencul
+    form (Sec. V) with circulant-embedded FFTs, as the stage-2 kernel uses it."""
+    M, N, B = 8, 24, 6
+    h = host_plan(M, N, B, delta=1e-2)
+    try:
+        L = F.fbst_plan_info(h).L
+        gen = F.fbst_plan_table(h, F.FBST_TABLE_GENERATOR, np.zeros((B, L), complex))
+        p = od.line_problem(M, N, B, fc=2.0, delta=1e-2)
+        rng = np.random.default_rng(0)
+        P = 2 * L
+        for b in range(B):
+            x = gen[b]
+            yt = np.zeros(L, complex)
+            yt[1:] = np.conj(x[:0:-1])
+            w = rng.standard_normal(L) + 1j * rng.standard_normal(L)
+            G1 = np.fft.fft(x, P)
+            G2 = np.fft.fft(yt, P)
+            V = np.fft.fft(w, P)
+            p1 = np.fft.ifft(np.conj(G1) * V)[:L]
+            p2 = np.fft.ifft(np.conj(G2) * V)[:L]
+            beta = np.fft.ifft(G1 * np.fft.fft(p1, P) - G2 * np.fft.fft(p2, P))[:L] / x[0].real
+            ref = od.solve(od.toeplitz_system(p, b), w)
+            assert np.linalg.norm(beta - ref) < 1e-9 * np.linalg.norm(ref)
+    finally:
+        F.fbst_destroy(h)
+
+
+def test_invalid_arguments():
+    band = F.make_band(2.0, 0.5, 1.0)
+    opts = F.make_options(1e-3, flags=F.FBST_FLAG_HOST_ONLY)
+    bad = [
+        dict(M=0, N=8, B=4, band=band, opts=opts),
+        dict(M=4, N=8, B=4, band=None, opts=opts),
+        dict(M=4, N=8, B=4, band=F.make_band(2.0, 0.5, 2.0), opts=opts),                  # ts > 1/(2 omega)
+        dict(M=4, N=8, B=4, band=band, opts=F.make_options(0.0, flags=1)),                # delta <= 0
+        dict(M=4, N=8, B=4, band=band, opts=F.make_options(1e-3, L=7, flags=1)),          # odd L
+        dict(M=4, N=8, B=4, band=band, opts=opts, geom=F.make_line(5)),                   # mx != M
+        dict(M=6, N=8, B=4, band=band, opts=opts, geom=F.make_grid_geometry(2, 3)),       # grid without beam grid
+        dict(M=6, N=8, B=4, band=band, opts=opts, geom=F.make_grid_geometry(2, 3),
+             grid=F.make_beam_grid(3, 2)),                                                # bu*bv != B
+        dict(M=4, N=8, B=4, band=band, opts=F.make_options(1e-3, precision=9, flags=1)),
+    ]
+    for case in bad:
+        st, hnd = F.fbst_plan_create_status(case["M"], case["N"], case["B"], case.get("geom"),
+                                            case["band"], case.get("grid"), case["opts"])
+        assert st == F.FBST_E_INVALID, (case, st)
+        assert hnd is None
+        assert F.fbst_last_error() != ""
+    # an FFT size beyond one workgroup's LDS is reported as unsupported
+    st, hnd = F.fbst_plan_create_status(4, 8192, 4, None, band, None,
+                                        F.make_options(1e-3, flags=F.FBST_FLAG_HOST_ONLY))
+    assert st == F.FBST_E_UNSUPPORTED and hnd is None
+
+
+def test_null_and_host_only_plan_calls():
+    lib = F.lib()
+    lib.fbst_destroy(None)                                  # no-op
+    assert lib.fbst_workspace_bytes(None, 1) == 0
+    assert lib.fbst_plan_device_bytes(None) == 0
+    assert lib.fbst_execute(None, None, None, None, None) == F.FBST_E_INVALID
+    h = host_plan(8, 16, 4)
+    try:
+        assert lib.fbst_execute(h, ctypes.c_void_p(16), ctypes.c_void_p(16), None, None) == F.FBST_E_INVALID
+        assert lib.fbst_execute_stage(h, 3, 1, ctypes.c_void_p(16), ctypes.c_void_p(16), None, None) == F.FBST_E_INVALID
+        info = F.fbst_plan_info(h)
+        assert (info.p1, info.p2x, info.p3) == (64, 32, 64)
+        assert F.fbst_workspace_bytes(h, 3) == 3 * (8 + 4) * 32 * 8
+    finally:
+        F.fbst_destroy(h)
+
+
+def test_generator_accurate_at_paper_delta():
+    """At the paper's delta = 1e-5 (cond(A) ~ 8e8 here) the plan's generator
+    x_b = A_b^{-1} e_0 is accurate to float64 working precision: it matches a
+    Cholesky solve of the plan's own Toeplitz matrix polished by iterative
+    refinement with long-double residuals (a plain Levinson recursion misses
+    by cond(A) * u ~ 1e-7..1e-5), and that matrix matches the oracle's A_b to
+    rounding."""
+    M, N, B = 16, 256, 16
+    h = host_plan(M, N, B, delta=1e-5)
+    try:
+        L = F.fbst_plan_info(h).L
+        gen = F.fbst_plan_table(h, F.FBST_TABLE_GENERATOR, np.zeros((B, L), complex))
+        gram = F.fbst_plan_table(h, F.FBST_TABLE_GRAM, np.zeros((B, L), complex))
+        p = od.line_problem(M, N, B, fc=2.0, delta=1e-5)
+        e0 = np.zeros(L, complex)
+        e0[0] = 1.0
+        for b in (0, 5, 8, 15):
+            A = od.toeplitz_system(p, b)
+            assert np.abs(gram[b] - A[:, 0]).max() < 1e-13 * np.abs(A[0, 0])
+            Ap = scipy.linalg.toeplitz(gram[b], np.conj(gram[b]))
+            x = od.solve(Ap, e0)
+            Al = Ap.astype(np.clongdouble)
+            for _ in range(3):
+                r = (e0 - Al @ x.astype(np.clongdouble)).astype(complex)
+                x = x + od.solve(Ap, r)
+            assert np.linalg.norm(gen[b] - x) < 1e-9 * np.linalg.norm(x)
+    finally:
+        F.fbst_destroy(h)

@@ -3,7 +3,7 @@
 Each test names the passage it checks.  None of them re-types the oracle's
 own formula: they use the explicit matrices, the paper's other printed forms
 (eq. DFT_1), library routines (scipy czt, numpy FFT), limits with textbook
-answers, physics of a plane wave, and the Sec. VI statistics.
+answers, physics of a plane wave, and the Sec. VII statistics.
 """
 import numpy as np
 import pytest
@@ -143,7 +143,7 @@ def test_narrowband_limit_is_spatial_fft():
 
 # --------------------------------------------------------------------------
 # T7: a noise-free plane wave from a grid direction is recovered at the bias
-# level and peaks in its own beam (Sec. III, delay-and-sum ideal; Sec. V).
+# level and peaks in its own beam (Sec. III, delay-and-sum ideal; Sec. VI).
 # --------------------------------------------------------------------------
 def test_plane_wave_on_grid():
     M, N, B = 64, 256, 64
@@ -163,7 +163,7 @@ def test_plane_wave_on_grid():
 
 
 # --------------------------------------------------------------------------
-# T15: no beam squint (Sec. V, beam pattern across the band): a single tone at
+# T15: no beam squint (Sec. VI, beam pattern across the band): a single tone at
 # any of 20 frequencies across [-Omega, Omega] from the steered direction comes
 # out of that beam with unit gain and zero phase.
 # --------------------------------------------------------------------------

@@ -1,4 +1,4 @@
-"""Sec. VI pins: the oracle's beams on Monte-Carlo noise and Monte-Carlo
+"""Sec. VII pins: the oracle's beams on Monte-Carlo noise and Monte-Carlo
 band-limited Gaussian sources against the paper's variance and bias formulas."""
 import numpy as np
 
@@ -37,7 +37,7 @@ def test_variance_monte_carlo():
 
 
 def test_variance_approaches_array_gain():
-    """Per-sample variance falls towards sigma^2 / M as N grows (Sec. VI)."""
+    """Per-sample variance falls towards sigma^2 / M as N grows (Sec. VII)."""
     M, sigma2 = 8, 1.0
     vals = []
     for N in (16, 32, 64, 128):
@@ -71,7 +71,7 @@ def test_bias_monte_carlo():
 
 
 def test_bias_falls_with_extension_factor():
-    """Bias drops steeply once gamma exceeds its lower bound (Sec. VI, Fig. 3c)."""
+    """Bias drops steeply once gamma exceeds its lower bound (Sec. VII, Fig. 3c)."""
     M, N = 8, 32
     band = synth.band_from_fb(0.5)
     vals = []
