@@ -1,6 +1,8 @@
 // C ABI of libfbst.so (declared in include/fbst.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <new>
 #include <string>
@@ -58,13 +60,25 @@ struct Upload {
   }
 };
 
+// Per-pass twiddle tables of every transform size (layout in fft_lds.h):
+// entry tw_offset(P, NS) + (r - 1) NS + k = exp(-2 pi j r k / (NS R)).
 std::vector<fbst::zd> twiddles() {
-  std::vector<fbst::zd> tw(fbst::PMAX);
+  std::vector<fbst::zd> tw(fbst::TW_ENTRIES, fbst::zd(0.0, 0.0));
   const double pi = 3.141592653589793238462643383279502884;
-  for (int i = 0; i < fbst::PMAX; ++i) {
-    // exp(-2 pi j i / PMAX) from the symmetric octant to keep every entry correctly rounded
-    const double a = 2.0 * pi * i / fbst::PMAX;
-    tw[i] = fbst::zd(std::cos(a), -std::sin(a));
+  for (int P = 32; P <= fbst::PMAX; P *= 2) {
+    for (int NS = 1; NS < P;) {
+      const int R = std::min(fbst::FFT_E, P / NS);
+      if (NS > 1) {
+        const int off = fbst::tw_offset(P, NS);
+        const long long NR = 1LL * NS * R;
+        for (int r = 1; r < R; ++r)
+          for (int k = 0; k < NS; ++k) {
+            const double a = 2.0 * pi * static_cast<double>((1LL * r * k) % NR) / static_cast<double>(NR);
+            tw[off + (r - 1) * NS + k] = fbst::zd(std::cos(a), -std::sin(a));
+          }
+      }
+      NS *= R;
+    }
   }
   return tw;
 }
@@ -154,7 +168,7 @@ hipError_t run_stage1(const fbst_plan* pl, int nb, const void* yhat, void* w, vo
 
 hipError_t run_stage2(const fbst_plan* pl, int nb, const void* w, void* beams, hipStream_t st) {
   const fbst::Params& p = pl->p;
-  const int rows = nb * p.B;
+  const int rows = nb;
   switch (p.prec) {
     case FBST_PREC_FP64:
       return fbst::launch_toeplitz_fu<double, double, double>(p.p3, w, beams, pl->G1, pl->G2,

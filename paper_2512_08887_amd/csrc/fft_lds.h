@@ -17,11 +17,20 @@
 // and every pass in between exchanges through LDS, so a transform of
 // k passes costs k - 1 LDS round trips.
 //
+// Pruning: a caller that zero-pads its input declares how many leading
+// register slots can be non-zero (NZ_IN); the first pass, whose butterfly
+// inputs are exactly the slots, then skips the zero operands.  Outputs the
+// caller never reads are removed by dead-code elimination of the last pass.
+//
 // LDS addresses are padded, i -> i + (i >> 4), which keeps the radix-16 and
 // remainder-pass writes and reads free of bank conflicts for complex64.
 //
-// Twiddles come from one table tw[i] = exp(-2 pi j i / PMAX) (computed in
-// float64 on the host, rounded once), indexed with stride PMAX / (NS R).
+// Twiddles: each pass reads w_{NS R}^{r k} from its own contiguous table,
+// laid out [r - 1][k] so that consecutive threads read consecutive entries.
+// The tables of size P occupy entries [P, 2P) of one array; the pass with span
+// NS starts NS - E entries into it (the pass tables tile the range exactly,
+// since (R - 1) NS = NS_next - NS).  Values are computed in float64 on the
+// host and rounded once.
 #pragma once
 
 #include "cx.h"
@@ -29,14 +38,19 @@
 namespace fbst {
 
 constexpr int PMAX = 16384;      // largest supported transform size
+constexpr int FFT_E = 16;        // elements per thread (radix of the full passes)
+constexpr int TW_ENTRIES = 2 * PMAX;
 
 __host__ __device__ constexpr int lds_pad(int i) { return i + (i >> 4); }
 // per-transform LDS stride in elements (padding + 2 keeps sub-groups apart in banks)
 __host__ __device__ constexpr int lds_stride(int P) { return P + P / 16 + 2; }
+// first entry of the twiddle table of the pass with span NS of a P-point transform
+__host__ __device__ constexpr int tw_offset(int P, int NS) { return P + NS - FFT_E; }
 
 // ---------------------------------------------------------------------------
 // Small DFTs in registers, natural order in and out.  DIR = -1: forward
-// (exp(-j ...)); DIR = +1: inverse without scaling.
+// (exp(-j ...)); DIR = +1: inverse without scaling.  NZ: inputs [NZ, R) are
+// known to be zero.
 // ---------------------------------------------------------------------------
 namespace detail {
 constexpr double kC1 = 0.92387953251128675613;   // cos(pi/8)
@@ -62,7 +76,6 @@ __device__ __forceinline__ cx<T> tw16(cx<T> a) {
     constexpr int c_sign = (m == 2 || m == 14) ? 1 : -1;      // sign of cos
     constexpr int s_sign = (m == 2 || m == 6) ? 1 : -1;       // sign of sin
     constexpr int s = s_sign * DIR;                           // sign of imaginary part of factor
-    // factor = r * (c_sign + j s)
     T re, im;
     if constexpr (c_sign > 0) {
       if constexpr (s > 0) { re = a.re - a.im; im = a.re + a.im; }
@@ -85,28 +98,50 @@ __device__ __forceinline__ cx<T> tw16(cx<T> a) {
   }
 }
 
-template <int DIR, typename T>
+// 4-point DFT in place; inputs [NZ, 4) are zero.
+template <int DIR, int NZ, typename T>
 __device__ __forceinline__ void dft4(cx<T>& a0, cx<T>& a1, cx<T>& a2, cx<T>& a3) {
-  const cx<T> t0 = a0 + a2, t1 = a0 - a2, t2 = a1 + a3, t3 = rot90<DIR>(a1 - a3);
-  a0 = t0 + t2;
-  a2 = t0 - t2;
-  a1 = t1 + t3;
-  a3 = t1 - t3;
+  if constexpr (NZ <= 0) {
+    a0 = a1 = a2 = a3 = cx<T>{0, 0};
+  } else if constexpr (NZ == 1) {
+    a1 = a0;
+    a2 = a0;
+    a3 = a0;
+  } else if constexpr (NZ == 2) {
+    const cx<T> r1 = rot90<DIR>(a1);
+    const cx<T> x0 = a0;
+    a0 = x0 + a1;
+    a2 = x0 - a1;
+    a1 = x0 + r1;
+    a3 = x0 - r1;
+  } else {
+    const cx<T> t0 = (NZ >= 3) ? a0 + a2 : a0, t1 = (NZ >= 3) ? a0 - a2 : a0;
+    const cx<T> t2 = (NZ >= 4) ? a1 + a3 : a1;
+    const cx<T> t3 = rot90<DIR>((NZ >= 4) ? a1 - a3 : a1);
+    a0 = t0 + t2;
+    a2 = t0 - t2;
+    a1 = t1 + t3;
+    a3 = t1 - t3;
+  }
 }
 
-template <int R, int DIR, typename T>
+template <int R, int DIR, int NZ, typename T>
 __device__ __forceinline__ void dft(cx<T> (&v)[R]) {
   if constexpr (R == 1) {
   } else if constexpr (R == 2) {
-    const cx<T> a = v[0];
-    v[0] = a + v[1];
-    v[1] = a - v[1];
+    if constexpr (NZ >= 2) {
+      const cx<T> a = v[0];
+      v[0] = a + v[1];
+      v[1] = a - v[1];
+    } else {
+      v[1] = v[0];
+    }
   } else if constexpr (R == 4) {
-    dft4<DIR>(v[0], v[1], v[2], v[3]);
+    dft4<DIR, NZ>(v[0], v[1], v[2], v[3]);
   } else if constexpr (R == 8) {
-    // n = 2 n1 + n2, k = k1 + 4 k2
-    dft4<DIR>(v[0], v[2], v[4], v[6]);
-    dft4<DIR>(v[1], v[3], v[5], v[7]);
+    // n = 2 n1 + n2, k = k1 + 4 k2; input 2 n1 + n2 is non-zero iff < NZ
+    dft4<DIR, (NZ + 1) / 2>(v[0], v[2], v[4], v[6]);
+    dft4<DIR, NZ / 2>(v[1], v[3], v[5], v[7]);
     v[3] = tw16<2, DIR>(v[3]);
     v[5] = tw16<4, DIR>(v[5]);
     v[7] = tw16<6, DIR>(v[7]);
@@ -119,11 +154,11 @@ __device__ __forceinline__ void dft(cx<T> (&v)[R]) {
 #pragma unroll
     for (int i = 0; i < 8; ++i) v[i] = o[i];
   } else if constexpr (R == 16) {
-    // n = 4 n1 + n2, k = k1 + 4 k2
-    dft4<DIR>(v[0], v[4], v[8], v[12]);
-    dft4<DIR>(v[1], v[5], v[9], v[13]);
-    dft4<DIR>(v[2], v[6], v[10], v[14]);
-    dft4<DIR>(v[3], v[7], v[11], v[15]);
+    // n = 4 n1 + n2, k = k1 + 4 k2; input 4 n1 + n2 is non-zero iff < NZ
+    dft4<DIR, (NZ + 3) / 4>(v[0], v[4], v[8], v[12]);
+    dft4<DIR, (NZ + 2) / 4>(v[1], v[5], v[9], v[13]);
+    dft4<DIR, (NZ + 1) / 4>(v[2], v[6], v[10], v[14]);
+    dft4<DIR, NZ / 4>(v[3], v[7], v[11], v[15]);
     // Y[n2][k1] sits in v[4 k1 + n2]; multiply by w16^(n2 k1)
     v[5] = tw16<1, DIR>(v[5]);
     v[6] = tw16<2, DIR>(v[6]);
@@ -134,10 +169,11 @@ __device__ __forceinline__ void dft(cx<T> (&v)[R]) {
     v[13] = tw16<3, DIR>(v[13]);
     v[14] = tw16<6, DIR>(v[14]);
     v[15] = tw16<9, DIR>(v[15]);
-    dft4<DIR>(v[0], v[1], v[2], v[3]);
-    dft4<DIR>(v[4], v[5], v[6], v[7]);
-    dft4<DIR>(v[8], v[9], v[10], v[11]);
-    dft4<DIR>(v[12], v[13], v[14], v[15]);
+    constexpr int nz2 = NZ >= 4 ? 4 : NZ;     // non-zero inputs of the second stage
+    dft4<DIR, nz2>(v[0], v[1], v[2], v[3]);
+    dft4<DIR, nz2>(v[4], v[5], v[6], v[7]);
+    dft4<DIR, nz2>(v[8], v[9], v[10], v[11]);
+    dft4<DIR, nz2>(v[12], v[13], v[14], v[15]);
     // X[k1 + 4 k2] sits in v[4 k1 + k2]: transpose 4 x 4
     cx<T> o[16];
 #pragma unroll
@@ -154,7 +190,7 @@ __device__ __forceinline__ void dft(cx<T> (&v)[R]) {
 // ---------------------------------------------------------------------------
 // One Stockham pass.
 // ---------------------------------------------------------------------------
-template <typename T, int P, int E, int R, int NS, int DIR, bool FIRST, bool LAST>
+template <typename T, int P, int E, int R, int NS, int DIR, bool FIRST, bool LAST, int NZ_IN>
 __device__ __forceinline__ void stockham_pass(cx<T> (&v)[E], cx<T>* __restrict__ buf,
                                               const cx<T>* __restrict__ tw, int t) {
   constexpr int TT = P / E;
@@ -171,11 +207,15 @@ __device__ __forceinline__ void stockham_pass(cx<T> (&v)[E], cx<T>* __restrict__
     }
     if constexpr (NS > 1) {
       const int k = j & (NS - 1);
-      constexpr int STRIDE = PMAX / (NS * R);
+      const cx<T>* twp = tw + tw_offset(P, NS) + k;
 #pragma unroll
-      for (int r = 1; r < R; ++r) b[q][r] = cmul_dir<DIR>(b[q][r], tw[r * k * STRIDE]);
+      for (int r = 1; r < R; ++r) b[q][r] = cmul_dir<DIR>(b[q][r], twp[(r - 1) * NS]);
     }
-    dft<R, DIR>(b[q]);
+    if constexpr (FIRST && NB == 1) {
+      dft<R, DIR, NZ_IN>(b[q]);
+    } else {
+      dft<R, DIR, R>(b[q]);
+    }
   }
   if constexpr (LAST) {
 #pragma unroll
@@ -196,24 +236,113 @@ __device__ __forceinline__ void stockham_pass(cx<T> (&v)[E], cx<T>* __restrict__
   }
 }
 
-template <typename T, int P, int E, int DIR, int NS>
+// The same pass over two independent transforms (separate LDS buffers)
+// sharing the barriers and the twiddles.
+template <typename T, int P, int E, int R, int NS, int DIR, bool FIRST, bool LAST, int NZ_IN>
+__device__ __forceinline__ void stockham_pass2(cx<T> (&v1)[E], cx<T> (&v2)[E],
+                                               cx<T>* __restrict__ buf1, cx<T>* __restrict__ buf2,
+                                               const cx<T>* __restrict__ tw, int t) {
+  constexpr int TT = P / E;
+  constexpr int NB = E / R;
+  static_assert(E % R == 0, "radix must divide the per-thread element count");
+  cx<T> a[NB][R], b[NB][R];
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    const int j = t + q * TT;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if constexpr (FIRST) {
+        a[q][r] = v1[q + r * NB];
+        b[q][r] = v2[q + r * NB];
+      } else {
+        a[q][r] = buf1[lds_pad(j + r * (P / R))];
+        b[q][r] = buf2[lds_pad(j + r * (P / R))];
+      }
+    }
+    if constexpr (NS > 1) {
+      const int k = j & (NS - 1);
+      const cx<T>* twp = tw + tw_offset(P, NS) + k;
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        const cx<T> w = twp[(r - 1) * NS];
+        a[q][r] = cmul_dir<DIR>(a[q][r], w);
+        b[q][r] = cmul_dir<DIR>(b[q][r], w);
+      }
+    }
+    if constexpr (FIRST && NB == 1) {
+      dft<R, DIR, NZ_IN>(a[q]);
+      dft<R, DIR, NZ_IN>(b[q]);
+    } else {
+      dft<R, DIR, R>(a[q]);
+      dft<R, DIR, R>(b[q]);
+    }
+  }
+  if constexpr (LAST) {
+#pragma unroll
+    for (int q = 0; q < NB; ++q)
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        v1[q + r * NB] = a[q][r];
+        v2[q + r * NB] = b[q][r];
+      }
+  } else {
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int j = t + q * TT;
+      const int k = j & (NS - 1);
+      const int base = (j - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        buf1[lds_pad(base + r * NS)] = a[q][r];
+        buf2[lds_pad(base + r * NS)] = b[q][r];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T, int P, int E, int DIR, int NS, int NZ_IN>
+__device__ __forceinline__ void fft2_passes(cx<T> (&v1)[E], cx<T> (&v2)[E], cx<T>* buf1,
+                                            cx<T>* buf2, const cx<T>* tw, int t) {
+  constexpr int REM = P / NS;
+  constexpr int R = (REM >= E) ? E : REM;
+  constexpr bool FIRST = (NS == 1);
+  constexpr bool LAST = (REM == R);
+  stockham_pass2<T, P, E, R, NS, DIR, FIRST, LAST, NZ_IN>(v1, v2, buf1, buf2, tw, t);
+  if constexpr (!LAST) fft2_passes<T, P, E, DIR, NS * R, NZ_IN>(v1, v2, buf1, buf2, tw, t);
+}
+
+template <typename T, int P, int E, int DIR, int NS, int NZ_IN>
 __device__ __forceinline__ void fft_passes(cx<T> (&v)[E], cx<T>* buf, const cx<T>* tw, int t) {
   constexpr int REM = P / NS;
   constexpr int R = (REM >= E) ? E : REM;
   constexpr bool FIRST = (NS == 1);
   constexpr bool LAST = (REM == R);
-  stockham_pass<T, P, E, R, NS, DIR, FIRST, LAST>(v, buf, tw, t);
-  if constexpr (!LAST) fft_passes<T, P, E, DIR, NS * R>(v, buf, tw, t);
+  stockham_pass<T, P, E, R, NS, DIR, FIRST, LAST, NZ_IN>(v, buf, tw, t);
+  if constexpr (!LAST) fft_passes<T, P, E, DIR, NS * R, NZ_IN>(v, buf, tw, t);
 }
 
 // In-register P-point DFT (DIR = -1) or unscaled inverse (DIR = +1) of the
 // transform held by the TT = P / E threads t = 0..TT-1 sharing buf (at least
-// lds_stride(P) elements).  Must be reached by every thread of the workgroup
-// (it contains workgroup barriers).
-template <typename T, int P, int E, int DIR>
+// lds_stride(P) elements).  v[s] for s >= NZ_IN must be zero on entry.
+// Must be reached by every thread of the workgroup (it contains workgroup
+// barriers).
+template <typename T, int P, int E, int DIR, int NZ_IN = E>
 __device__ __forceinline__ void fft(cx<T> (&v)[E], cx<T>* buf, const cx<T>* tw, int t) {
   static_assert((P & (P - 1)) == 0 && P >= E && P <= PMAX, "P must be a power of two in [E, PMAX]");
-  fft_passes<T, P, E, DIR, 1>(v, buf, tw, t);
+  static_assert(E == FFT_E, "twiddle tables are laid out for FFT_E elements per thread");
+  fft_passes<T, P, E, DIR, 1, NZ_IN>(v, buf, tw, t);
+}
+
+// Two independent transforms of the same size and direction at once (their
+// passes share barriers and twiddle loads); buf1 and buf2 must not overlap.
+template <typename T, int P, int E, int DIR, int NZ_IN = E>
+__device__ __forceinline__ void fft2(cx<T> (&v1)[E], cx<T> (&v2)[E], cx<T>* buf1, cx<T>* buf2,
+                                     const cx<T>* tw, int t) {
+  static_assert((P & (P - 1)) == 0 && P >= E && P <= PMAX, "P must be a power of two in [E, PMAX]");
+  static_assert(E == FFT_E, "twiddle tables are laid out for FFT_E elements per thread");
+  fft2_passes<T, P, E, DIR, 1, NZ_IN>(v1, v2, buf1, buf2, tw, t);
 }
 
 }  // namespace fbst

@@ -1,7 +1,8 @@
 // Host-side launchers of the FBST kernels (kernels.hip).  Pointers are device
 // pointers to interleaved complex arrays of the template element type; P is
 // the FFT size of the launch (power of two, 32..16384; 8192 at most for
-// double).  All return the HIP error of the launch.
+// double); tw is the twiddle array of fft_lds.h (TW_ENTRIES entries).  All
+// return the HIP error of the launch.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -20,10 +21,10 @@ hipError_t launch_axis_czt(int P, const void* in, void* out, const void* pre, co
                            const void* post, const void* tw, int a_in, int a_out, int pre_n,
                            int post_n, int L, int nblocks, hipStream_t st);
 
-// Stage 2: beams[row][n], rows = nb * B, from w[row][0..L-1].
+// Stage 2: beams[blk][b][n] from w[blk][b][0..L-1], blk < nblocks; needs 2L <= P.
 template <typename T, typename TIN, typename TOUT>
 hipError_t launch_toeplitz_fu(int P, const void* w, void* beams, const void* G1, const void* G2,
                               const void* pre3, const void* H3, const void* post3, const void* tw,
-                              int B, int L, int N, int rows, hipStream_t st);
+                              int B, int L, int N, int nblocks, hipStream_t st);
 
 }  // namespace fbst

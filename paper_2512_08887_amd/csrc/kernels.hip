@@ -8,16 +8,45 @@
 // chirp premultiply while loading, forward FFT in LDS, product with the
 // precomputed kernel spectrum in registers, inverse FFT, postmultiply while
 // storing, so each operand crosses HBM once per stage.
+//
+// Zero padding is declared to the FFTs at compile time (SI = register slots
+// that can hold input, SO = register slots whose output is used), so first
+// passes skip zero operands and last passes compute only used outputs.
+//
+// Workgroups are remapped so that each XCD (each L2) receives a contiguous
+// range of the logical work: per-frequency tables of K2 and per-beam spectra
+// of K3 are then fetched into one L2 and reused there.
 #include <hip/hip_runtime.h>
 
 #include "fft_lds.h"
 #include "kernels.h"
 
+#ifndef FBST_K3_DUAL
+#define FBST_K3_DUAL 1            // run the two Gohberg-Semencul branches as one dual FFT
+#endif
+#ifndef FBST_K3_WAVES
+#define FBST_K3_WAVES 2           // minimum waves per SIMD the register allocation must allow
+#endif
+#ifndef FBST_K12_WAVES
+#define FBST_K12_WAVES 0
+#endif
+#if FBST_K3_WAVES > 0
+#define FBST_K3_ATTR __attribute__((amdgpu_waves_per_eu(FBST_K3_WAVES)))
+#else
+#define FBST_K3_ATTR
+#endif
+#if FBST_K12_WAVES > 0
+#define FBST_K12_ATTR __attribute__((amdgpu_waves_per_eu(FBST_K12_WAVES)))
+#else
+#define FBST_K12_ATTR
+#endif
+
 namespace fbst {
 
 namespace {
 
-constexpr int kE = 16;          // elements per thread in every transform
+constexpr int kE = FFT_E;
+constexpr int kXCD = 8;          // XCDs of an MI355X; workgroups are dealt round-robin
 
 template <int P>
 struct Shape {
@@ -27,6 +56,15 @@ struct Shape {
   static constexpr int S = lds_stride(P);                  // LDS elements per transform
 };
 
+// Logical index of this workgroup such that the workgroups the hardware
+// sends to one XCD (blockIdx % 8) form a contiguous logical range.
+__device__ __forceinline__ int xcd_linear(int nwg) {
+  const int b = blockIdx.x;
+  const int x = b % kXCD, i = b / kXCD;
+  const int q = nwg / kXCD, r = nwg % kXCD;
+  return (x < r) ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
 template <typename T>
 __device__ __forceinline__ cx<T> ldg(const cx<T>* p) { return *p; }
 
@@ -34,9 +72,10 @@ __device__ __forceinline__ cx<T> ldg(const cx<T>* p) { return *p; }
 // K1: Yhat[row][i] = post[i] * IFFT(FFT(x[row][n] * pre[n]) * H)[i],  i < L.
 // rows are (block, sensor) pairs; lane = g * TT + t (a transform owns a
 // contiguous run of lanes, so row loads and stores are coalesced).
+// SI >= ceil(N / TT), SO >= ceil(L / TT).
 // ---------------------------------------------------------------------------
-template <typename T, int P>
-__global__ __launch_bounds__(Shape<P>::THREADS) void k_time_czt(
+template <typename T, int P, int SI, int SO>
+__global__ __launch_bounds__(Shape<P>::THREADS) FBST_K12_ATTR void k_time_czt(
     const cx<T>* __restrict__ x, cx<T>* __restrict__ yhat, const cx<T>* __restrict__ pre,
     const cx<T>* __restrict__ H, const cx<T>* __restrict__ post, const cx<T>* __restrict__ tw,
     int N, int L, int rows) {
@@ -53,15 +92,15 @@ __global__ __launch_bounds__(Shape<P>::THREADS) void k_time_czt(
 #pragma unroll
   for (int s = 0; s < kE; ++s) {
     const int n = t + s * SH::TT;
-    v[s] = (active && n < N) ? cmul(ldg(src + n), ldg(pre + n)) : cx<T>{0, 0};
+    v[s] = (s < SI && active && n < N) ? cmul(ldg(src + n), ldg(pre + n)) : cx<T>{0, 0};
   }
-  fft<T, P, kE, -1>(v, buf, tw, t);
+  fft<T, P, kE, -1, SI>(v, buf, tw, t);
 #pragma unroll
   for (int s = 0; s < kE; ++s) v[s] = cmul(v[s], ldg(H + t + s * SH::TT));
   fft<T, P, kE, +1>(v, buf, tw, t);
   cx<T>* dst = yhat + static_cast<size_t>(row) * L;
 #pragma unroll
-  for (int s = 0; s < kE; ++s) {
+  for (int s = 0; s < SO; ++s) {
     const int i = t + s * SH::TT;
     if (active && i < L) dst[i] = cmul(v[s], ldg(post + i));
   }
@@ -72,24 +111,26 @@ __global__ __launch_bounds__(Shape<P>::THREADS) void k_time_czt(
 // (A = a_in on input, a_out on output); a workgroup takes G consecutive l for
 // one (blk, p, q) and lane = t * G + g, so lanes with the same t read G
 // consecutive l of one element.  Tables are l-fastest: pre [a_in][L],
-// H [P][L], post [a_out][L].
+// H [P][L], post [a_out][L].  Logical work order: l-tile outermost, so the
+// workgroups of one XCD share the tables of a few tiles.
+// SI >= ceil(a_in / TT), SO >= ceil(a_out / TT).
 // ---------------------------------------------------------------------------
-template <typename T, int P>
-__global__ __launch_bounds__(Shape<P>::THREADS) void k_axis_czt(
+template <typename T, int P, int SI, int SO>
+__global__ __launch_bounds__(Shape<P>::THREADS) FBST_K12_ATTR void k_axis_czt(
     const cx<T>* __restrict__ in, cx<T>* __restrict__ out, const cx<T>* __restrict__ pre,
     const cx<T>* __restrict__ H, const cx<T>* __restrict__ post, const cx<T>* __restrict__ tw,
-    int a_in, int a_out, int pre_n, int post_n, int L, int n_tiles) {
+    int a_in, int a_out, int pre_n, int post_n, int L, int nblocks, int n_tiles) {
   using SH = Shape<P>;
   __shared__ cx<T> lds[SH::G * SH::S];
   const int g = threadIdx.x % SH::G;
   const int t = threadIdx.x / SH::G;
-  int wg = blockIdx.x;
-  const int tile = wg % n_tiles;
-  wg /= n_tiles;
-  const int q = wg % post_n;
-  wg /= post_n;
-  const int p = wg % pre_n;
-  const int blk = wg / pre_n;
+  int w = xcd_linear(gridDim.x);
+  const int q = w % post_n;
+  w /= post_n;
+  const int p = w % pre_n;
+  w /= pre_n;
+  const int blk = w % nblocks;
+  const int tile = w / nblocks;
   const int l = tile * SH::G + g;
   const bool active = l < L;
   cx<T>* buf = lds + g * SH::S;
@@ -100,10 +141,11 @@ __global__ __launch_bounds__(Shape<P>::THREADS) void k_axis_czt(
 #pragma unroll
   for (int s = 0; s < kE; ++s) {
     const int i = t + s * SH::TT;
-    v[s] = (active && i < a_in) ? cmul(ldg(src + i * stride), ldg(pre + static_cast<size_t>(i) * L + l))
-                                : cx<T>{0, 0};
+    v[s] = (s < SI && active && i < a_in)
+               ? cmul(ldg(src + i * stride), ldg(pre + static_cast<size_t>(i) * L + l))
+               : cx<T>{0, 0};
   }
-  fft<T, P, kE, -1>(v, buf, tw, t);
+  fft<T, P, kE, -1, SI>(v, buf, tw, t);
 #pragma unroll
   for (int s = 0; s < kE; ++s) {
     const int i = t + s * SH::TT;
@@ -112,7 +154,7 @@ __global__ __launch_bounds__(Shape<P>::THREADS) void k_axis_czt(
   fft<T, P, kE, +1>(v, buf, tw, t);
   cx<T>* dst = out + ((static_cast<size_t>(blk) * pre_n + p) * a_out * post_n + q) * L + l;
 #pragma unroll
-  for (int s = 0; s < kE; ++s) {
+  for (int s = 0; s < SO; ++s) {
     const int a = t + s * SH::TT;
     if (active && a < a_out) dst[a * stride] = cmul(v[s], ldg(post + static_cast<size_t>(a) * L + l));
   }
@@ -124,83 +166,119 @@ __global__ __launch_bounds__(Shape<P>::THREADS) void k_axis_czt(
 // with each triangular Toeplitz product done by circulant embedding in P
 // points (G1 = FFT(x) and G2 = FFT(y~), both scaled by 1 / (P sqrt(x0))), then
 // b = F_u beta as a Bluestein chirp-z in the same P points:
-//   V = FFT(w);  p_k = IFFT(conj(G_k) V)[0:L];  Z = G1 FFT(p_1) - G2 FFT(p_2)
-//   beta = IFFT(Z)[0:L];  b = post3 * IFFT(FFT(beta * pre3) * H3)[0:N]
-// Eight P-point transforms, all in LDS/registers.
+//   V = FFT(w);  u_k = conj(G_k) V;  p_k = IFFT(u_k)[0:L]
+//   Z = G1 FFT(p_1) - G2 FFT(p_2);  beta = IFFT(Z)[0:L]
+//   b = post3 * IFFT(FFT(beta * pre3) * H3)[0:N]
+// Eight P-point transforms, all in LDS/registers.  L <= P/2 always (P >= 2L - 1),
+// so every L-long operand fills the first P/2 slots (SL = E/2); SN >= ceil(N / TT).
+// Both products with V are formed at once so V is dead before the branches.
+// Logical order: beam outermost, so the spectra of one beam are reused by the
+// workgroups of all blocks on one XCD.
 // ---------------------------------------------------------------------------
-template <typename T, typename TIN, typename TOUT, int P>
-__global__ __launch_bounds__(Shape<P>::THREADS) void k_toeplitz_fu(
+template <typename T, typename TIN, typename TOUT, int P, int SN>
+__global__ __launch_bounds__(Shape<P>::THREADS) FBST_K3_ATTR void k_toeplitz_fu(
     const cx<TIN>* __restrict__ w, cx<TOUT>* __restrict__ beams, const cx<T>* __restrict__ G1,
     const cx<T>* __restrict__ G2, const cx<T>* __restrict__ pre3, const cx<T>* __restrict__ H3,
-    const cx<T>* __restrict__ post3, const cx<T>* __restrict__ tw, int B, int L, int N, int rows) {
+    const cx<T>* __restrict__ post3, const cx<T>* __restrict__ tw, int B, int L, int N,
+    int nblocks) {
   using SH = Shape<P>;
-  __shared__ cx<T> lds[SH::G * SH::S];
+  constexpr int SL = kE / 2;
+  constexpr int NBUF = FBST_K3_DUAL ? 2 : 1;
+  __shared__ cx<T> lds[SH::G * NBUF * SH::S];
   const int g = threadIdx.x / SH::TT;
   const int t = threadIdx.x % SH::TT;
-  const int row = blockIdx.x * SH::G + g;
-  const bool active = row < rows;
-  const int b = active ? row % B : 0;
-  cx<T>* buf = lds + g * SH::S;
+  const int rows = nblocks * B;
+  const int lw = xcd_linear(gridDim.x) * SH::G + g;     // beam-major logical row
+  const bool active = lw < rows;
+  const int b = active ? lw / nblocks : 0;
+  const int blk = active ? lw % nblocks : 0;
+  const size_t row = static_cast<size_t>(blk) * B + b;
+  cx<T>* buf = lds + g * NBUF * SH::S;
   const cx<T>* g1 = G1 + static_cast<size_t>(b) * P;
   const cx<T>* g2 = G2 + static_cast<size_t>(b) * P;
 
-  cx<T> V[kE];
-  const cx<TIN>* src = w + static_cast<size_t>(row) * L;
+  cx<T> u1[kE], u2[kE];
+  const cx<TIN>* src = w + row * L;
 #pragma unroll
   for (int s = 0; s < kE; ++s) {
     const int i = t + s * SH::TT;
-    V[s] = (active && i < L) ? cvt<T>(src[i]) : cx<T>{0, 0};
+    u1[s] = (s < SL && active && i < L) ? cvt<T>(src[i]) : cx<T>{0, 0};
   }
-  fft<T, P, kE, -1>(V, buf, tw, t);
-
-  cx<T> Z[kE];
-  cx<T> u[kE];
-  // branch 1: Z = G1 * FFT(trunc_L(IFFT(conj(G1) V)))
+  fft<T, P, kE, -1, SL>(u1, buf, tw, t);
 #pragma unroll
-  for (int s = 0; s < kE; ++s) u[s] = cmulc(V[s], ldg(g1 + t + s * SH::TT));
-  fft<T, P, kE, +1>(u, buf, tw, t);
+  for (int s = 0; s < kE; ++s) {
+    const cx<T> V = u1[s];
+    u1[s] = cmulc(V, ldg(g1 + t + s * SH::TT));
+    u2[s] = cmulc(V, ldg(g2 + t + s * SH::TT));
+  }
+  if constexpr (FBST_K3_DUAL) {
+    // both branches: u_k <- FFT(trunc_L(IFFT(u_k)))
+    fft2<T, P, kE, +1>(u1, u2, buf, buf + SH::S, tw, t);
 #pragma unroll
-  for (int s = 0; s < kE; ++s)
-    if (t + s * SH::TT >= L) u[s] = cx<T>{0, 0};
-  fft<T, P, kE, -1>(u, buf, tw, t);
+    for (int s = 0; s < kE; ++s)
+      if (s >= SL || t + s * SH::TT >= L) {
+        u1[s] = cx<T>{0, 0};
+        u2[s] = cx<T>{0, 0};
+      }
+    fft2<T, P, kE, -1, SL>(u1, u2, buf, buf + SH::S, tw, t);
 #pragma unroll
-  for (int s = 0; s < kE; ++s) Z[s] = cmul(u[s], ldg(g1 + t + s * SH::TT));
-  // branch 2: Z -= G2 * FFT(trunc_L(IFFT(conj(G2) V)))
+    for (int s = 0; s < kE; ++s)
+      u1[s] = cmul(u1[s], ldg(g1 + t + s * SH::TT)) - cmul(u2[s], ldg(g2 + t + s * SH::TT));
+  } else {
+    // branch 1: u1 <- G1 * FFT(trunc_L(IFFT(u1)))
+    fft<T, P, kE, +1>(u1, buf, tw, t);
 #pragma unroll
-  for (int s = 0; s < kE; ++s) u[s] = cmulc(V[s], ldg(g2 + t + s * SH::TT));
-  fft<T, P, kE, +1>(u, buf, tw, t);
+    for (int s = 0; s < kE; ++s)
+      if (s >= SL || t + s * SH::TT >= L) u1[s] = cx<T>{0, 0};
+    fft<T, P, kE, -1, SL>(u1, buf, tw, t);
 #pragma unroll
-  for (int s = 0; s < kE; ++s)
-    if (t + s * SH::TT >= L) u[s] = cx<T>{0, 0};
-  fft<T, P, kE, -1>(u, buf, tw, t);
+    for (int s = 0; s < kE; ++s) u1[s] = cmul(u1[s], ldg(g1 + t + s * SH::TT));
+    // branch 2: u1 -= G2 * FFT(trunc_L(IFFT(u2)))
+    fft<T, P, kE, +1>(u2, buf, tw, t);
 #pragma unroll
-  for (int s = 0; s < kE; ++s) Z[s] = Z[s] - cmul(u[s], ldg(g2 + t + s * SH::TT));
+    for (int s = 0; s < kE; ++s)
+      if (s >= SL || t + s * SH::TT >= L) u2[s] = cx<T>{0, 0};
+    fft<T, P, kE, -1, SL>(u2, buf, tw, t);
+#pragma unroll
+    for (int s = 0; s < kE; ++s) u1[s] = u1[s] - cmul(u2[s], ldg(g2 + t + s * SH::TT));
+  }
   // beta = trunc_L(IFFT(Z)), then the F_u chirp-z
-  fft<T, P, kE, +1>(Z, buf, tw, t);
+  fft<T, P, kE, +1>(u1, buf, tw, t);
 #pragma unroll
   for (int s = 0; s < kE; ++s) {
     const int i = t + s * SH::TT;
-    Z[s] = (i < L) ? cmul(Z[s], ldg(pre3 + i)) : cx<T>{0, 0};
+    u1[s] = (s < SL && i < L) ? cmul(u1[s], ldg(pre3 + i)) : cx<T>{0, 0};
   }
-  fft<T, P, kE, -1>(Z, buf, tw, t);
+  fft<T, P, kE, -1, SL>(u1, buf, tw, t);
 #pragma unroll
-  for (int s = 0; s < kE; ++s) Z[s] = cmul(Z[s], ldg(H3 + t + s * SH::TT));
-  fft<T, P, kE, +1>(Z, buf, tw, t);
-  cx<TOUT>* dst = beams + static_cast<size_t>(row) * N;
+  for (int s = 0; s < kE; ++s) u1[s] = cmul(u1[s], ldg(H3 + t + s * SH::TT));
+  fft<T, P, kE, +1>(u1, buf, tw, t);
+  cx<TOUT>* dst = beams + row * N;
 #pragma unroll
-  for (int s = 0; s < kE; ++s) {
+  for (int s = 0; s < SN; ++s) {
     const int n = t + s * SH::TT;
-    if (active && n < N) dst[n] = cvt<TOUT>(cmul(Z[s], ldg(post3 + n)));
+    if (active && n < N) dst[n] = cvt<TOUT>(cmul(u1[s], ldg(post3 + n)));
   }
 }
 
 template <int P>
 int grid_for(int rows) { return (rows + Shape<P>::G - 1) / Shape<P>::G; }
 
+// smallest of {E/4, E/2, E} slots covering n elements of a P-point transform
+template <int P>
+int slots_for(int n) {
+  const int tt = Shape<P>::TT;
+  const int s = (n + tt - 1) / tt;
+  return s <= kE / 4 ? kE / 4 : (s <= kE / 2 ? kE / 2 : kE);
+}
+
+template <typename T, int P, int NBUF = 1>
+constexpr bool fits_lds() { return sizeof(T) * 2 * lds_stride(P) * NBUF * Shape<P>::G <= 160 * 1024; }
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// Launchers: dispatch the runtime FFT size to the compiled instances.
+// Launchers: dispatch the runtime FFT size and slot counts to compiled instances.
 // ---------------------------------------------------------------------------
 #define FBST_FOR_EACH_P(X) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096) X(8192) X(16384)
 
@@ -209,14 +287,27 @@ hipError_t launch_time_czt(int P, const void* x, void* yhat, const void* pre, co
                            const void* post, const void* tw, int N, int L, int rows,
                            hipStream_t st) {
   switch (P) {
-#define CASE(PP)                                                                             \
-  case PP:                                                                                   \
-    if constexpr (sizeof(T) * 2 * lds_stride(PP) <= 160 * 1024) {                            \
-      hipLaunchKernelGGL((k_time_czt<T, PP>), dim3(grid_for<PP>(rows)), dim3(Shape<PP>::THREADS), \
-                         0, st, (const cx<T>*)x, (cx<T>*)yhat, (const cx<T>*)pre,             \
-                         (const cx<T>*)H, (const cx<T>*)post, (const cx<T>*)tw, N, L, rows);  \
-      return hipGetLastError();                                                              \
-    }                                                                                        \
+#define CASE(PP)                                                                               \
+  case PP:                                                                                     \
+    if constexpr (fits_lds<T, PP>()) {                                                         \
+      const int si = slots_for<PP>(N), so = slots_for<PP>(L);                                  \
+      const dim3 grid(grid_for<PP>(rows)), block(Shape<PP>::THREADS);                          \
+      const auto a = (const cx<T>*)x;                                                          \
+      const auto o = (cx<T>*)yhat;                                                             \
+      if (si <= kE / 4 && so <= kE / 2)                                                        \
+        hipLaunchKernelGGL((k_time_czt<T, PP, kE / 4, kE / 2>), grid, block, 0, st, a, o,      \
+                           (const cx<T>*)pre, (const cx<T>*)H, (const cx<T>*)post,             \
+                           (const cx<T>*)tw, N, L, rows);                                      \
+      else if (si <= kE / 2)                                                                   \
+        hipLaunchKernelGGL((k_time_czt<T, PP, kE / 2, kE>), grid, block, 0, st, a, o,          \
+                           (const cx<T>*)pre, (const cx<T>*)H, (const cx<T>*)post,             \
+                           (const cx<T>*)tw, N, L, rows);                                      \
+      else                                                                                     \
+        hipLaunchKernelGGL((k_time_czt<T, PP, kE, kE>), grid, block, 0, st, a, o,              \
+                           (const cx<T>*)pre, (const cx<T>*)H, (const cx<T>*)post,             \
+                           (const cx<T>*)tw, N, L, rows);                                      \
+      return hipGetLastError();                                                                \
+    }                                                                                          \
     break;
     FBST_FOR_EACH_P(CASE)
 #undef CASE
@@ -231,18 +322,26 @@ hipError_t launch_axis_czt(int P, const void* in, void* out, const void* pre, co
                            const void* post, const void* tw, int a_in, int a_out, int pre_n,
                            int post_n, int L, int nblocks, hipStream_t st) {
   switch (P) {
-#define CASE(PP)                                                                             \
-  case PP:                                                                                   \
-    if constexpr (sizeof(T) * 2 * lds_stride(PP) <= 160 * 1024) {                            \
-      const int n_tiles = (L + Shape<PP>::G - 1) / Shape<PP>::G;                             \
-      const long long grid = 1LL * nblocks * pre_n * post_n * n_tiles;                       \
-      if (grid <= 0 || grid > 0x7fffffffLL) return hipErrorInvalidValue;                    \
-      hipLaunchKernelGGL((k_axis_czt<T, PP>), dim3((unsigned)grid), dim3(Shape<PP>::THREADS), 0, \
-                         st, (const cx<T>*)in, (cx<T>*)out, (const cx<T>*)pre,               \
-                         (const cx<T>*)H, (const cx<T>*)post, (const cx<T>*)tw, a_in, a_out,  \
-                         pre_n, post_n, L, n_tiles);                                         \
-      return hipGetLastError();                                                              \
-    }                                                                                        \
+#define CASE(PP)                                                                               \
+  case PP:                                                                                     \
+    if constexpr (fits_lds<T, PP>()) {                                                         \
+      const int n_tiles = (L + Shape<PP>::G - 1) / Shape<PP>::G;                               \
+      const long long ng = 1LL * nblocks * pre_n * post_n * n_tiles;                           \
+      if (ng <= 0 || ng > 0x7fffffffLL) return hipErrorInvalidValue;                          \
+      const dim3 grid((unsigned)ng), block(Shape<PP>::THREADS);                                \
+      const bool half = slots_for<PP>(a_in) <= kE / 2 && slots_for<PP>(a_out) <= kE / 2;      \
+      if (half)                                                                                \
+        hipLaunchKernelGGL((k_axis_czt<T, PP, kE / 2, kE / 2>), grid, block, 0, st,            \
+                           (const cx<T>*)in, (cx<T>*)out, (const cx<T>*)pre, (const cx<T>*)H,  \
+                           (const cx<T>*)post, (const cx<T>*)tw, a_in, a_out, pre_n, post_n,   \
+                           L, nblocks, n_tiles);                                               \
+      else                                                                                     \
+        hipLaunchKernelGGL((k_axis_czt<T, PP, kE, kE>), grid, block, 0, st,                    \
+                           (const cx<T>*)in, (cx<T>*)out, (const cx<T>*)pre, (const cx<T>*)H,  \
+                           (const cx<T>*)post, (const cx<T>*)tw, a_in, a_out, pre_n, post_n,   \
+                           L, nblocks, n_tiles);                                               \
+      return hipGetLastError();                                                                \
+    }                                                                                          \
     break;
     FBST_FOR_EACH_P(CASE)
 #undef CASE
@@ -255,17 +354,33 @@ hipError_t launch_axis_czt(int P, const void* in, void* out, const void* pre, co
 template <typename T, typename TIN, typename TOUT>
 hipError_t launch_toeplitz_fu(int P, const void* w, void* beams, const void* G1, const void* G2,
                               const void* pre3, const void* H3, const void* post3, const void* tw,
-                              int B, int L, int N, int rows, hipStream_t st) {
+                              int B, int L, int N, int nblocks, hipStream_t st) {
   switch (P) {
-#define CASE(PP)                                                                             \
-  case PP:                                                                                   \
-    if constexpr (sizeof(T) * 2 * lds_stride(PP) <= 160 * 1024) {                            \
-      hipLaunchKernelGGL((k_toeplitz_fu<T, TIN, TOUT, PP>), dim3(grid_for<PP>(rows)),         \
-                         dim3(Shape<PP>::THREADS), 0, st, (const cx<TIN>*)w, (cx<TOUT>*)beams, \
-                         (const cx<T>*)G1, (const cx<T>*)G2, (const cx<T>*)pre3,              \
-                         (const cx<T>*)H3, (const cx<T>*)post3, (const cx<T>*)tw, B, L, N, rows); \
-      return hipGetLastError();                                                              \
-    }                                                                                        \
+#define CASE(PP)                                                                               \
+  case PP:                                                                                     \
+    if constexpr (fits_lds<T, PP, (FBST_K3_DUAL ? 2 : 1)>()) {                                 \
+      if (2 * L > PP) return hipErrorInvalidValue;                                             \
+      const dim3 grid(grid_for<PP>(nblocks * B)), block(Shape<PP>::THREADS);                   \
+      const int sn = slots_for<PP>(N);                                                         \
+      const auto a = (const cx<TIN>*)w;                                                        \
+      const auto o = (cx<TOUT>*)beams;                                                         \
+      if (sn <= kE / 4)                                                                        \
+        hipLaunchKernelGGL((k_toeplitz_fu<T, TIN, TOUT, PP, kE / 4>), grid, block, 0, st, a, o, \
+                           (const cx<T>*)G1, (const cx<T>*)G2, (const cx<T>*)pre3,              \
+                           (const cx<T>*)H3, (const cx<T>*)post3, (const cx<T>*)tw, B, L, N,    \
+                           nblocks);                                                           \
+      else if (sn <= kE / 2)                                                                   \
+        hipLaunchKernelGGL((k_toeplitz_fu<T, TIN, TOUT, PP, kE / 2>), grid, block, 0, st, a, o, \
+                           (const cx<T>*)G1, (const cx<T>*)G2, (const cx<T>*)pre3,              \
+                           (const cx<T>*)H3, (const cx<T>*)post3, (const cx<T>*)tw, B, L, N,    \
+                           nblocks);                                                           \
+      else                                                                                     \
+        hipLaunchKernelGGL((k_toeplitz_fu<T, TIN, TOUT, PP, kE>), grid, block, 0, st, a, o,     \
+                           (const cx<T>*)G1, (const cx<T>*)G2, (const cx<T>*)pre3,              \
+                           (const cx<T>*)H3, (const cx<T>*)post3, (const cx<T>*)tw, B, L, N,    \
+                           nblocks);                                                           \
+      return hipGetLastError();                                                                \
+    }                                                                                          \
     break;
     FBST_FOR_EACH_P(CASE)
 #undef CASE

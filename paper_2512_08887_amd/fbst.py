@@ -63,38 +63,43 @@ class FbstError(RuntimeError):
 _lib = None
 
 
+def load_library(path: str = LIB_PATH):
+    """Open a libfbst.so and declare the C signatures of include/fbst.h."""
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with "
+                           "`python -m paper_2512_08887_amd.build`")
+    L = ctypes.CDLL(path)
+    L.fbst_plan_create.argtypes = [c_int, c_int, c_int, POINTER(fbst_geometry), POINTER(fbst_band),
+                                   POINTER(fbst_grid), POINTER(fbst_options), POINTER(c_void_p)]
+    L.fbst_plan_create.restype = c_int
+    L.fbst_execute.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
+    L.fbst_execute.restype = c_int
+    L.fbst_execute_batched.argtypes = [c_void_p, c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p]
+    L.fbst_execute_batched.restype = c_int
+    L.fbst_execute_stage.argtypes = [c_void_p, c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p]
+    L.fbst_execute_stage.restype = c_int
+    L.fbst_workspace_bytes.argtypes = [c_void_p, c_int]
+    L.fbst_workspace_bytes.restype = c_size_t
+    L.fbst_plan_device_bytes.argtypes = [c_void_p]
+    L.fbst_plan_device_bytes.restype = c_size_t
+    L.fbst_plan_info.argtypes = [c_void_p, POINTER(fbst_info)]
+    L.fbst_plan_info.restype = c_int
+    L.fbst_plan_table.argtypes = [c_void_p, c_int, c_void_p, c_size_t]
+    L.fbst_plan_table.restype = c_int
+    L.fbst_destroy.argtypes = [c_void_p]
+    L.fbst_destroy.restype = None
+    L.fbst_last_error.argtypes = []
+    L.fbst_last_error.restype = c_char_p
+    L.fbst_version.argtypes = []
+    L.fbst_version.restype = c_char_p
+    return L
+
+
 def lib():
-    """Load libfbst.so once (raises if it has not been built)."""
+    """The in-tree libfbst.so, loaded once (raises if it has not been built)."""
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH):
-            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
-                               "`python -m paper_2512_08887_amd.build`")
-        L = ctypes.CDLL(LIB_PATH)
-        L.fbst_plan_create.argtypes = [c_int, c_int, c_int, POINTER(fbst_geometry), POINTER(fbst_band),
-                                       POINTER(fbst_grid), POINTER(fbst_options), POINTER(c_void_p)]
-        L.fbst_plan_create.restype = c_int
-        L.fbst_execute.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
-        L.fbst_execute.restype = c_int
-        L.fbst_execute_batched.argtypes = [c_void_p, c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p]
-        L.fbst_execute_batched.restype = c_int
-        L.fbst_execute_stage.argtypes = [c_void_p, c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p]
-        L.fbst_execute_stage.restype = c_int
-        L.fbst_workspace_bytes.argtypes = [c_void_p, c_int]
-        L.fbst_workspace_bytes.restype = c_size_t
-        L.fbst_plan_device_bytes.argtypes = [c_void_p]
-        L.fbst_plan_device_bytes.restype = c_size_t
-        L.fbst_plan_info.argtypes = [c_void_p, POINTER(fbst_info)]
-        L.fbst_plan_info.restype = c_int
-        L.fbst_plan_table.argtypes = [c_void_p, c_int, c_void_p, c_size_t]
-        L.fbst_plan_table.restype = c_int
-        L.fbst_destroy.argtypes = [c_void_p]
-        L.fbst_destroy.restype = None
-        L.fbst_last_error.argtypes = []
-        L.fbst_last_error.restype = c_char_p
-        L.fbst_version.argtypes = []
-        L.fbst_version.restype = c_char_p
-        _lib = L
+        _lib = load_library(LIB_PATH)
     return _lib
 
 
