@@ -72,7 +72,71 @@ def cpu_baseline(cfg, y, delta, n_beams=16):
                       f"{n_beams} of {cfg.B} beams, {dt:.1f} s"}
 
 
+def rocprof_summary(kt_dir, pmc_dirs, copy_dirs):
+    """Text summary of rocprofv3 CSV output: per-kernel dispatch durations
+    (kernel trace) and HBM counters per dispatch, scaled by what the same
+    counters read for a plain copy of known size."""
+    import csv
+    import glob
+    import re
+    from collections import defaultdict
+
+    def short(name):
+        n = name.replace("void fbst::(anonymous namespace)::", "").replace("void ", "")
+        return re.sub(r"\(.*", "", n)
+
+    out = []
+    dur = defaultdict(list)
+    for f in glob.glob(os.path.join(kt_dir, "*kernel_trace.csv")):
+        for r in csv.DictReader(open(f)):
+            key = (short(r["Kernel_Name"]), int(r["Grid_Size_X"]))
+            dur[key].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    out.append("kernel | grid (work-items) | dispatches | avg us | min us | max us")
+    out.append("---|---|---|---|---|---")
+    for (k, g), v in sorted(dur.items(), key=lambda kv: -sum(kv[1])):
+        out.append(f"{k} | {g} | {len(v)} | {np.mean(v) / 1e3:.1f} | {np.min(v) / 1e3:.1f} | {np.max(v) / 1e3:.1f}")
+    scale = {}
+    for cdir in copy_dirs:
+        for f in glob.glob(os.path.join(cdir, "*counter_collection.csv")):
+            rows = [r for r in csv.DictReader(open(f)) if "copyBuffer" in r["Kernel_Name"]]
+            for r in rows:
+                scale.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    copy_bytes = None
+    for cdir in copy_dirs:
+        for f in glob.glob(os.path.join(cdir, "*.log")) + glob.glob(cdir + ".log"):
+            m = re.search(r'"copy_calib_bytes_each_way": (\d+)', open(f).read())
+            if m:
+                copy_bytes = int(m.group(1))
+    factors = {}
+    if copy_bytes:
+        for c, v in scale.items():
+            factors[c] = copy_bytes / (np.median(v) * 1024.0)
+    out.append("")
+    out.append(f"copy calibration: {copy_bytes} bytes each way; counter KiB read per copy: "
+               + ", ".join(f"{c} {np.median(v):.0f}" for c, v in scale.items())
+               + "; scale factors (true bytes per counted byte): "
+               + ", ".join(f"{c} {f:.3f}" for c, f in factors.items()))
+    cnt = defaultdict(list)
+    for pdir in pmc_dirs:
+        for f in glob.glob(os.path.join(pdir, "*counter_collection.csv")):
+            for r in csv.DictReader(open(f)):
+                cnt[(short(r["Kernel_Name"]), int(r["Grid_Size"]), r["Counter_Name"])].append(float(r["Counter_Value"]))
+    out.append("")
+    out.append("kernel | grid | counter | dispatches | KiB per dispatch | scaled MB per dispatch")
+    out.append("---|---|---|---|---|---")
+    for (k, g, c), v in sorted(cnt.items()):
+        if not k.startswith("k_"):
+            continue
+        f = factors.get(c, 1.0)
+        out.append(f"{k} | {g} | {c} | {len(v)} | {np.median(v):.0f} | {np.median(v) * 1024 * f / 1e6:.1f}")
+    return "\n".join(out)
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "--rocprof-summary":
+        # bench.py --rocprof-summary KT_DIR PMC_DIR[,PMC_DIR] COPY_DIR[,COPY_DIR]
+        print(rocprof_summary(sys.argv[2], sys.argv[3].split(","), sys.argv[4].split(",")))
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
