@@ -141,7 +141,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--chunk", type=int, default=0, help="blocks per launch (0 = all 64)")
+    ap.add_argument("--chunk", type=int, default=16, help="blocks per launch (0 = all 64)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--latency-reps", type=int, default=200)
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",

@@ -48,13 +48,19 @@ namespace {
 constexpr int kE = FFT_E;
 constexpr int kXCD = 8;          // XCDs of an MI355X; workgroups are dealt round-robin
 
-template <int P>
+template <int P, int WG = 256>
 struct Shape {
   static constexpr int TT = P / kE;                        // threads per transform
-  static constexpr int G = (TT >= 256) ? 1 : 256 / TT;     // transforms per workgroup
+  static constexpr int G = (TT >= WG) ? 1 : WG / TT;       // transforms per workgroup
   static constexpr int THREADS = TT * G;
   static constexpr int S = lds_stride(P);                  // LDS elements per transform
 };
+
+#ifndef FBST_K2_THREADS
+#define FBST_K2_THREADS 512       // workgroup size of the space chirp-z (frequencies per tile x TT)
+#endif
+template <int P>
+using ShapeK2 = Shape<P, FBST_K2_THREADS>;
 
 // Logical index of this workgroup such that the workgroups the hardware
 // sends to one XCD (blockIdx % 8) form a contiguous logical range.
@@ -116,11 +122,11 @@ __global__ __launch_bounds__(Shape<P>::THREADS) FBST_K12_ATTR void k_time_czt(
 // SI >= ceil(a_in / TT), SO >= ceil(a_out / TT).
 // ---------------------------------------------------------------------------
 template <typename T, int P, int SI, int SO>
-__global__ __launch_bounds__(Shape<P>::THREADS) FBST_K12_ATTR void k_axis_czt(
+__global__ __launch_bounds__(ShapeK2<P>::THREADS) FBST_K12_ATTR void k_axis_czt(
     const cx<T>* __restrict__ in, cx<T>* __restrict__ out, const cx<T>* __restrict__ pre,
     const cx<T>* __restrict__ H, const cx<T>* __restrict__ post, const cx<T>* __restrict__ tw,
     int a_in, int a_out, int pre_n, int post_n, int L, int nblocks, int n_tiles) {
-  using SH = Shape<P>;
+  using SH = ShapeK2<P>;
   __shared__ cx<T> lds[SH::G * SH::S];
   const int g = threadIdx.x % SH::G;
   const int t = threadIdx.x / SH::G;
@@ -175,6 +181,12 @@ __global__ __launch_bounds__(Shape<P>::THREADS) FBST_K12_ATTR void k_axis_czt(
 // Logical order: beam outermost, so the spectra of one beam are reused by the
 // workgroups of all blocks on one XCD.
 // ---------------------------------------------------------------------------
+// Dual-branch stage 2 when two transforms of P points fit the LDS of a CU.
+template <typename T, int P>
+constexpr bool k3_dual() {
+  return FBST_K3_DUAL && sizeof(T) * 2 * lds_stride(P) * 2 * Shape<P>::G <= 160 * 1024;
+}
+
 template <typename T, typename TIN, typename TOUT, int P, int SN>
 __global__ __launch_bounds__(Shape<P>::THREADS) FBST_K3_ATTR void k_toeplitz_fu(
     const cx<TIN>* __restrict__ w, cx<TOUT>* __restrict__ beams, const cx<T>* __restrict__ G1,
@@ -183,7 +195,8 @@ __global__ __launch_bounds__(Shape<P>::THREADS) FBST_K3_ATTR void k_toeplitz_fu(
     int nblocks) {
   using SH = Shape<P>;
   constexpr int SL = kE / 2;
-  constexpr int NBUF = FBST_K3_DUAL ? 2 : 1;
+  constexpr bool DUAL = k3_dual<T, P>();
+  constexpr int NBUF = DUAL ? 2 : 1;
   __shared__ cx<T> lds[SH::G * NBUF * SH::S];
   const int g = threadIdx.x / SH::TT;
   const int t = threadIdx.x % SH::TT;
@@ -211,7 +224,7 @@ __global__ __launch_bounds__(Shape<P>::THREADS) FBST_K3_ATTR void k_toeplitz_fu(
     u1[s] = cmulc(V, ldg(g1 + t + s * SH::TT));
     u2[s] = cmulc(V, ldg(g2 + t + s * SH::TT));
   }
-  if constexpr (FBST_K3_DUAL) {
+  if constexpr (DUAL) {
     // both branches: u_k <- FFT(trunc_L(IFFT(u_k)))
     fft2<T, P, kE, +1>(u1, u2, buf, buf + SH::S, tw, t);
 #pragma unroll
@@ -324,11 +337,11 @@ hipError_t launch_axis_czt(int P, const void* in, void* out, const void* pre, co
   switch (P) {
 #define CASE(PP)                                                                               \
   case PP:                                                                                     \
-    if constexpr (fits_lds<T, PP>()) {                                                         \
-      const int n_tiles = (L + Shape<PP>::G - 1) / Shape<PP>::G;                               \
+    if constexpr ((sizeof(T) * 2 * lds_stride(PP) * ShapeK2<PP>::G <= 160 * 1024)) {                                                         \
+      const int n_tiles = (L + ShapeK2<PP>::G - 1) / ShapeK2<PP>::G;                               \
       const long long ng = 1LL * nblocks * pre_n * post_n * n_tiles;                           \
       if (ng <= 0 || ng > 0x7fffffffLL) return hipErrorInvalidValue;                          \
-      const dim3 grid((unsigned)ng), block(Shape<PP>::THREADS);                                \
+      const dim3 grid((unsigned)ng), block(ShapeK2<PP>::THREADS);                                \
       const bool half = slots_for<PP>(a_in) <= kE / 2 && slots_for<PP>(a_out) <= kE / 2;      \
       if (half)                                                                                \
         hipLaunchKernelGGL((k_axis_czt<T, PP, kE / 2, kE / 2>), grid, block, 0, st,            \
@@ -358,7 +371,7 @@ hipError_t launch_toeplitz_fu(int P, const void* w, void* beams, const void* G1,
   switch (P) {
 #define CASE(PP)                                                                               \
   case PP:                                                                                     \
-    if constexpr (fits_lds<T, PP, (FBST_K3_DUAL ? 2 : 1)>()) {                                 \
+    if constexpr (fits_lds<T, PP>()) {                                                         \
       if (2 * L > PP) return hipErrorInvalidValue;                                             \
       const dim3 grid(grid_for<PP>(nblocks * B)), block(Shape<PP>::THREADS);                   \
       const int sn = slots_for<PP>(N);                                                         \
