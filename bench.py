@@ -132,6 +132,92 @@ def rocprof_summary(kt_dir, pmc_dirs, copy_dirs):
     return "\n".join(out)
 
 
+def serve_bench(F, torch, configs, *, seconds=2.0, loads=(0.5, 0.8, 0.95), burst=768,
+                slots=16, seed=0, log=print):
+    """Continuous-batching server over resident plans: saturation throughput
+    from a burst, then Poisson arrivals at fractions of it (arrays chosen
+    uniformly); latency = completion - submission on the server clock."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    t0 = time.perf_counter()
+
+    def mk(c):
+        return F.plan_for_config(c)
+
+    with ThreadPoolExecutor(4) as ex:
+        plans = list(ex.map(mk, configs))
+    plan_s = time.perf_counter() - t0
+    rng = np.random.default_rng(seed)
+    xs, outs = [], []
+    for c, p in zip(configs, plans):
+        x = (torch.randn((c.M, c.N), dtype=torch.complex64, device="cuda"))
+        xs.append(x)
+        outs.append([torch.empty((c.B, c.N), dtype=torch.complex64, device="cuda") for _ in range(slots)])
+    torch.cuda.synchronize()
+    srv = F.Server(workspace_bytes=4 << 30, streams=4, max_batch=16)
+    samples = [c.B * c.N for c in configs]
+    A = len(configs)
+
+    def run_point(arrivals_us, choice):
+        free = [list(range(slots)) for _ in range(A)]
+        inflight = {}
+        lat, done_samples = [], 0
+        base = srv.clock_us()
+        k = 0
+        tag = 0
+        pending_start = time.perf_counter()
+
+        def harvest():
+            nonlocal done_samples
+            for comp in srv.poll(4096):
+                a, s, sub = inflight.pop(comp.tag)
+                free[a].append(s)
+                lat.append(comp.done_us - comp.submit_us)
+                done_samples += samples[a]
+
+        while k < len(arrivals_us):
+            now = srv.clock_us() - base
+            if now < arrivals_us[k]:
+                harvest()
+                continue
+            a = choice[k]
+            if not free[a]:
+                harvest()
+                continue
+            s = free[a].pop()
+            inflight[tag] = (a, s, now)
+            srv.submit(plans[a], xs[a], outs[a][s], tag)
+            tag += 1
+            k += 1
+        srv.drain(timeout_s=120)
+        harvest()
+        elapsed_s = (srv.clock_us() - base) / 1e6
+        return np.array(lat) / 1e3, done_samples / elapsed_s, len(lat) / elapsed_s
+
+    # saturation: everything submitted at once
+    choice = rng.integers(0, A, burst)
+    lat, sat_samples, sat_blocks = run_point(np.zeros(burst), choice)
+    log(f"[serve] {A} arrays, plans {plan_s:.1f} s; saturation {sat_blocks:.0f} blocks/s, "
+        f"{sat_samples:.3e} beam-samples/s")
+    res = {"arrays": A, "plan_build_s": plan_s, "saturation_blocks_per_s": sat_blocks,
+           "saturation_beam_samples_per_s": sat_samples, "points": []}
+    for load in loads:
+        rate = load * sat_blocks
+        n = max(50, int(rate * seconds))
+        arr = np.cumsum(rng.exponential(1e6 / rate, n))
+        choice = rng.integers(0, A, n)
+        lat, thr, blk = run_point(arr, choice)
+        pt = {"load": load, "offered_blocks_per_s": rate, "blocks": int(len(lat)),
+              "beam_samples_per_s": thr, "p50_ms": float(np.percentile(lat, 50)),
+              "p99_ms": float(np.percentile(lat, 99))}
+        log(f"[serve] load {load:.2f}: {blk:.0f} blocks/s, p50 {pt['p50_ms']:.3f} ms, p99 {pt['p99_ms']:.3f} ms")
+        res["points"].append(pt)
+    srv.close()
+    for p in plans:
+        p.close()
+    return res
+
+
 def main():
     if len(sys.argv) > 1 and sys.argv[1] == "--rocprof-summary":
         # bench.py --rocprof-summary KT_DIR PMC_DIR[,PMC_DIR] COPY_DIR[,COPY_DIR]
@@ -144,6 +230,9 @@ def main():
     ap.add_argument("--chunk", type=int, default=16, help="blocks per launch (0 = all 64)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--latency-reps", type=int, default=200)
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving-mix measurement")
+    ap.add_argument("--serve-only", action="store_true", help="only the serving-mix measurement")
+    ap.add_argument("--serve-seconds", type=float, default=2.0)
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run plain device copies of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -278,6 +367,16 @@ def main():
                      "avg_launch_ms": k3_ms,
                      "flops_per_launch": k3_flops_launch},
     }
+    if not args.no_serve:
+        print("[bench] serving mix", file=sys.stderr, flush=True)
+        log = lambda m: print(m, file=sys.stderr, flush=True)
+        result["serving"] = {
+            "mix": serve_bench(F, torch, synth.serving_arrays(), seconds=args.serve_seconds, log=log),
+            "ula256_stream": serve_bench(F, torch, [cfg], seconds=args.serve_seconds, loads=(0.8,),
+                                         log=log),
+            "what": "continuous-batching server (4 streams, up to 16 blocks of one plan per launch); "
+                    "latency = completion - submission",
+        }
     if not args.no_cpu:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
         y0 = x[0].cpu().numpy().astype(np.complex128)

@@ -206,6 +206,67 @@ const char* fbst_last_error(void);
 /* Library version string. */
 const char* fbst_version(void);
 
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of independent blocks of many resident plans.
+ *
+ * The method's blocks are independent (Sec. III-A streaming remark; Sec. VI
+ * notes the per-beam and per-frequency independence), so a server can batch
+ * whatever blocks are waiting.  A server owns a device workspace budget, a
+ * few launch streams and one scheduler thread.  Whenever a stream is idle
+ * the scheduler takes the oldest waiting request, gathers up to max_batch
+ * waiting requests of the same plan (arrival order), admits them when their
+ * workspace fits in the budget (halving the batch until it does) and launches
+ * the whole path for them with per-block input/output pointers.  Launches on
+ * different streams overlap on the GPU; requests arriving meanwhile join the
+ * next launch.  Each block's result is bitwise the same alone or batched.
+ * Streams are created with default priority.
+ * ------------------------------------------------------------------------ */
+typedef struct fbst_server fbst_server;
+
+typedef struct {
+  size_t workspace_bytes; /* device workspace for blocks in flight (> 0)            */
+  int streams;            /* concurrent launch streams, 1..16                        */
+  int max_batch;          /* blocks of one plan per launch, 1..64                    */
+  int device;             /* HIP device, or -1 for the calling thread's current one  */
+} fbst_server_options;
+
+typedef struct {
+  unsigned long long tag; /* the caller's tag of the request                         */
+  int status;             /* FBST_OK; FBST_E_NOMEM if the budget cannot hold one block
+                             of its plan; FBST_E_DEVICE on a launch or device error;
+                             FBST_E_INVALID if cancelled by fbst_server_destroy       */
+  int batch;              /* blocks in the launch that served it                     */
+  double submit_us;       /* server clock (fbst_server_clock_us) at submit           */
+  double start_us;        /* ... when its launch was issued                           */
+  double done_us;         /* ... when the scheduler saw the launch complete            */
+} fbst_completion;
+
+/* Create a server (NULL options: 1 GiB workspace, 4 streams, batches of 16,
+ * current device).  Allocates the workspace and starts the scheduler. */
+fbst_status fbst_server_create(const fbst_server_options* options, fbst_server** out);
+
+/* Queue one block: x [M][N] -> beams [B][N] of plan (layouts as fbst_execute).
+ * Returns at once; x and beams must stay valid, and beams untouched, until the
+ * request's completion has been polled.  The plan must outlive its requests. */
+fbst_status fbst_server_submit(fbst_server* server, const fbst_plan* plan, const void* x,
+                               void* beams, unsigned long long tag);
+
+/* Move up to max completions (oldest first) into out; returns how many, or a
+ * negative status on invalid arguments. */
+int fbst_server_poll(fbst_server* server, fbst_completion* out, int max);
+
+/* Block until nothing is queued or running (timeout_s <= 0: no timeout);
+ * FBST_E_DEVICE on timeout. */
+fbst_status fbst_server_drain(fbst_server* server, double timeout_s);
+
+/* The server's clock in microseconds since creation (steady clock). */
+double fbst_server_clock_us(const fbst_server* server);
+
+/* Stop the scheduler: queued requests are completed as cancelled, running
+ * launches are waited for, then the streams and workspace are freed.
+ * NULL is a no-op. */
+void fbst_server_destroy(fbst_server* server);
+
 #ifdef __cplusplus
 }
 #endif

@@ -21,6 +21,12 @@ fbst_status fail(fbst_status st, const std::string& msg) {
   return st;
 }
 
+}  // namespace
+
+void fbst::set_last_error(const std::string& msg) { g_last_error = msg; }
+
+namespace {
+
 fbst_status hip_fail(hipError_t e, const char* what) {
   return fail(FBST_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
@@ -142,11 +148,14 @@ fbst_status upload(fbst_plan* pl) {
   return FBST_OK;
 }
 
+size_t io_elem(const fbst::Params& p) { return p.prec == FBST_PREC_FP64 ? 16 : 8; }
+
 template <typename T1>
-hipError_t run_stage0(const fbst_plan* pl, int nb, const void* x, void* yhat, hipStream_t st) {
+hipError_t run_stage0(const fbst_plan* pl, int nb, const fbst::InPtrs& xs, void* yhat,
+                      hipStream_t st) {
   const fbst::Params& p = pl->p;
-  return fbst::launch_time_czt<T1>(p.p1, x, yhat, pl->pre1, pl->H1, pl->post1, pl->tw1, p.N, p.L,
-                                   nb * p.M, st);
+  return fbst::launch_time_czt<T1>(p.p1, xs, nb, yhat, pl->pre1, pl->H1, pl->post1, pl->tw1, p.M,
+                                   p.N, p.L, st);
 }
 
 template <typename T1>
@@ -166,48 +175,70 @@ hipError_t run_stage1(const fbst_plan* pl, int nb, const void* yhat, void* w, vo
                                    p.bu, 1, p.L, nb, st);
 }
 
-hipError_t run_stage2(const fbst_plan* pl, int nb, const void* w, void* beams, hipStream_t st) {
+hipError_t run_stage2(const fbst_plan* pl, int nb, const void* w, const fbst::OutPtrs& outs,
+                      hipStream_t st) {
   const fbst::Params& p = pl->p;
-  const int rows = nb;
   switch (p.prec) {
     case FBST_PREC_FP64:
-      return fbst::launch_toeplitz_fu<double, double, double>(p.p3, w, beams, pl->G1, pl->G2,
+      return fbst::launch_toeplitz_fu<double, double, double>(p.p3, w, outs, pl->G1, pl->G2,
                                                               pl->pre3, pl->H3, pl->post3, pl->tw2,
-                                                              p.B, p.L, p.N, rows, st);
+                                                              p.B, p.L, p.N, nb, st);
     case FBST_PREC_FP64_STAGE2:
-      return fbst::launch_toeplitz_fu<double, float, float>(p.p3, w, beams, pl->G1, pl->G2,
+      return fbst::launch_toeplitz_fu<double, float, float>(p.p3, w, outs, pl->G1, pl->G2,
                                                             pl->pre3, pl->H3, pl->post3, pl->tw2,
-                                                            p.B, p.L, p.N, rows, st);
+                                                            p.B, p.L, p.N, nb, st);
     default:
-      return fbst::launch_toeplitz_fu<float, float, float>(p.p3, w, beams, pl->G1, pl->G2,
+      return fbst::launch_toeplitz_fu<float, float, float>(p.p3, w, outs, pl->G1, pl->G2,
                                                            pl->pre3, pl->H3, pl->post3, pl->tw2,
-                                                           p.B, p.L, p.N, rows, st);
+                                                           p.B, p.L, p.N, nb, st);
   }
 }
 
-hipError_t run_stage(const fbst_plan* pl, int stage, int nb, const void* in, void* out, void* z,
-                     hipStream_t st) {
-  const bool d1 = stage1_double(pl->p);
-  if (stage == 0) return d1 ? run_stage0<double>(pl, nb, in, out, st) : run_stage0<float>(pl, nb, in, out, st);
-  if (stage == 1)
-    return d1 ? run_stage1<double>(pl, nb, in, out, z, st) : run_stage1<float>(pl, nb, in, out, z, st);
-  return run_stage2(pl, nb, in, out, st);
-}
+}  // namespace
 
-// Whole path for nb blocks with the given workspace [yhat | w | z].
-hipError_t run_all(const fbst_plan* pl, int nb, const void* x, void* beams, void* ws, hipStream_t st) {
-  const fbst::Params& p = pl->p;
+namespace fbst {
+
+// Whole path for nb <= MAX_LAUNCH_BLOCKS blocks with inputs xs, outputs outs
+// and the workspace [yhat | w | z] of nb blocks.
+hipError_t run_blocks(const fbst_plan* pl, int nb, const InPtrs& xs, const OutPtrs& outs, void* ws,
+                      hipStream_t st) {
+  const Params& p = pl->p;
   const size_t e1 = s1_elem(p);
   unsigned char* base = static_cast<unsigned char*>(ws);
   void* yhat = base;
   void* w = base + static_cast<size_t>(nb) * p.M * p.L * e1;
   void* z = static_cast<unsigned char*>(w) + static_cast<size_t>(nb) * p.B * p.L * e1;
-  hipError_t e = run_stage(pl, 0, nb, x, yhat, nullptr, st);
+  const bool d1 = stage1_double(p);
+  hipError_t e = d1 ? run_stage0<double>(pl, nb, xs, yhat, st) : run_stage0<float>(pl, nb, xs, yhat, st);
   if (e != hipSuccess) return e;
-  e = run_stage(pl, 1, nb, yhat, w, z, st);
+  e = d1 ? run_stage1<double>(pl, nb, yhat, w, z, st) : run_stage1<float>(pl, nb, yhat, w, z, st);
   if (e != hipSuccess) return e;
-  return run_stage(pl, 2, nb, w, beams, nullptr, st);
+  return run_stage2(pl, nb, w, outs, st);
 }
+
+// Whole path for nb contiguous blocks, at most `chunk` (<= MAX_LAUNCH_BLOCKS) per launch.
+hipError_t run_contiguous(const fbst_plan* pl, int nb, int chunk, const void* x, void* beams,
+                          void* ws, hipStream_t st) {
+  const Params& p = pl->p;
+  const size_t in_blk = static_cast<size_t>(p.M) * p.N * io_elem(p);
+  const size_t out_blk = static_cast<size_t>(p.B) * p.N * io_elem(p);
+  for (int b0 = 0; b0 < nb; b0 += chunk) {
+    const int n = (nb - b0 < chunk) ? nb - b0 : chunk;
+    InPtrs xs{};
+    OutPtrs outs{};
+    for (int i = 0; i < n; ++i) {
+      xs.p[i] = static_cast<const unsigned char*>(x) + (b0 + i) * in_blk;
+      outs.p[i] = static_cast<unsigned char*>(beams) + (b0 + i) * out_blk;
+    }
+    hipError_t e = run_blocks(pl, n, xs, outs, ws, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace fbst
+
+namespace {
 
 fbst_status check_exec(const fbst_plan* plan) {
   if (!plan) return fail(FBST_E_INVALID, "plan is NULL");
@@ -263,7 +294,7 @@ fbst_status fbst_execute(const fbst_plan* plan, const void* x, void* beams, void
   if (s != FBST_OK) return s;
   if (!x || !beams) return fail(FBST_E_INVALID, "x and beams must not be NULL");
   void* ws = workspace ? workspace : plan->own_ws;
-  hipError_t e = run_all(plan, 1, x, beams, ws, static_cast<hipStream_t>(hip_stream));
+  hipError_t e = fbst::run_contiguous(plan, 1, 1, x, beams, ws, static_cast<hipStream_t>(hip_stream));
   if (e != hipSuccess) return hip_fail(e, "fbst_execute launch");
   return FBST_OK;
 }
@@ -275,23 +306,16 @@ fbst_status fbst_execute_batched(const fbst_plan* plan, int nblocks, int max_chu
   if (nblocks < 0) return fail(FBST_E_INVALID, "nblocks must be >= 0");
   if (nblocks == 0) return FBST_OK;
   if (!x || !beams) return fail(FBST_E_INVALID, "x and beams must not be NULL");
-  const int chunk = (max_chunk <= 0 || max_chunk > nblocks) ? nblocks : max_chunk;
+  int chunk = (max_chunk <= 0 || max_chunk > nblocks) ? nblocks : max_chunk;
+  if (chunk > fbst::MAX_LAUNCH_BLOCKS) chunk = fbst::MAX_LAUNCH_BLOCKS;
   void* ws = workspace;
   if (!ws) {
     if (chunk != 1) return fail(FBST_E_INVALID, "workspace is NULL but chunk > 1");
     ws = plan->own_ws;
   }
-  const fbst::Params& p = plan->p;
-  const size_t io = (p.prec == FBST_PREC_FP64) ? 16 : 8;
-  const size_t in_blk = static_cast<size_t>(p.M) * p.N * io;
-  const size_t out_blk = static_cast<size_t>(p.B) * p.N * io;
-  hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  for (int b0 = 0; b0 < nblocks; b0 += chunk) {
-    const int nb = (nblocks - b0 < chunk) ? nblocks - b0 : chunk;
-    hipError_t e = run_all(plan, nb, static_cast<const unsigned char*>(x) + b0 * in_blk,
-                           static_cast<unsigned char*>(beams) + b0 * out_blk, ws, st);
-    if (e != hipSuccess) return hip_fail(e, "fbst_execute_batched launch");
-  }
+  hipError_t e = fbst::run_contiguous(plan, nblocks, chunk, x, beams, ws,
+                                      static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return hip_fail(e, "fbst_execute_batched launch");
   return FBST_OK;
 }
 
@@ -302,15 +326,39 @@ fbst_status fbst_execute_stage(const fbst_plan* plan, int stage, int nblocks, co
   if (stage < 0 || stage > 2) return fail(FBST_E_INVALID, "stage must be 0, 1 or 2");
   if (nblocks < 1) return fail(FBST_E_INVALID, "nblocks must be >= 1");
   if (!in || !out) return fail(FBST_E_INVALID, "in and out must not be NULL");
-  void* z = nullptr;
-  if (stage == 1 && plan->p.kind == FBST_GRID) {
-    if (!workspace) {
-      if (nblocks != 1) return fail(FBST_E_INVALID, "a grid stage 1 over several blocks needs a workspace");
-      workspace = plan->own_ws;
+  const fbst::Params& p = plan->p;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const size_t e1 = s1_elem(p), eio = io_elem(p);
+  hipError_t e = hipSuccess;
+  if (stage == 1) {
+    void* z = nullptr;
+    if (p.kind == FBST_GRID) {
+      if (!workspace) {
+        if (nblocks != 1) return fail(FBST_E_INVALID, "a grid stage 1 over several blocks needs a workspace");
+        workspace = plan->own_ws;
+      }
+      z = workspace;
     }
-    z = workspace;
+    e = stage1_double(p) ? run_stage1<double>(plan, nblocks, in, out, z, st)
+                         : run_stage1<float>(plan, nblocks, in, out, z, st);
+  } else {
+    for (int b0 = 0; b0 < nblocks && e == hipSuccess; b0 += fbst::MAX_LAUNCH_BLOCKS) {
+      const int n = std::min(fbst::MAX_LAUNCH_BLOCKS, nblocks - b0);
+      if (stage == 0) {
+        fbst::InPtrs xs{};
+        for (int i = 0; i < n; ++i)
+          xs.p[i] = static_cast<const unsigned char*>(in) + static_cast<size_t>(b0 + i) * p.M * p.N * eio;
+        void* yh = static_cast<unsigned char*>(out) + static_cast<size_t>(b0) * p.M * p.L * e1;
+        e = stage1_double(p) ? run_stage0<double>(plan, n, xs, yh, st) : run_stage0<float>(plan, n, xs, yh, st);
+      } else {
+        fbst::OutPtrs outs{};
+        for (int i = 0; i < n; ++i)
+          outs.p[i] = static_cast<unsigned char*>(out) + static_cast<size_t>(b0 + i) * p.B * p.N * eio;
+        const void* w = static_cast<const unsigned char*>(in) + static_cast<size_t>(b0) * p.B * p.L * e1;
+        e = run_stage2(plan, n, w, outs, st);
+      }
+    }
   }
-  hipError_t e = run_stage(plan, stage, nblocks, in, out, z, static_cast<hipStream_t>(hip_stream));
   if (e != hipSuccess) return hip_fail(e, "fbst_execute_stage launch");
   return FBST_OK;
 }

@@ -47,6 +47,24 @@ __host__ __device__ constexpr int lds_stride(int P) { return P + P / 16 + 2; }
 // first entry of the twiddle table of the pass with span NS of a P-point transform
 __host__ __device__ constexpr int tw_offset(int P, int NS) { return P + NS - FFT_E; }
 
+// Padded LDS slots of the operands of a pass.  The padding is additive over
+// multiples of 16, pad(i + 16 m) = pad(i) + 17 m, so every operand of a
+// butterfly sits at a compile-time offset from one computed base and the
+// accesses use the instruction's immediate offset instead of one address
+// register per operand.
+template <int P, int R>
+__device__ __forceinline__ int read_slot(int j, int r) {
+  constexpr int S = P / R;
+  if constexpr (S % 16 == 0) return lds_pad(j) + r * (S / 16) * 17;
+  else return lds_pad(j + r * S);
+}
+template <int R, int NS>
+__device__ __forceinline__ int write_slot(int base, int r) {
+  if constexpr (NS == 1 && 16 % R == 0) return lds_pad(base) + r;   // base = j R, r < R
+  else if constexpr (NS % 16 == 0) return lds_pad(base) + r * (NS / 16) * 17;
+  else return lds_pad(base + r * NS);
+}
+
 // ---------------------------------------------------------------------------
 // Small DFTs in registers, natural order in and out.  DIR = -1: forward
 // (exp(-j ...)); DIR = +1: inverse without scaling.  NZ: inputs [NZ, R) are
@@ -203,7 +221,7 @@ __device__ __forceinline__ void stockham_pass(cx<T> (&v)[E], cx<T>* __restrict__
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       if constexpr (FIRST) b[q][r] = v[q + r * NB];
-      else b[q][r] = buf[lds_pad(j + r * (P / R))];
+      else b[q][r] = buf[read_slot<P, R>(j, r)];
     }
     if constexpr (NS > 1) {
       const int k = j & (NS - 1);
@@ -230,7 +248,7 @@ __device__ __forceinline__ void stockham_pass(cx<T> (&v)[E], cx<T>* __restrict__
       const int k = j & (NS - 1);
       const int base = (j - k) * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[lds_pad(base + r * NS)] = b[q][r];
+      for (int r = 0; r < R; ++r) buf[write_slot<R, NS>(base, r)] = b[q][r];
     }
     __syncthreads();   // the new contents are visible to every thread
   }
@@ -255,8 +273,8 @@ __device__ __forceinline__ void stockham_pass2(cx<T> (&v1)[E], cx<T> (&v2)[E],
         a[q][r] = v1[q + r * NB];
         b[q][r] = v2[q + r * NB];
       } else {
-        a[q][r] = buf1[lds_pad(j + r * (P / R))];
-        b[q][r] = buf2[lds_pad(j + r * (P / R))];
+        a[q][r] = buf1[read_slot<P, R>(j, r)];
+        b[q][r] = buf2[read_slot<P, R>(j, r)];
       }
     }
     if constexpr (NS > 1) {
@@ -294,8 +312,8 @@ __device__ __forceinline__ void stockham_pass2(cx<T> (&v1)[E], cx<T> (&v2)[E],
       const int base = (j - k) * R + k;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        buf1[lds_pad(base + r * NS)] = a[q][r];
-        buf2[lds_pad(base + r * NS)] = b[q][r];
+        buf1[write_slot<R, NS>(base, r)] = a[q][r];
+        buf2[write_slot<R, NS>(base, r)] = b[q][r];
       }
     }
     __syncthreads();

@@ -9,10 +9,21 @@
 
 namespace fbst {
 
-// Stage 1a: yhat[row][i] = sum_n x[row][n] exp(-j omega_{i+1} t_n), rows = nb * M.
+// Blocks of one launch: each block's input (or output) buffer is given by its
+// own pointer, passed by value in the kernel arguments, so one launch can
+// serve blocks that live anywhere (a contiguous batch or separate requests).
+constexpr int MAX_LAUNCH_BLOCKS = 64;
+struct InPtrs {
+  const void* p[MAX_LAUNCH_BLOCKS];
+};
+struct OutPtrs {
+  void* p[MAX_LAUNCH_BLOCKS];
+};
+
+// Stage 1a: yhat[blk][m][i] = sum_n x_blk[m][n] exp(-j omega_{i+1} t_n), blk < nblocks.
 template <typename T>
-hipError_t launch_time_czt(int P, const void* x, void* yhat, const void* pre, const void* H,
-                           const void* post, const void* tw, int N, int L, int rows,
+hipError_t launch_time_czt(int P, const InPtrs& xs, int nblocks, void* yhat, const void* pre,
+                           const void* H, const void* post, const void* tw, int M, int N, int L,
                            hipStream_t st);
 
 // Stage 1b, one axis: layout [nb][pre_n][A][post_n][L], A = a_in -> a_out.
@@ -21,10 +32,10 @@ hipError_t launch_axis_czt(int P, const void* in, void* out, const void* pre, co
                            const void* post, const void* tw, int a_in, int a_out, int pre_n,
                            int post_n, int L, int nblocks, hipStream_t st);
 
-// Stage 2: beams[blk][b][n] from w[blk][b][0..L-1], blk < nblocks; needs 2L <= P.
+// Stage 2: beams_blk[b][n] from w[blk][b][0..L-1], blk < nblocks; needs 2L <= P.
 template <typename T, typename TIN, typename TOUT>
-hipError_t launch_toeplitz_fu(int P, const void* w, void* beams, const void* G1, const void* G2,
-                              const void* pre3, const void* H3, const void* post3, const void* tw,
-                              int B, int L, int N, int nblocks, hipStream_t st);
+hipError_t launch_toeplitz_fu(int P, const void* w, const OutPtrs& outs, const void* G1,
+                              const void* G2, const void* pre3, const void* H3, const void* post3,
+                              const void* tw, int B, int L, int N, int nblocks, hipStream_t st);
 
 }  // namespace fbst

@@ -82,9 +82,9 @@ __device__ __forceinline__ cx<T> ldg(const cx<T>* p) { return *p; }
 // ---------------------------------------------------------------------------
 template <typename T, int P, int SI, int SO>
 __global__ __launch_bounds__(Shape<P>::THREADS) FBST_K12_ATTR void k_time_czt(
-    const cx<T>* __restrict__ x, cx<T>* __restrict__ yhat, const cx<T>* __restrict__ pre,
+    const InPtrs xs, cx<T>* __restrict__ yhat, const cx<T>* __restrict__ pre,
     const cx<T>* __restrict__ H, const cx<T>* __restrict__ post, const cx<T>* __restrict__ tw,
-    int N, int L, int rows) {
+    int M, int N, int L, int rows) {
   using SH = Shape<P>;
   __shared__ cx<T> lds[SH::G * SH::S];
   const int g = threadIdx.x / SH::TT;
@@ -94,7 +94,8 @@ __global__ __launch_bounds__(Shape<P>::THREADS) FBST_K12_ATTR void k_time_czt(
   cx<T>* buf = lds + g * SH::S;
 
   cx<T> v[kE];
-  const cx<T>* src = x + static_cast<size_t>(row) * N;
+  const int blk = active ? row / M : 0;
+  const cx<T>* src = static_cast<const cx<T>*>(xs.p[blk]) + static_cast<size_t>(row - blk * M) * N;
 #pragma unroll
   for (int s = 0; s < kE; ++s) {
     const int n = t + s * SH::TT;
@@ -189,7 +190,7 @@ constexpr bool k3_dual() {
 
 template <typename T, typename TIN, typename TOUT, int P, int SN>
 __global__ __launch_bounds__(Shape<P>::THREADS) FBST_K3_ATTR void k_toeplitz_fu(
-    const cx<TIN>* __restrict__ w, cx<TOUT>* __restrict__ beams, const cx<T>* __restrict__ G1,
+    const cx<TIN>* __restrict__ w, const OutPtrs outs, const cx<T>* __restrict__ G1,
     const cx<T>* __restrict__ G2, const cx<T>* __restrict__ pre3, const cx<T>* __restrict__ H3,
     const cx<T>* __restrict__ post3, const cx<T>* __restrict__ tw, int B, int L, int N,
     int nblocks) {
@@ -266,7 +267,7 @@ __global__ __launch_bounds__(Shape<P>::THREADS) FBST_K3_ATTR void k_toeplitz_fu(
 #pragma unroll
   for (int s = 0; s < kE; ++s) u1[s] = cmul(u1[s], ldg(H3 + t + s * SH::TT));
   fft<T, P, kE, +1>(u1, buf, tw, t);
-  cx<TOUT>* dst = beams + row * N;
+  cx<TOUT>* dst = static_cast<cx<TOUT>*>(outs.p[blk]) + static_cast<size_t>(b) * N;
 #pragma unroll
   for (int s = 0; s < SN; ++s) {
     const int n = t + s * SH::TT;
@@ -296,29 +297,31 @@ constexpr bool fits_lds() { return sizeof(T) * 2 * lds_stride(P) * NBUF * Shape<
 #define FBST_FOR_EACH_P(X) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096) X(8192) X(16384)
 
 template <typename T>
-hipError_t launch_time_czt(int P, const void* x, void* yhat, const void* pre, const void* H,
-                           const void* post, const void* tw, int N, int L, int rows,
+hipError_t launch_time_czt(int P, const InPtrs& xs, int nblocks, void* yhat, const void* pre,
+                           const void* H, const void* post, const void* tw, int M, int N, int L,
                            hipStream_t st) {
+  if (nblocks < 1 || nblocks > MAX_LAUNCH_BLOCKS) return hipErrorInvalidValue;
+  const int rows = nblocks * M;
   switch (P) {
 #define CASE(PP)                                                                               \
   case PP:                                                                                     \
     if constexpr (fits_lds<T, PP>()) {                                                         \
       const int si = slots_for<PP>(N), so = slots_for<PP>(L);                                  \
       const dim3 grid(grid_for<PP>(rows)), block(Shape<PP>::THREADS);                          \
-      const auto a = (const cx<T>*)x;                                                          \
+      const auto& a = xs;                                                                      \
       const auto o = (cx<T>*)yhat;                                                             \
       if (si <= kE / 4 && so <= kE / 2)                                                        \
         hipLaunchKernelGGL((k_time_czt<T, PP, kE / 4, kE / 2>), grid, block, 0, st, a, o,      \
                            (const cx<T>*)pre, (const cx<T>*)H, (const cx<T>*)post,             \
-                           (const cx<T>*)tw, N, L, rows);                                      \
+                           (const cx<T>*)tw, M, N, L, rows);                                   \
       else if (si <= kE / 2)                                                                   \
         hipLaunchKernelGGL((k_time_czt<T, PP, kE / 2, kE>), grid, block, 0, st, a, o,          \
                            (const cx<T>*)pre, (const cx<T>*)H, (const cx<T>*)post,             \
-                           (const cx<T>*)tw, N, L, rows);                                      \
+                           (const cx<T>*)tw, M, N, L, rows);                                   \
       else                                                                                     \
         hipLaunchKernelGGL((k_time_czt<T, PP, kE, kE>), grid, block, 0, st, a, o,              \
                            (const cx<T>*)pre, (const cx<T>*)H, (const cx<T>*)post,             \
-                           (const cx<T>*)tw, N, L, rows);                                      \
+                           (const cx<T>*)tw, M, N, L, rows);                                   \
       return hipGetLastError();                                                                \
     }                                                                                          \
     break;
@@ -365,9 +368,10 @@ hipError_t launch_axis_czt(int P, const void* in, void* out, const void* pre, co
 }
 
 template <typename T, typename TIN, typename TOUT>
-hipError_t launch_toeplitz_fu(int P, const void* w, void* beams, const void* G1, const void* G2,
-                              const void* pre3, const void* H3, const void* post3, const void* tw,
-                              int B, int L, int N, int nblocks, hipStream_t st) {
+hipError_t launch_toeplitz_fu(int P, const void* w, const OutPtrs& outs, const void* G1,
+                              const void* G2, const void* pre3, const void* H3, const void* post3,
+                              const void* tw, int B, int L, int N, int nblocks, hipStream_t st) {
+  if (nblocks < 1 || nblocks > MAX_LAUNCH_BLOCKS) return hipErrorInvalidValue;
   switch (P) {
 #define CASE(PP)                                                                               \
   case PP:                                                                                     \
@@ -376,7 +380,7 @@ hipError_t launch_toeplitz_fu(int P, const void* w, void* beams, const void* G1,
       const dim3 grid(grid_for<PP>(nblocks * B)), block(Shape<PP>::THREADS);                   \
       const int sn = slots_for<PP>(N);                                                         \
       const auto a = (const cx<TIN>*)w;                                                        \
-      const auto o = (cx<TOUT>*)beams;                                                         \
+      const auto& o = outs;                                                                    \
       if (sn <= kE / 4)                                                                        \
         hipLaunchKernelGGL((k_toeplitz_fu<T, TIN, TOUT, PP, kE / 4>), grid, block, 0, st, a, o, \
                            (const cx<T>*)G1, (const cx<T>*)G2, (const cx<T>*)pre3,              \
@@ -403,28 +407,24 @@ hipError_t launch_toeplitz_fu(int P, const void* w, void* beams, const void* G1,
   return hipErrorInvalidValue;
 }
 
-template hipError_t launch_time_czt<float>(int, const void*, void*, const void*, const void*,
+template hipError_t launch_time_czt<float>(int, const InPtrs&, int, void*, const void*, const void*,
                                            const void*, const void*, int, int, int, hipStream_t);
-template hipError_t launch_time_czt<double>(int, const void*, void*, const void*, const void*,
-                                            const void*, const void*, int, int, int, hipStream_t);
+template hipError_t launch_time_czt<double>(int, const InPtrs&, int, void*, const void*, const void*,
+                                           const void*, const void*, int, int, int, hipStream_t);
 template hipError_t launch_axis_czt<float>(int, const void*, void*, const void*, const void*,
                                            const void*, const void*, int, int, int, int, int, int,
                                            hipStream_t);
 template hipError_t launch_axis_czt<double>(int, const void*, void*, const void*, const void*,
                                             const void*, const void*, int, int, int, int, int, int,
                                             hipStream_t);
-template hipError_t launch_toeplitz_fu<float, float, float>(int, const void*, void*, const void*,
-                                                            const void*, const void*, const void*,
-                                                            const void*, const void*, int, int,
-                                                            int, int, hipStream_t);
-template hipError_t launch_toeplitz_fu<double, float, float>(int, const void*, void*, const void*,
-                                                             const void*, const void*, const void*,
-                                                             const void*, const void*, int, int,
-                                                             int, int, hipStream_t);
-template hipError_t launch_toeplitz_fu<double, double, double>(int, const void*, void*, const void*,
-                                                               const void*, const void*,
-                                                               const void*, const void*,
-                                                               const void*, int, int, int, int,
-                                                               hipStream_t);
+template hipError_t launch_toeplitz_fu<float, float, float>(
+    int, const void*, const OutPtrs&, const void*, const void*, const void*, const void*, const void*,
+    const void*, int, int, int, int, hipStream_t);
+template hipError_t launch_toeplitz_fu<double, float, float>(
+    int, const void*, const OutPtrs&, const void*, const void*, const void*, const void*, const void*,
+    const void*, int, int, int, int, hipStream_t);
+template hipError_t launch_toeplitz_fu<double, double, double>(
+    int, const void*, const OutPtrs&, const void*, const void*, const void*, const void*, const void*,
+    const void*, int, int, int, int, hipStream_t);
 
 }  // namespace fbst

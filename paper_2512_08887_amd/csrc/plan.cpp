@@ -2,6 +2,8 @@
 // Toeplitz generators and Gohberg-Semencul spectra.
 #include "plan.h"
 
+#include <sched.h>
+
 #include <algorithm>
 #include <atomic>
 #include <cmath>
@@ -163,6 +165,30 @@ void refine_generator(const zd* col, int L, int P, std::vector<zd>* x) {
   (*x)[0] = zd((*x)[0].real(), 0.0);
 }
 
+// Run fn(i0, i1) over [0, n) on the hardware threads when the work is large.
+int cpu_threads() {
+  cpu_set_t set;
+  if (sched_getaffinity(0, sizeof(set), &set) == 0) return std::max(1, CPU_COUNT(&set));
+  return std::max(1, static_cast<int>(std::thread::hardware_concurrency()));
+}
+
+template <typename F>
+void parallel_for(int n, long long cost, F&& fn) {
+  const int hw = cpu_threads();
+  const int nthreads = std::min({hw, n, 64});
+  if (nthreads <= 1 || cost < 4'000'000LL) {
+    fn(0, n);
+    return;
+  }
+  std::vector<std::thread> th;
+  const int per = (n + nthreads - 1) / nthreads;
+  for (int i = 0; i < nthreads; ++i) {
+    const int a = i * per, b = std::min(n, a + per);
+    if (a < b) th.emplace_back([&fn, a, b] { fn(a, b); });
+  }
+  for (auto& x : th) x.join();
+}
+
 }  // namespace
 
 void fft64(zd* a, int n, int sign) {
@@ -212,6 +238,28 @@ bool levinson_first_column(const zd* col, int L, zd* x) {
       }
     }
     err -= (g * std::conj(eta)).real();
+    if (!(err > 0.0)) return false;
+  }
+  for (int i = 0; i < L; ++i) x[i] = a[i] / err;
+  return true;
+}
+
+bool levinson_real(const double* col, int L, double* x) {
+  // The real symmetric case of levinson_first_column.
+  std::vector<double> a(L, 0.0);
+  a[0] = 1.0;
+  double err = col[0];
+  if (!(err > 0.0)) return false;
+  for (int k = 0; k + 1 < L; ++k) {
+    double eta = 0.0;
+    for (int i = 0; i <= k; ++i) eta += col[k + 1 - i] * a[i];
+    const double g = eta / err;
+    for (int i = 0, j = k + 1; i <= j; ++i, --j) {
+      const double ai = a[i], aj = a[j];
+      a[i] = ai - g * aj;
+      if (i != j) a[j] = aj - g * ai;
+    }
+    err -= g * eta;
     if (!(err > 0.0)) return false;
   }
   for (int i = 0; i < L; ++i) x[i] = a[i] / err;
@@ -409,38 +457,81 @@ fbst_status build_tables(const Params& p, bool keep_gram_gen, HostTables* t, std
     t->gram.clear();
     t->gen.clear();
   }
-  std::vector<zd> time_sum(L);
-  for (int d = 0; d < L; ++d) {
-    const double kd = 2.0 * kPi * p.eps * d / L;
-    time_sum[d] = geometric_sum(N, 0.0, -kd);
-  }
+  // In a frame centred in time and on the array, c_b(d) = exp(-j kd s_b) r_b(d)
+  // with kd = 2 pi eps d / L, s_b = (N-1)/2 - u dx (x0 + (mx-1)/2) - v dy (y0 + (my-1)/2)
+  // (samples) and r_b(d) = D_N(kd) D_mx(kd u dx) D_my(kd v dy), D_K(y) =
+  // sin(K y / 2) / sin(y / 2) real and even.  So A_b = D (R_b + delta I) D^H with
+  // D = diag(exp(-j kd_l s_b)) and R_b real symmetric Toeplitz depending on
+  // (|u|, |v|) only: x_b = A_b^{-1} e_0 = D (R_b + delta I)^{-1} e_0, one real
+  // Levinson recursion per distinct (|u|, |v|).
   const double dxs = p.dx / p.ts, dys = p.dy / p.ts;
+  auto dirichlet = [](int K, double y) {
+    const double s = std::sin(0.5 * y);
+    return s == 0.0 ? static_cast<double>(K) : std::sin(0.5 * K * y) / s;
+  };
+  std::vector<double> rt(L);
+  for (int d = 0; d < L; ++d) rt[d] = dirichlet(N, 2.0 * kPi * p.eps * d / L);
+  std::vector<int> key_of(B);
+  std::vector<std::pair<double, double>> keys;
+  {
+    std::vector<std::pair<std::pair<double, double>, int>> seen;
+    for (int b = 0; b < B; ++b) {
+      const std::pair<double, double> k(std::fabs(t->u[b]), std::fabs(t->v[b]));
+      int idx = -1;
+      for (const auto& e : seen)
+        if (e.first == k) { idx = e.second; break; }
+      if (idx < 0) {
+        idx = static_cast<int>(keys.size());
+        keys.push_back(k);
+        seen.push_back({k, idx});
+      }
+      key_of[b] = idx;
+    }
+  }
+  const int K = static_cast<int>(keys.size());
+  std::vector<std::vector<double>> rcol(K), xr(K);
   std::atomic<bool> ok{true};
   std::mutex fail_mu;
   std::string fail;
-  // refine the Levinson generators when cond(A) ~ 2MN/delta makes their
-  // float64 forward error visible (above ~1e6)
+  auto real_work = [&](int k0, int k1) {
+    for (int k = k0; k < k1 && ok.load(); ++k) {
+      std::vector<double>& r = rcol[k];
+      r.resize(L);
+      const double au = keys[k].first, av = keys[k].second;
+      for (int d = 0; d < L; ++d) {
+        const double kd = 2.0 * kPi * p.eps * d / L;
+        double v = rt[d] * dirichlet(p.mx, kd * au * dxs);
+        if (p.kind == FBST_GRID) v *= dirichlet(p.my, kd * av * dys);
+        r[d] = v;
+      }
+      r[0] += p.delta;
+      xr[k].resize(L);
+      if (!levinson_real(r.data(), L, xr[k].data())) {
+        std::lock_guard<std::mutex> lk(fail_mu);
+        ok = false;
+        fail = "Toeplitz system not positive definite in float64 (delta too small?)";
+      }
+    }
+  };
+  // refine the generators when cond(A) ~ 2MN/delta makes their float64
+  // forward error visible (above ~1e6)
   const bool refine = 2.0 * p.M * p.N / p.delta > 1e6;
   auto work = [&](int b0, int b1) {
     std::vector<zd> col(L), x(L), buf(P3);
     for (int b = b0; b < b1; ++b) {
       const double ub = t->u[b], vb = t->v[b];
+      const double sb = 0.5 * (N - 1) - ub * dxs * (p.x0 + 0.5 * (p.mx - 1)) -
+                        ((p.kind == FBST_GRID) ? vb * dys * (p.y0 + 0.5 * (p.my - 1)) : 0.0);
+      const std::vector<double>& r = rcol[key_of[b]];
+      const std::vector<double>& xk = xr[key_of[b]];
       for (int d = 0; d < L; ++d) {
-        const double kd = 2.0 * kPi * p.eps * d / L;
-        zd sx = geometric_sum(p.mx, kd * ub * p.x0 * dxs, kd * ub * dxs);
-        zd sy = (p.kind == FBST_GRID) ? geometric_sum(p.my, kd * vb * p.y0 * dys, kd * vb * dys)
-                                      : zd(1.0, 0.0);
-        col[d] = time_sum[d] * sx * sy;
+        const zd ph = cis(-2.0 * kPi * p.eps * d / L * sb);
+        col[d] = ph * r[d];
+        x[d] = ph * xk[d];
       }
-      col[0] = zd(col[0].real() + p.delta, 0.0);
+      col[0] = zd(r[0], 0.0);
+      x[0] = zd(xk[0], 0.0);
       if (keep_gram_gen) std::copy(col.begin(), col.end(), t->gram.begin() + static_cast<size_t>(b) * L);
-      if (!ok.load()) return;
-      if (!levinson_first_column(col.data(), L, x.data())) {
-        std::lock_guard<std::mutex> lk(fail_mu);
-        ok = false;
-        fail = "Toeplitz system not positive definite in float64 (delta too small?)";
-        return;
-      }
       if (refine) refine_generator(col.data(), L, P3, &x);
       if (keep_gram_gen) std::copy(x.begin(), x.end(), t->gen.begin() + static_cast<size_t>(b) * L);
       const double x0r = x[0].real();
@@ -457,23 +548,12 @@ fbst_status build_tables(const Params& p, bool keep_gram_gen, HostTables* t, std
       for (int i = 0; i < P3; ++i) t->G2[static_cast<size_t>(b) * P3 + i] = buf[i] * scale;
     }
   };
-  const int nt = std::max(1, std::min<int>(static_cast<int>(std::thread::hardware_concurrency()), B));
-  const int nthreads = std::min(nt, 64);
-  if (nthreads <= 1 || 1LL * B * L * L < 4'000'000LL) {
-    work(0, B);
-  } else {
-    std::vector<std::thread> th;
-    const int per = (B + nthreads - 1) / nthreads;
-    for (int i = 0; i < nthreads; ++i) {
-      const int b0 = i * per, b1 = std::min(B, b0 + per);
-      if (b0 < b1) th.emplace_back(work, b0, b1);
-    }
-    for (auto& x : th) x.join();
-  }
+  parallel_for(K, 1LL * K * L * L, real_work);
   if (!ok) {
     *msg = fail;
     return FBST_E_INVALID;
   }
+  parallel_for(B, 1LL * B * P3 * 64, work);
   return FBST_OK;
 }
 

@@ -55,6 +55,12 @@ fbst_status build_tables(const Params& p, bool keep_gram_gen, HostTables* t, std
 // first column col: returns x = A^{-1} e_0.  false if a pivot is not positive.
 bool levinson_first_column(const zd* col, int L, zd* x);
 
+// Real symmetric positive definite case: x = A^{-1} e_0 for A = toeplitz(col).
+bool levinson_real(const double* col, int L, double* x);
+
+// Thread-local message returned by fbst_last_error().
+void set_last_error(const std::string& msg);
+
 // In-place power-of-two DFT in float64, sign = -1 (forward) or +1 (unscaled inverse).
 void fft64(zd* a, int n, int sign);
 

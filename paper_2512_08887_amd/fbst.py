@@ -54,6 +54,16 @@ class fbst_info(ctypes.Structure):
                 ("device_bytes", c_size_t), ("workspace_per_block", c_size_t)]
 
 
+class fbst_server_options(ctypes.Structure):
+    _fields_ = [("workspace_bytes", c_size_t), ("streams", c_int), ("max_batch", c_int),
+                ("device", c_int)]
+
+
+class fbst_completion(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_ulonglong), ("status", c_int), ("batch", c_int),
+                ("submit_us", c_double), ("start_us", c_double), ("done_us", c_double)]
+
+
 class FbstError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"fbst status {status}: {msg}")
@@ -92,6 +102,18 @@ def load_library(path: str = LIB_PATH):
     L.fbst_last_error.restype = c_char_p
     L.fbst_version.argtypes = []
     L.fbst_version.restype = c_char_p
+    L.fbst_server_create.argtypes = [POINTER(fbst_server_options), POINTER(c_void_p)]
+    L.fbst_server_create.restype = c_int
+    L.fbst_server_submit.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, ctypes.c_ulonglong]
+    L.fbst_server_submit.restype = c_int
+    L.fbst_server_poll.argtypes = [c_void_p, POINTER(fbst_completion), c_int]
+    L.fbst_server_poll.restype = c_int
+    L.fbst_server_drain.argtypes = [c_void_p, c_double]
+    L.fbst_server_drain.restype = c_int
+    L.fbst_server_clock_us.argtypes = [c_void_p]
+    L.fbst_server_clock_us.restype = c_double
+    L.fbst_server_destroy.argtypes = [c_void_p]
+    L.fbst_server_destroy.restype = None
     return L
 
 
@@ -179,6 +201,36 @@ def fbst_plan_table(plan, table, out_array):
 
 def fbst_destroy(plan):
     lib().fbst_destroy(plan)
+
+
+def fbst_server_create(options=None) -> int:
+    h = c_void_p()
+    _check(lib().fbst_server_create(byref(options) if options is not None else None, byref(h)))
+    return h.value
+
+
+def fbst_server_submit(server, plan, x, beams, tag):
+    _check(lib().fbst_server_submit(server, plan, x, beams, tag))
+
+
+def fbst_server_poll(server, max_n=256):
+    buf = (fbst_completion * max_n)()
+    n = lib().fbst_server_poll(server, buf, max_n)
+    if n < 0:
+        raise FbstError(n, "fbst_server_poll: invalid arguments")
+    return [buf[i] for i in range(n)]
+
+
+def fbst_server_drain(server, timeout_s=0.0):
+    _check(lib().fbst_server_drain(server, timeout_s))
+
+
+def fbst_server_clock_us(server) -> float:
+    return float(lib().fbst_server_clock_us(server))
+
+
+def fbst_server_destroy(server):
+    lib().fbst_server_destroy(server)
 
 
 # ---------------------------------------------------------------------------
@@ -275,6 +327,37 @@ class Plan:
     def close(self):
         if getattr(self, "handle", None):
             fbst_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """A continuous-batching block server (fbst_server_*): submit blocks of any
+    resident plan with torch tensors; poll completions with their times."""
+
+    def __init__(self, workspace_bytes=1 << 30, streams=4, max_batch=16, device=-1):
+        self.handle = fbst_server_create(fbst_server_options(workspace_bytes, streams, max_batch, device))
+
+    def submit(self, plan, x, beams, tag):
+        fbst_server_submit(self.handle, plan.handle, x.data_ptr(), beams.data_ptr(), tag)
+
+    def poll(self, max_n=256):
+        return fbst_server_poll(self.handle, max_n)
+
+    def drain(self, timeout_s=0.0):
+        fbst_server_drain(self.handle, timeout_s)
+
+    def clock_us(self):
+        return fbst_server_clock_us(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            fbst_server_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -166,3 +166,20 @@ def test_generator_accurate_at_paper_delta():
             assert np.linalg.norm(gen[b] - x) < 1e-9 * np.linalg.norm(x)
     finally:
         F.fbst_destroy(h)
+
+
+def test_server_argument_validation():
+    """Server options and null arguments are rejected before any device work."""
+    lib = F.lib()
+    h = ctypes.c_void_p()
+    bad = [F.fbst_server_options(0, 4, 16, -1), F.fbst_server_options(1 << 20, 0, 16, -1),
+           F.fbst_server_options(1 << 20, 17, 16, -1), F.fbst_server_options(1 << 20, 4, 0, -1),
+           F.fbst_server_options(1 << 20, 4, 65, -1)]
+    for o in bad:
+        assert lib.fbst_server_create(ctypes.byref(o), ctypes.byref(h)) == F.FBST_E_INVALID
+        assert h.value is None
+    assert lib.fbst_server_create(None, None) == F.FBST_E_INVALID
+    assert lib.fbst_server_submit(None, None, None, None, 0) == F.FBST_E_INVALID
+    assert lib.fbst_server_poll(None, None, 0) == F.FBST_E_INVALID
+    assert lib.fbst_server_drain(None, 0.0) == F.FBST_E_INVALID
+    lib.fbst_server_destroy(None)

@@ -1,0 +1,100 @@
+"""GPU tests of the continuous-batching server (fbst_server_* through the C ABI).
+
+Each block's result is the same alone and in the mix (bitwise: a block's
+arithmetic does not depend on which other blocks share its launch), every
+request completes, workspace admission holds, and times are ordered.
+"""
+import numpy as np
+import pytest
+
+import synth
+from tests.helpers import crandn
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2512_08887_amd import fbst as F  # noqa: E402
+
+
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def make_plans():
+    shapes = [(16, 256, 16, 0.5), (24, 100, 9, 0.3), (64, 512, 64, 0.7)]
+    plans = []
+    for M, N, B, fb in shapes:
+        band = synth.band_from_fb(fb)
+        plans.append(F.Plan(M, N, B, band=F.make_band(band.fc, band.omega),
+                            options=F.make_options(0.1 * 2 * N)))
+    return plans
+
+
+def test_mix_equals_alone():
+    need_gpu()
+    plans = make_plans()
+    rng = np.random.default_rng(0)
+    reqs = []
+    for i in range(60):
+        k = int(rng.integers(0, len(plans)))
+        p = plans[k]
+        x = torch.from_numpy(crandn(rng, p.M, p.N)).to(torch.complex64).cuda()
+        reqs.append((k, x, torch.empty((p.B, p.N), dtype=torch.complex64, device="cuda")))
+    torch.cuda.synchronize()
+    srv = F.Server(workspace_bytes=64 << 20, streams=3, max_batch=8)
+    for tag, (k, x, out) in enumerate(reqs):
+        srv.submit(plans[k], x, out, tag)
+    srv.drain(timeout_s=60)
+    comps = srv.poll(1000)
+    srv.close()
+    assert sorted(c.tag for c in comps) == list(range(len(reqs)))
+    assert all(c.status == F.FBST_OK for c in comps)
+    assert all(c.submit_us <= c.start_us <= c.done_us for c in comps)
+    assert max(c.batch for c in comps) > 1          # batching happened
+    torch.cuda.synchronize()
+    for k, x, out in reqs:
+        alone = plans[k].execute(x)
+        torch.cuda.synchronize()
+        assert torch.equal(alone, out)
+
+
+def test_budget_smaller_than_one_block_fails_cleanly():
+    need_gpu()
+    plans = make_plans()
+    p = plans[2]
+    per_block = F.fbst_workspace_bytes(p.handle, 1)
+    srv = F.Server(workspace_bytes=per_block // 2, streams=1, max_batch=4)
+    x = torch.zeros((p.M, p.N), dtype=torch.complex64, device="cuda")
+    out = torch.empty((p.B, p.N), dtype=torch.complex64, device="cuda")
+    srv.submit(p, x, out, 7)
+    # a block of a smaller plan still fits and is served
+    q = plans[0]
+    xq = torch.zeros((q.M, q.N), dtype=torch.complex64, device="cuda")
+    oq = torch.empty((q.B, q.N), dtype=torch.complex64, device="cuda")
+    srv.submit(q, xq, oq, 8)
+    srv.drain(timeout_s=30)
+    comps = {c.tag: c for c in srv.poll()}
+    srv.close()
+    assert comps[7].status == F.FBST_E_NOMEM
+    assert comps[8].status == F.FBST_OK
+
+
+def test_admission_limits_batch_to_budget():
+    """With room for two blocks, batches never exceed two and all complete."""
+    need_gpu()
+    p = make_plans()[0]
+    per_block = F.fbst_workspace_bytes(p.handle, 1)
+    srv = F.Server(workspace_bytes=2 * per_block + 256, streams=2, max_batch=16)
+    rng = np.random.default_rng(1)
+    xs = [torch.from_numpy(crandn(rng, p.M, p.N)).to(torch.complex64).cuda() for _ in range(12)]
+    outs = [torch.empty((p.B, p.N), dtype=torch.complex64, device="cuda") for _ in xs]
+    for i, (x, o) in enumerate(zip(xs, outs)):
+        srv.submit(p, x, o, i)
+    srv.drain(timeout_s=30)
+    comps = srv.poll()
+    srv.close()
+    assert len(comps) == 12 and all(c.status == F.FBST_OK for c in comps)
+    assert max(c.batch for c in comps) <= 2
+    for x, o in zip(xs, outs):
+        assert torch.equal(p.execute(x), o)
