@@ -64,12 +64,12 @@ def cpu_baseline(cfg, y, delta, n_beams=16):
                         gamma=cfg.gamma, delta=delta)
     idx = np.linspace(0, cfg.B - 1, n_beams).round().astype(int)
     t0 = time.perf_counter()
-    od.beams(y, p, idx)
+    ref = od.beams(y, p, idx)
     dt = time.perf_counter() - t0
-    return {"value": n_beams * cfg.N / dt, "unit": "beam-samples/s", "cores": int(threads),
-            "kind": "oracle",
-            "sample": f"FP64 oracle (definition: dense projection sums + Cholesky), one block, "
-                      f"{n_beams} of {cfg.B} beams, {dt:.1f} s"}
+    return ({"value": n_beams * cfg.N / dt, "unit": "beam-samples/s", "cores": int(threads),
+             "kind": "oracle",
+             "sample": f"FP64 oracle (definition: dense projection sums + Cholesky), one block, "
+                       f"{n_beams} of {cfg.B} beams, {dt:.1f} s"}, idx, ref)
 
 
 def rocprof_summary(kt_dir, pmc_dirs, copy_dirs):
@@ -231,6 +231,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--latency-reps", type=int, default=200)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-mix measurement")
+    ap.add_argument("--no-variants", action="store_true", help="skip the bf16/fp16 split variants")
     ap.add_argument("--serve-only", action="store_true", help="only the serving-mix measurement")
     ap.add_argument("--serve-seconds", type=float, default=2.0)
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
@@ -367,6 +368,49 @@ def main():
                      "avg_launch_ms": k3_ms,
                      "flops_per_launch": k3_flops_launch},
     }
+    # the matrix-core split-precision stage 1a: same 64 blocks, same launches
+    variants = {}
+    if not args.no_variants:
+        for prec in ("bf16_split", "fp16_split"):
+            vp = F.plan_for_config(cfg, precision=prec)
+            vb = torch.empty_like(beams)
+            vws = vp.workspace(chunk)
+
+            def vstep():
+                vp.execute_batched(x, beams=vb, workspace=vws, max_chunk=chunk)
+
+            for _ in range(args.warmup):
+                vstep()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            nst = max(1, min(args.steps, 10))
+            for _ in range(nst):
+                vstep()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            vms = e0.elapsed_time(e1) / nst
+            # stage 1a alone, the stage this variant changes
+            s0a = torch.cuda.Event(enable_timing=True)
+            s0b = torch.cuda.Event(enable_timing=True)
+            s0a.record(stream)
+            F.fbst_execute_stage(vp.handle, 0, chunk, x[0].data_ptr(), yhat.data_ptr(), 0, sptr)
+            s0b.record(stream)
+            torch.cuda.synchronize()
+            variants[prec] = {"value": samples / (vms / 1e3), "ms_per_step": vms,
+                              "stage1a_ms_per_launch": s0a.elapsed_time(s0b),
+                              "beams0": vb[0].cpu().numpy()}
+            print(f"[bench] {prec}: {vms:.3f} ms/step", file=sys.stderr, flush=True)
+            vp.close()
+    s1a = torch.cuda.Event(enable_timing=True)
+    s1b = torch.cuda.Event(enable_timing=True)
+    s1a.record(stream)
+    F.fbst_execute_stage(plan.handle, 0, chunk, x[0].data_ptr(), yhat.data_ptr(), 0, sptr)
+    s1b.record(stream)
+    torch.cuda.synchronize()
+    result["stage1a_ms_per_launch"] = s1a.elapsed_time(s1b)
+
     if not args.no_serve:
         print("[bench] serving mix", file=sys.stderr, flush=True)
         log = lambda m: print(m, file=sys.stderr, flush=True)
@@ -377,10 +421,18 @@ def main():
             "what": "continuous-batching server (4 streams, up to 16 blocks of one plan per launch); "
                     "latency = completion - submission",
         }
+    fp32_0 = beams[0].cpu().numpy()
     if not args.no_cpu:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
         y0 = x[0].cpu().numpy().astype(np.complex128)
-        result["cpu_baseline"] = cpu_baseline(cfg, y0, cfg.delta_noise)
+        result["cpu_baseline"], idx, ref = cpu_baseline(cfg, y0, cfg.delta_noise)
+        acc = {"fp32": float(np.linalg.norm(fp32_0[idx] - ref) / np.linalg.norm(ref))}
+        for k, v in variants.items():
+            acc[k] = float(np.linalg.norm(v["beams0"][idx] - ref) / np.linalg.norm(ref))
+        result["accuracy_vs_oracle"] = {"rel_l2": acc, "sample": "block 0, the 16 oracle beams"}
+    if variants:
+        result["variants"] = {k: {kk: vv for kk, vv in v.items() if kk != "beams0"}
+                              for k, v in variants.items()}
     print(json.dumps(result), flush=True)
     plan.close()
 

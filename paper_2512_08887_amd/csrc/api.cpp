@@ -154,6 +154,9 @@ template <typename T1>
 hipError_t run_stage0(const fbst_plan* pl, int nb, const fbst::InPtrs& xs, void* yhat,
                       hipStream_t st) {
   const fbst::Params& p = pl->p;
+  if (p.prec == FBST_PREC_BF16_SPLIT || p.prec == FBST_PREC_FP16_SPLIT)
+    return fbst::launch_time_czt_mfma(p.p1, p.prec == FBST_PREC_FP16_SPLIT, xs, nb, yhat, pl->pre1,
+                                      pl->H1, pl->post1, pl->tw1, p.M, p.N, p.L, st);
   return fbst::launch_time_czt<T1>(p.p1, xs, nb, yhat, pl->pre1, pl->H1, pl->post1, pl->tw1, p.M,
                                    p.N, p.L, st);
 }

@@ -26,6 +26,13 @@ hipError_t launch_time_czt(int P, const InPtrs& xs, int nblocks, void* yhat, con
                            const void* H, const void* post, const void* tw, int M, int N, int L,
                            hipStream_t st);
 
+// Stage 1a on the matrix cores (bfloat16, or float16 when fp16), split
+// precision with float32 accumulation; complex64 in and out; P in
+// {1024, 2048, 4096, 8192, 16384}.
+hipError_t launch_time_czt_mfma(int P, bool fp16, const InPtrs& xs, int nblocks, void* yhat,
+                                const void* pre, const void* H, const void* post, const void* tw,
+                                int M, int N, int L, hipStream_t st);
+
 // Stage 1b, one axis: layout [nb][pre_n][A][post_n][L], A = a_in -> a_out.
 template <typename T>
 hipError_t launch_axis_czt(int P, const void* in, void* out, const void* pre, const void* H,

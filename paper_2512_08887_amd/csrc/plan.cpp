@@ -388,8 +388,8 @@ fbst_status resolve_params(int M, int N, int B, const fbst_geometry* geom, const
   if (p.kind == FBST_GRID) p.p2y = std::max(p.p2y, 32);
   p.p1 = std::max(p.p1, 32);
   p.p3 = std::max(p.p3, 32);
-  if (p.prec == FBST_PREC_BF16_SPLIT || p.prec == FBST_PREC_FP16_SPLIT) {
-    *msg = "the bf16/fp16 split-precision stage 1a is not available in this build";
+  if ((p.prec == FBST_PREC_BF16_SPLIT || p.prec == FBST_PREC_FP16_SPLIT) && p.p1 < 1024) {
+    *msg = "the matrix-core stage 1a needs a time FFT of at least 1024 points (N + L - 1 > 512)";
     return FBST_E_UNSUPPORTED;
   }
   const int lim1 = (p.prec == FBST_PREC_FP64) ? 8192 : PMAX;
