@@ -82,6 +82,9 @@ def rocprof_summary(kt_dir, pmc_dirs, copy_dirs):
     from collections import defaultdict
 
     def short(name):
+        m = re.match(r"_ZN4fbst12_GLOBAL__N_1\d+(k_\w+?)ILi(\d+)EDv8_DF16(b|_)", name)
+        if m:   # names the profiler leaves mangled (16-bit vector template arguments)
+            return f"{m.group(1)}<{m.group(2)}, {'bf16x8' if m.group(3) == 'b' else 'f16x8'}>"
         n = name.replace("void fbst::(anonymous namespace)::", "").replace("void ", "")
         return re.sub(r"\(.*", "", n)
 
@@ -124,12 +127,47 @@ def rocprof_summary(kt_dir, pmc_dirs, copy_dirs):
     out.append("")
     out.append("kernel | grid | counter | dispatches | KiB per dispatch | scaled MB per dispatch")
     out.append("---|---|---|---|---|---")
+    scaled = {}
     for (k, g, c), v in sorted(cnt.items()):
         if not k.startswith("k_"):
             continue
         f = factors.get(c, 1.0)
+        scaled.setdefault(f"{k} | {g}", {})[c] = float(np.median(v) * 1024 * f)
         out.append(f"{k} | {g} | {c} | {len(v)} | {np.median(v):.0f} | {np.median(v) * 1024 * f / 1e6:.1f}")
-    return "\n".join(out)
+    return "\n".join(out), scaled
+
+
+# Sources whose change invalidates stored HBM counter readings of the kernels.
+KERNEL_SOURCES = ["cx.h", "fft_lds.h", "kernels.h", "kernels.hip", "mfma_czt.hip"]
+COUNTERS_JSON = os.path.join(ROOT, "profiles", "hbm_counters_ula256_16blk.json")
+
+
+def kernel_source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2512_08887_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    with open(os.path.join(ROOT, "paper_2512_08887_amd", "build.py"), "rb") as fh:
+        h.update(fh.read())
+    return h.hexdigest()
+
+
+def stored_traffic(kernel, grid):
+    """HBM bytes per dispatch (FETCH_SIZE + WRITE_SIZE, copy-calibrated) of a
+    kernel from the committed counter readings, or None when the kernel sources
+    changed since they were taken."""
+    try:
+        with open(COUNTERS_JSON) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if d.get("source_sha256") != kernel_source_digest():
+        return None
+    c = d.get("kernels", {}).get(f"{kernel} | {grid}")
+    if not c or "FETCH_SIZE" not in c or "WRITE_SIZE" not in c:
+        return None
+    return c["FETCH_SIZE"] + c["WRITE_SIZE"]
 
 
 def serve_bench(F, torch, configs, *, seconds=2.0, loads=(0.5, 0.8, 0.95), burst=768,
@@ -220,8 +258,14 @@ def serve_bench(F, torch, configs, *, seconds=2.0, loads=(0.5, 0.8, 0.95), burst
 
 def main():
     if len(sys.argv) > 1 and sys.argv[1] == "--rocprof-summary":
-        # bench.py --rocprof-summary KT_DIR PMC_DIR[,PMC_DIR] COPY_DIR[,COPY_DIR]
-        print(rocprof_summary(sys.argv[2], sys.argv[3].split(","), sys.argv[4].split(",")))
+        # bench.py --rocprof-summary KT_DIR PMC_DIR[,PMC_DIR] COPY_DIR[,COPY_DIR] [COUNTERS_JSON]
+        text, scaled = rocprof_summary(sys.argv[2], sys.argv[3].split(","), sys.argv[4].split(","))
+        print(text)
+        if len(sys.argv) > 5:
+            with open(sys.argv[5], "w") as fh:
+                json.dump({"what": "HBM bytes per dispatch: FETCH_SIZE and WRITE_SIZE medians, scaled "
+                                   "by a plain-copy calibration; keyed 'kernel | grid work-items'",
+                           "source_sha256": kernel_source_digest(), "kernels": scaled}, fh, indent=1)
         return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -338,6 +382,38 @@ def main():
         if i >= 5:
             lat.append((time.perf_counter() - t0) * 1e3)
     lat = np.array(lat)
+    # the same single block replayed from a captured graph (one launch call)
+    g1 = plan.graph(one.unsqueeze(0), out1.unsqueeze(0), workspace=ws1)
+    glat = []
+    for i in range(args.latency_reps + 5):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g1.launch()
+        stream.synchronize()
+        if i >= 5:
+            glat.append((time.perf_counter() - t0) * 1e3)
+    glat = np.array(glat)
+    g1.close()
+    # the whole 64-block step as one graph, and the autotuned blocks per launch
+    gb = torch.empty_like(beams)
+    gall = plan.graph(x, gb, workspace=ws, max_chunk=chunk)
+    gall.launch()
+    torch.cuda.synchronize()
+    ga = torch.cuda.Event(enable_timing=True)
+    gz = torch.cuda.Event(enable_timing=True)
+    ga.record(stream)
+    for _ in range(args.steps):
+        gall.launch()
+    gz.record(stream)
+    torch.cuda.synchronize()
+    graph_ms = ga.elapsed_time(gz) / args.steps
+    assert torch.equal(gb, beams), "graph replay differs from the eager step"
+    gall.close()
+    tune_ws = plan.workspace(min(nblk, F.MAX_LAUNCH_BLOCKS))
+    tuned_chunk, tuned_ms = plan.autotune(x, beams=gb, workspace=tune_ws)
+    del tune_ws, gb
+    print(f"[bench] graph step {graph_ms:.3f} ms; autotune chunk {tuned_chunk} ({tuned_ms:.3f} ms)",
+          file=sys.stderr, flush=True)
 
     s0, s1, s2 = stage_flops(info)
     k3_flops_launch = s2 * chunk
@@ -360,11 +436,17 @@ def main():
                    "blocks_per_step": nblk, "blocks_per_launch": chunk, "precision": "fp32"},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "what": "one block alone: execute + stream sync, host clock"},
+        "graph": {"latency_ms": {"p50": float(np.percentile(glat, 50)), "p99": float(np.percentile(glat, 99))},
+                  "ms_per_step": graph_ms,
+                  "what": "the single block and the 64-block step replayed from captured HIP graphs"},
+        "autotune": {"blocks_per_launch": tuned_chunk, "ms_per_step": tuned_ms},
         "stage_gflop_per_block": [s0 / 1e9, s1 / 1e9, s2 / 1e9],
         "path_tflops": (s0 + s1 + s2) * nblk / (ms_step / 1e3) / 1e12,
         "roofline": {"kernel": "k_toeplitz_fu (stage 2: Gohberg-Semencul apply + F_u chirp-z)",
                      "bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32,
+                     "traffic": stored_traffic("k_toeplitz_fu<float, float, float, 4096, 4>",
+                                               chunk * cfg.B * 256),
                      "avg_launch_ms": k3_ms,
                      "flops_per_launch": k3_flops_launch},
     }

@@ -174,6 +174,32 @@ fbst_status fbst_execute_stage(const fbst_plan* plan, int stage, int nblocks,
                                const void* in, void* out, void* workspace,
                                void* hip_stream);
 
+/* ---- Graph capture and tuning of batched launches ---------------------- */
+typedef struct fbst_graph fbst_graph;
+
+/* Capture the launches of fbst_execute_batched(plan, nblocks, max_chunk, x,
+ * beams, workspace) into an instantiated HIP graph bound to these buffers
+ * (they must stay valid while the graph is used).  The capture runs on a
+ * private stream and executes nothing.  The graph holds no memset node. */
+fbst_status fbst_graph_create(const fbst_plan* plan, int nblocks, int max_chunk, const void* x,
+                              void* beams, void* workspace, fbst_graph** out);
+
+/* Replay the captured launches on hip_stream (asynchronous). */
+fbst_status fbst_graph_launch(const fbst_graph* graph, void* hip_stream);
+
+/* Free a graph (after its launches finished); NULL is a no-op. */
+void fbst_graph_destroy(fbst_graph* graph);
+
+/* Autotune the blocks per launch of fbst_execute_batched for nblocks blocks of
+ * this plan: times chunk = 1, 2, 4, ... (<= min(nblocks, 64)) on the given
+ * buffers (x [nblocks][M][N], beams, workspace of fbst_workspace_bytes(plan,
+ * min(nblocks, 64)) bytes) on hip_stream, synchronising it, and returns the
+ * fastest chunk and its ms per batch.  Results are cached per plan shape and
+ * precision for the process; force != 0 re-measures.  beams is overwritten. */
+fbst_status fbst_autotune(const fbst_plan* plan, int nblocks, const void* x, void* beams,
+                          void* workspace, void* hip_stream, int force, int* best_chunk,
+                          float* best_ms);
+
 /* Workspace bytes for nblocks blocks processed in one launch (0 on NULL plan). */
 size_t fbst_workspace_bytes(const fbst_plan* plan, int nblocks);
 

@@ -4,7 +4,10 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -363,6 +366,119 @@ fbst_status fbst_execute_stage(const fbst_plan* plan, int stage, int nblocks, co
     }
   }
   if (e != hipSuccess) return hip_fail(e, "fbst_execute_stage launch");
+  return FBST_OK;
+}
+
+fbst_status fbst_graph_create(const fbst_plan* plan, int nblocks, int max_chunk, const void* x,
+                              void* beams, void* workspace, fbst_graph** out) {
+  if (!out) return fail(FBST_E_INVALID, "out is NULL");
+  *out = nullptr;
+  fbst_status s = check_exec(plan);
+  if (s != FBST_OK) return s;
+  if (nblocks < 1) return fail(FBST_E_INVALID, "nblocks must be >= 1");
+  if (!x || !beams) return fail(FBST_E_INVALID, "x and beams must not be NULL");
+  int chunk = (max_chunk <= 0 || max_chunk > nblocks) ? nblocks : max_chunk;
+  if (chunk > fbst::MAX_LAUNCH_BLOCKS) chunk = fbst::MAX_LAUNCH_BLOCKS;
+  void* ws = workspace;
+  if (!ws) {
+    if (chunk != 1) return fail(FBST_E_INVALID, "workspace is NULL but chunk > 1");
+    ws = plan->own_ws;
+  }
+  hipStream_t cs = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (e != hipSuccess) return hip_fail(e, "capture stream");
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
+  if (e == hipSuccess) {
+    const hipError_t le = fbst::run_contiguous(plan, nblocks, chunk, x, beams, ws, cs);
+    e = hipStreamEndCapture(cs, &graph);
+    if (le != hipSuccess) e = le;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (graph) (void)hipGraphDestroy(graph);
+  (void)hipStreamDestroy(cs);
+  if (e != hipSuccess) {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    return hip_fail(e, "graph capture");
+  }
+  fbst_graph* g = new (std::nothrow) fbst_graph();
+  if (!g) {
+    (void)hipGraphExecDestroy(exec);
+    return fail(FBST_E_NOMEM, "host allocation failed");
+  }
+  g->exec = exec;
+  *out = g;
+  return FBST_OK;
+}
+
+fbst_status fbst_graph_launch(const fbst_graph* graph, void* hip_stream) {
+  if (!graph) return fail(FBST_E_INVALID, "graph is NULL");
+  const hipError_t e = hipGraphLaunch(graph->exec, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  return FBST_OK;
+}
+
+void fbst_graph_destroy(fbst_graph* graph) {
+  if (!graph) return;
+  (void)hipGraphExecDestroy(graph->exec);
+  delete graph;
+}
+
+fbst_status fbst_autotune(const fbst_plan* plan, int nblocks, const void* x, void* beams,
+                          void* workspace, void* hip_stream, int force, int* best_chunk,
+                          float* best_ms) {
+  fbst_status s = check_exec(plan);
+  if (s != FBST_OK) return s;
+  if (nblocks < 1 || !x || !beams || !workspace || !best_chunk)
+    return fail(FBST_E_INVALID, "nblocks >= 1, x, beams, workspace and best_chunk are required");
+  const fbst::Params& p = plan->p;
+  const auto key = std::make_tuple(p.M, p.N, p.B, p.L, p.mx * 65536 + p.my, p.bu * 65536 + p.bv,
+                                   static_cast<int>(p.prec), nblocks);
+  static std::mutex mu;
+  static std::map<decltype(key), std::pair<int, float>> cache;
+  if (!force) {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) {
+      *best_chunk = it->second.first;
+      if (best_ms) *best_ms = it->second.second;
+      return FBST_OK;
+    }
+  }
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  int best = 0;
+  float bms = 0.0f;
+  for (int chunk = 1; e == hipSuccess && chunk <= std::min(nblocks, fbst::MAX_LAUNCH_BLOCKS); chunk *= 2) {
+    e = fbst::run_contiguous(plan, nblocks, chunk, x, beams, workspace, st);   // warm-up
+    float acc = 0.0f;
+    for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+      e = hipEventRecord(e0, st);
+      if (e == hipSuccess) e = fbst::run_contiguous(plan, nblocks, chunk, x, beams, workspace, st);
+      if (e == hipSuccess) e = hipEventRecord(e1, st);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      acc += ms;
+    }
+    const float ms = acc / 3.0f;
+    if (e == hipSuccess && (best == 0 || ms < bms)) {
+      best = chunk;
+      bms = ms;
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return hip_fail(e, "fbst_autotune");
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    cache[key] = {best, bms};
+  }
+  *best_chunk = best;
+  if (best_ms) *best_ms = bms;
   return FBST_OK;
 }
 

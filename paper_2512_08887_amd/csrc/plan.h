@@ -1,6 +1,8 @@
 // Plan object and FP64 host table builder of the FBST library.
 #pragma once
 
+#include <hip/hip_runtime.h>
+
 #include <complex>
 #include <cstddef>
 #include <string>
@@ -65,6 +67,11 @@ void set_last_error(const std::string& msg);
 void fft64(zd* a, int n, int sign);
 
 }  // namespace fbst
+
+// A captured and instantiated launch sequence of one plan.
+struct fbst_graph {
+  hipGraphExec_t exec = nullptr;
+};
 
 // The plan: parameters, optional FP64 host tables and device tables.
 struct fbst_plan {

@@ -23,6 +23,7 @@ FBST_LINE, FBST_GRID = 0, 1
 FBST_PREC_FP32, FBST_PREC_FP64_STAGE2, FBST_PREC_FP64, FBST_PREC_BF16_SPLIT, FBST_PREC_FP16_SPLIT = range(5)
 FBST_FLAG_HOST_ONLY, FBST_FLAG_KEEP_HOST_TABLES = 1, 2
 FBST_TABLE_BEAM_U, FBST_TABLE_BEAM_V, FBST_TABLE_GRAM, FBST_TABLE_GENERATOR = 0, 1, 2, 3
+MAX_LAUNCH_BLOCKS = 64  # blocks per kernel launch (per-block pointer arrays in the kernel arguments)
 
 PRECISIONS = {"fp32": FBST_PREC_FP32, "fp64_stage2": FBST_PREC_FP64_STAGE2, "fp64": FBST_PREC_FP64,
               "bf16_split": FBST_PREC_BF16_SPLIT, "fp16_split": FBST_PREC_FP16_SPLIT}
@@ -102,6 +103,15 @@ def load_library(path: str = LIB_PATH):
     L.fbst_last_error.restype = c_char_p
     L.fbst_version.argtypes = []
     L.fbst_version.restype = c_char_p
+    L.fbst_graph_create.argtypes = [c_void_p, c_int, c_int, c_void_p, c_void_p, c_void_p, POINTER(c_void_p)]
+    L.fbst_graph_create.restype = c_int
+    L.fbst_graph_launch.argtypes = [c_void_p, c_void_p]
+    L.fbst_graph_launch.restype = c_int
+    L.fbst_graph_destroy.argtypes = [c_void_p]
+    L.fbst_graph_destroy.restype = None
+    L.fbst_autotune.argtypes = [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_int,
+                                POINTER(c_int), POINTER(ctypes.c_float)]
+    L.fbst_autotune.restype = c_int
     L.fbst_server_create.argtypes = [POINTER(fbst_server_options), POINTER(c_void_p)]
     L.fbst_server_create.restype = c_int
     L.fbst_server_submit.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, ctypes.c_ulonglong]
@@ -201,6 +211,29 @@ def fbst_plan_table(plan, table, out_array):
 
 def fbst_destroy(plan):
     lib().fbst_destroy(plan)
+
+
+def fbst_graph_create(plan, nblocks, max_chunk, x, beams, workspace=0) -> int:
+    h = c_void_p()
+    _check(lib().fbst_graph_create(plan, nblocks, max_chunk, x, beams, workspace or None, byref(h)))
+    return h.value
+
+
+def fbst_graph_launch(graph, stream=0):
+    _check(lib().fbst_graph_launch(graph, stream or None))
+
+
+def fbst_graph_destroy(graph):
+    lib().fbst_graph_destroy(graph)
+
+
+def fbst_autotune(plan, nblocks, x, beams, workspace, stream=0, force=False):
+    """Returns (best_chunk, ms_per_batch)."""
+    c = c_int()
+    ms = ctypes.c_float()
+    _check(lib().fbst_autotune(plan, nblocks, x, beams, workspace, stream or None, int(force),
+                               byref(c), byref(ms)))
+    return c.value, ms.value
 
 
 def fbst_server_create(options=None) -> int:
@@ -324,9 +357,54 @@ class Plan:
                            workspace.data_ptr() if workspace is not None else 0, self._stream())
         return out
 
+    def autotune(self, x, beams=None, workspace=None, force=False):
+        """Fastest blocks per launch for x [nblocks, M, N]; returns (chunk, ms per batch)."""
+        import torch
+        self._check_in(x, (self.M, self.N))
+        nb = x.shape[0]
+        if beams is None:
+            beams = torch.empty((nb, self.B, self.N), dtype=self.complex_dtype, device=x.device)
+        if workspace is None:
+            workspace = self.workspace(min(nb, MAX_LAUNCH_BLOCKS))
+        return fbst_autotune(self.handle, nb, x.data_ptr(), beams.data_ptr(), workspace.data_ptr(),
+                             self._stream(), force)
+
+    def graph(self, x, beams, workspace=None, max_chunk=0):
+        """Capture execute_batched(x -> beams) as a replayable graph bound to these tensors."""
+        self._check_in(x, (self.M, self.N))
+        nb = x.shape[0]
+        chunk = nb if max_chunk <= 0 else min(max_chunk, nb)
+        if workspace is None and chunk > 1:
+            workspace = self.workspace(chunk)
+        return Graph(self, x, beams, workspace, nb, chunk)
+
     def close(self):
         if getattr(self, "handle", None):
             fbst_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Graph:
+    """An instantiated HIP graph of one batched execution; keeps its tensors alive."""
+
+    def __init__(self, plan, x, beams, workspace, nblocks, chunk):
+        self._keep = (plan, x, beams, workspace)
+        self.handle = fbst_graph_create(plan.handle, nblocks, chunk, x.data_ptr(), beams.data_ptr(),
+                                        workspace.data_ptr() if workspace is not None else 0)
+
+    def launch(self):
+        import torch
+        fbst_graph_launch(self.handle, torch.cuda.current_stream().cuda_stream)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            fbst_graph_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

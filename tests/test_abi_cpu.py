@@ -127,10 +127,19 @@ def test_null_and_host_only_plan_calls():
     assert lib.fbst_workspace_bytes(None, 1) == 0
     assert lib.fbst_plan_device_bytes(None) == 0
     assert lib.fbst_execute(None, None, None, None, None) == F.FBST_E_INVALID
+    assert lib.fbst_graph_launch(None, None) == F.FBST_E_INVALID
+    lib.fbst_graph_destroy(None)                            # no-op
     h = host_plan(8, 16, 4)
     try:
         assert lib.fbst_execute(h, ctypes.c_void_p(16), ctypes.c_void_p(16), None, None) == F.FBST_E_INVALID
         assert lib.fbst_execute_stage(h, 3, 1, ctypes.c_void_p(16), ctypes.c_void_p(16), None, None) == F.FBST_E_INVALID
+        g = ctypes.c_void_p(1)
+        assert lib.fbst_graph_create(h, 1, 1, ctypes.c_void_p(16), ctypes.c_void_p(16), None,
+                                     ctypes.byref(g)) == F.FBST_E_INVALID
+        assert g.value is None                              # *out cleared on failure
+        c, ms = ctypes.c_int(), ctypes.c_float()
+        assert lib.fbst_autotune(h, 4, ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(16),
+                                 None, 0, ctypes.byref(c), ctypes.byref(ms)) == F.FBST_E_INVALID
         info = F.fbst_plan_info(h)
         assert (info.p1, info.p2x, info.p3) == (64, 32, 64)
         assert F.fbst_workspace_bytes(h, 3) == 3 * (8 + 4) * 32 * 8
