@@ -139,7 +139,7 @@ def rocprof_summary(kt_dir, pmc_dirs, copy_dirs):
 
 # Sources whose change invalidates stored HBM counter readings of the kernels.
 KERNEL_SOURCES = ["cx.h", "fft_lds.h", "kernels.h", "kernels.hip", "mfma_czt.hip"]
-COUNTERS_JSON = os.path.join(ROOT, "profiles", "hbm_counters_ula256_16blk.json")
+COUNTERS_JSON = os.path.join(ROOT, "profiles", "hbm_counters_ula256.json")
 
 
 def kernel_source_digest():
@@ -271,7 +271,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--chunk", type=int, default=16, help="blocks per launch (0 = all 64)")
+    ap.add_argument("--chunk", type=int, default=-1,
+                    help="blocks per launch (-1: chosen by fbst_autotune, 0: all 64)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--latency-reps", type=int, default=200)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-mix measurement")
@@ -320,7 +321,16 @@ def main():
 
     x = torch.from_numpy(ys).to(torch.complex64).cuda()
     beams = torch.empty((nblk, cfg.B, cfg.N), dtype=torch.complex64, device="cuda")
-    chunk = nblk if args.chunk <= 0 else min(args.chunk, nblk)
+    tuned_chunk = tuned_ms = None
+    if args.chunk < 0:
+        tune_ws = plan.workspace(min(nblk, F.MAX_LAUNCH_BLOCKS))
+        tuned_chunk, tuned_ms = plan.autotune(x, beams=beams, workspace=tune_ws)
+        del tune_ws
+        chunk = tuned_chunk
+        print(f"[bench] autotuned blocks per launch: {chunk} ({tuned_ms:.3f} ms per 64 blocks)",
+              file=sys.stderr, flush=True)
+    else:
+        chunk = nblk if args.chunk == 0 else min(args.chunk, nblk)
     ws = plan.workspace(chunk)
     yhat = ws[: chunk * cfg.M * info.L * 8].view(torch.complex64).view(chunk, cfg.M, info.L)
     w = ws[chunk * cfg.M * info.L * 8: chunk * (cfg.M + cfg.B) * info.L * 8].view(torch.complex64).view(chunk, cfg.B, info.L)
@@ -409,9 +419,11 @@ def main():
     graph_ms = ga.elapsed_time(gz) / args.steps
     assert torch.equal(gb, beams), "graph replay differs from the eager step"
     gall.close()
-    tune_ws = plan.workspace(min(nblk, F.MAX_LAUNCH_BLOCKS))
-    tuned_chunk, tuned_ms = plan.autotune(x, beams=gb, workspace=tune_ws)
-    del tune_ws, gb
+    if tuned_chunk is None:
+        tune_ws = plan.workspace(min(nblk, F.MAX_LAUNCH_BLOCKS))
+        tuned_chunk, tuned_ms = plan.autotune(x, beams=gb, workspace=tune_ws)
+        del tune_ws
+    del gb
     print(f"[bench] graph step {graph_ms:.3f} ms; autotune chunk {tuned_chunk} ({tuned_ms:.3f} ms)",
           file=sys.stderr, flush=True)
 

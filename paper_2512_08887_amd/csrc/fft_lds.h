@@ -206,14 +206,62 @@ __device__ __forceinline__ void dft(cx<T> (&v)[R]) {
 }
 
 // ---------------------------------------------------------------------------
-// One Stockham pass.
+// How a pass obtains its twiddles (global loads, L2/L1 latency):
+//   TW_LAZY      each one loaded where it is used (fewest live registers; the
+//                register-pressure-driven scheduler then tends to serialise
+//                the loads, one round trip each);
+//   TW_BATCH     the pass's loads issued together after its LDS reads (an
+//                empty asm with a memory clobber keeps them above the
+//                multiplies), so their latencies overlap;
+//   TW_PREFETCH  loaded by the previous pass before its barriers, so their
+//                latency overlaps the barrier waits and the LDS exchange (a
+//                load issued before a workgroup barrier stays before it: the
+//                barrier's release fence orders it); costs one more pass's
+//                twiddles in registers across the exchange.
 // ---------------------------------------------------------------------------
-template <typename T, int P, int E, int R, int NS, int DIR, bool FIRST, bool LAST, int NZ_IN>
+enum TwiddleMode { TW_LAZY = 0, TW_PREFETCH = 1, TW_BATCH = 2 };
+
+
+template <typename T, int P, int E, int NS>
+struct PassTw {
+  static constexpr int REM = P / NS;
+  static constexpr int R = (REM >= E) ? E : REM;
+  static constexpr int NB = E / R;
+  static constexpr int N = (NS > 1) ? NB * (R - 1) : 1;
+  cx<T> w[N];
+};
+
+template <typename T, int P, int E, int NS>
+__device__ __forceinline__ void load_tw(PassTw<T, P, E, NS>& pt, const cx<T>* __restrict__ tw,
+                                        int t) {
+  using PT = PassTw<T, P, E, NS>;
+  if constexpr (NS > 1) {
+    constexpr int TT = P / E;
+#pragma unroll
+    for (int q = 0; q < PT::NB; ++q) {
+      const int k = (t + q * TT) & (NS - 1);
+      const cx<T>* twp = tw + tw_offset(P, NS) + k;
+#pragma unroll
+      for (int r = 1; r < PT::R; ++r) pt.w[q * (PT::R - 1) + r - 1] = twp[(r - 1) * NS];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// One Stockham pass.  `cur` holds this pass's twiddles; `before_barrier` is
+// called once the butterflies are computed and before the first barrier (the
+// hook that issues the next pass's twiddle loads).
+// ---------------------------------------------------------------------------
+template <typename T, int P, int E, int R, int NS, int DIR, bool FIRST, bool LAST, int NZ_IN,
+          int TWM, typename Hook>
 __device__ __forceinline__ void stockham_pass(cx<T> (&v)[E], cx<T>* __restrict__ buf,
-                                              const cx<T>* __restrict__ tw, int t) {
+                                              const PassTw<T, P, E, NS>& cur,
+                                              const cx<T>* __restrict__ tw, int t,
+                                              Hook&& before_barrier) {
   constexpr int TT = P / E;
   constexpr int NB = E / R;
   static_assert(E % R == 0, "radix must divide the per-thread element count");
+  static_assert(PassTw<T, P, E, NS>::R == R, "twiddle set of another radix");
   cx<T> b[NB][R];
 #pragma unroll
   for (int q = 0; q < NB; ++q) {
@@ -224,10 +272,18 @@ __device__ __forceinline__ void stockham_pass(cx<T> (&v)[E], cx<T>* __restrict__
       else b[q][r] = buf[read_slot<P, R>(j, r)];
     }
     if constexpr (NS > 1) {
-      const int k = j & (NS - 1);
-      const cx<T>* twp = tw + tw_offset(P, NS) + k;
+      const cx<T>* twp = tw + tw_offset(P, NS) + (j & (NS - 1));
+      cx<T> wb[R - 1];
+      if constexpr (TWM == TW_BATCH) {
 #pragma unroll
-      for (int r = 1; r < R; ++r) b[q][r] = cmul_dir<DIR>(b[q][r], twp[(r - 1) * NS]);
+        for (int r = 1; r < R; ++r) wb[r - 1] = twp[(r - 1) * NS];
+        asm volatile("" ::: "memory");   // issue the loads together (see TW_BATCH)
+      }
+#pragma unroll
+      for (int r = 1; r < R; ++r)
+        b[q][r] = cmul_dir<DIR>(b[q][r], TWM == TW_PREFETCH ? cur.w[q * (R - 1) + r - 1]
+                                         : TWM == TW_BATCH  ? wb[r - 1]
+                                                            : twp[(r - 1) * NS]);
     }
     if constexpr (FIRST && NB == 1) {
       dft<R, DIR, NZ_IN>(b[q]);
@@ -241,6 +297,7 @@ __device__ __forceinline__ void stockham_pass(cx<T> (&v)[E], cx<T>* __restrict__
 #pragma unroll
       for (int r = 0; r < R; ++r) v[q + r * NB] = b[q][r];
   } else {
+    before_barrier();
     __syncthreads();   // every thread has finished reading the previous contents
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
@@ -256,13 +313,17 @@ __device__ __forceinline__ void stockham_pass(cx<T> (&v)[E], cx<T>* __restrict__
 
 // The same pass over two independent transforms (separate LDS buffers)
 // sharing the barriers and the twiddles.
-template <typename T, int P, int E, int R, int NS, int DIR, bool FIRST, bool LAST, int NZ_IN>
+template <typename T, int P, int E, int R, int NS, int DIR, bool FIRST, bool LAST, int NZ_IN,
+          int TWM, typename Hook>
 __device__ __forceinline__ void stockham_pass2(cx<T> (&v1)[E], cx<T> (&v2)[E],
                                                cx<T>* __restrict__ buf1, cx<T>* __restrict__ buf2,
-                                               const cx<T>* __restrict__ tw, int t) {
+                                               const PassTw<T, P, E, NS>& cur,
+                                               const cx<T>* __restrict__ tw, int t,
+                                               Hook&& before_barrier) {
   constexpr int TT = P / E;
   constexpr int NB = E / R;
   static_assert(E % R == 0, "radix must divide the per-thread element count");
+  static_assert(PassTw<T, P, E, NS>::R == R, "twiddle set of another radix");
   cx<T> a[NB][R], b[NB][R];
 #pragma unroll
   for (int q = 0; q < NB; ++q) {
@@ -278,11 +339,18 @@ __device__ __forceinline__ void stockham_pass2(cx<T> (&v1)[E], cx<T> (&v2)[E],
       }
     }
     if constexpr (NS > 1) {
-      const int k = j & (NS - 1);
-      const cx<T>* twp = tw + tw_offset(P, NS) + k;
+      const cx<T>* twp = tw + tw_offset(P, NS) + (j & (NS - 1));
+      cx<T> wb[R - 1];
+      if constexpr (TWM == TW_BATCH) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) wb[r - 1] = twp[(r - 1) * NS];
+        asm volatile("" ::: "memory");
+      }
 #pragma unroll
       for (int r = 1; r < R; ++r) {
-        const cx<T> w = twp[(r - 1) * NS];
+        const cx<T> w = TWM == TW_PREFETCH ? cur.w[q * (R - 1) + r - 1]
+                        : TWM == TW_BATCH  ? wb[r - 1]
+                                           : twp[(r - 1) * NS];
         a[q][r] = cmul_dir<DIR>(a[q][r], w);
         b[q][r] = cmul_dir<DIR>(b[q][r], w);
       }
@@ -304,6 +372,7 @@ __device__ __forceinline__ void stockham_pass2(cx<T> (&v1)[E], cx<T> (&v2)[E],
         v2[q + r * NB] = b[q][r];
       }
   } else {
+    before_barrier();
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
@@ -320,25 +389,44 @@ __device__ __forceinline__ void stockham_pass2(cx<T> (&v1)[E], cx<T> (&v2)[E],
   }
 }
 
-template <typename T, int P, int E, int DIR, int NS, int NZ_IN>
-__device__ __forceinline__ void fft2_passes(cx<T> (&v1)[E], cx<T> (&v2)[E], cx<T>* buf1,
-                                            cx<T>* buf2, const cx<T>* tw, int t) {
+// Pass drivers.  TWM selects how a pass gets its twiddles (TwiddleMode).
+template <typename T, int P, int E, int DIR, int NS, int NZ_IN, int TWM>
+__device__ __forceinline__ void fft_passes(cx<T> (&v)[E], cx<T>* buf, const cx<T>* tw, int t,
+                                           PassTw<T, P, E, NS>& cur) {
   constexpr int REM = P / NS;
   constexpr int R = (REM >= E) ? E : REM;
   constexpr bool FIRST = (NS == 1);
   constexpr bool LAST = (REM == R);
-  stockham_pass2<T, P, E, R, NS, DIR, FIRST, LAST, NZ_IN>(v1, v2, buf1, buf2, tw, t);
-  if constexpr (!LAST) fft2_passes<T, P, E, DIR, NS * R, NZ_IN>(v1, v2, buf1, buf2, tw, t);
+  if constexpr (LAST) {
+    stockham_pass<T, P, E, R, NS, DIR, FIRST, true, NZ_IN, TWM>(v, buf, cur, tw, t, [] {});
+  } else {
+    PassTw<T, P, E, NS * R> nxt;
+    stockham_pass<T, P, E, R, NS, DIR, FIRST, false, NZ_IN, TWM>(v, buf, cur, tw, t, [&] {
+      if constexpr (TWM == TW_PREFETCH) load_tw(nxt, tw, t);
+    });
+    fft_passes<T, P, E, DIR, NS * R, NZ_IN, TWM>(v, buf, tw, t, nxt);
+  }
 }
 
-template <typename T, int P, int E, int DIR, int NS, int NZ_IN>
-__device__ __forceinline__ void fft_passes(cx<T> (&v)[E], cx<T>* buf, const cx<T>* tw, int t) {
+template <typename T, int P, int E, int DIR, int NS, int NZ_IN, int TWM>
+__device__ __forceinline__ void fft2_passes(cx<T> (&v1)[E], cx<T> (&v2)[E], cx<T>* buf1,
+                                            cx<T>* buf2, const cx<T>* tw, int t,
+                                            PassTw<T, P, E, NS>& cur) {
   constexpr int REM = P / NS;
   constexpr int R = (REM >= E) ? E : REM;
   constexpr bool FIRST = (NS == 1);
   constexpr bool LAST = (REM == R);
-  stockham_pass<T, P, E, R, NS, DIR, FIRST, LAST, NZ_IN>(v, buf, tw, t);
-  if constexpr (!LAST) fft_passes<T, P, E, DIR, NS * R, NZ_IN>(v, buf, tw, t);
+  if constexpr (LAST) {
+    stockham_pass2<T, P, E, R, NS, DIR, FIRST, true, NZ_IN, TWM>(v1, v2, buf1, buf2, cur, tw, t,
+                                                                [] {});
+  } else {
+    PassTw<T, P, E, NS * R> nxt;
+    stockham_pass2<T, P, E, R, NS, DIR, FIRST, false, NZ_IN, TWM>(v1, v2, buf1, buf2, cur, tw, t,
+                                                                 [&] {
+      if constexpr (TWM == TW_PREFETCH) load_tw(nxt, tw, t);
+    });
+    fft2_passes<T, P, E, DIR, NS * R, NZ_IN, TWM>(v1, v2, buf1, buf2, tw, t, nxt);
+  }
 }
 
 // In-register P-point DFT (DIR = -1) or unscaled inverse (DIR = +1) of the
@@ -346,21 +434,23 @@ __device__ __forceinline__ void fft_passes(cx<T> (&v)[E], cx<T>* buf, const cx<T
 // lds_stride(P) elements).  v[s] for s >= NZ_IN must be zero on entry.
 // Must be reached by every thread of the workgroup (it contains workgroup
 // barriers).
-template <typename T, int P, int E, int DIR, int NZ_IN = E>
+template <typename T, int P, int E, int DIR, int NZ_IN = E, int TWM = TW_PREFETCH>
 __device__ __forceinline__ void fft(cx<T> (&v)[E], cx<T>* buf, const cx<T>* tw, int t) {
   static_assert((P & (P - 1)) == 0 && P >= E && P <= PMAX, "P must be a power of two in [E, PMAX]");
   static_assert(E == FFT_E, "twiddle tables are laid out for FFT_E elements per thread");
-  fft_passes<T, P, E, DIR, 1, NZ_IN>(v, buf, tw, t);
+  PassTw<T, P, E, 1> none;
+  fft_passes<T, P, E, DIR, 1, NZ_IN, TWM>(v, buf, tw, t, none);
 }
 
 // Two independent transforms of the same size and direction at once (their
 // passes share barriers and twiddle loads); buf1 and buf2 must not overlap.
-template <typename T, int P, int E, int DIR, int NZ_IN = E>
+template <typename T, int P, int E, int DIR, int NZ_IN = E, int TWM = TW_PREFETCH>
 __device__ __forceinline__ void fft2(cx<T> (&v1)[E], cx<T> (&v2)[E], cx<T>* buf1, cx<T>* buf2,
                                      const cx<T>* tw, int t) {
   static_assert((P & (P - 1)) == 0 && P >= E && P <= PMAX, "P must be a power of two in [E, PMAX]");
   static_assert(E == FFT_E, "twiddle tables are laid out for FFT_E elements per thread");
-  fft2_passes<T, P, E, DIR, 1, NZ_IN>(v1, v2, buf1, buf2, tw, t);
+  PassTw<T, P, E, 1> none;
+  fft2_passes<T, P, E, DIR, 1, NZ_IN, TWM>(v1, v2, buf1, buf2, tw, t, none);
 }
 
 }  // namespace fbst

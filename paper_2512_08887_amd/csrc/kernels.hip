@@ -27,6 +27,16 @@
 #ifndef FBST_K3_WAVES
 #define FBST_K3_WAVES 2           // minimum waves per SIMD the register allocation must allow
 #endif
+// Twiddle modes of the transforms (TwiddleMode in fft_lds.h), per kernel.
+#ifndef FBST_K12_TW
+#define FBST_K12_TW 1             // stages 1a and 1b: prefetched across barriers
+#endif
+#ifndef FBST_K3_TW
+#define FBST_K3_TW 1              // stage 2, single transforms
+#endif
+#ifndef FBST_K3_TW_DUAL
+#define FBST_K3_TW_DUAL 0         // stage 2, dual transforms
+#endif
 #ifndef FBST_K12_WAVES
 #define FBST_K12_WAVES 0
 #endif
@@ -74,6 +84,48 @@ __device__ __forceinline__ int xcd_linear(int nwg) {
 template <typename T>
 __device__ __forceinline__ cx<T> ldg(const cx<T>* p) { return *p; }
 
+#ifndef FBST_BATCH
+#define FBST_BATCH 1              // issue each group of independent table/data loads together
+#endif
+
+// Loads above this point are issued before anything below it (an empty asm
+// statement with a memory clobber).  The register-pressure-driven scheduler
+// otherwise places each table load right before its use, one L2 round trip
+// after another; batched, their latencies overlap.
+template <bool ON = FBST_BATCH>
+__device__ __forceinline__ void issue_fence() {
+  if constexpr (ON) asm volatile("" ::: "memory");
+}
+
+#ifndef FBST_K3_GB
+#define FBST_K3_GB 16             // stage-2 spectrum loads issued this many at a time (0: as used)
+#endif
+
+// use(s, a[s], b[s]) for s < N, where a[s] = A[s * TT] and b[s] = B[s * TT]
+// (B may be null: then b[s] is unused), loading GB slots at a time.
+template <int GB, int N, int TT, typename T, typename Use>
+__device__ __forceinline__ void with_tables(const cx<T>* __restrict__ A, const cx<T>* __restrict__ B,
+                                            Use&& use) {
+  if constexpr (GB <= 0) {
+#pragma unroll
+    for (int s = 0; s < N; ++s) use(s, ldg(A + s * TT), B ? ldg(B + s * TT) : cx<T>{0, 0});
+  } else {
+    static_assert(N % GB == 0, "group size must divide the slot count");
+#pragma unroll
+    for (int s0 = 0; s0 < N; s0 += GB) {
+      cx<T> a[GB], b[GB];
+#pragma unroll
+      for (int i = 0; i < GB; ++i) {
+        a[i] = ldg(A + (s0 + i) * TT);
+        if (B) b[i] = ldg(B + (s0 + i) * TT);
+      }
+      issue_fence<true>();
+#pragma unroll
+      for (int i = 0; i < GB; ++i) use(s0 + i, a[i], b[i]);
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // K1: Yhat[row][i] = post[i] * IFFT(FFT(x[row][n] * pre[n]) * H)[i],  i < L.
 // rows are (block, sensor) pairs; lane = g * TT + t (a transform owns a
@@ -94,22 +146,48 @@ __global__ __launch_bounds__(Shape<P>::THREADS) FBST_K12_ATTR void k_time_czt(
   cx<T>* buf = lds + g * SH::S;
 
   cx<T> v[kE];
-  const int blk = active ? row / M : 0;
-  const cx<T>* src = static_cast<const cx<T>*>(xs.p[blk]) + static_cast<size_t>(row - blk * M) * N;
+  const int rr = active ? row : 0;                    // inactive lanes read row 0, store nothing
+  const int blk = rr / M;
+  const cx<T>* src = static_cast<const cx<T>*>(xs.p[blk]) + static_cast<size_t>(rr - blk * M) * N;
+  // Loads at clamped indices and a select afterwards (no branch per load, so
+  // the loads are issued together rather than one round trip each).
+  {
+    cx<T> xa[SI], pa[SI];
 #pragma unroll
-  for (int s = 0; s < kE; ++s) {
-    const int n = t + s * SH::TT;
-    v[s] = (s < SI && active && n < N) ? cmul(ldg(src + n), ldg(pre + n)) : cx<T>{0, 0};
+    for (int s = 0; s < SI; ++s) {
+      const int n = t + s * SH::TT;
+      const int nc = n < N ? n : N - 1;
+      xa[s] = ldg(src + nc);
+      pa[s] = ldg(pre + nc);
+    }
+    issue_fence();
+#pragma unroll
+    for (int s = 0; s < SI; ++s) v[s] = (t + s * SH::TT < N) ? cmul(xa[s], pa[s]) : cx<T>{0, 0};
   }
-  fft<T, P, kE, -1, SI>(v, buf, tw, t);
 #pragma unroll
-  for (int s = 0; s < kE; ++s) v[s] = cmul(v[s], ldg(H + t + s * SH::TT));
-  fft<T, P, kE, +1>(v, buf, tw, t);
+  for (int s = SI; s < kE; ++s) v[s] = cx<T>{0, 0};
+  fft<T, P, kE, -1, SI, FBST_K12_TW>(v, buf, tw, t);
+  {
+    cx<T> h[kE];
+#pragma unroll
+    for (int s = 0; s < kE; ++s) h[s] = ldg(H + t + s * SH::TT);
+    issue_fence();
+#pragma unroll
+    for (int s = 0; s < kE; ++s) v[s] = cmul(v[s], h[s]);
+  }
+  fft<T, P, kE, +1, kE, FBST_K12_TW>(v, buf, tw, t);
   cx<T>* dst = yhat + static_cast<size_t>(row) * L;
+  cx<T> po[SO];
 #pragma unroll
   for (int s = 0; s < SO; ++s) {
     const int i = t + s * SH::TT;
-    if (active && i < L) dst[i] = cmul(v[s], ldg(post + i));
+    po[s] = ldg(post + (i < L ? i : L - 1));
+  }
+  issue_fence();
+#pragma unroll
+  for (int s = 0; s < SO; ++s) {
+    const int i = t + s * SH::TT;
+    if (active && i < L) dst[i] = cmul(v[s], po[s]);
   }
 }
 
@@ -142,28 +220,48 @@ __global__ __launch_bounds__(ShapeK2<P>::THREADS) FBST_K12_ATTR void k_axis_czt(
   const bool active = l < L;
   cx<T>* buf = lds + g * SH::S;
 
+  const int lc = active ? l : L - 1;                  // inactive lanes read a valid l, store nothing
   const size_t stride = static_cast<size_t>(post_n) * L;
-  const cx<T>* src = in + ((static_cast<size_t>(blk) * pre_n + p) * a_in * post_n + q) * L + l;
+  const cx<T>* src = in + ((static_cast<size_t>(blk) * pre_n + p) * a_in * post_n + q) * L + lc;
   cx<T> v[kE];
+  {
+    cx<T> xa[SI], pa[SI];
 #pragma unroll
-  for (int s = 0; s < kE; ++s) {
-    const int i = t + s * SH::TT;
-    v[s] = (s < SI && active && i < a_in)
-               ? cmul(ldg(src + i * stride), ldg(pre + static_cast<size_t>(i) * L + l))
-               : cx<T>{0, 0};
-  }
-  fft<T, P, kE, -1, SI>(v, buf, tw, t);
+    for (int s = 0; s < SI; ++s) {
+      const int i = t + s * SH::TT;
+      const int ic = i < a_in ? i : a_in - 1;
+      xa[s] = ldg(src + ic * stride);
+      pa[s] = ldg(pre + static_cast<size_t>(ic) * L + lc);
+    }
+    issue_fence();
 #pragma unroll
-  for (int s = 0; s < kE; ++s) {
-    const int i = t + s * SH::TT;
-    v[s] = active ? cmul(v[s], ldg(H + static_cast<size_t>(i) * L + l)) : cx<T>{0, 0};
+    for (int s = 0; s < SI; ++s)
+      v[s] = (active && t + s * SH::TT < a_in) ? cmul(xa[s], pa[s]) : cx<T>{0, 0};
   }
-  fft<T, P, kE, +1>(v, buf, tw, t);
+#pragma unroll
+  for (int s = SI; s < kE; ++s) v[s] = cx<T>{0, 0};
+  fft<T, P, kE, -1, SI, FBST_K12_TW>(v, buf, tw, t);
+  {
+    cx<T> h[kE];
+#pragma unroll
+    for (int s = 0; s < kE; ++s) h[s] = ldg(H + static_cast<size_t>(t + s * SH::TT) * L + lc);
+    issue_fence();
+#pragma unroll
+    for (int s = 0; s < kE; ++s) v[s] = cmul(v[s], h[s]);
+  }
+  fft<T, P, kE, +1, kE, FBST_K12_TW>(v, buf, tw, t);
   cx<T>* dst = out + ((static_cast<size_t>(blk) * pre_n + p) * a_out * post_n + q) * L + l;
+  cx<T> po[SO];
 #pragma unroll
   for (int s = 0; s < SO; ++s) {
     const int a = t + s * SH::TT;
-    if (active && a < a_out) dst[a * stride] = cmul(v[s], ldg(post + static_cast<size_t>(a) * L + l));
+    po[s] = ldg(post + static_cast<size_t>(a < a_out ? a : a_out - 1) * L + lc);
+  }
+  issue_fence();
+#pragma unroll
+  for (int s = 0; s < SO; ++s) {
+    const int a = t + s * SH::TT;
+    if (active && a < a_out) dst[a * stride] = cmul(v[s], po[s]);
   }
 }
 
@@ -212,61 +310,60 @@ __global__ __launch_bounds__(Shape<P>::THREADS) FBST_K3_ATTR void k_toeplitz_fu(
   const cx<T>* g2 = G2 + static_cast<size_t>(b) * P;
 
   cx<T> u1[kE], u2[kE];
-  const cx<TIN>* src = w + row * L;
+  const cx<TIN>* src = w + row * L;                   // row of block 0, beam 0 when inactive
 #pragma unroll
   for (int s = 0; s < kE; ++s) {
     const int i = t + s * SH::TT;
     u1[s] = (s < SL && active && i < L) ? cvt<T>(src[i]) : cx<T>{0, 0};
   }
-  fft<T, P, kE, -1, SL>(u1, buf, tw, t);
-#pragma unroll
-  for (int s = 0; s < kE; ++s) {
+  fft<T, P, kE, -1, SL, FBST_K3_TW>(u1, buf, tw, t);
+  with_tables<FBST_K3_GB, kE, SH::TT>(g1 + t, g2 + t, [&](int s, cx<T> a, cx<T> c) {
     const cx<T> V = u1[s];
-    u1[s] = cmulc(V, ldg(g1 + t + s * SH::TT));
-    u2[s] = cmulc(V, ldg(g2 + t + s * SH::TT));
-  }
+    u1[s] = cmulc(V, a);
+    u2[s] = cmulc(V, c);
+  });
   if constexpr (DUAL) {
     // both branches: u_k <- FFT(trunc_L(IFFT(u_k)))
-    fft2<T, P, kE, +1>(u1, u2, buf, buf + SH::S, tw, t);
+    fft2<T, P, kE, +1, kE, FBST_K3_TW_DUAL>(u1, u2, buf, buf + SH::S, tw, t);
 #pragma unroll
     for (int s = 0; s < kE; ++s)
       if (s >= SL || t + s * SH::TT >= L) {
         u1[s] = cx<T>{0, 0};
         u2[s] = cx<T>{0, 0};
       }
-    fft2<T, P, kE, -1, SL>(u1, u2, buf, buf + SH::S, tw, t);
-#pragma unroll
-    for (int s = 0; s < kE; ++s)
-      u1[s] = cmul(u1[s], ldg(g1 + t + s * SH::TT)) - cmul(u2[s], ldg(g2 + t + s * SH::TT));
+    fft2<T, P, kE, -1, SL, FBST_K3_TW_DUAL>(u1, u2, buf, buf + SH::S, tw, t);
+    with_tables<FBST_K3_GB, kE, SH::TT>(g1 + t, g2 + t, [&](int s, cx<T> a, cx<T> c) {
+      u1[s] = cmul(u1[s], a) - cmul(u2[s], c);
+    });
   } else {
     // branch 1: u1 <- G1 * FFT(trunc_L(IFFT(u1)))
-    fft<T, P, kE, +1>(u1, buf, tw, t);
+    fft<T, P, kE, +1, kE, FBST_K3_TW>(u1, buf, tw, t);
 #pragma unroll
     for (int s = 0; s < kE; ++s)
       if (s >= SL || t + s * SH::TT >= L) u1[s] = cx<T>{0, 0};
-    fft<T, P, kE, -1, SL>(u1, buf, tw, t);
+    fft<T, P, kE, -1, SL, FBST_K3_TW>(u1, buf, tw, t);
 #pragma unroll
     for (int s = 0; s < kE; ++s) u1[s] = cmul(u1[s], ldg(g1 + t + s * SH::TT));
     // branch 2: u1 -= G2 * FFT(trunc_L(IFFT(u2)))
-    fft<T, P, kE, +1>(u2, buf, tw, t);
+    fft<T, P, kE, +1, kE, FBST_K3_TW>(u2, buf, tw, t);
 #pragma unroll
     for (int s = 0; s < kE; ++s)
       if (s >= SL || t + s * SH::TT >= L) u2[s] = cx<T>{0, 0};
-    fft<T, P, kE, -1, SL>(u2, buf, tw, t);
+    fft<T, P, kE, -1, SL, FBST_K3_TW>(u2, buf, tw, t);
 #pragma unroll
     for (int s = 0; s < kE; ++s) u1[s] = u1[s] - cmul(u2[s], ldg(g2 + t + s * SH::TT));
   }
   // beta = trunc_L(IFFT(Z)), then the F_u chirp-z
-  fft<T, P, kE, +1>(u1, buf, tw, t);
+  fft<T, P, kE, +1, kE, FBST_K3_TW>(u1, buf, tw, t);
 #pragma unroll
   for (int s = 0; s < kE; ++s) {
     const int i = t + s * SH::TT;
     u1[s] = (s < SL && i < L) ? cmul(u1[s], ldg(pre3 + i)) : cx<T>{0, 0};
   }
-  fft<T, P, kE, -1, SL>(u1, buf, tw, t);
-#pragma unroll
-  for (int s = 0; s < kE; ++s) u1[s] = cmul(u1[s], ldg(H3 + t + s * SH::TT));
-  fft<T, P, kE, +1>(u1, buf, tw, t);
+  fft<T, P, kE, -1, SL, FBST_K3_TW>(u1, buf, tw, t);
+  with_tables<FBST_K3_GB, kE, SH::TT>(H3 + t, static_cast<const cx<T>*>(nullptr),
+                                      [&](int s, cx<T> a, cx<T>) { u1[s] = cmul(u1[s], a); });
+  fft<T, P, kE, +1, kE, FBST_K3_TW>(u1, buf, tw, t);
   cx<TOUT>* dst = static_cast<cx<TOUT>*>(outs.p[blk]) + static_cast<size_t>(b) * N;
 #pragma unroll
   for (int s = 0; s < SN; ++s) {

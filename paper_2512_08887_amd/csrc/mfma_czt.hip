@@ -150,7 +150,9 @@ __device__ __forceinline__ void mfma_passes(c32* buf, const c32* tw, const DftA<
   } else {
     // remainder radix (P = 16^a * REM): one float32 Stockham pass through LDS
     c32 unused[FFT_E];
-    stockham_pass<float, P, FFT_E, REM, NS, DIR, false, false, FFT_E>(unused, buf, tw, t);
+    PassTw<float, P, FFT_E, NS> none;
+    stockham_pass<float, P, FFT_E, REM, NS, DIR, false, false, FFT_E, TW_LAZY>(unused, buf, none, tw,
+                                                                            t, [] {});
   }
 }
 
@@ -174,7 +176,9 @@ __global__ __launch_bounds__(P / FFT_E) void k_time_czt_mfma(
 #pragma unroll
   for (int s = 0; s < FFT_E; ++s) {
     const int n = t + s * TT;
-    buf[lds_pad(n)] = (n < N) ? cmul(src[n], pre[n]) : c32{0.f, 0.f};
+    const int nc = n < N ? n : N - 1;                 // clamped load, select after
+    const c32 x = cmul(src[nc], pre[nc]);
+    buf[lds_pad(n)] = (n < N) ? x : c32{0.f, 0.f};
   }
   __syncthreads();
   mfma_passes<P, 1, -1>(buf, tw, Af, wave, lane, t);
@@ -189,7 +193,8 @@ __global__ __launch_bounds__(P / FFT_E) void k_time_czt_mfma(
 #pragma unroll
   for (int s = 0; s < FFT_E; ++s) {
     const int i = t + s * TT;
-    if (i < L) dst[i] = cmul(buf[lds_pad(i)], post[i]);
+    const c32 o = cmul(buf[lds_pad(i)], post[i < L ? i : L - 1]);
+    if (i < L) dst[i] = o;
   }
 }
 
