@@ -40,7 +40,10 @@ def stage_flops(info):
     """Algorithmic flops per block and per stage (5 P log2 P per FFT, 6 per
     complex product, 2 per complex add)."""
     M, N, B, L = info.M, info.N, info.B, info.L
-    s0 = M * (2 * fft_flops(info.p1) + 6 * (N + info.p1 + L))
+    if info.p1_split:   # one forward and two inverse transforms of p1_split points
+        s0 = M * (3 * fft_flops(info.p1_split) + 6 * (N + 2 * info.p1_split + L))
+    else:
+        s0 = M * (2 * fft_flops(info.p1) + 6 * (N + info.p1 + L))
     if info.bv > 1:
         s1 = (info.my * L * (2 * fft_flops(info.p2x) + 6 * (info.mx + info.p2x + info.bu))
               + info.bu * L * (2 * fft_flops(info.p2y) + 6 * (info.my + info.p2y + info.bv)))

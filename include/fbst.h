@@ -102,6 +102,9 @@ typedef struct {
 #define FBST_FLAG_HOST_ONLY 1u        /* build the FP64 host tables only; no device memory,
                                          execute calls fail (introspection and CPU tests) */
 #define FBST_FLAG_KEEP_HOST_TABLES 2u /* keep FP64 host copies for fbst_plan_table()      */
+#define FBST_FLAG_NO_SPLIT 4u         /* stage 1a as one convolution of p1 points, even
+                                         where two half-length output convolutions of
+                                         p1_split points would be cheaper             */
 
 /* Basis and solver options.  eps: band expansion epsilon > 0 (0 selects 1.01).
  * L: number of basis frequencies, even and >= 2 (0 selects 2N, i.e.
@@ -129,6 +132,9 @@ typedef struct {
   size_t io_elem_bytes;      /* 8 (complex64) or 16 (complex128)                */
   size_t device_bytes;       /* device tables owned by the plan                  */
   size_t workspace_per_block;/* bytes of workspace one block needs               */
+  int p1_split;      /* 0, or the FFT size of stage 1a in split-output form: the
+                        L outputs as two halves, each a convolution of
+                        p1_split >= N + L/2 - 1 points sharing one forward FFT */
 } fbst_info;
 
 typedef struct fbst_plan fbst_plan;

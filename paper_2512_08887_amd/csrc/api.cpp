@@ -101,6 +101,7 @@ fbst_status upload(fbst_plan* pl) {
   const size_t o_tw1 = up.add(tw, d1);
   const size_t o_tw2 = (d1 == d2) ? o_tw1 : up.add(tw, d2);
   const size_t o_pre1 = up.add(h.pre1, d1), o_H1 = up.add(h.H1, d1), o_post1 = up.add(h.post1, d1);
+  const size_t o_H1a = up.add(h.H1a, d1), o_H1b = up.add(h.H1b, d1);
   const size_t o_axp = up.add(h.ax.pre, d1), o_axH = up.add(h.ax.H, d1), o_axq = up.add(h.ax.post, d1);
   size_t o_ayp = 0, o_ayH = 0, o_ayq = 0;
   if (p.kind == FBST_GRID) {
@@ -134,6 +135,10 @@ fbst_status upload(fbst_plan* pl) {
   pl->pre1 = b + o_pre1;
   pl->H1 = b + o_H1;
   pl->post1 = b + o_post1;
+  if (p.p1s) {
+    pl->H1a = b + o_H1a;
+    pl->H1b = b + o_H1b;
+  }
   pl->axp = b + o_axp;
   pl->axH = b + o_axH;
   pl->axq = b + o_axq;
@@ -160,6 +165,9 @@ hipError_t run_stage0(const fbst_plan* pl, int nb, const fbst::InPtrs& xs, void*
   if (p.prec == FBST_PREC_BF16_SPLIT || p.prec == FBST_PREC_FP16_SPLIT)
     return fbst::launch_time_czt_mfma(p.p1, p.prec == FBST_PREC_FP16_SPLIT, xs, nb, yhat, pl->pre1,
                                       pl->H1, pl->post1, pl->tw1, p.M, p.N, p.L, st);
+  if (p.p1s)
+    return fbst::launch_time_czt_split<T1>(p.p1s, xs, nb, yhat, pl->pre1, pl->H1a, pl->H1b,
+                                           pl->post1, pl->tw1, p.M, p.N, p.L, p.ls1, st);
   return fbst::launch_time_czt<T1>(p.p1, xs, nb, yhat, pl->pre1, pl->H1, pl->post1, pl->tw1, p.M,
                                    p.N, p.L, st);
 }
@@ -508,6 +516,7 @@ fbst_status fbst_plan_info(const fbst_plan* plan, fbst_info* info) {
   info->io_elem_bytes = (p.prec == FBST_PREC_FP64) ? 16 : 8;
   info->device_bytes = plan->dev_bytes;
   info->workspace_per_block = plan->ws_bytes_per_block;
+  info->p1_split = p.p1s;
   return FBST_OK;
 }
 

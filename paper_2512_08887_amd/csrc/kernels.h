@@ -26,6 +26,14 @@ hipError_t launch_time_czt(int P, const InPtrs& xs, int nblocks, void* yhat, con
                            const void* H, const void* post, const void* tw, int M, int N, int L,
                            hipStream_t st);
 
+// Stage 1a in split-output form: outputs [0, Ls) and [Ls, L) from two
+// P-point convolutions sharing one forward FFT (P >= N + Ls - 1, L - Ls <= Ls);
+// Ha, Hb are the kernel spectra of the two halves.
+template <typename T>
+hipError_t launch_time_czt_split(int P, const InPtrs& xs, int nblocks, void* yhat, const void* pre,
+                                 const void* Ha, const void* Hb, const void* post, const void* tw,
+                                 int M, int N, int L, int Ls, hipStream_t st);
+
 // Stage 1a on the matrix cores (bfloat16, or float16 when fp16), split
 // precision with float32 accumulation; complex64 in and out; P in
 // {1024, 2048, 4096, 8192, 16384}.

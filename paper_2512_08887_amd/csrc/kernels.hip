@@ -192,6 +192,103 @@ __global__ __launch_bounds__(Shape<P>::THREADS) FBST_K12_ATTR void k_time_czt(
 }
 
 // ---------------------------------------------------------------------------
+// K1, split-output form.  The L outputs are two halves of Ls = L/2 each; half
+// h needs the chirp kernel only over [-(N-1), Ls-1] shifted by h Ls, so both
+// halves are circular convolutions of P >= N + Ls - 1 points (P1 / 2 when
+// L = 2N) that share the forward transform of the premultiplied input:
+//   X = FFT(x pre);  Yhat[h Ls + i] = post[h Ls + i] IFFT(X Hh)[i],  h = 0, 1,
+// three P-point transforms instead of two of 2P (the two inverses run as one
+// dual transform).  SI >= ceil(N / TT), SO >= ceil(Ls / TT).
+// ---------------------------------------------------------------------------
+#ifndef FBST_K1S_DUAL
+#define FBST_K1S_DUAL 1           // run the two inverse transforms as one dual transform
+#endif
+constexpr int kK1sBufs = FBST_K1S_DUAL ? 2 : 1;
+#ifndef FBST_K1S_WAVES
+#define FBST_K1S_WAVES 0          // minimum waves per SIMD for the split stage 1a (0: compiler's choice)
+#endif
+#if FBST_K1S_WAVES > 0
+#define FBST_K1S_ATTR __attribute__((amdgpu_waves_per_eu(FBST_K1S_WAVES)))
+#else
+#define FBST_K1S_ATTR
+#endif
+
+template <typename T, int P>
+constexpr bool k1s_fits() {
+  return sizeof(T) * 2 * lds_stride(P) * kK1sBufs * Shape<P>::G <= 160 * 1024;
+}
+
+template <typename T, int P, int SI, int SO>
+__global__ __launch_bounds__(Shape<P>::THREADS) FBST_K1S_ATTR void k_time_czt_split(
+    const InPtrs xs, cx<T>* __restrict__ yhat, const cx<T>* __restrict__ pre,
+    const cx<T>* __restrict__ Ha, const cx<T>* __restrict__ Hb, const cx<T>* __restrict__ post,
+    const cx<T>* __restrict__ tw, int M, int N, int L, int Ls, int rows) {
+  using SH = Shape<P>;
+  __shared__ cx<T> lds[SH::G * kK1sBufs * SH::S];
+  const int g = threadIdx.x / SH::TT;
+  const int t = threadIdx.x % SH::TT;
+  const int row = blockIdx.x * SH::G + g;
+  const bool active = row < rows;
+  cx<T>* buf = lds + g * kK1sBufs * SH::S;
+
+  cx<T> v[kE], u[kE];
+  const int rr = active ? row : 0;                    // inactive lanes read row 0, store nothing
+  const int blk = rr / M;
+  const cx<T>* src = static_cast<const cx<T>*>(xs.p[blk]) + static_cast<size_t>(rr - blk * M) * N;
+  {
+    cx<T> xa[SI], pa[SI];
+#pragma unroll
+    for (int s = 0; s < SI; ++s) {
+      const int n = t + s * SH::TT;
+      const int nc = n < N ? n : N - 1;
+      xa[s] = ldg(src + nc);
+      pa[s] = ldg(pre + nc);
+    }
+    issue_fence();
+#pragma unroll
+    for (int s = 0; s < SI; ++s) v[s] = (t + s * SH::TT < N) ? cmul(xa[s], pa[s]) : cx<T>{0, 0};
+  }
+#pragma unroll
+  for (int s = SI; s < kE; ++s) v[s] = cx<T>{0, 0};
+  fft<T, P, kE, -1, SI, FBST_K12_TW>(v, buf, tw, t);
+  {
+    cx<T> ha[kE], hb[kE];
+#pragma unroll
+    for (int s = 0; s < kE; ++s) {
+      ha[s] = ldg(Ha + t + s * SH::TT);
+      hb[s] = ldg(Hb + t + s * SH::TT);
+    }
+    issue_fence();
+#pragma unroll
+    for (int s = 0; s < kE; ++s) {
+      u[s] = cmul(v[s], hb[s]);
+      v[s] = cmul(v[s], ha[s]);
+    }
+  }
+  if constexpr (FBST_K1S_DUAL) {
+    fft2<T, P, kE, +1, kE, FBST_K12_TW>(v, u, buf, buf + SH::S, tw, t);
+  } else {
+    fft<T, P, kE, +1, kE, FBST_K12_TW>(v, buf, tw, t);
+    fft<T, P, kE, +1, kE, FBST_K12_TW>(u, buf, tw, t);
+  }
+  cx<T>* dst = yhat + static_cast<size_t>(row) * L;
+  cx<T> pa[SO], pb[SO];
+#pragma unroll
+  for (int s = 0; s < SO; ++s) {
+    const int i = t + s * SH::TT;
+    pa[s] = ldg(post + (i < Ls ? i : Ls - 1));
+    pb[s] = ldg(post + (i < L - Ls ? Ls + i : L - 1));
+  }
+  issue_fence();
+#pragma unroll
+  for (int s = 0; s < SO; ++s) {
+    const int i = t + s * SH::TT;
+    if (active && i < Ls) dst[i] = cmul(v[s], pa[s]);
+    if (active && i < L - Ls) dst[Ls + i] = cmul(u[s], pb[s]);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // K2: one axis of the space chirp-z.  Data layout [blk][pre_n][A][post_n][L]
 // (A = a_in on input, a_out on output); a workgroup takes G consecutive l for
 // one (blk, p, q) and lane = t * G + g, so lanes with the same t read G
@@ -431,6 +528,39 @@ hipError_t launch_time_czt(int P, const InPtrs& xs, int nblocks, void* yhat, con
 }
 
 template <typename T>
+hipError_t launch_time_czt_split(int P, const InPtrs& xs, int nblocks, void* yhat, const void* pre,
+                                 const void* Ha, const void* Hb, const void* post, const void* tw,
+                                 int M, int N, int L, int Ls, hipStream_t st) {
+  if (nblocks < 1 || nblocks > MAX_LAUNCH_BLOCKS) return hipErrorInvalidValue;
+  if (Ls < 1 || Ls > L || L - Ls > Ls || N + Ls - 1 > P) return hipErrorInvalidValue;
+  const int rows = nblocks * M;
+  switch (P) {
+#define CASE(PP)                                                                               \
+  case PP:                                                                                     \
+    if constexpr (k1s_fits<T, PP>()) {                                                         \
+      const int si = slots_for<PP>(N), so = slots_for<PP>(Ls);                                 \
+      const dim3 grid(grid_for<PP>(rows)), block(Shape<PP>::THREADS);                          \
+      const auto o = (cx<T>*)yhat;                                                             \
+      const auto a1 = (const cx<T>*)pre, a2 = (const cx<T>*)Ha, a3 = (const cx<T>*)Hb;        \
+      const auto a4 = (const cx<T>*)post, a5 = (const cx<T>*)tw;                               \
+      if (si <= kE / 2 && so <= kE / 2)                                                        \
+        hipLaunchKernelGGL((k_time_czt_split<T, PP, kE / 2, kE / 2>), grid, block, 0, st, xs,  \
+                           o, a1, a2, a3, a4, a5, M, N, L, Ls, rows);                          \
+      else                                                                                     \
+        hipLaunchKernelGGL((k_time_czt_split<T, PP, kE, kE>), grid, block, 0, st, xs, o, a1,   \
+                           a2, a3, a4, a5, M, N, L, Ls, rows);                                 \
+      return hipGetLastError();                                                                \
+    }                                                                                          \
+    break;
+    FBST_FOR_EACH_P(CASE)
+#undef CASE
+    default:
+      break;
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
 hipError_t launch_axis_czt(int P, const void* in, void* out, const void* pre, const void* H,
                            const void* post, const void* tw, int a_in, int a_out, int pre_n,
                            int post_n, int L, int nblocks, hipStream_t st) {
@@ -508,6 +638,12 @@ template hipError_t launch_time_czt<float>(int, const InPtrs&, int, void*, const
                                            const void*, const void*, int, int, int, hipStream_t);
 template hipError_t launch_time_czt<double>(int, const InPtrs&, int, void*, const void*, const void*,
                                            const void*, const void*, int, int, int, hipStream_t);
+template hipError_t launch_time_czt_split<float>(int, const InPtrs&, int, void*, const void*,
+                                                 const void*, const void*, const void*,
+                                                 const void*, int, int, int, int, hipStream_t);
+template hipError_t launch_time_czt_split<double>(int, const InPtrs&, int, void*, const void*,
+                                                  const void*, const void*, const void*,
+                                                  const void*, int, int, int, int, hipStream_t);
 template hipError_t launch_axis_czt<float>(int, const void*, void*, const void*, const void*,
                                            const void*, const void*, int, int, int, int, int, int,
                                            hipStream_t);

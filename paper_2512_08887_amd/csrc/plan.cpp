@@ -392,6 +392,19 @@ fbst_status resolve_params(int M, int N, int B, const fbst_geometry* geom, const
     *msg = "the matrix-core stage 1a needs a time FFT of at least 1024 points (N + L - 1 > 512)";
     return FBST_E_UNSUPPORTED;
   }
+  // Stage 1a in split-output form when it is smaller: the two output halves
+  // need the chirp kernel over N + L/2 - 1 taps each, so two convolutions of
+  // p1s points sharing one forward FFT replace one of p1 points (3 p1s
+  // against 2 p1 transform points; p1s = p1 / 2 whenever L = 2N).
+  if (!(p.flags & FBST_FLAG_NO_SPLIT) && p.prec != FBST_PREC_BF16_SPLIT &&
+      p.prec != FBST_PREC_FP16_SPLIT) {
+    const int ls = p.L / 2;
+    const int ps = std::max(next_pow2(static_cast<long long>(p.N) + ls - 1), 32);
+    if (2 * ps < 2 * p.p1 - ps) {       // 3 ps < 2 p1
+      p.p1s = ps;
+      p.ls1 = ls;
+    }
+  }
   const int lim1 = (p.prec == FBST_PREC_FP64) ? 8192 : PMAX;
   const int lim2 = (p.prec == FBST_PREC_FP32) ? PMAX : 8192;
   if (p.p1 > lim1 || p.p2x > lim1 || p.p2y > lim1 || p.p3 > lim2) {
@@ -413,7 +426,15 @@ fbst_status build_tables(const Params& p, bool keep_gram_gen, HostTables* t, std
   t->pre1.resize(N);
   for (int n = 0; n < N; ++n) t->pre1[n] = cispi(-c_pi * static_cast<double>(1LL * n * n));
   // h1[s] = exp(+j (kappa/2) (s + lp0)^2) for s in [-(N-1), L-1]
-  t->H1 = kernel_spectrum_int(p.p1, -(N - 1), L - 1, static_cast<long long>(lp0), c_pi);
+  if (p.p1s) {
+    // output half h covers i = h ls1 + i', i' < len_h: kernel h1[s + h ls1], s in [-(N-1), len_h - 1]
+    const long long ls = p.ls1;
+    t->H1a = kernel_spectrum_int(p.p1s, -(N - 1), ls - 1, static_cast<long long>(lp0), c_pi);
+    t->H1b = kernel_spectrum_int(p.p1s, -(N - 1), (L - ls) - 1, static_cast<long long>(lp0) + ls,
+                                 c_pi);
+  } else {
+    t->H1 = kernel_spectrum_int(p.p1, -(N - 1), L - 1, static_cast<long long>(lp0), c_pi);
+  }
   t->post1.resize(L);
   for (int i = 0; i < L; ++i) {
     const long long q = static_cast<long long>(i + lp0);

@@ -24,6 +24,7 @@ struct AxisTables {
 
 struct HostTables {
   std::vector<zd> pre1, H1, post1;        // stage 1a: [N], [P1], [L]
+  std::vector<zd> H1a, H1b;               // split-output stage 1a: [P1s] per output half
   AxisTables ax, ay;                      // stage 1b (ay unused for a line)
   std::vector<zd> G1, G2;                 // stage 2: [B][P3] spectra of x_b and y~_b
   std::vector<zd> pre3, H3, post3;        // F_u chirp-z: [L], [P3], [N]
@@ -42,6 +43,7 @@ struct Params {
   fbst_precision prec = FBST_PREC_FP32;
   unsigned flags = 0;
   int p1 = 0, p2x = 0, p2y = 0, p3 = 0;
+  int p1s = 0, ls1 = 0;                   // split-output stage 1a: FFT size, first-half length
 };
 
 // Validate and complete the user parameters (defaults, FFT sizes).  Returns
@@ -87,7 +89,7 @@ struct fbst_plan {
   // device table pointers (element type per stage precision)
   const void* tw1 = nullptr;       // twiddles in the stage-1 type
   const void* tw2 = nullptr;       // twiddles in the stage-2 type
-  const void *pre1 = nullptr, *H1 = nullptr, *post1 = nullptr;
+  const void *pre1 = nullptr, *H1 = nullptr, *post1 = nullptr, *H1a = nullptr, *H1b = nullptr;
   const void *axp = nullptr, *axH = nullptr, *axq = nullptr;
   const void *ayp = nullptr, *ayH = nullptr, *ayq = nullptr;
   const void *G1 = nullptr, *G2 = nullptr, *pre3 = nullptr, *H3 = nullptr, *post3 = nullptr;

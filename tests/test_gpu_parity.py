@@ -194,3 +194,56 @@ def test_plane_wave_peaks_in_its_beam():
     bias = rel(od.beams(y32, p, [b0])[0], s)
     assert rel(out[b0], s) < 2e-3
     assert abs(rel(out[b0], s) - bias) < 1e-5
+
+
+@pytest.mark.parametrize("M,N,L", [(6, 100, 256), (5, 200, 400), (4, 37, 128), (3, 256, 512),
+                                   (2, 1000, 2000)])
+def test_split_stage1a_matches_definition(M, N, L):
+    """Stage 1a in split-output form (two half-length output convolutions
+    sharing one forward FFT) and in the one-convolution form (FBST_FLAG_NO_SPLIT)
+    against the definition, including L != 2N and N off the tile size; the
+    whole chain of both forms against the oracle."""
+    need_gpu()
+    rng = np.random.default_rng(M + N + L)
+    band = F.make_band(2.0, 0.5, 1.0)
+    B = 5
+    delta = 0.1 * L
+    p = od.line_problem(M, N, B, fc=2.0, omega=0.5, delta=delta, gamma=L / N)
+    assert p.L == L
+    y = crandn(rng, M, N)
+    x = torch.from_numpy(y.astype(np.complex64)).cuda()
+    y32 = x.cpu().numpy().astype(np.complex128)
+    ref1 = od.stage1a(y32, p)
+    refb = od.beams(y32, p)
+    outs = {}
+    for flags in (0, F.FBST_FLAG_NO_SPLIT):
+        plan = F.Plan(M, N, B, band=band, options=F.make_options(delta, L=L, flags=flags))
+        split = plan.info.p1_split
+        assert (split > 0) == (flags == 0), (split, plan.info.p1)
+        yhat = plan.stage(0, x)
+        out = plan.execute(x)
+        torch.cuda.synchronize()
+        e1 = rel(yhat[0].cpu().numpy(), ref1)
+        eb = rel(out.cpu().numpy(), refb)
+        print(f"M={M} N={N} L={L} p1={plan.info.p1} p1_split={split}: stage 1a {e1:.2e} beams {eb:.2e}")
+        assert e1 < TOL32 and eb < TOL32
+        outs[flags] = out.cpu().numpy()
+    assert rel(outs[0], outs[F.FBST_FLAG_NO_SPLIT]) < TOL32
+
+
+def test_split_stage1a_fp64():
+    """The split form in float64 (the FP64 precision runs every stage in float64)."""
+    need_gpu()
+    M, N, B, L = 4, 128, 6, 256
+    rng = np.random.default_rng(11)
+    band = F.make_band(2.0, 0.5, 1.0)
+    plan = F.Plan(M, N, B, band=band, options=F.make_options(1e-5, L=L, precision="fp64"))
+    assert plan.info.p1_split == 256 and plan.info.p1 == 512
+    y = crandn(rng, M, N)
+    x = torch.from_numpy(y).cuda()
+    yhat = plan.stage(0, x)
+    torch.cuda.synchronize()
+    p = od.line_problem(M, N, B, fc=2.0, omega=0.5, delta=1e-5)
+    e = rel(yhat[0].cpu().numpy(), od.stage1a(y, p))
+    print(f"fp64 split stage 1a rel err {e:.2e}")
+    assert e < 1e-12
