@@ -192,3 +192,23 @@ def test_server_argument_validation():
     assert lib.fbst_server_poll(None, None, 0) == F.FBST_E_INVALID
     assert lib.fbst_server_drain(None, 0.0) == F.FBST_E_INVALID
     lib.fbst_server_destroy(None)
+
+
+@pytest.mark.parametrize("N,L,flags,prec,expect", [
+    (1024, 2048, 0, "fp32", (4096, 2048)),       # L = 2N: half-size convolutions
+    (100, 256, 0, "fp32", (512, 256)),           # L != 2N, still 3 p1s < 2 p1
+    (100, 100, 0, "fp32", (256, 0)),             # p1s = 256 = p1: no gain, one convolution
+    (1024, 2048, 4, "fp32", (4096, 0)),          # FBST_FLAG_NO_SPLIT
+    (1024, 2048, 0, "bf16_split", (4096, 0)),    # the matrix-core stage 1a has no split form
+    (1024, 2048, 0, "fp64", (4096, 2048)),
+])
+def test_stage1a_split_selection(N, L, flags, prec, expect):
+    """Which stage-1a form a plan selects (fbst_info.p1 / p1_split)."""
+    band = F.make_band(2.0, 0.5, 1.0)
+    opts = F.make_options(0.1 * L, L=L, precision=prec, flags=flags | F.FBST_FLAG_HOST_ONLY)
+    h = F.fbst_plan_create(4, N, 4, None, band, None, opts)
+    try:
+        info = F.fbst_plan_info(h)
+        assert (info.p1, info.p1_split) == expect
+    finally:
+        F.fbst_destroy(h)
