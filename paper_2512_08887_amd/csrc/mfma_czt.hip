@@ -173,28 +173,51 @@ __global__ __launch_bounds__(P / FFT_E) void k_time_czt_mfma(
   const c32* src = static_cast<const c32*>(xs.p[blk]) + static_cast<size_t>(row - blk * M) * N;
   const DftA<V8> Af = make_dft_a<-1, V8>(lane);
   const DftA<V8> Ai = make_dft_a<+1, V8>(lane);
+  {
+    // loads at clamped indices, issued together (empty asm with a memory
+    // clobber), then the select; see the float32 kernels
+    c32 xa[FFT_E], pa[FFT_E];
 #pragma unroll
-  for (int s = 0; s < FFT_E; ++s) {
-    const int n = t + s * TT;
-    const int nc = n < N ? n : N - 1;                 // clamped load, select after
-    const c32 x = cmul(src[nc], pre[nc]);
-    buf[lds_pad(n)] = (n < N) ? x : c32{0.f, 0.f};
+    for (int s = 0; s < FFT_E; ++s) {
+      const int n = t + s * TT;
+      const int nc = n < N ? n : N - 1;
+      xa[s] = src[nc];
+      pa[s] = pre[nc];
+    }
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int s = 0; s < FFT_E; ++s) {
+      const int n = t + s * TT;
+      buf[lds_pad(n)] = (n < N) ? cmul(xa[s], pa[s]) : c32{0.f, 0.f};
+    }
   }
   __syncthreads();
   mfma_passes<P, 1, -1>(buf, tw, Af, wave, lane, t);
+  {
+    c32 h[FFT_E];
 #pragma unroll
-  for (int s = 0; s < FFT_E; ++s) {
-    const int i = t + s * TT;
-    buf[lds_pad(i)] = cmul(buf[lds_pad(i)], H[i]);
+    for (int s = 0; s < FFT_E; ++s) h[s] = H[t + s * TT];
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int s = 0; s < FFT_E; ++s) {
+      const int i = t + s * TT;
+      buf[lds_pad(i)] = cmul(buf[lds_pad(i)], h[s]);
+    }
   }
   __syncthreads();
   mfma_passes<P, 1, +1>(buf, tw, Ai, wave, lane, t);
   c32* dst = yhat + static_cast<size_t>(row) * L;
+  c32 po[FFT_E];
 #pragma unroll
   for (int s = 0; s < FFT_E; ++s) {
     const int i = t + s * TT;
-    const c32 o = cmul(buf[lds_pad(i)], post[i < L ? i : L - 1]);
-    if (i < L) dst[i] = o;
+    po[s] = post[i < L ? i : L - 1];
+  }
+  asm volatile("" ::: "memory");
+#pragma unroll
+  for (int s = 0; s < FFT_E; ++s) {
+    const int i = t + s * TT;
+    if (i < L) dst[i] = cmul(buf[lds_pad(i)], po[s]);
   }
 }
 
