@@ -22,8 +22,9 @@
 // inputs are exactly the slots, then skips the zero operands.  Outputs the
 // caller never reads are removed by dead-code elimination of the last pass.
 //
-// LDS addresses are padded, i -> i + (i >> 4), which keeps the radix-16 and
-// remainder-pass writes and reads free of bank conflicts for complex64.
+// LDS addresses are padded, i -> i + (i >> 4) (one slot every 16 elements, a
+// compile-time choice), which spreads the strided radix-16 writes over the
+// banks for complex64.
 //
 // Twiddles: each pass reads w_{NS R}^{r k} from its own contiguous table,
 // laid out [r - 1][k] so that consecutive threads read consecutive entries.
@@ -41,27 +42,38 @@ constexpr int PMAX = 16384;      // largest supported transform size
 constexpr int FFT_E = 16;        // elements per thread (radix of the full passes)
 constexpr int TW_ENTRIES = 2 * PMAX;
 
-__host__ __device__ constexpr int lds_pad(int i) { return i + (i >> 4); }
-// per-transform LDS stride in elements (padding + 2 keeps sub-groups apart in banks)
-__host__ __device__ constexpr int lds_stride(int P) { return P + P / 16 + 2; }
+#ifndef FBST_LDS_PAD_SHIFT
+#define FBST_LDS_PAD_SHIFT 4
+#endif
+constexpr int kPadShift = FBST_LDS_PAD_SHIFT;    // one padding slot every 2^kPadShift elements
+constexpr int kPadRun = 1 << kPadShift;
+
+__host__ __device__ constexpr int lds_pad(int i) { return i + (i >> kPadShift); }
+// per-transform LDS stride in elements: the padded size plus a skew that
+// places the transforms of one workgroup (same element index, consecutive
+// lanes) in different banks
+#ifndef FBST_LDS_SKEW
+#define FBST_LDS_SKEW 1
+#endif
+__host__ __device__ constexpr int lds_stride(int P) { return P + (P >> kPadShift) + FBST_LDS_SKEW; }
 // first entry of the twiddle table of the pass with span NS of a P-point transform
 __host__ __device__ constexpr int tw_offset(int P, int NS) { return P + NS - FFT_E; }
 
 // Padded LDS slots of the operands of a pass.  The padding is additive over
-// multiples of 16, pad(i + 16 m) = pad(i) + 17 m, so every operand of a
-// butterfly sits at a compile-time offset from one computed base and the
-// accesses use the instruction's immediate offset instead of one address
-// register per operand.
+// multiples of the run length, pad(i + m 2^s) = pad(i) + m (2^s + 1), so every
+// operand of a butterfly sits at a compile-time offset from one computed base
+// and the accesses use the instruction's immediate offset instead of one
+// address register per operand.
 template <int P, int R>
 __device__ __forceinline__ int read_slot(int j, int r) {
   constexpr int S = P / R;
-  if constexpr (S % 16 == 0) return lds_pad(j) + r * (S / 16) * 17;
+  if constexpr (S % kPadRun == 0) return lds_pad(j) + r * (S / kPadRun) * (kPadRun + 1);
   else return lds_pad(j + r * S);
 }
 template <int R, int NS>
 __device__ __forceinline__ int write_slot(int base, int r) {
-  if constexpr (NS == 1 && 16 % R == 0) return lds_pad(base) + r;   // base = j R, r < R
-  else if constexpr (NS % 16 == 0) return lds_pad(base) + r * (NS / 16) * 17;
+  if constexpr (NS == 1 && kPadRun % R == 0) return lds_pad(base) + r;   // base = j R, r < R
+  else if constexpr (NS % kPadRun == 0) return lds_pad(base) + r * (NS / kPadRun) * (kPadRun + 1);
   else return lds_pad(base + r * NS);
 }
 
