@@ -173,6 +173,74 @@ def stored_traffic(kernel, grid):
     return c["FETCH_SIZE"] + c["WRITE_SIZE"]
 
 
+def precompute_bench(F, torch, *, steps=10, warmup=2, nblk=1024, chunk=64, log=print):
+    """The paper's operating point (128-element line, N = 64, L = 128, 128
+    beams; synthetic stand-in, 1024 blocks): stage 2 as the Gohberg-Semencul
+    kernel against the precomputed per-beam product on the matrix cores."""
+    import synth
+    from oracle import direct as od
+    cfg = synth.config("ula128n64")
+    sc = cfg.scene()
+    base = np.stack([sc.block(k) for k in range(64)])
+    x = torch.from_numpy(np.concatenate([base] * (nblk // 64))).to(torch.complex64).cuda()
+    stream = torch.cuda.current_stream()
+    out = {"workload": "ula128n64: line M=B=128, N=64, L=128, FB=0.5, 3 sources, 10 dB SNR, "
+                       f"delta=sigma^2 L=12.8, {nblk} blocks per step, {chunk} per launch"}
+    samples = nblk * cfg.B * cfg.N
+    beams = {}
+    for name, flags in (("gohberg_semencul", 0), ("precomputed", F.FBST_FLAG_PRECOMPUTE)):
+        t0 = time.perf_counter()
+        plan = F.plan_for_config(cfg, flags=flags)
+        torch.cuda.synchronize()
+        plan_s = time.perf_counter() - t0
+        ws = plan.workspace(chunk)
+        bo = torch.empty((nblk, cfg.B, cfg.N), dtype=torch.complex64, device="cuda")
+        for _ in range(warmup):
+            plan.execute_batched(x, beams=bo, workspace=ws, max_chunk=chunk)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(steps):
+            plan.execute_batched(x, beams=bo, workspace=ws, max_chunk=chunk)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        r = {"value": samples / (ms / 1e3), "unit": "beam-samples/s", "ms_per_step": ms,
+             "plan_s": plan_s, "device_MiB": F.fbst_plan_device_bytes(plan.handle) / 2**20}
+        # stage 2 alone, one launch of `chunk` blocks, on the stage-1 output
+        w = plan.stage(1, plan.stage(0, x[:chunk].contiguous(), nblocks=chunk), nblocks=chunk)
+        o2 = torch.empty((chunk, cfg.B, cfg.N), dtype=torch.complex64, device="cuda")
+        plan.stage(2, w, nblocks=chunk, out=o2)
+        a0 = torch.cuda.Event(enable_timing=True)
+        a1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a0.record(stream)
+        for _ in range(20):
+            plan.stage(2, w, nblocks=chunk, out=o2)
+        a1.record(stream)
+        torch.cuda.synchronize()
+        r["stage2_ms_per_launch"] = a0.elapsed_time(a1) / 20
+        if flags:
+            flops = 8.0 * cfg.B * cfg.N * plan.L * chunk     # complex multiply-add = 8 flops
+            ach = flops / (r["stage2_ms_per_launch"] / 1e3)
+            r["roofline"] = {"kernel": "k_precomputed_apply (per-beam complex product, float32 MFMA)",
+                             "bound": "mfma", "achieved": ach / 1e12, "peak": 157.3,
+                             "unit": "TFLOP/s", "frac": ach / 157.3e12,
+                             "flops_per_launch": flops}
+        beams[name] = bo[0].cpu().numpy()
+        out[name] = r
+        log(f"[bench] n64 {name}: {ms:.3f} ms per {nblk} blocks, stage 2 "
+            f"{r['stage2_ms_per_launch'] * 1e3:.1f} us per {chunk}-block launch, plan {plan_s:.2f} s")
+        plan.close()
+    p = od.line_problem(cfg.M, cfg.N, cfg.B, fc=cfg.band.fc, omega=cfg.band.omega, ts=cfg.band.ts,
+                        eps=cfg.eps, gamma=cfg.gamma, delta=cfg.delta_noise)
+    ref = od.beams(x[0].cpu().numpy().astype(np.complex128), p)
+    out["accuracy_vs_oracle"] = {k: float(np.linalg.norm(v - ref) / np.linalg.norm(ref))
+                                 for k, v in beams.items()}
+    return out
+
+
 def serve_bench(F, torch, configs, *, seconds=2.0, loads=(0.5, 0.8, 0.95), burst=768,
                 slots=16, seed=0, log=print):
     """Continuous-batching server over resident plans: saturation throughput
@@ -279,6 +347,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--latency-reps", type=int, default=200)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-mix measurement")
+    ap.add_argument("--no-n64", action="store_true",
+                    help="skip the N = 64 Gohberg-Semencul vs precomputed stage-2 comparison")
     ap.add_argument("--no-variants", action="store_true", help="skip the bf16/fp16 split variants")
     ap.add_argument("--serve-only", action="store_true", help="only the serving-mix measurement")
     ap.add_argument("--serve-seconds", type=float, default=2.0)
@@ -508,6 +578,10 @@ def main():
     torch.cuda.synchronize()
     result["stage1a_ms_per_launch"] = s1a.elapsed_time(s1b)
 
+    if not args.no_n64:
+        result["precompute_n64"] = precompute_bench(
+            F, torch, steps=max(2, min(args.steps, 10)), warmup=1,
+            log=lambda m: print(m, file=sys.stderr, flush=True))
     if not args.no_serve:
         print("[bench] serving mix", file=sys.stderr, flush=True)
         log = lambda m: print(m, file=sys.stderr, flush=True)

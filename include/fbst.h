@@ -105,6 +105,15 @@ typedef struct {
 #define FBST_FLAG_NO_SPLIT 4u         /* stage 1a as one convolution of p1 points, even
                                          where two half-length output convolutions of
                                          p1_split points would be cheaper             */
+#define FBST_FLAG_PRECOMPUTE 8u       /* stage 2 in precomputed form (the paper's FBST-
+                                         Precompute variant, Sec. V / Table I): the plan
+                                         builds K_b = F_u A_b^{-1} (N x L per beam) on the
+                                         device with the float64 Gohberg-Semencul kernel,
+                                         and execution applies it as a complex matrix
+                                         product on the float32 matrix cores.  Costs
+                                         8 B N L bytes of device memory (at most 16 GiB)
+                                         and needs P3 <= 8192; not with FBST_PREC_FP64
+                                         (otherwise FBST_E_UNSUPPORTED)                   */
 
 /* Basis and solver options.  eps: band expansion epsilon > 0 (0 selects 1.01).
  * L: number of basis frequencies, even and >= 2 (0 selects 2N, i.e.
@@ -135,6 +144,7 @@ typedef struct {
   int p1_split;      /* 0, or the FFT size of stage 1a in split-output form: the
                         L outputs as two halves, each a convolution of
                         p1_split >= N + L/2 - 1 points sharing one forward FFT */
+  int stage2_precomputed; /* 1 when stage 2 applies a precomputed K (FBST_FLAG_PRECOMPUTE) */
 } fbst_info;
 
 typedef struct fbst_plan fbst_plan;

@@ -192,6 +192,7 @@ hipError_t run_stage1(const fbst_plan* pl, int nb, const void* yhat, void* w, vo
 hipError_t run_stage2(const fbst_plan* pl, int nb, const void* w, const fbst::OutPtrs& outs,
                       hipStream_t st) {
   const fbst::Params& p = pl->p;
+  if (pl->K) return fbst::launch_precomputed_apply(pl->K, w, outs, p.B, p.L, p.N, nb, st);
   switch (p.prec) {
     case FBST_PREC_FP64:
       return fbst::launch_toeplitz_fu<double, double, double>(p.p3, w, outs, pl->G1, pl->G2,
@@ -206,6 +207,79 @@ hipError_t run_stage2(const fbst_plan* pl, int nb, const void* w, const fbst::Ou
                                                            pl->pre3, pl->H3, pl->post3, pl->tw2,
                                                            p.B, p.L, p.N, nb, st);
   }
+}
+
+// Stage 2 in precomputed form: K_b = F_u A_b^{-1} for every beam, built on
+// the device by the Gohberg-Semencul kernel applied to the unit vectors e_l
+// (block j of a launch carries e_{l0 + j} for every beam, and its output
+// block is column l0 + j of every K_b).  The build runs in float64
+// arithmetic whatever the plan's stage-2 precision (float64 copies of the
+// stage-2 tables are staged for it when the plan's are float32): it is a
+// one-time cost, and the product then adds only float32 rounding, so the
+// precomputed stage 2 is at least as accurate as the plan's own.
+fbst_status build_precomputed(fbst_plan* pl) {
+  const fbst::Params& p = pl->p;
+  const size_t kbytes = static_cast<size_t>(p.L) * p.B * p.N * 8;
+  const int chunk = fbst::MAX_LAUNCH_BLOCKS;
+  const void *tw = pl->tw2, *g1 = pl->G1, *g2 = pl->G2, *pre = pl->pre3, *h3 = pl->H3,
+             *post = pl->post3;
+  void* d64 = nullptr;
+  if (!stage2_double(p)) {
+    const fbst::HostTables& h = pl->host;
+    Upload up;
+    const size_t o_tw = up.add(twiddles(), true), o_g1 = up.add(h.G1, true),
+                 o_g2 = up.add(h.G2, true), o_pre = up.add(h.pre3, true),
+                 o_h3 = up.add(h.H3, true), o_post = up.add(h.post3, true);
+    hipError_t e = hipMalloc(&d64, up.blob.size());
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(FBST_E_NOMEM, "hipMalloc of the float64 stage-2 tables failed");
+    }
+    e = hipMemcpy(d64, up.blob.data(), up.blob.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      (void)hipFree(d64);
+      return hip_fail(e, "hipMemcpy of the float64 stage-2 tables");
+    }
+    const unsigned char* b = static_cast<const unsigned char*>(d64);
+    tw = b + o_tw;
+    g1 = b + o_g1;
+    g2 = b + o_g2;
+    pre = b + o_pre;
+    h3 = b + o_h3;
+    post = b + o_post;
+  }
+  void* K = nullptr;
+  void* unit = nullptr;
+  hipError_t e = hipMalloc(&K, kbytes);
+  if (e == hipSuccess) e = hipMalloc(&unit, static_cast<size_t>(chunk) * p.B * p.L * 8);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    if (K) (void)hipFree(K);
+    if (d64) (void)hipFree(d64);
+    return fail(FBST_E_NOMEM, "hipMalloc of " + std::to_string(kbytes) + " bytes of K failed");
+  }
+  const hipStream_t st = nullptr;
+  for (int l0 = 0; l0 < p.L && e == hipSuccess; l0 += chunk) {
+    const int n = (p.L - l0 < chunk) ? p.L - l0 : chunk;
+    fbst::OutPtrs outs{};
+    for (int j = 0; j < n; ++j)
+      outs.p[j] = static_cast<unsigned char*>(K) + static_cast<size_t>(l0 + j) * p.B * p.N * 8;
+    e = fbst::launch_unit_rows(unit, p.B, p.L, l0, n, st);
+    if (e == hipSuccess)
+      e = fbst::launch_toeplitz_fu<double, float, float>(p.p3, unit, outs, g1, g2, pre, h3, post,
+                                                         tw, p.B, p.L, p.N, n, st);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(unit);
+  if (d64) (void)hipFree(d64);
+  if (e != hipSuccess) {
+    (void)hipFree(K);
+    return hip_fail(e, "building the precomputed stage 2");
+  }
+  pl->K = K;
+  pl->K_bytes = kbytes;
+  pl->dev_bytes += kbytes;
+  return FBST_OK;
 }
 
 }  // namespace
@@ -294,6 +368,14 @@ fbst_status fbst_plan_create(int M, int N, int B, const fbst_geometry* geometry,
     if (st != FBST_OK) {
       delete pl;
       return st;
+    }
+    if (p.flags & FBST_FLAG_PRECOMPUTE) {
+      st = build_precomputed(pl);
+      if (st != FBST_OK) {
+        (void)hipFree(pl->dev);
+        delete pl;
+        return st;
+      }
     }
     // device copies are the working set; keep only what was asked for on the host
     if (!pl->kept) pl->host = fbst::HostTables();
@@ -517,6 +599,7 @@ fbst_status fbst_plan_info(const fbst_plan* plan, fbst_info* info) {
   info->device_bytes = plan->dev_bytes;
   info->workspace_per_block = plan->ws_bytes_per_block;
   info->p1_split = p.p1s;
+  info->stage2_precomputed = plan->K ? 1 : 0;
   return FBST_OK;
 }
 
@@ -555,6 +638,7 @@ fbst_status fbst_plan_table(const fbst_plan* plan, int table, void* dst, size_t 
 void fbst_destroy(fbst_plan* plan) {
   if (!plan) return;
   if (plan->dev) (void)hipFree(plan->dev);
+  if (plan->K) (void)hipFree(plan->K);
   delete plan;
 }
 

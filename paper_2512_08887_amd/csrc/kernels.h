@@ -53,4 +53,13 @@ hipError_t launch_toeplitz_fu(int P, const void* w, const OutPtrs& outs, const v
                               const void* G2, const void* pre3, const void* H3, const void* post3,
                               const void* tw, int B, int L, int N, int nblocks, hipStream_t st);
 
+// Stage 2 in precomputed form: beams_blk[b][n] = sum_l K[l][b][n] w[blk][b][l]
+// (complex64, K = F_u A_b^{-1} per beam stored [L][B][N]) on the float32
+// matrix cores.
+hipError_t launch_precomputed_apply(const void* K, const void* w, const OutPtrs& outs, int B,
+                                    int L, int N, int nblocks, hipStream_t st);
+
+// w[j][b][l] = (l == l0 + j) for j < rows (complex64, [rows][B][L]).
+hipError_t launch_unit_rows(void* w, int B, int L, int l0, int rows, hipStream_t st);
+
 }  // namespace fbst

@@ -405,6 +405,22 @@ fbst_status resolve_params(int M, int N, int B, const fbst_geometry* geom, const
       p.ls1 = ls;
     }
   }
+  if (p.flags & FBST_FLAG_PRECOMPUTE) {
+    if (p.prec == FBST_PREC_FP64) {
+      *msg = "the precomputed stage 2 takes complex64 data (any precision but FBST_PREC_FP64)";
+      return FBST_E_UNSUPPORTED;
+    }
+    if (p.p3 > 8192) {
+      *msg = "the precomputed stage 2 is built by the float64 stage-2 kernel (P3 <= 8192)";
+      return FBST_E_UNSUPPORTED;
+    }
+    const double kbytes = 8.0 * p.L * p.B * p.N;
+    if (kbytes > 16.0 * (1ULL << 30)) {
+      *msg = "the precomputed stage 2 would hold " + std::to_string(kbytes / (1ULL << 30)) +
+             " GiB of K (limit 16 GiB)";
+      return FBST_E_UNSUPPORTED;
+    }
+  }
   const int lim1 = (p.prec == FBST_PREC_FP64) ? 8192 : PMAX;
   const int lim2 = (p.prec == FBST_PREC_FP32) ? PMAX : 8192;
   if (p.p1 > lim1 || p.p2x > lim1 || p.p2y > lim1 || p.p3 > lim2) {

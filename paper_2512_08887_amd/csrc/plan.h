@@ -93,5 +93,8 @@ struct fbst_plan {
   const void *axp = nullptr, *axH = nullptr, *axq = nullptr;
   const void *ayp = nullptr, *ayH = nullptr, *ayq = nullptr;
   const void *G1 = nullptr, *G2 = nullptr, *pre3 = nullptr, *H3 = nullptr, *post3 = nullptr;
+  // stage 2 in precomputed form: K [L][B][N] complex64 (own allocation), or null
+  void* K = nullptr;
+  size_t K_bytes = 0;
   int device = 0;
 };

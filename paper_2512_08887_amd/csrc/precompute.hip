@@ -1,0 +1,171 @@
+// Stage 2 in precomputed form (the FBST-Precompute variant, Sec. V and
+// Table I): for a fixed beam set the map from w_b to the beam is the fixed
+// N x L matrix K_b = F_u A_b^{-1}, so a plan may build it once and apply it
+// as a matrix product.  Across the blocks of one launch that product is, per
+// beam, a complex GEMM
+//     beams_blk[b][n] = sum_l K_b[n][l] W[blk][b][l],
+// done here on the float32 matrix cores (v_mfma_f32_16x16x4f32, float32
+// operands and accumulation, so no precision is given up against the
+// Gohberg-Semencul path).
+//
+// K is stored [L][B][N] (the output layout of the stage-2 kernel run on unit
+// vectors, which is how the plan builds it): column l of K_b is contiguous in
+// n.
+#include <hip/hip_runtime.h>
+
+#include "cx.h"
+#include "kernels.h"
+
+namespace fbst {
+
+namespace {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kXCD = 8;
+constexpr int PT_N = 64;    // outputs n per workgroup
+constexpr int PT_B = 32;    // blocks per workgroup
+constexpr int PT_KC = 32;   // basis frequencies per LDS chunk
+constexpr int PT_AS = PT_N + 1;    // LDS row strides (elements): rows of consecutive lanes
+constexpr int PT_BS = PT_KC + 1;   // fall in different banks
+
+__device__ __forceinline__ int xcd_linear(int nwg) {
+  const int b = blockIdx.x;
+  const int x = b % kXCD, i = b / kXCD;
+  const int q = nwg / kXCD, r = nwg % kXCD;
+  return (x < r) ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
+// Workgroup: one beam, PT_N outputs x PT_B blocks, 4 waves as 2 (n) x 2
+// (blocks); a wave owns 32 n x 16 blocks = two 16 x 16 tiles.  Matrix-core
+// operand layouts (16x16x4, float32): A lane l holds A[l % 16][l / 16],
+// B lane l holds B[l / 16][l % 16], accumulator lane l holds
+// D[4 (l / 16) + e][l % 16], e < 4.
+__global__ __launch_bounds__(256) void k_precomputed_apply(const c32* __restrict__ K,
+                                                           const c32* __restrict__ W,
+                                                           const OutPtrs outs, int B, int L,
+                                                           int N, int nb, int n_ntiles,
+                                                           int n_btiles) {
+  __shared__ c32 As[PT_KC * PT_AS];   // [k][n]
+  __shared__ c32 Bs[PT_B * PT_BS];    // [blk][k]
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  // logical order: beam outermost, so the workgroups sharing K_b sit on one XCD
+  int w = xcd_linear(gridDim.x);
+  const int bt = w % n_btiles;
+  w /= n_btiles;
+  const int nt = w % n_ntiles;
+  const int b = w / n_ntiles;
+  const int n0 = nt * PT_N, blk0 = bt * PT_B;
+
+  // global -> register staging of one chunk: A 64 x 32 (8 per thread),
+  // B 32 x 32 (4 per thread), zero outside [N) x [L) and [nb) x [L)
+  const int an = tid % PT_N, ak = tid / PT_N;          // + 4 i
+  const int bk = tid % PT_KC, bb = tid / PT_KC;        // + 8 i
+  const bool a_ok = n0 + an < N;
+  const c32* Kb = K + static_cast<size_t>(b) * N + n0 + (a_ok ? an : 0);
+  c32 ra[8], rb[4];
+  auto load_chunk = [&](int l0) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int l = l0 + ak + 4 * i;
+      const c32 v = Kb[static_cast<size_t>(l < L ? l : L - 1) * B * N];
+      ra[i] = (a_ok && l < L) ? v : c32{0.f, 0.f};
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int blk = blk0 + bb + 8 * i;
+      const int l = l0 + bk;
+      const bool ok = blk < nb && l < L;
+      const c32 v = W[(static_cast<size_t>(ok ? blk : 0) * B + b) * L + (ok ? l : 0)];
+      rb[i] = ok ? v : c32{0.f, 0.f};
+    }
+    asm volatile("" ::: "memory");   // issue the chunk's loads together
+  };
+  auto store_chunk = [&]() {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) As[(ak + 4 * i) * PT_AS + an] = ra[i];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) Bs[(bb + 8 * i) * PT_BS + bk] = rb[i];
+  };
+
+  const int wn = wave & 1, wb = wave >> 1;
+  const int row = lane & 15, kq = lane >> 4;
+  f32x4 accR[2], accI[2];
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt) {
+    accR[rt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    accI[rt] = f32x4{0.f, 0.f, 0.f, 0.f};
+  }
+  load_chunk(0);
+  for (int l0 = 0; l0 < L; l0 += PT_KC) {
+    __syncthreads();                 // the previous chunk has been consumed
+    store_chunk();
+    __syncthreads();
+    if (l0 + PT_KC < L) load_chunk(l0 + PT_KC);   // in flight during the products
+#pragma unroll
+    for (int ks = 0; ks < PT_KC / 4; ++ks) {
+      const int k = 4 * ks + kq;
+      const c32 bv = Bs[(16 * wb + row) * PT_BS + k];
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt) {
+        const c32 av = As[k * PT_AS + 32 * wn + 16 * rt + row];
+        accR[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.re, bv.re, accR[rt], 0, 0, 0);
+        accR[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(-av.im, bv.im, accR[rt], 0, 0, 0);
+        accI[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.re, bv.im, accI[rt], 0, 0, 0);
+        accI[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.im, bv.re, accI[rt], 0, 0, 0);
+      }
+    }
+  }
+  // accumulator lane l: n = n0 + 32 wn + 16 rt + 4 (l / 16) + e, block blk0 + 16 wb + l % 16
+  const int blk = blk0 + 16 * wb + row;
+  if (blk < nb) {
+    c32* dst = static_cast<c32*>(outs.p[blk]) + static_cast<size_t>(b) * N;
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int n = n0 + 32 * wn + 16 * rt + 4 * kq + e;
+        if (n < N) dst[n] = c32{accR[rt][e], accI[rt][e]};
+      }
+  }
+}
+
+// w[j][b][l] = (l == l0 + j), j < rows: the unit vectors whose stage-2 images
+// are the columns of K.
+__global__ __launch_bounds__(256) void k_unit_rows(c32* __restrict__ w, int B, int L, int l0,
+                                                   int rows) {
+  const size_t i = static_cast<size_t>(blockIdx.x) * 256 + threadIdx.x;
+  const size_t total = static_cast<size_t>(rows) * B * L;
+  if (i >= total) return;
+  const int l = static_cast<int>(i % L);
+  const int j = static_cast<int>(i / (static_cast<size_t>(B) * L));
+  w[i] = c32{l == l0 + j ? 1.f : 0.f, 0.f};
+}
+
+}  // namespace
+
+hipError_t launch_precomputed_apply(const void* K, const void* w, const OutPtrs& outs, int B,
+                                    int L, int N, int nblocks, hipStream_t st) {
+  if (nblocks < 1 || nblocks > MAX_LAUNCH_BLOCKS || B < 1 || L < 1 || N < 1)
+    return hipErrorInvalidValue;
+  const int n_ntiles = (N + PT_N - 1) / PT_N, n_btiles = (nblocks + PT_B - 1) / PT_B;
+  const long long ng = 1LL * B * n_ntiles * n_btiles;
+  if (ng > 0x7fffffffLL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_precomputed_apply, dim3(static_cast<unsigned>(ng)), dim3(256), 0, st,
+                     static_cast<const c32*>(K), static_cast<const c32*>(w), outs, B, L, N,
+                     nblocks, n_ntiles, n_btiles);
+  return hipGetLastError();
+}
+
+hipError_t launch_unit_rows(void* w, int B, int L, int l0, int rows, hipStream_t st) {
+  if (rows < 1 || B < 1 || L < 1) return hipErrorInvalidValue;
+  const size_t total = static_cast<size_t>(rows) * B * L;
+  const size_t grid = (total + 255) / 256;
+  if (grid > 0x7fffffffULL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_unit_rows, dim3(static_cast<unsigned>(grid)), dim3(256), 0, st,
+                     static_cast<c32*>(w), B, L, l0, rows);
+  return hipGetLastError();
+}
+
+}  // namespace fbst

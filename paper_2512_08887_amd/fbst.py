@@ -21,7 +21,7 @@ HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))
 FBST_OK, FBST_E_INVALID, FBST_E_UNSUPPORTED, FBST_E_NOMEM, FBST_E_DEVICE = 0, -1, -2, -3, -4
 FBST_LINE, FBST_GRID = 0, 1
 FBST_PREC_FP32, FBST_PREC_FP64_STAGE2, FBST_PREC_FP64, FBST_PREC_BF16_SPLIT, FBST_PREC_FP16_SPLIT = range(5)
-FBST_FLAG_HOST_ONLY, FBST_FLAG_KEEP_HOST_TABLES, FBST_FLAG_NO_SPLIT = 1, 2, 4
+FBST_FLAG_HOST_ONLY, FBST_FLAG_KEEP_HOST_TABLES, FBST_FLAG_NO_SPLIT, FBST_FLAG_PRECOMPUTE = 1, 2, 4, 8
 FBST_TABLE_BEAM_U, FBST_TABLE_BEAM_V, FBST_TABLE_GRAM, FBST_TABLE_GENERATOR = 0, 1, 2, 3
 MAX_LAUNCH_BLOCKS = 64  # blocks per kernel launch (per-block pointer arrays in the kernel arguments)
 
@@ -52,7 +52,8 @@ class fbst_info(ctypes.Structure):
     _fields_ = [("M", c_int), ("N", c_int), ("B", c_int), ("L", c_int), ("mx", c_int), ("my", c_int),
                 ("bu", c_int), ("bv", c_int), ("p1", c_int), ("p2x", c_int), ("p2y", c_int),
                 ("p3", c_int), ("precision", c_int), ("io_elem_bytes", c_size_t),
-                ("device_bytes", c_size_t), ("workspace_per_block", c_size_t), ("p1_split", c_int)]
+                ("device_bytes", c_size_t), ("workspace_per_block", c_size_t), ("p1_split", c_int),
+                ("stage2_precomputed", c_int)]
 
 
 class fbst_server_options(ctypes.Structure):

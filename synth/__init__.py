@@ -263,6 +263,10 @@ CONFIGS = {
     # precision study: 1024-element line, 32 sources over 40 dB, 0 dB SNR
     "ula1024": Config("ula1024", "ula", M=1024, N=4096, B=1024, fb=0.5, n_sources=32,
                       power_db_range=40.0, sigma2=1.0, index=4),
+    # the paper's experimental operating point (128-element line, N = 64 snapshots per
+    # block) streamed as 1024 short blocks: 3 unit-power sources, 10 dB SNR
+    "ula128n64": Config("ula128n64", "ula", M=128, N=64, B=128, fb=0.5, n_sources=3,
+                        power_db_range=0.0, sigma2=0.1, n_blocks=1024, index=5),
 }
 
 

@@ -212,3 +212,26 @@ def test_stage1a_split_selection(N, L, flags, prec, expect):
         assert (info.p1, info.p1_split) == expect
     finally:
         F.fbst_destroy(h)
+
+
+def test_precompute_flag_validation():
+    """FBST_FLAG_PRECOMPUTE needs complex64 data and a K of at most 16 GiB."""
+    band = F.make_band(2.0, 0.5, 1.0)
+    host = F.FBST_FLAG_HOST_ONLY | F.FBST_FLAG_PRECOMPUTE
+    st, h = F.fbst_plan_create_status(8, 32, 8, None, band, None,
+                                      F.make_options(1.0, precision="fp64", flags=host))
+    assert st == F.FBST_E_UNSUPPORTED and h is None
+    assert "complex64" in F.fbst_last_error()
+    # 1024 beams x N = 4096 x L = 8192 x 8 B = 256 GiB (and P3 = 16384)
+    st, h = F.fbst_plan_create_status(4, 4096, 1024, None, band, None,
+                                      F.make_options(1.0, flags=host))
+    assert st == F.FBST_E_UNSUPPORTED and h is None
+    # 4096 beams x N = 2048 x L = 4096 x 8 B = 256 GiB at P3 = 8192
+    st, h = F.fbst_plan_create_status(4, 2048, 4096, None, band, None,
+                                      F.make_options(1.0, flags=host))
+    assert st == F.FBST_E_UNSUPPORTED and h is None and "GiB" in F.fbst_last_error()
+    for prec in ("fp32", "fp64_stage2", "bf16_split"):
+        st, h = F.fbst_plan_create_status(8, 512, 8, None, band, None,
+                                          F.make_options(1.0, precision=prec, flags=host))
+        assert st == F.FBST_OK, prec
+        F.fbst_destroy(h)
