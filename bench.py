@@ -173,7 +173,7 @@ def stored_traffic(kernel, grid):
     return c["FETCH_SIZE"] + c["WRITE_SIZE"]
 
 
-def precompute_bench(F, torch, *, steps=10, warmup=2, nblk=1024, chunk=64, log=print):
+def precompute_bench(F, torch, *, steps=10, warmup=2, nblk=1024, chunk=256, log=print):
     """The paper's operating point (128-element line, N = 64, L = 128, 128
     beams; synthetic stand-in, 1024 blocks): stage 2 as the Gohberg-Semencul
     kernel against the precomputed per-beam product on the matrix cores."""

@@ -168,11 +168,15 @@ fbst_status fbst_plan_create(int M, int N, int B, const fbst_geometry* geometry,
 fbst_status fbst_execute(const fbst_plan* plan, const void* x, void* beams,
                          void* workspace, void* hip_stream);
 
+/* Most blocks one kernel launch takes (their pointers travel in the kernel
+ * arguments). */
+#define FBST_MAX_LAUNCH_BLOCKS 256
+
 /* nblocks independent blocks of one plan in one set of launches:
- * x [nblocks][M][N] -> beams [nblocks][B][N].  workspace: at least
- * fbst_workspace_bytes(plan, chunk) bytes where chunk = min(nblocks,
- * max_chunk) (max_chunk <= 0: all blocks at once; the blocks are then
- * processed chunk blocks per launch), or NULL when chunk == 1. */
+ * x [nblocks][M][N] -> beams [nblocks][B][N], processed chunk blocks per
+ * launch, chunk = min(nblocks, max_chunk, FBST_MAX_LAUNCH_BLOCKS)
+ * (max_chunk <= 0: no limit of its own).  workspace: at least
+ * fbst_workspace_bytes(plan, chunk) bytes, or NULL when chunk == 1. */
 fbst_status fbst_execute_batched(const fbst_plan* plan, int nblocks, int max_chunk,
                                  const void* x, void* beams, void* workspace,
                                  void* hip_stream);
@@ -207,9 +211,9 @@ fbst_status fbst_graph_launch(const fbst_graph* graph, void* hip_stream);
 void fbst_graph_destroy(fbst_graph* graph);
 
 /* Autotune the blocks per launch of fbst_execute_batched for nblocks blocks of
- * this plan: times chunk = 1, 2, 4, ... (<= min(nblocks, 64)) on the given
+ * this plan: times chunk = 1, 2, 4, ... (<= min(nblocks, FBST_MAX_LAUNCH_BLOCKS)) on the given
  * buffers (x [nblocks][M][N], beams, workspace of fbst_workspace_bytes(plan,
- * min(nblocks, 64)) bytes) on hip_stream, synchronising it, and returns the
+ * min(nblocks, FBST_MAX_LAUNCH_BLOCKS)) bytes) on hip_stream, synchronising it, and returns the
  * fastest chunk and its ms per batch.  Results are cached per plan shape and
  * precision for the process; force != 0 re-measures.  beams is overwritten. */
 fbst_status fbst_autotune(const fbst_plan* plan, int nblocks, const void* x, void* beams,
@@ -268,7 +272,7 @@ typedef struct fbst_server fbst_server;
 typedef struct {
   size_t workspace_bytes; /* device workspace for blocks in flight (> 0)            */
   int streams;            /* concurrent launch streams, 1..16                        */
-  int max_batch;          /* blocks of one plan per launch, 1..64                    */
+  int max_batch;          /* blocks of one plan per launch, 1..FBST_MAX_LAUNCH_BLOCKS */
   int device;             /* HIP device, or -1 for the calling thread's current one  */
 } fbst_server_options;
 

@@ -220,7 +220,7 @@ hipError_t run_stage2(const fbst_plan* pl, int nb, const void* w, const fbst::Ou
 fbst_status build_precomputed(fbst_plan* pl) {
   const fbst::Params& p = pl->p;
   const size_t kbytes = static_cast<size_t>(p.L) * p.B * p.N * 8;
-  const int chunk = fbst::MAX_LAUNCH_BLOCKS;
+  const int chunk = 64;    // unit-vector blocks per launch (bounds the staging buffer)
   const void *tw = pl->tw2, *g1 = pl->G1, *g2 = pl->G2, *pre = pl->pre3, *h3 = pl->H3,
              *post = pl->post3;
   void* d64 = nullptr;

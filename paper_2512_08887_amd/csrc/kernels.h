@@ -7,12 +7,14 @@
 
 #include <hip/hip_runtime.h>
 
+#include "../../include/fbst.h"
+
 namespace fbst {
 
 // Blocks of one launch: each block's input (or output) buffer is given by its
 // own pointer, passed by value in the kernel arguments, so one launch can
 // serve blocks that live anywhere (a contiguous batch or separate requests).
-constexpr int MAX_LAUNCH_BLOCKS = 64;
+constexpr int MAX_LAUNCH_BLOCKS = FBST_MAX_LAUNCH_BLOCKS;
 struct InPtrs {
   const void* p[MAX_LAUNCH_BLOCKS];
 };

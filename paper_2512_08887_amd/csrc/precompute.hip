@@ -24,7 +24,10 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kXCD = 8;
 constexpr int PT_N = 64;    // outputs n per workgroup
-constexpr int PT_B = 32;    // blocks per workgroup
+#ifndef FBST_PT_B
+#define FBST_PT_B 32
+#endif
+constexpr int PT_B = FBST_PT_B;    // blocks per workgroup (32 or 16)
 constexpr int PT_KC = 32;   // basis frequencies per LDS chunk
 constexpr int PT_AS = PT_N + 1;    // LDS row strides (elements): rows of consecutive lanes
 constexpr int PT_BS = PT_KC + 1;   // fall in different banks
@@ -37,7 +40,8 @@ __device__ __forceinline__ int xcd_linear(int nwg) {
 }
 
 // Workgroup: one beam, PT_N outputs x PT_B blocks, 4 waves as 2 (n) x 2
-// (blocks); a wave owns 32 n x 16 blocks = two 16 x 16 tiles.  Matrix-core
+// (blocks) for 32 blocks (a wave owns 32 n x 16 blocks, two 16 x 16 tiles) or
+// 4 (n) x 1 for 16 blocks (one tile per wave, twice the workgroups).  Matrix-core
 // operand layouts (16x16x4, float32): A lane l holds A[l % 16][l / 16],
 // B lane l holds B[l / 16][l % 16], accumulator lane l holds
 // D[4 (l / 16) + e][l % 16], e < 4.
@@ -60,11 +64,13 @@ __global__ __launch_bounds__(256) void k_precomputed_apply(const c32* __restrict
 
   // global -> register staging of one chunk: A 64 x 32 (8 per thread),
   // B 32 x 32 (4 per thread), zero outside [N) x [L) and [nb) x [L)
+  static_assert(PT_B == 16 || PT_B == 32, "block tile of 16 or 32");
+  constexpr int BI = PT_B / 8;                          // B loads per thread
   const int an = tid % PT_N, ak = tid / PT_N;          // + 4 i
   const int bk = tid % PT_KC, bb = tid / PT_KC;        // + 8 i
   const bool a_ok = n0 + an < N;
   const c32* Kb = K + static_cast<size_t>(b) * N + n0 + (a_ok ? an : 0);
-  c32 ra[8], rb[4];
+  c32 ra[8], rb[BI];
   auto load_chunk = [&](int l0) {
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
@@ -73,7 +79,7 @@ __global__ __launch_bounds__(256) void k_precomputed_apply(const c32* __restrict
       ra[i] = (a_ok && l < L) ? v : c32{0.f, 0.f};
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < BI; ++i) {
       const int blk = blk0 + bb + 8 * i;
       const int l = l0 + bk;
       const bool ok = blk < nb && l < L;
@@ -86,14 +92,16 @@ __global__ __launch_bounds__(256) void k_precomputed_apply(const c32* __restrict
 #pragma unroll
     for (int i = 0; i < 8; ++i) As[(ak + 4 * i) * PT_AS + an] = ra[i];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) Bs[(bb + 8 * i) * PT_BS + bk] = rb[i];
+    for (int i = 0; i < BI; ++i) Bs[(bb + 8 * i) * PT_BS + bk] = rb[i];
   };
 
-  const int wn = wave & 1, wb = wave >> 1;
+  constexpr int WN = PT_B == 32 ? 2 : 4;               // waves along n
+  constexpr int RT = PT_N / (16 * WN);                  // 16-row tiles per wave
+  const int wn = wave % WN, wb = wave / WN;
   const int row = lane & 15, kq = lane >> 4;
-  f32x4 accR[2], accI[2];
+  f32x4 accR[RT], accI[RT];
 #pragma unroll
-  for (int rt = 0; rt < 2; ++rt) {
+  for (int rt = 0; rt < RT; ++rt) {
     accR[rt] = f32x4{0.f, 0.f, 0.f, 0.f};
     accI[rt] = f32x4{0.f, 0.f, 0.f, 0.f};
   }
@@ -108,8 +116,8 @@ __global__ __launch_bounds__(256) void k_precomputed_apply(const c32* __restrict
       const int k = 4 * ks + kq;
       const c32 bv = Bs[(16 * wb + row) * PT_BS + k];
 #pragma unroll
-      for (int rt = 0; rt < 2; ++rt) {
-        const c32 av = As[k * PT_AS + 32 * wn + 16 * rt + row];
+      for (int rt = 0; rt < RT; ++rt) {
+        const c32 av = As[k * PT_AS + 16 * RT * wn + 16 * rt + row];
         accR[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.re, bv.re, accR[rt], 0, 0, 0);
         accR[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(-av.im, bv.im, accR[rt], 0, 0, 0);
         accI[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.re, bv.im, accI[rt], 0, 0, 0);
@@ -117,15 +125,15 @@ __global__ __launch_bounds__(256) void k_precomputed_apply(const c32* __restrict
       }
     }
   }
-  // accumulator lane l: n = n0 + 32 wn + 16 rt + 4 (l / 16) + e, block blk0 + 16 wb + l % 16
+  // accumulator lane l: n = n0 + 16 RT wn + 16 rt + 4 (l / 16) + e, block blk0 + 16 wb + l % 16
   const int blk = blk0 + 16 * wb + row;
   if (blk < nb) {
     c32* dst = static_cast<c32*>(outs.p[blk]) + static_cast<size_t>(b) * N;
 #pragma unroll
-    for (int rt = 0; rt < 2; ++rt)
+    for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int n = n0 + 32 * wn + 16 * rt + 4 * kq + e;
+        const int n = n0 + 16 * RT * wn + 16 * rt + 4 * kq + e;
         if (n < N) dst[n] = c32{accR[rt][e], accI[rt][e]};
       }
   }

@@ -281,7 +281,7 @@ fbst_status fbst_server_create(const fbst_server_options* opt, fbst_server** out
   if (opt) o = *opt;
   if (o.workspace_bytes == 0 || o.streams < 1 || o.streams > 16 || o.max_batch < 1 ||
       o.max_batch > fbst::MAX_LAUNCH_BLOCKS)
-    return sfail(FBST_E_INVALID, "need workspace_bytes > 0, 1 <= streams <= 16, 1 <= max_batch <= 64");
+    return sfail(FBST_E_INVALID, "need workspace_bytes > 0, 1 <= streams <= 16, 1 <= max_batch <= FBST_MAX_LAUNCH_BLOCKS");
   fbst_server* s = new (std::nothrow) fbst_server();
   if (!s) return sfail(FBST_E_NOMEM, "host allocation failed");
   hipError_t e = hipSuccess;

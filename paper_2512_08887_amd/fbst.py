@@ -23,7 +23,7 @@ FBST_LINE, FBST_GRID = 0, 1
 FBST_PREC_FP32, FBST_PREC_FP64_STAGE2, FBST_PREC_FP64, FBST_PREC_BF16_SPLIT, FBST_PREC_FP16_SPLIT = range(5)
 FBST_FLAG_HOST_ONLY, FBST_FLAG_KEEP_HOST_TABLES, FBST_FLAG_NO_SPLIT, FBST_FLAG_PRECOMPUTE = 1, 2, 4, 8
 FBST_TABLE_BEAM_U, FBST_TABLE_BEAM_V, FBST_TABLE_GRAM, FBST_TABLE_GENERATOR = 0, 1, 2, 3
-MAX_LAUNCH_BLOCKS = 64  # blocks per kernel launch (per-block pointer arrays in the kernel arguments)
+MAX_LAUNCH_BLOCKS = 256  # FBST_MAX_LAUNCH_BLOCKS: blocks per kernel launch (pointers in the kernel arguments)
 
 PRECISIONS = {"fp32": FBST_PREC_FP32, "fp64_stage2": FBST_PREC_FP64_STAGE2, "fp64": FBST_PREC_FP64,
               "bf16_split": FBST_PREC_BF16_SPLIT, "fp16_split": FBST_PREC_FP16_SPLIT}

@@ -183,7 +183,7 @@ def test_server_argument_validation():
     h = ctypes.c_void_p()
     bad = [F.fbst_server_options(0, 4, 16, -1), F.fbst_server_options(1 << 20, 0, 16, -1),
            F.fbst_server_options(1 << 20, 17, 16, -1), F.fbst_server_options(1 << 20, 4, 0, -1),
-           F.fbst_server_options(1 << 20, 4, 65, -1)]
+           F.fbst_server_options(1 << 20, 4, F.MAX_LAUNCH_BLOCKS + 1, -1)]
     for o in bad:
         assert lib.fbst_server_create(ctypes.byref(o), ctypes.byref(h)) == F.FBST_E_INVALID
         assert h.value is None
