@@ -18,6 +18,9 @@ direct
 analysis
     The bias and variance expressions of Sec. VII (discrete-time reading) used
     by the Monte-Carlo pins.
+nulling
+    Beamspace interference nulling of Sec. VIII (eq. interfer_beam_space) and
+    the array-space projection it is derived from (explicit matrices).
 
 Pins (tests/test_oracle_*.py, run with ``-m "not gpu"``)
 ------------------------------------------------------
@@ -37,4 +40,4 @@ Readings of the paper that the oracle takes (where it is silent or garbled)
 are listed in the project design notes; each function cites the passage it
 follows.
 """
-from . import direct, analysis  # noqa: F401
+from . import direct, analysis, nulling  # noqa: F401
