@@ -220,6 +220,37 @@ fbst_status fbst_autotune(const fbst_plan* plan, int nblocks, const void* x, voi
                           void* workspace, void* hip_stream, int force, int* best_chunk,
                           float* best_ms);
 
+/* ---- Beamspace interference nulling (Sec. VIII, eq. interfer_beam_space) -- */
+typedef struct fbst_nulls fbst_nulls;
+
+/* Interferers at the plan's own beams beams[0..n_interferers-1] (1..64
+ * indices in [0, B)).  Builds, in float64 on the host, G_{b,q} =
+ * F_b^H F_q (F_q^H F_q + delta I)^{-1} for every beam b and interferer q
+ * (closed-form cross-Gram, Gohberg-Semencul applies of the refined
+ * generator of A_q; about 3e4 B P L^2 log2(L) flops on the host) and uploads
+ * it as complex64: 8 B P L^2 bytes of device memory (at most 16 GiB, else
+ * FBST_E_UNSUPPORTED).  Several interferers are removed as the sum of their
+ * separate projections, as in the paper.  Not for FBST_PREC_FP64 plans
+ * (FBST_E_UNSUPPORTED).  The plan must outlive it. */
+fbst_status fbst_nulls_create(const fbst_plan* plan, int n_interferers, const int* beams,
+                              fbst_nulls** out);
+
+/* Free nulling tables (after their launches finished); NULL is a no-op. */
+void fbst_nulls_destroy(fbst_nulls* nulls);
+
+/* Workspace bytes of fbst_execute_nulled for nblocks blocks per launch
+ * (0 on NULL arguments). */
+size_t fbst_workspace_bytes_nulled(const fbst_plan* plan, const fbst_nulls* nulls, int nblocks);
+
+/* Beams with the interferers nulled: as fbst_execute_batched (x [nblocks][M][N]
+ * complex64 -> beams [nblocks][B][N]), with, between the two stages,
+ *   w~_b = w_b - sum_q G_{b,q} w_q
+ * on the float32 matrix cores, and stage 2 applied to w~.  workspace (required)
+ * holds fbst_workspace_bytes_nulled(plan, nulls, chunk) bytes. */
+fbst_status fbst_execute_nulled(const fbst_plan* plan, const fbst_nulls* nulls, int nblocks,
+                                int max_chunk, const void* x, void* beams, void* workspace,
+                                void* hip_stream);
+
 /* Workspace bytes for nblocks blocks processed in one launch (0 on NULL plan). */
 size_t fbst_workspace_bytes(const fbst_plan* plan, int nblocks);
 

@@ -328,6 +328,46 @@ hipError_t run_contiguous(const fbst_plan* pl, int nb, int chunk, const void* x,
 
 namespace {
 
+// Workspace of one nulled block: the path's own, then the interferers' rows
+// of W and the nulled W, [P][L] and [B][L] complex64.
+size_t nulled_ws_per_block(const fbst_plan* pl, const fbst_nulls* nl) {
+  const fbst::Params& p = pl->p;
+  return align_up(pl->ws_bytes_per_block) + static_cast<size_t>(nl->P + p.B) * p.L * 8;
+}
+
+// Whole path of nb blocks with the interferers nulled in beamspace
+// (eq. interfer_beam_space): after stage 1, the interferers' rows w_q are
+// gathered, w~_b = w_b - sum_q G_{b,q} w_q (one product over the P L stacked
+// rows), and stage 2 runs on w~.
+hipError_t run_blocks_nulled(const fbst_plan* pl, const fbst_nulls* nl, int nb,
+                             const fbst::InPtrs& xs, const fbst::OutPtrs& outs, void* ws,
+                             hipStream_t st) {
+  const fbst::Params& p = pl->p;
+  unsigned char* base = static_cast<unsigned char*>(ws);
+  void* yhat = base;
+  void* w = base + static_cast<size_t>(nb) * p.M * p.L * 8;
+  void* z = static_cast<unsigned char*>(w) + static_cast<size_t>(nb) * p.B * p.L * 8;
+  auto* wq = reinterpret_cast<fbst::c32*>(base + align_up(pl->ws_bytes_per_block * nb));
+  fbst::c32* wt = wq + static_cast<size_t>(nb) * nl->P * p.L;
+  hipError_t e = run_stage0<float>(pl, nb, xs, yhat, st);
+  if (e == hipSuccess) e = run_stage1<float>(pl, nb, yhat, w, z, st);
+  if (e == hipSuccess) e = fbst::launch_gather_rows(w, nl->map, wq, p.B, nl->P, p.L, nb, st);
+  if (e != hipSuccess) return e;
+  fbst::ProductArgs c{};
+  c.K = static_cast<const fbst::c32*>(nl->G);
+  c.in = wq;
+  c.in_rows = 1;
+  c.out = wt;
+  c.base = static_cast<const fbst::c32*>(w);
+  c.NG = p.B;
+  c.KL = nl->P * p.L;
+  c.NO = p.L;
+  c.nb = nb;
+  e = fbst::launch_beam_product(c, st);
+  if (e != hipSuccess) return e;
+  return run_stage2(pl, nb, wt, outs, st);
+}
+
 fbst_status check_exec(const fbst_plan* plan) {
   if (!plan) return fail(FBST_E_INVALID, "plan is NULL");
   if (plan->host_only) return fail(FBST_E_INVALID, "plan was created host-only");
@@ -569,6 +609,100 @@ fbst_status fbst_autotune(const fbst_plan* plan, int nblocks, const void* x, voi
   }
   *best_chunk = best;
   if (best_ms) *best_ms = bms;
+  return FBST_OK;
+}
+
+fbst_status fbst_nulls_create(const fbst_plan* plan, int n_interferers, const int* beams,
+                              fbst_nulls** out) {
+  if (!out) return fail(FBST_E_INVALID, "out is NULL");
+  *out = nullptr;
+  fbst_status s = check_exec(plan);
+  if (s != FBST_OK) return s;
+  const fbst::Params& p = plan->p;
+  if (n_interferers < 1 || n_interferers > 64 || !beams)
+    return fail(FBST_E_INVALID, "need 1..64 interferer beams");
+  if (p.prec == FBST_PREC_FP64)
+    return fail(FBST_E_UNSUPPORTED, "beamspace nulling takes complex64 data (not FBST_PREC_FP64)");
+  std::vector<int> qs(beams, beams + n_interferers);
+  for (int q : qs)
+    if (q < 0 || q >= p.B) return fail(FBST_E_INVALID, "interferer beam index out of range");
+  const double cbytes = 8.0 * n_interferers * p.L * p.B * p.L;   // G
+  if (cbytes > 16.0 * (1ULL << 30))
+    return fail(FBST_E_UNSUPPORTED, "the nulling tables would exceed 16 GiB");
+  std::vector<fbst::zd> G;
+  std::string msg;
+  try {
+    s = fbst::build_null_tables(p, qs, &G, &msg);
+  } catch (const std::bad_alloc&) {
+    s = FBST_E_NOMEM;
+    msg = "host allocation of the nulling tables failed";
+  }
+  if (s != FBST_OK) return fail(s, msg);
+  Upload up;
+  const size_t o_map = 0;
+  up.blob.resize(align_up(sizeof(int) * qs.size()));
+  std::memcpy(up.blob.data(), qs.data(), sizeof(int) * qs.size());
+  const size_t o_g = up.add(G, false);
+  fbst_nulls* nl = new (std::nothrow) fbst_nulls();
+  if (!nl) return fail(FBST_E_NOMEM, "host allocation failed");
+  hipError_t e = hipMalloc(&nl->dev, up.blob.size());
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    delete nl;
+    return fail(FBST_E_NOMEM, "hipMalloc of the nulling tables failed");
+  }
+  e = hipMemcpy(nl->dev, up.blob.data(), up.blob.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(nl->dev);
+    delete nl;
+    return hip_fail(e, "hipMemcpy of the nulling tables");
+  }
+  const unsigned char* b = static_cast<const unsigned char*>(nl->dev);
+  nl->plan = plan;
+  nl->P = n_interferers;
+  nl->map = reinterpret_cast<const int*>(b + o_map);
+  nl->G = b + o_g;
+  nl->dev_bytes = up.blob.size();
+  *out = nl;
+  return FBST_OK;
+}
+
+void fbst_nulls_destroy(fbst_nulls* nulls) {
+  if (!nulls) return;
+  if (nulls->dev) (void)hipFree(nulls->dev);
+  delete nulls;
+}
+
+size_t fbst_workspace_bytes_nulled(const fbst_plan* plan, const fbst_nulls* nulls, int nblocks) {
+  if (!plan || !nulls || nblocks < 1) return 0;
+  return nulled_ws_per_block(plan, nulls) * static_cast<size_t>(nblocks);
+}
+
+fbst_status fbst_execute_nulled(const fbst_plan* plan, const fbst_nulls* nulls, int nblocks,
+                                int max_chunk, const void* x, void* beams, void* workspace,
+                                void* hip_stream) {
+  fbst_status s = check_exec(plan);
+  if (s != FBST_OK) return s;
+  if (!nulls || nulls->plan != plan) return fail(FBST_E_INVALID, "nulls were not made for this plan");
+  if (nblocks < 0) return fail(FBST_E_INVALID, "nblocks must be >= 0");
+  if (nblocks == 0) return FBST_OK;
+  if (!x || !beams || !workspace) return fail(FBST_E_INVALID, "x, beams and workspace are required");
+  int chunk = (max_chunk <= 0 || max_chunk > nblocks) ? nblocks : max_chunk;
+  if (chunk > fbst::MAX_LAUNCH_BLOCKS) chunk = fbst::MAX_LAUNCH_BLOCKS;
+  const fbst::Params& p = plan->p;
+  const size_t in_blk = static_cast<size_t>(p.M) * p.N * 8, out_blk = static_cast<size_t>(p.B) * p.N * 8;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  for (int b0 = 0; b0 < nblocks; b0 += chunk) {
+    const int n = (nblocks - b0 < chunk) ? nblocks - b0 : chunk;
+    fbst::InPtrs xs{};
+    fbst::OutPtrs outs{};
+    for (int i = 0; i < n; ++i) {
+      xs.p[i] = static_cast<const unsigned char*>(x) + (b0 + i) * in_blk;
+      outs.p[i] = static_cast<unsigned char*>(beams) + (b0 + i) * out_blk;
+    }
+    const hipError_t e = run_blocks_nulled(plan, nulls, n, xs, outs, workspace, st);
+    if (e != hipSuccess) return hip_fail(e, "fbst_execute_nulled launch");
+  }
   return FBST_OK;
 }
 

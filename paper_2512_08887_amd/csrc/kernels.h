@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include "../../include/fbst.h"
+#include "cx.h"
 
 namespace fbst {
 
@@ -55,11 +56,33 @@ hipError_t launch_toeplitz_fu(int P, const void* w, const OutPtrs& outs, const v
                               const void* G2, const void* pre3, const void* H3, const void* post3,
                               const void* tw, int B, int L, int N, int nblocks, hipStream_t st);
 
+// Per-group complex product over the blocks of a launch (complex64):
+//   out[blk][g][n] = sum_k K[k][g][n] in[blk][row(g)][k]        (g < NG, n < NO, k < KL)
+// row(g) = in_map[g] (a device array) if given, else 0 when in_rows == 1, else g;
+// the input of block blk is the rows in[blk * in_rows ... ][KL].  The result
+// goes to out [nb][NG][NO] when out is given, else to outs.p[blk] + g NO; with
+// base ([nb][NG][NO]) the stored value is base - product.
+struct ProductArgs {
+  const cx<float>* K = nullptr;
+  const cx<float>* in = nullptr;
+  const int* in_map = nullptr;
+  int in_rows = 1;
+  OutPtrs outs{};
+  cx<float>* out = nullptr;
+  const cx<float>* base = nullptr;
+  int NG = 0, KL = 0, NO = 0, nb = 0;
+};
+hipError_t launch_beam_product(const ProductArgs& a, hipStream_t st);
+
 // Stage 2 in precomputed form: beams_blk[b][n] = sum_l K[l][b][n] w[blk][b][l]
 // (complex64, K = F_u A_b^{-1} per beam stored [L][B][N]) on the float32
 // matrix cores.
 hipError_t launch_precomputed_apply(const void* K, const void* w, const OutPtrs& outs, int B,
                                     int L, int N, int nblocks, hipStream_t st);
+
+// out[blk][q][l] = w[blk][map[q]][l] (complex64; map: P device ints).
+hipError_t launch_gather_rows(const void* w, const int* map, void* out, int B, int P, int L,
+                              int nblocks, hipStream_t st);
 
 // w[j][b][l] = (l == l0 + j) for j < rows (complex64, [rows][B][L]).
 hipError_t launch_unit_rows(void* w, int B, int L, int l0, int rows, hipStream_t st);

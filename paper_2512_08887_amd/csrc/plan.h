@@ -55,6 +55,11 @@ fbst_status resolve_params(int M, int N, int B, const fbst_geometry* geom, const
 // Build every table in float64.  keep_gram_gen: also fill gram/gen.
 fbst_status build_tables(const Params& p, bool keep_gram_gen, HostTables* t, std::string* msg);
 
+// Beamspace nulling table for interferer beams qs (Sec. VIII):
+// G [q L + k][b][n] = (F_b^H F_q A_q^{-1})[n][k], float64.
+fbst_status build_null_tables(const Params& p, const std::vector<int>& qs, std::vector<zd>* G,
+                              std::string* msg);
+
 // Levinson recursion for a Hermitian positive definite Toeplitz matrix with
 // first column col: returns x = A^{-1} e_0.  false if a pivot is not positive.
 bool levinson_first_column(const zd* col, int L, zd* x);
@@ -69,6 +74,18 @@ void set_last_error(const std::string& msg);
 void fft64(zd* a, int n, int sign);
 
 }  // namespace fbst
+
+// Beamspace nulling table of one plan (one device allocation): interferer
+// beam indices [P] (int) and G_{b,q} = F_b^H F_q A_q^{-1} as [P L][B][L]
+// (complex64).
+struct fbst_nulls {
+  const fbst_plan* plan = nullptr;
+  int P = 0;
+  void* dev = nullptr;
+  size_t dev_bytes = 0;
+  const int* map = nullptr;
+  const void* G = nullptr;
+};
 
 // A captured and instantiated launch sequence of one plan.
 struct fbst_graph {

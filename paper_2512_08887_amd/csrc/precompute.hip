@@ -1,3 +1,6 @@
+// Per-beam complex products on the float32 matrix cores: stage 2 in
+// precomputed form and the product of beamspace nulling.
+//
 // Stage 2 in precomputed form (the FBST-Precompute variant, Sec. V and
 // Table I): for a fixed beam set the map from w_b to the beam is the fixed
 // N x L matrix K_b = F_u A_b^{-1}, so a plan may build it once and apply it
@@ -39,51 +42,52 @@ __device__ __forceinline__ int xcd_linear(int nwg) {
   return (x < r) ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
 }
 
-// Workgroup: one beam, PT_N outputs x PT_B blocks, 4 waves as 2 (n) x 2
-// (blocks) for 32 blocks (a wave owns 32 n x 16 blocks, two 16 x 16 tiles) or
-// 4 (n) x 1 for 16 blocks (one tile per wave, twice the workgroups).  Matrix-core
-// operand layouts (16x16x4, float32): A lane l holds A[l % 16][l / 16],
-// B lane l holds B[l / 16][l % 16], accumulator lane l holds
-// D[4 (l / 16) + e][l % 16], e < 4.
-__global__ __launch_bounds__(256) void k_precomputed_apply(const c32* __restrict__ K,
-                                                           const c32* __restrict__ W,
-                                                           const OutPtrs outs, int B, int L,
-                                                           int N, int nb, int n_ntiles,
-                                                           int n_btiles) {
+// out[blk][g][n] = sum_k K[k][g][n] in[blk][row(g)][k] for every output group
+// g < NG (a beam), n < NO, k < KL.  Workgroup: one group, PT_N outputs x PT_B
+// blocks, 4 waves as 2 (n) x 2 (blocks) for 32 blocks (a wave owns 32 n x 16
+// blocks, two 16 x 16 tiles) or 4 (n) x 1 for 16 blocks (one tile per wave,
+// twice the workgroups).  Matrix-core operand layouts (16x16x4, float32):
+// A lane l holds A[l % 16][l / 16], B lane l holds B[l / 16][l % 16],
+// accumulator lane l holds D[4 (l / 16) + e][l % 16], e < 4.
+__global__ __launch_bounds__(256) void k_beam_product(const ProductArgs a, int n_ntiles,
+                                                      int n_btiles) {
   __shared__ c32 As[PT_KC * PT_AS];   // [k][n]
   __shared__ c32 Bs[PT_B * PT_BS];    // [blk][k]
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  // logical order: beam outermost, so the workgroups sharing K_b sit on one XCD
+  const int NG = a.NG, KL = a.KL, NO = a.NO, nb = a.nb;
+  // logical order: group outermost, so the workgroups sharing K_g sit on one XCD
   int w = xcd_linear(gridDim.x);
   const int bt = w % n_btiles;
   w /= n_btiles;
   const int nt = w % n_ntiles;
-  const int b = w / n_ntiles;
+  const int g = w / n_ntiles;
   const int n0 = nt * PT_N, blk0 = bt * PT_B;
+  const int row = a.in_map ? a.in_map[g] : (a.in_rows == 1 ? 0 : g);
 
   // global -> register staging of one chunk: A 64 x 32 (8 per thread),
-  // B 32 x 32 (4 per thread), zero outside [N) x [L) and [nb) x [L)
+  // B PT_B x 32 (PT_B / 8 per thread), zero outside [NO) x [KL) and [nb) x [KL)
   static_assert(PT_B == 16 || PT_B == 32, "block tile of 16 or 32");
-  constexpr int BI = PT_B / 8;                          // B loads per thread
+  constexpr int BI = PT_B / 8;
   const int an = tid % PT_N, ak = tid / PT_N;          // + 4 i
   const int bk = tid % PT_KC, bb = tid / PT_KC;        // + 8 i
-  const bool a_ok = n0 + an < N;
-  const c32* Kb = K + static_cast<size_t>(b) * N + n0 + (a_ok ? an : 0);
+  const bool a_ok = n0 + an < NO;
+  const c32* Kg = a.K + static_cast<size_t>(g) * NO + n0 + (a_ok ? an : 0);
   c32 ra[8], rb[BI];
-  auto load_chunk = [&](int l0) {
+  auto load_chunk = [&](int k0) {
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-      const int l = l0 + ak + 4 * i;
-      const c32 v = Kb[static_cast<size_t>(l < L ? l : L - 1) * B * N];
-      ra[i] = (a_ok && l < L) ? v : c32{0.f, 0.f};
+      const int k = k0 + ak + 4 * i;
+      const c32 v = Kg[static_cast<size_t>(k < KL ? k : KL - 1) * NG * NO];
+      ra[i] = (a_ok && k < KL) ? v : c32{0.f, 0.f};
     }
 #pragma unroll
     for (int i = 0; i < BI; ++i) {
       const int blk = blk0 + bb + 8 * i;
-      const int l = l0 + bk;
-      const bool ok = blk < nb && l < L;
-      const c32 v = W[(static_cast<size_t>(ok ? blk : 0) * B + b) * L + (ok ? l : 0)];
+      const int k = k0 + bk;
+      const bool ok = blk < nb && k < KL;
+      const c32 v =
+          a.in[(static_cast<size_t>(ok ? blk : 0) * a.in_rows + row) * KL + (ok ? k : 0)];
       rb[i] = ok ? v : c32{0.f, 0.f};
     }
     asm volatile("" ::: "memory");   // issue the chunk's loads together
@@ -98,7 +102,7 @@ __global__ __launch_bounds__(256) void k_precomputed_apply(const c32* __restrict
   constexpr int WN = PT_B == 32 ? 2 : 4;               // waves along n
   constexpr int RT = PT_N / (16 * WN);                  // 16-row tiles per wave
   const int wn = wave % WN, wb = wave / WN;
-  const int row = lane & 15, kq = lane >> 4;
+  const int r16 = lane & 15, kq = lane >> 4;
   f32x4 accR[RT], accI[RT];
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt) {
@@ -106,18 +110,18 @@ __global__ __launch_bounds__(256) void k_precomputed_apply(const c32* __restrict
     accI[rt] = f32x4{0.f, 0.f, 0.f, 0.f};
   }
   load_chunk(0);
-  for (int l0 = 0; l0 < L; l0 += PT_KC) {
+  for (int k0 = 0; k0 < KL; k0 += PT_KC) {
     __syncthreads();                 // the previous chunk has been consumed
     store_chunk();
     __syncthreads();
-    if (l0 + PT_KC < L) load_chunk(l0 + PT_KC);   // in flight during the products
+    if (k0 + PT_KC < KL) load_chunk(k0 + PT_KC);   // in flight during the products
 #pragma unroll
     for (int ks = 0; ks < PT_KC / 4; ++ks) {
       const int k = 4 * ks + kq;
-      const c32 bv = Bs[(16 * wb + row) * PT_BS + k];
+      const c32 bv = Bs[(16 * wb + r16) * PT_BS + k];
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt) {
-        const c32 av = As[k * PT_AS + 16 * RT * wn + 16 * rt + row];
+        const c32 av = As[k * PT_AS + 16 * RT * wn + 16 * rt + r16];
         accR[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.re, bv.re, accR[rt], 0, 0, 0);
         accR[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(-av.im, bv.im, accR[rt], 0, 0, 0);
         accI[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.re, bv.im, accI[rt], 0, 0, 0);
@@ -126,15 +130,23 @@ __global__ __launch_bounds__(256) void k_precomputed_apply(const c32* __restrict
     }
   }
   // accumulator lane l: n = n0 + 16 RT wn + 16 rt + 4 (l / 16) + e, block blk0 + 16 wb + l % 16
-  const int blk = blk0 + 16 * wb + row;
+  const int blk = blk0 + 16 * wb + r16;
   if (blk < nb) {
-    c32* dst = static_cast<c32*>(outs.p[blk]) + static_cast<size_t>(b) * N;
+    const size_t o = (static_cast<size_t>(blk) * NG + g) * NO;
+    c32* dst = a.out ? a.out + o : static_cast<c32*>(a.outs.p[blk]) + static_cast<size_t>(g) * NO;
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int n = n0 + 16 * RT * wn + 16 * rt + 4 * kq + e;
-        if (n < N) dst[n] = c32{accR[rt][e], accI[rt][e]};
+        if (n < NO) {
+          c32 v = c32{accR[rt][e], accI[rt][e]};
+          if (a.base) {
+            const c32 bsv = a.base[o + n];
+            v = c32{bsv.re - v.re, bsv.im - v.im};
+          }
+          dst[n] = v;
+        }
       }
   }
 }
@@ -151,19 +163,58 @@ __global__ __launch_bounds__(256) void k_unit_rows(c32* __restrict__ w, int B, i
   w[i] = c32{l == l0 + j ? 1.f : 0.f, 0.f};
 }
 
+// out[blk][q][l] = w[blk][map[q]][l]: the rows of the interferer beams.
+__global__ __launch_bounds__(256) void k_gather_rows(const c32* __restrict__ w,
+                                                     const int* __restrict__ map,
+                                                     c32* __restrict__ out, int B, int P, int L,
+                                                     int nb) {
+  const size_t i = static_cast<size_t>(blockIdx.x) * 256 + threadIdx.x;
+  const size_t total = static_cast<size_t>(nb) * P * L;
+  if (i >= total) return;
+  const int l = static_cast<int>(i % L);
+  const size_t r = i / L;
+  const int q = static_cast<int>(r % P);
+  const size_t blk = r / P;
+  out[i] = w[(blk * B + map[q]) * L + l];
+}
+
 }  // namespace
+
+hipError_t launch_gather_rows(const void* w, const int* map, void* out, int B, int P, int L,
+                              int nblocks, hipStream_t st) {
+  if (nblocks < 1 || B < 1 || P < 1 || L < 1 || !map) return hipErrorInvalidValue;
+  const size_t total = static_cast<size_t>(nblocks) * P * L;
+  const size_t grid = (total + 255) / 256;
+  if (grid > 0x7fffffffULL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_gather_rows, dim3(static_cast<unsigned>(grid)), dim3(256), 0, st,
+                     static_cast<const c32*>(w), map, static_cast<c32*>(out), B, P, L, nblocks);
+  return hipGetLastError();
+}
+
+hipError_t launch_beam_product(const ProductArgs& a, hipStream_t st) {
+  if (a.nb < 1 || a.nb > MAX_LAUNCH_BLOCKS || a.NG < 1 || a.KL < 1 || a.NO < 1 || a.in_rows < 1 ||
+      !a.K || !a.in)
+    return hipErrorInvalidValue;
+  const int n_ntiles = (a.NO + PT_N - 1) / PT_N, n_btiles = (a.nb + PT_B - 1) / PT_B;
+  const long long ng = 1LL * a.NG * n_ntiles * n_btiles;
+  if (ng > 0x7fffffffLL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_beam_product, dim3(static_cast<unsigned>(ng)), dim3(256), 0, st, a,
+                     n_ntiles, n_btiles);
+  return hipGetLastError();
+}
 
 hipError_t launch_precomputed_apply(const void* K, const void* w, const OutPtrs& outs, int B,
                                     int L, int N, int nblocks, hipStream_t st) {
-  if (nblocks < 1 || nblocks > MAX_LAUNCH_BLOCKS || B < 1 || L < 1 || N < 1)
-    return hipErrorInvalidValue;
-  const int n_ntiles = (N + PT_N - 1) / PT_N, n_btiles = (nblocks + PT_B - 1) / PT_B;
-  const long long ng = 1LL * B * n_ntiles * n_btiles;
-  if (ng > 0x7fffffffLL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_precomputed_apply, dim3(static_cast<unsigned>(ng)), dim3(256), 0, st,
-                     static_cast<const c32*>(K), static_cast<const c32*>(w), outs, B, L, N,
-                     nblocks, n_ntiles, n_btiles);
-  return hipGetLastError();
+  ProductArgs a{};
+  a.K = static_cast<const c32*>(K);
+  a.in = static_cast<const c32*>(w);
+  a.in_rows = B;
+  a.outs = outs;
+  a.NG = B;
+  a.KL = L;
+  a.NO = N;
+  a.nb = nblocks;
+  return launch_beam_product(a, st);
 }
 
 hipError_t launch_unit_rows(void* w, int B, int L, int l0, int rows, hipStream_t st) {

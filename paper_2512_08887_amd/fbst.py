@@ -113,6 +113,15 @@ def load_library(path: str = LIB_PATH):
     L.fbst_autotune.argtypes = [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_int,
                                 POINTER(c_int), POINTER(ctypes.c_float)]
     L.fbst_autotune.restype = c_int
+    L.fbst_nulls_create.argtypes = [c_void_p, c_int, POINTER(c_int), POINTER(c_void_p)]
+    L.fbst_nulls_create.restype = c_int
+    L.fbst_nulls_destroy.argtypes = [c_void_p]
+    L.fbst_nulls_destroy.restype = None
+    L.fbst_workspace_bytes_nulled.argtypes = [c_void_p, c_void_p, c_int]
+    L.fbst_workspace_bytes_nulled.restype = c_size_t
+    L.fbst_execute_nulled.argtypes = [c_void_p, c_void_p, c_int, c_int, c_void_p, c_void_p, c_void_p,
+                                      c_void_p]
+    L.fbst_execute_nulled.restype = c_int
     L.fbst_server_create.argtypes = [POINTER(fbst_server_options), POINTER(c_void_p)]
     L.fbst_server_create.restype = c_int
     L.fbst_server_submit.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, ctypes.c_ulonglong]
@@ -235,6 +244,26 @@ def fbst_autotune(plan, nblocks, x, beams, workspace, stream=0, force=False):
     _check(lib().fbst_autotune(plan, nblocks, x, beams, workspace, stream or None, int(force),
                                byref(c), byref(ms)))
     return c.value, ms.value
+
+
+def fbst_nulls_create(plan, beams) -> int:
+    arr = (c_int * len(beams))(*[int(b) for b in beams])
+    h = c_void_p()
+    _check(lib().fbst_nulls_create(plan, len(beams), arr, byref(h)))
+    return h.value
+
+
+def fbst_nulls_destroy(nulls):
+    lib().fbst_nulls_destroy(nulls)
+
+
+def fbst_workspace_bytes_nulled(plan, nulls, nblocks) -> int:
+    return lib().fbst_workspace_bytes_nulled(plan, nulls, nblocks)
+
+
+def fbst_execute_nulled(plan, nulls, nblocks, max_chunk, x, beams, workspace, stream=0):
+    _check(lib().fbst_execute_nulled(plan, nulls, nblocks, max_chunk, x, beams, workspace,
+                                     stream or None))
 
 
 def fbst_server_create(options=None) -> int:
@@ -382,6 +411,49 @@ class Plan:
     def close(self):
         if getattr(self, "handle", None):
             fbst_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Nulls:
+    """Beamspace nulling of interferers at beams of a plan (fbst_nulls_*)."""
+
+    def __init__(self, plan, beams):
+        self.plan = plan
+        self.beams = [int(b) for b in beams]
+        self.handle = fbst_nulls_create(plan.handle, self.beams)
+
+    def workspace(self, nblocks=1):
+        import torch
+        n = fbst_workspace_bytes_nulled(self.plan.handle, self.handle, nblocks)
+        return torch.empty(n, dtype=torch.uint8, device="cuda")
+
+    def execute(self, x, beams=None, workspace=None, max_chunk=0):
+        """x [nblocks, M, N] (or [M, N]) complex64 -> nulled beams of the same leading shape."""
+        import torch
+        p = self.plan
+        single = x.dim() == 2
+        xb = x.unsqueeze(0) if single else x
+        p._check_in(xb, (p.M, p.N))
+        nb = xb.shape[0]
+        chunk = nb if max_chunk <= 0 else min(max_chunk, nb)
+        chunk = min(chunk, MAX_LAUNCH_BLOCKS)
+        if beams is None:
+            beams = torch.empty((nb, p.B, p.N), dtype=torch.complex64, device=x.device)
+        if workspace is None:
+            workspace = self.workspace(chunk)
+        fbst_execute_nulled(p.handle, self.handle, nb, chunk, xb.data_ptr(), beams.data_ptr(),
+                            workspace.data_ptr(), torch.cuda.current_stream().cuda_stream)
+        return beams[0] if single else beams
+
+    def close(self):
+        if getattr(self, "handle", None):
+            fbst_nulls_destroy(self.handle)
             self.handle = None
 
     def __del__(self):
