@@ -238,6 +238,37 @@ def precompute_bench(F, torch, *, steps=10, warmup=2, nblk=1024, chunk=256, log=
     ref = od.beams(x[0].cpu().numpy().astype(np.complex128), p)
     out["accuracy_vs_oracle"] = {k: float(np.linalg.norm(v - ref) / np.linalg.norm(ref))
                                  for k, v in beams.items()}
+
+    # beamspace nulling of interferers at 1 and 4 beams (Sec. VIII), precomputed stage 2
+    from oracle import nulling as on
+    plan = F.plan_for_config(cfg, flags=F.FBST_FLAG_PRECOMPUTE)
+    nul = {}
+    for qs in ([40], [20, 40, 60, 100]):
+        t0 = time.perf_counter()
+        nl = F.Nulls(plan, qs)
+        build_s = time.perf_counter() - t0
+        ws = nl.workspace(chunk)
+        bo = torch.empty((nblk, cfg.B, cfg.N), dtype=torch.complex64, device="cuda")
+        nl.execute(x, beams=bo, workspace=ws, max_chunk=chunk)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(steps):
+            nl.execute(x, beams=bo, workspace=ws, max_chunk=chunk)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        idx = [0, qs[0], 77]
+        refn = on.nulled_beams(x[0].cpu().numpy().astype(np.complex128), p, qs, beam_idx=idx)
+        got = bo[0].cpu().numpy()[idx]
+        nul[f"P={len(qs)}"] = {"value": samples / (ms / 1e3), "unit": "beam-samples/s",
+                               "ms_per_step": ms, "tables_build_s": build_s,
+                               "rel_l2_vs_oracle": float(np.linalg.norm(got - refn) / np.linalg.norm(refn))}
+        log(f"[bench] n64 nulling P={len(qs)}: {ms:.3f} ms per {nblk} blocks, tables {build_s:.2f} s")
+        nl.close()
+    plan.close()
+    out["nulling"] = nul
     return out
 
 
