@@ -235,6 +235,16 @@ typedef struct fbst_nulls fbst_nulls;
 fbst_status fbst_nulls_create(const fbst_plan* plan, int n_interferers, const int* beams,
                               fbst_nulls** out);
 
+/* Interferers at arbitrary directions (u[i], v[i]) (direction cosines; v
+ * NULL or ignored for a line), on or off the beam grid (Sec. VIII: the
+ * interferer need not align with the grid).  As fbst_nulls_create, plus the
+ * projection phases exp(j (2 pi f_c + omega_l) tau_{q,m}) (8 P M L bytes):
+ * each interferer's beam vector w_q = F_q^H y is formed exactly from stage
+ * 1a's output (M L complex products per interferer and block) instead of
+ * being interpolated from neighbouring grid beams. */
+fbst_status fbst_nulls_create_directions(const fbst_plan* plan, int n_interferers, const double* u,
+                                         const double* v, fbst_nulls** out);
+
 /* Free nulling tables (after their launches finished); NULL is a no-op. */
 void fbst_nulls_destroy(fbst_nulls* nulls);
 

@@ -336,9 +336,10 @@ size_t nulled_ws_per_block(const fbst_plan* pl, const fbst_nulls* nl) {
 }
 
 // Whole path of nb blocks with the interferers nulled in beamspace
-// (eq. interfer_beam_space): after stage 1, the interferers' rows w_q are
-// gathered, w~_b = w_b - sum_q G_{b,q} w_q (one product over the P L stacked
-// rows), and stage 2 runs on w~.
+// (eq. interfer_beam_space): after stage 1, the interferers' beam vectors w_q
+// are gathered from W (on-grid) or projected from Yhat (any direction),
+// w~_b = w_b - sum_q G_{b,q} w_q (one product over the P L stacked rows), and
+// stage 2 runs on w~.
 hipError_t run_blocks_nulled(const fbst_plan* pl, const fbst_nulls* nl, int nb,
                              const fbst::InPtrs& xs, const fbst::OutPtrs& outs, void* ws,
                              hipStream_t st) {
@@ -351,7 +352,9 @@ hipError_t run_blocks_nulled(const fbst_plan* pl, const fbst_nulls* nl, int nb,
   fbst::c32* wt = wq + static_cast<size_t>(nb) * nl->P * p.L;
   hipError_t e = run_stage0<float>(pl, nb, xs, yhat, st);
   if (e == hipSuccess) e = run_stage1<float>(pl, nb, yhat, w, z, st);
-  if (e == hipSuccess) e = fbst::launch_gather_rows(w, nl->map, wq, p.B, nl->P, p.L, nb, st);
+  if (e == hipSuccess)
+    e = nl->map ? fbst::launch_gather_rows(w, nl->map, wq, p.B, nl->P, p.L, nb, st)
+                : fbst::launch_project_dirs(yhat, nl->E, wq, p.M, nl->P, p.L, nb, st);
   if (e != hipSuccess) return e;
   fbst::ProductArgs c{};
   c.K = static_cast<const fbst::c32*>(nl->G);
@@ -371,6 +374,70 @@ hipError_t run_blocks_nulled(const fbst_plan* pl, const fbst_nulls* nl, int nb,
 fbst_status check_exec(const fbst_plan* plan) {
   if (!plan) return fail(FBST_E_INVALID, "plan is NULL");
   if (plan->host_only) return fail(FBST_E_INVALID, "plan was created host-only");
+  return FBST_OK;
+}
+
+// Nulling tables for n on-grid interferers (beam indices qs) or for n
+// explicit directions (u, v; qs null).
+fbst_status make_nulls(const fbst_plan* plan, int n, const int* qs, const double* u,
+                       const double* v, fbst_nulls** out) {
+  const fbst::Params& p = plan->p;
+  if (p.prec == FBST_PREC_FP64)
+    return fail(FBST_E_UNSUPPORTED, "beamspace nulling takes complex64 data (not FBST_PREC_FP64)");
+  const double gbytes = 8.0 * n * p.L * p.B * p.L;
+  if (gbytes > 16.0 * (1ULL << 30))
+    return fail(FBST_E_UNSUPPORTED, "the nulling tables would exceed 16 GiB");
+  std::vector<double> uq(n), vq(n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    if (qs) {
+      uq[i] = p.u0 + (qs[i] / p.bv) * p.du;
+      vq[i] = (p.kind == FBST_GRID) ? p.v0 + (qs[i] % p.bv) * p.dv : 0.0;
+    } else {
+      uq[i] = u[i];
+      vq[i] = (v && p.kind == FBST_GRID) ? v[i] : 0.0;
+    }
+  }
+  std::vector<fbst::zd> G, E;
+  std::string msg;
+  fbst_status s;
+  try {
+    s = fbst::build_null_tables(p, uq, vq, &G, qs ? nullptr : &E, &msg);
+  } catch (const std::bad_alloc&) {
+    s = FBST_E_NOMEM;
+    msg = "host allocation of the nulling tables failed";
+  }
+  if (s != FBST_OK) return fail(s, msg);
+  Upload up;
+  size_t o_map = 0, o_e = 0;
+  if (qs) {
+    up.blob.resize(align_up(sizeof(int) * n));
+    std::memcpy(up.blob.data(), qs, sizeof(int) * n);
+  } else {
+    o_e = up.add(E, false);
+  }
+  const size_t o_g = up.add(G, false);
+  fbst_nulls* nl = new (std::nothrow) fbst_nulls();
+  if (!nl) return fail(FBST_E_NOMEM, "host allocation failed");
+  hipError_t e = hipMalloc(&nl->dev, up.blob.size());
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    delete nl;
+    return fail(FBST_E_NOMEM, "hipMalloc of the nulling tables failed");
+  }
+  e = hipMemcpy(nl->dev, up.blob.data(), up.blob.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(nl->dev);
+    delete nl;
+    return hip_fail(e, "hipMemcpy of the nulling tables");
+  }
+  const unsigned char* b = static_cast<const unsigned char*>(nl->dev);
+  nl->plan = plan;
+  nl->P = n;
+  if (qs) nl->map = reinterpret_cast<const int*>(b + o_map);
+  else nl->E = b + o_e;
+  nl->G = b + o_g;
+  nl->dev_bytes = up.blob.size();
+  *out = nl;
   return FBST_OK;
 }
 
@@ -618,53 +685,27 @@ fbst_status fbst_nulls_create(const fbst_plan* plan, int n_interferers, const in
   *out = nullptr;
   fbst_status s = check_exec(plan);
   if (s != FBST_OK) return s;
-  const fbst::Params& p = plan->p;
   if (n_interferers < 1 || n_interferers > 64 || !beams)
     return fail(FBST_E_INVALID, "need 1..64 interferer beams");
-  if (p.prec == FBST_PREC_FP64)
-    return fail(FBST_E_UNSUPPORTED, "beamspace nulling takes complex64 data (not FBST_PREC_FP64)");
+  const fbst::Params& p = plan->p;
   std::vector<int> qs(beams, beams + n_interferers);
   for (int q : qs)
     if (q < 0 || q >= p.B) return fail(FBST_E_INVALID, "interferer beam index out of range");
-  const double cbytes = 8.0 * n_interferers * p.L * p.B * p.L;   // G
-  if (cbytes > 16.0 * (1ULL << 30))
-    return fail(FBST_E_UNSUPPORTED, "the nulling tables would exceed 16 GiB");
-  std::vector<fbst::zd> G;
-  std::string msg;
-  try {
-    s = fbst::build_null_tables(p, qs, &G, &msg);
-  } catch (const std::bad_alloc&) {
-    s = FBST_E_NOMEM;
-    msg = "host allocation of the nulling tables failed";
-  }
-  if (s != FBST_OK) return fail(s, msg);
-  Upload up;
-  const size_t o_map = 0;
-  up.blob.resize(align_up(sizeof(int) * qs.size()));
-  std::memcpy(up.blob.data(), qs.data(), sizeof(int) * qs.size());
-  const size_t o_g = up.add(G, false);
-  fbst_nulls* nl = new (std::nothrow) fbst_nulls();
-  if (!nl) return fail(FBST_E_NOMEM, "host allocation failed");
-  hipError_t e = hipMalloc(&nl->dev, up.blob.size());
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    delete nl;
-    return fail(FBST_E_NOMEM, "hipMalloc of the nulling tables failed");
-  }
-  e = hipMemcpy(nl->dev, up.blob.data(), up.blob.size(), hipMemcpyHostToDevice);
-  if (e != hipSuccess) {
-    (void)hipFree(nl->dev);
-    delete nl;
-    return hip_fail(e, "hipMemcpy of the nulling tables");
-  }
-  const unsigned char* b = static_cast<const unsigned char*>(nl->dev);
-  nl->plan = plan;
-  nl->P = n_interferers;
-  nl->map = reinterpret_cast<const int*>(b + o_map);
-  nl->G = b + o_g;
-  nl->dev_bytes = up.blob.size();
-  *out = nl;
-  return FBST_OK;
+  return make_nulls(plan, n_interferers, qs.data(), nullptr, nullptr, out);
+}
+
+fbst_status fbst_nulls_create_directions(const fbst_plan* plan, int n_interferers, const double* u,
+                                         const double* v, fbst_nulls** out) {
+  if (!out) return fail(FBST_E_INVALID, "out is NULL");
+  *out = nullptr;
+  fbst_status s = check_exec(plan);
+  if (s != FBST_OK) return s;
+  if (n_interferers < 1 || n_interferers > 64 || !u)
+    return fail(FBST_E_INVALID, "need 1..64 interferer directions");
+  for (int i = 0; i < n_interferers; ++i)
+    if (!std::isfinite(u[i]) || (v && !std::isfinite(v[i])))
+      return fail(FBST_E_INVALID, "interferer directions must be finite");
+  return make_nulls(plan, n_interferers, nullptr, u, v, out);
 }
 
 void fbst_nulls_destroy(fbst_nulls* nulls) {

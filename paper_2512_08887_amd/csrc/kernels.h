@@ -84,6 +84,11 @@ hipError_t launch_precomputed_apply(const void* K, const void* w, const OutPtrs&
 hipError_t launch_gather_rows(const void* w, const int* map, void* out, int B, int P, int L,
                               int nblocks, hipStream_t st);
 
+// out[blk][q][l] = sum_m yhat[blk][m][l] E[q][m][l] (complex64; yhat [nb][M][L],
+// E [P][M][L]).
+hipError_t launch_project_dirs(const void* yhat, const void* E, void* out, int M, int P, int L,
+                               int nblocks, hipStream_t st);
+
 // w[j][b][l] = (l == l0 + j) for j < rows (complex64, [rows][B][L]).
 hipError_t launch_unit_rows(void* w, int B, int L, int l0, int rows, hipStream_t st);
 

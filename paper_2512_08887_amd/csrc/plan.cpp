@@ -596,16 +596,18 @@ fbst_status build_tables(const Params& p, bool keep_gram_gen, HostTables* t, std
 
 // --- beamspace nulling tables (Sec. VIII, eq. interfer_beam_space) ------------
 // G [q L + k][b][n] = (G_{b,q})[n][k] with G_{b,q} = F_b^H F_q A_q^{-1}, for the
-// interferer beams qs and every beam b of the grid of p.  F_b^H F_q is the
+// interferer directions (uq, vq) (on or off the grid) and every beam b of the
+// grid of p.  F_b^H F_q is the
 // product of a time sum and a sensor sum (closed forms); row n of G_{b,q} is
 // conj(A_q^{-1} conj(row n of F_b^H F_q)) (A_q Hermitian), applied with the
 // Gohberg-Semencul form of the refined generator of A_q, all in float64.
 // G maps w_q to the part of w_b that interferer q's fit contributes; its
 // entries are O(1) (for b = q, G = I - delta A_q^{-1}), so storing it in
 // float32 costs only float32 rounding of the data.
-fbst_status build_null_tables(const Params& p, const std::vector<int>& qs, std::vector<zd>* G,
-                              std::string* msg) {
-  const int L = p.L, N = p.N, B = p.B, P = static_cast<int>(qs.size());
+fbst_status build_null_tables(const Params& p, const std::vector<double>& uq,
+                              const std::vector<double>& vq, std::vector<zd>* G,
+                              std::vector<zd>* E, std::string* msg) {
+  const int L = p.L, N = p.N, B = p.B, P = static_cast<int>(uq.size());
   const int PG = next_pow2(2LL * L);
   const double lp0 = 1.0 - 0.5 * L;
   const double kap = 2.0 * kPi * p.eps / L;                     // rad per sample per unit l'
@@ -615,13 +617,14 @@ fbst_status build_null_tables(const Params& p, const std::vector<int>& qs, std::
   // time factor sum_n exp(-j kappa d n), d = l - k in (-L, L)
   std::vector<zd> tf(2 * L - 1);
   for (int d = -(L - 1); d <= L - 1; ++d) tf[d + L - 1] = geometric_sum(N, 0.0, -kap * d);
-  // sensor factor sum_m exp(j (a_n tau_{b,m} - a_k tau_{q,m})), tau in samples,
-  // a_l = 2 pi (f_c T_s) + kappa l' (rad per sample of delay), separable per axis
-  auto sensor = [&](double an, double ak, int b, int q) {
-    const double thx = (an * beam_u(b) - ak * beam_u(q)) * dxs;
+  // sensor factor sum_m exp(j (a_n tau_{b,m} - a_k tau_{q,m})) between direction
+  // (ub, vb) and (uq, vq), tau in samples, a_l = 2 pi (f_c T_s) + kappa l'
+  // (rad per sample of delay), separable per axis
+  auto sensor2 = [&](double an, double ak, double ub, double vb, double u2, double v2) {
+    const double thx = (an * ub - ak * u2) * dxs;
     zd s = geometric_sum(p.mx, thx * p.x0, thx);
     if (p.kind == FBST_GRID) {
-      const double thy = (an * beam_v(b) - ak * beam_v(q)) * dys;
+      const double thy = (an * vb - ak * v2) * dys;
       s *= geometric_sum(p.my, thy * p.y0, thy);
     }
     return s;
@@ -630,10 +633,10 @@ fbst_status build_null_tables(const Params& p, const std::vector<int>& qs, std::
   // generators x_q = A_q^{-1} e_0 of A_q = F_q^H F_q + delta I (Sec. V), refined
   std::vector<std::vector<zd>> xq(P);
   for (int qi = 0; qi < P; ++qi) {
-    const int q = qs[qi];
     std::vector<zd> col(L);
     xq[qi].resize(L);
-    for (int d = 0; d < L; ++d) col[d] = tf[d + L - 1] * sensor(a_of(d), a_of(0), q, q);
+    for (int d = 0; d < L; ++d)
+      col[d] = tf[d + L - 1] * sensor2(a_of(d), a_of(0), uq[qi], vq[qi], uq[qi], vq[qi]);
     col[0] += p.delta;
     if (!levinson_first_column(col.data(), L, xq[qi].data())) {
       *msg = "interferer Toeplitz system not positive definite in float64";
@@ -649,12 +652,27 @@ fbst_status build_null_tables(const Params& p, const std::vector<int>& qs, std::
         for (int n = 0; n < L; ++n) {
           const double an = a_of(n);
           for (int k = 0; k < L; ++k)
-            row[k] = std::conj(tf[n - k + L - 1] * sensor(an, a_of(k), b, qs[qi]));
+            row[k] = std::conj(tf[n - k + L - 1] *
+                               sensor2(an, a_of(k), beam_u(b), beam_v(b), uq[qi], vq[qi]));
           gs_apply(xq[qi], row, L, PG, &g);
           for (int k = 0; k < L; ++k)
             (*G)[((static_cast<size_t>(qi) * L + k) * B + b) * L + n] = std::conj(g[k]);
         }
   });
+  // projection phases of the interferer directions, E [q][m][l] = exp(j a_l tau_{q,m}),
+  // m = k * my + k2 (so that w_q[l] = sum_m Yhat[m][l] E[q][m][l], Sec. IV)
+  if (E) {
+    const int M = p.M;
+    E->assign(static_cast<size_t>(P) * M * L, zd());
+    for (int qi = 0; qi < P; ++qi)
+      for (int m = 0; m < M; ++m) {
+        const int k1 = (p.kind == FBST_GRID) ? m / p.my : m, k2 = (p.kind == FBST_GRID) ? m % p.my : 0;
+        const double tau = uq[qi] * dxs * (p.x0 + k1) +
+                           ((p.kind == FBST_GRID) ? vq[qi] * dys * (p.y0 + k2) : 0.0);
+        for (int l = 0; l < L; ++l)
+          (*E)[(static_cast<size_t>(qi) * M + m) * L + l] = cis(a_of(l) * tau);
+      }
+  }
   return FBST_OK;
 }
 

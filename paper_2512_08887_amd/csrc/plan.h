@@ -55,10 +55,12 @@ fbst_status resolve_params(int M, int N, int B, const fbst_geometry* geom, const
 // Build every table in float64.  keep_gram_gen: also fill gram/gen.
 fbst_status build_tables(const Params& p, bool keep_gram_gen, HostTables* t, std::string* msg);
 
-// Beamspace nulling table for interferer beams qs (Sec. VIII):
-// G [q L + k][b][n] = (F_b^H F_q A_q^{-1})[n][k], float64.
-fbst_status build_null_tables(const Params& p, const std::vector<int>& qs, std::vector<zd>* G,
-                              std::string* msg);
+// Beamspace nulling tables for interferer directions (uq, vq) (Sec. VIII):
+// G [q L + k][b][n] = (F_b^H F_q A_q^{-1})[n][k] and, when E is given, the
+// projection phases E [q][m][l] = exp(j a_l tau_{q,m}); float64.
+fbst_status build_null_tables(const Params& p, const std::vector<double>& uq,
+                              const std::vector<double>& vq, std::vector<zd>* G,
+                              std::vector<zd>* E, std::string* msg);
 
 // Levinson recursion for a Hermitian positive definite Toeplitz matrix with
 // first column col: returns x = A^{-1} e_0.  false if a pivot is not positive.
@@ -75,15 +77,18 @@ void fft64(zd* a, int n, int sign);
 
 }  // namespace fbst
 
-// Beamspace nulling table of one plan (one device allocation): interferer
-// beam indices [P] (int) and G_{b,q} = F_b^H F_q A_q^{-1} as [P L][B][L]
-// (complex64).
+// Beamspace nulling tables of one plan (one device allocation):
+// G_{b,q} = F_b^H F_q A_q^{-1} as [P L][B][L] (complex64), and either the
+// interferer beam indices [P] (int, on-grid interferers: their rows of W are
+// gathered) or the projection phases E [P][M][L] (complex64, any direction:
+// their beam vectors are projected from stage 1a's output).
 struct fbst_nulls {
   const fbst_plan* plan = nullptr;
   int P = 0;
   void* dev = nullptr;
   size_t dev_bytes = 0;
   const int* map = nullptr;
+  const void* E = nullptr;
   const void* G = nullptr;
 };
 

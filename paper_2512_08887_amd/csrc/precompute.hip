@@ -178,7 +178,46 @@ __global__ __launch_bounds__(256) void k_gather_rows(const c32* __restrict__ w,
   out[i] = w[(blk * B + map[q]) * L + l];
 }
 
+// out[blk][q][l] = sum_m yhat[blk][m][l] E[q][m][l]: the beam vectors of
+// arbitrary directions from stage 1a's output (the sum over sensors of
+// eq. DFT_1 written out; M terms per output, float32 accumulation).
+__global__ __launch_bounds__(256) void k_project_dirs(const c32* __restrict__ yhat,
+                                                      const c32* __restrict__ E,
+                                                      c32* __restrict__ out, int M, int P, int L,
+                                                      int nb) {
+  const size_t i = static_cast<size_t>(blockIdx.x) * 256 + threadIdx.x;
+  const size_t total = static_cast<size_t>(nb) * P * L;
+  if (i >= total) return;
+  const int l = static_cast<int>(i % L);
+  const size_t r = i / L;
+  const int q = static_cast<int>(r % P);
+  const size_t blk = r / P;
+  const c32* y = yhat + blk * M * L + l;
+  const c32* e = E + static_cast<size_t>(q) * M * L + l;
+  float re = 0.f, im = 0.f;
+  for (int m = 0; m < M; ++m) {
+    const c32 a = y[static_cast<size_t>(m) * L], b = e[static_cast<size_t>(m) * L];
+    re = fmaf(a.re, b.re, re);
+    re = fmaf(-a.im, b.im, re);
+    im = fmaf(a.re, b.im, im);
+    im = fmaf(a.im, b.re, im);
+  }
+  out[i] = c32{re, im};
+}
+
 }  // namespace
+
+hipError_t launch_project_dirs(const void* yhat, const void* E, void* out, int M, int P, int L,
+                               int nblocks, hipStream_t st) {
+  if (nblocks < 1 || M < 1 || P < 1 || L < 1 || !E) return hipErrorInvalidValue;
+  const size_t total = static_cast<size_t>(nblocks) * P * L;
+  const size_t grid = (total + 255) / 256;
+  if (grid > 0x7fffffffULL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_project_dirs, dim3(static_cast<unsigned>(grid)), dim3(256), 0, st,
+                     static_cast<const c32*>(yhat), static_cast<const c32*>(E),
+                     static_cast<c32*>(out), M, P, L, nblocks);
+  return hipGetLastError();
+}
 
 hipError_t launch_gather_rows(const void* w, const int* map, void* out, int B, int P, int L,
                               int nblocks, hipStream_t st) {

@@ -115,6 +115,9 @@ def load_library(path: str = LIB_PATH):
     L.fbst_autotune.restype = c_int
     L.fbst_nulls_create.argtypes = [c_void_p, c_int, POINTER(c_int), POINTER(c_void_p)]
     L.fbst_nulls_create.restype = c_int
+    L.fbst_nulls_create_directions.argtypes = [c_void_p, c_int, POINTER(ctypes.c_double),
+                                               POINTER(ctypes.c_double), POINTER(c_void_p)]
+    L.fbst_nulls_create_directions.restype = c_int
     L.fbst_nulls_destroy.argtypes = [c_void_p]
     L.fbst_nulls_destroy.restype = None
     L.fbst_workspace_bytes_nulled.argtypes = [c_void_p, c_void_p, c_int]
@@ -250,6 +253,15 @@ def fbst_nulls_create(plan, beams) -> int:
     arr = (c_int * len(beams))(*[int(b) for b in beams])
     h = c_void_p()
     _check(lib().fbst_nulls_create(plan, len(beams), arr, byref(h)))
+    return h.value
+
+
+def fbst_nulls_create_directions(plan, u, v=None) -> int:
+    n = len(u)
+    ua = (ctypes.c_double * n)(*[float(a) for a in u])
+    va = (ctypes.c_double * n)(*[float(a) for a in v]) if v is not None else None
+    h = c_void_p()
+    _check(lib().fbst_nulls_create_directions(plan, n, ua, va, byref(h)))
     return h.value
 
 
@@ -423,10 +435,16 @@ class Plan:
 class Nulls:
     """Beamspace nulling of interferers at beams of a plan (fbst_nulls_*)."""
 
-    def __init__(self, plan, beams):
+    def __init__(self, plan, beams=None, *, u=None, v=None):
+        """Interferers at beams of the plan's grid, or at directions u (and v)."""
         self.plan = plan
-        self.beams = [int(b) for b in beams]
-        self.handle = fbst_nulls_create(plan.handle, self.beams)
+        if beams is not None:
+            self.beams = [int(b) for b in beams]
+            self.handle = fbst_nulls_create(plan.handle, self.beams)
+        else:
+            self.beams = None
+            self.handle = fbst_nulls_create_directions(plan.handle, list(u),
+                                                       None if v is None else list(v))
 
     def workspace(self, nblocks=1):
         import torch
