@@ -261,6 +261,37 @@ fbst_status fbst_execute_nulled(const fbst_plan* plan, const fbst_nulls* nulls, 
                                 int max_chunk, const void* x, void* beams, void* workspace,
                                 void* hip_stream);
 
+/* ---- Beams at arbitrary directions (Sec. VIII, off-grid angles) ----------- */
+typedef struct fbst_directions fbst_directions;
+
+/* Beams at directions (u[i], v[i]) (direction cosines; v NULL or ignored for a
+ * line), on or off the plan's grid.  Builds in float64 on the host, per
+ * direction d, K_d = F_u (F_d^H F_d + delta I)^{-1} (N x L, Gohberg-Semencul
+ * applies of the refined generator) and the projection phases of F_d^H, and
+ * uploads them as complex64: 8 D L (N + M) bytes (at most 16 GiB).  The
+ * paper interpolates off-grid beams from neighbouring grid beams with a
+ * spline; here they are formed exactly (the regularised least-squares beam of
+ * that direction) at a cost of M L + N L complex products per direction and
+ * block.  Not for FBST_PREC_FP64 plans (FBST_E_UNSUPPORTED).  The plan must
+ * outlive it. */
+fbst_status fbst_directions_create(const fbst_plan* plan, int n_directions, const double* u,
+                                   const double* v, fbst_directions** out);
+
+/* Free direction tables (after their launches finished); NULL is a no-op. */
+void fbst_directions_destroy(fbst_directions* dirs);
+
+/* Workspace bytes of fbst_execute_directions for nblocks blocks per launch. */
+size_t fbst_workspace_bytes_directions(const fbst_plan* plan, const fbst_directions* dirs,
+                                       int nblocks);
+
+/* x [nblocks][M][N] complex64 -> beams [nblocks][D][N] at the directions:
+ * stage 1a, w_d[l] = sum_m Yhat[m][l] exp(j (2 pi f_c + omega_l) tau_{d,m}),
+ * and b_d = K_d w_d on the float32 matrix cores, chunk = min(nblocks,
+ * max_chunk, FBST_MAX_LAUNCH_BLOCKS) blocks per launch; workspace required. */
+fbst_status fbst_execute_directions(const fbst_plan* plan, const fbst_directions* dirs,
+                                    int nblocks, int max_chunk, const void* x, void* beams,
+                                    void* workspace, void* hip_stream);
+
 /* Workspace bytes for nblocks blocks processed in one launch (0 on NULL plan). */
 size_t fbst_workspace_bytes(const fbst_plan* plan, int nblocks);
 

@@ -377,6 +377,35 @@ fbst_status check_exec(const fbst_plan* plan) {
   return FBST_OK;
 }
 
+// Beams at the directions of dr for nb blocks: stage 1a, the projection of
+// each direction's beam vector from Yhat, and b_d = K_d w_d on the matrix
+// cores (outputs [nb][D][N] at out).
+hipError_t run_blocks_directions(const fbst_plan* pl, const fbst_directions* dr, int nb,
+                                 const fbst::InPtrs& xs, void* out, void* ws, hipStream_t st) {
+  const fbst::Params& p = pl->p;
+  unsigned char* base = static_cast<unsigned char*>(ws);
+  void* yhat = base;
+  auto* wd = reinterpret_cast<fbst::c32*>(base + align_up(static_cast<size_t>(nb) * p.M * p.L * 8));
+  hipError_t e = run_stage0<float>(pl, nb, xs, yhat, st);
+  if (e == hipSuccess) e = fbst::launch_project_dirs(yhat, dr->E, wd, p.M, dr->D, p.L, nb, st);
+  if (e != hipSuccess) return e;
+  fbst::ProductArgs a{};
+  a.K = static_cast<const fbst::c32*>(dr->K);
+  a.in = wd;
+  a.in_rows = dr->D;
+  a.out = static_cast<fbst::c32*>(out);
+  a.NG = dr->D;
+  a.KL = p.L;
+  a.NO = p.N;
+  a.nb = nb;
+  return fbst::launch_beam_product(a, st);
+}
+
+size_t directions_ws_per_block(const fbst_plan* pl, const fbst_directions* dr) {
+  const fbst::Params& p = pl->p;
+  return align_up(static_cast<size_t>(p.M) * p.L * 8) + static_cast<size_t>(dr->D) * p.L * 8;
+}
+
 // Nulling tables for n on-grid interferers (beam indices qs) or for n
 // explicit directions (u, v; qs null).
 fbst_status make_nulls(const fbst_plan* plan, int n, const int* qs, const double* u,
@@ -706,6 +735,99 @@ fbst_status fbst_nulls_create_directions(const fbst_plan* plan, int n_interferer
     if (!std::isfinite(u[i]) || (v && !std::isfinite(v[i])))
       return fail(FBST_E_INVALID, "interferer directions must be finite");
   return make_nulls(plan, n_interferers, nullptr, u, v, out);
+}
+
+fbst_status fbst_directions_create(const fbst_plan* plan, int n_directions, const double* u,
+                                   const double* v, fbst_directions** out) {
+  if (!out) return fail(FBST_E_INVALID, "out is NULL");
+  *out = nullptr;
+  fbst_status s = check_exec(plan);
+  if (s != FBST_OK) return s;
+  const fbst::Params& p = plan->p;
+  if (n_directions < 1 || n_directions > 65536 || !u)
+    return fail(FBST_E_INVALID, "need 1..65536 directions");
+  if (p.prec == FBST_PREC_FP64)
+    return fail(FBST_E_UNSUPPORTED, "beams at directions take complex64 data (not FBST_PREC_FP64)");
+  std::vector<double> ud(u, u + n_directions), vd(n_directions, 0.0);
+  for (int i = 0; i < n_directions; ++i) {
+    if (v && p.kind == FBST_GRID) vd[i] = v[i];
+    if (!std::isfinite(ud[i]) || !std::isfinite(vd[i]))
+      return fail(FBST_E_INVALID, "directions must be finite");
+  }
+  if (8.0 * n_directions * p.L * (static_cast<double>(p.N) + p.M) > 16.0 * (1ULL << 30))
+    return fail(FBST_E_UNSUPPORTED, "the direction tables would exceed 16 GiB");
+  std::vector<fbst::zd> K, E;
+  std::string msg;
+  try {
+    s = fbst::build_direction_tables(p, ud, vd, &K, &E, &msg);
+  } catch (const std::bad_alloc&) {
+    s = FBST_E_NOMEM;
+    msg = "host allocation of the direction tables failed";
+  }
+  if (s != FBST_OK) return fail(s, msg);
+  Upload up;
+  const size_t o_e = up.add(E, false), o_k = up.add(K, false);
+  fbst_directions* dr = new (std::nothrow) fbst_directions();
+  if (!dr) return fail(FBST_E_NOMEM, "host allocation failed");
+  hipError_t e = hipMalloc(&dr->dev, up.blob.size());
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    delete dr;
+    return fail(FBST_E_NOMEM, "hipMalloc of the direction tables failed");
+  }
+  e = hipMemcpy(dr->dev, up.blob.data(), up.blob.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(dr->dev);
+    delete dr;
+    return hip_fail(e, "hipMemcpy of the direction tables");
+  }
+  const unsigned char* b = static_cast<const unsigned char*>(dr->dev);
+  dr->plan = plan;
+  dr->D = n_directions;
+  dr->E = b + o_e;
+  dr->K = b + o_k;
+  dr->dev_bytes = up.blob.size();
+  *out = dr;
+  return FBST_OK;
+}
+
+void fbst_directions_destroy(fbst_directions* dirs) {
+  if (!dirs) return;
+  if (dirs->dev) (void)hipFree(dirs->dev);
+  delete dirs;
+}
+
+size_t fbst_workspace_bytes_directions(const fbst_plan* plan, const fbst_directions* dirs,
+                                       int nblocks) {
+  if (!plan || !dirs || nblocks < 1) return 0;
+  return directions_ws_per_block(plan, dirs) * static_cast<size_t>(nblocks);
+}
+
+fbst_status fbst_execute_directions(const fbst_plan* plan, const fbst_directions* dirs,
+                                    int nblocks, int max_chunk, const void* x, void* beams,
+                                    void* workspace, void* hip_stream) {
+  fbst_status s = check_exec(plan);
+  if (s != FBST_OK) return s;
+  if (!dirs || dirs->plan != plan) return fail(FBST_E_INVALID, "directions were not made for this plan");
+  if (nblocks < 0) return fail(FBST_E_INVALID, "nblocks must be >= 0");
+  if (nblocks == 0) return FBST_OK;
+  if (!x || !beams || !workspace) return fail(FBST_E_INVALID, "x, beams and workspace are required");
+  int chunk = (max_chunk <= 0 || max_chunk > nblocks) ? nblocks : max_chunk;
+  if (chunk > fbst::MAX_LAUNCH_BLOCKS) chunk = fbst::MAX_LAUNCH_BLOCKS;
+  const fbst::Params& p = plan->p;
+  const size_t in_blk = static_cast<size_t>(p.M) * p.N * 8;
+  const size_t out_blk = static_cast<size_t>(dirs->D) * p.N * 8;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  for (int b0 = 0; b0 < nblocks; b0 += chunk) {
+    const int n = (nblocks - b0 < chunk) ? nblocks - b0 : chunk;
+    fbst::InPtrs xs{};
+    for (int i = 0; i < n; ++i) xs.p[i] = static_cast<const unsigned char*>(x) + (b0 + i) * in_blk;
+    const hipError_t e = run_blocks_directions(plan, dirs, n, xs,
+                                               static_cast<unsigned char*>(beams) + b0 * out_blk,
+                                               workspace, st);
+    if (e != hipSuccess) return hip_fail(e, "fbst_execute_directions launch");
+  }
+  return FBST_OK;
 }
 
 void fbst_nulls_destroy(fbst_nulls* nulls) {

@@ -594,6 +594,57 @@ fbst_status build_tables(const Params& p, bool keep_gram_gen, HostTables* t, std
   return FBST_OK;
 }
 
+// --- beams at arbitrary directions (Sec. VIII, off-grid angles) ---------------
+// For directions (ud, vd): K [l][d][n] = (F_u A_d^{-1})[n][l] (row n of
+// F_u A_d^{-1} is conj(A_d^{-1} conj(row n of F_u)), A_d Hermitian; applied with
+// the Gohberg-Semencul form of the refined generator of A_d), and the
+// projection phases E [d][m][l] = exp(j a_l tau_{d,m}); float64.
+fbst_status build_direction_tables(const Params& p, const std::vector<double>& ud,
+                                   const std::vector<double>& vd, std::vector<zd>* K,
+                                   std::vector<zd>* E, std::string* msg) {
+  const int L = p.L, N = p.N, M = p.M, D = static_cast<int>(ud.size());
+  const int PG = next_pow2(2LL * L);
+  const double lp0 = 1.0 - 0.5 * L;
+  const double kap = 2.0 * kPi * p.eps / L;
+  const double dxs = p.dx / p.ts, dys = p.dy / p.ts;
+  auto a_of = [&](int l) { return 2.0 * kPi * p.fc * p.ts + kap * (l + lp0); };
+  K->assign(static_cast<size_t>(L) * D * N, zd());
+  E->assign(static_cast<size_t>(D) * M * L, zd());
+  for (int di = 0; di < D; ++di) {
+    // A_d = F_d^H F_d + delta I: c(d) = [sum_n e^{-j kappa d n}][sum_m e^{j kappa d tau_m}] + delta
+    std::vector<zd> col(L), x(L);
+    for (int d = 0; d < L; ++d) {
+      const double kd = kap * d;
+      zd c = geometric_sum(N, 0.0, -kd) * geometric_sum(p.mx, kd * ud[di] * dxs * p.x0,
+                                                        kd * ud[di] * dxs);
+      if (p.kind == FBST_GRID) c *= geometric_sum(p.my, kd * vd[di] * dys * p.y0, kd * vd[di] * dys);
+      col[d] = c;
+    }
+    col[0] += p.delta;
+    if (!levinson_first_column(col.data(), L, x.data())) {
+      *msg = "direction Toeplitz system not positive definite in float64";
+      return FBST_E_INVALID;
+    }
+    refine_generator(col.data(), L, PG, &x);
+    parallel_for(N, 1LL * N * PG * 40, [&](int n0, int n1) {
+      std::vector<zd> row(L), g;
+      for (int n = n0; n < n1; ++n) {
+        // row n of F_u: exp(j omega_l t_n), omega_l t_n = kappa l' n (eq. bhatls)
+        for (int l = 0; l < L; ++l) row[l] = std::conj(cis(kap * (l + lp0) * n));
+        gs_apply(x, row, L, PG, &g);
+        for (int l = 0; l < L; ++l) (*K)[(static_cast<size_t>(l) * D + di) * N + n] = std::conj(g[l]);
+      }
+    });
+    for (int m = 0; m < M; ++m) {
+      const int k1 = (p.kind == FBST_GRID) ? m / p.my : m, k2 = (p.kind == FBST_GRID) ? m % p.my : 0;
+      const double tau = ud[di] * dxs * (p.x0 + k1) +
+                         ((p.kind == FBST_GRID) ? vd[di] * dys * (p.y0 + k2) : 0.0);
+      for (int l = 0; l < L; ++l) (*E)[(static_cast<size_t>(di) * M + m) * L + l] = cis(a_of(l) * tau);
+    }
+  }
+  return FBST_OK;
+}
+
 // --- beamspace nulling tables (Sec. VIII, eq. interfer_beam_space) ------------
 // G [q L + k][b][n] = (G_{b,q})[n][k] with G_{b,q} = F_b^H F_q A_q^{-1}, for the
 // interferer directions (uq, vq) (on or off the grid) and every beam b of the

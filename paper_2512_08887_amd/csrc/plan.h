@@ -55,6 +55,12 @@ fbst_status resolve_params(int M, int N, int B, const fbst_geometry* geom, const
 // Build every table in float64.  keep_gram_gen: also fill gram/gen.
 fbst_status build_tables(const Params& p, bool keep_gram_gen, HostTables* t, std::string* msg);
 
+// Beams at directions (ud, vd): K [l][d][n] = (F_u A_d^{-1})[n][l] and the
+// projection phases E [d][m][l] = exp(j a_l tau_{d,m}); float64.
+fbst_status build_direction_tables(const Params& p, const std::vector<double>& ud,
+                                   const std::vector<double>& vd, std::vector<zd>* K,
+                                   std::vector<zd>* E, std::string* msg);
+
 // Beamspace nulling tables for interferer directions (uq, vq) (Sec. VIII):
 // G [q L + k][b][n] = (F_b^H F_q A_q^{-1})[n][k] and, when E is given, the
 // projection phases E [q][m][l] = exp(j a_l tau_{q,m}); float64.
@@ -90,6 +96,17 @@ struct fbst_nulls {
   const int* map = nullptr;
   const void* E = nullptr;
   const void* G = nullptr;
+};
+
+// Beams at arbitrary directions of one plan (one device allocation): the
+// projection phases E [D][M][L] and K_d = F_u A_d^{-1} as [L][D][N] (complex64).
+struct fbst_directions {
+  const fbst_plan* plan = nullptr;
+  int D = 0;
+  void* dev = nullptr;
+  size_t dev_bytes = 0;
+  const void* E = nullptr;
+  const void* K = nullptr;
 };
 
 // A captured and instantiated launch sequence of one plan.

@@ -118,6 +118,16 @@ def load_library(path: str = LIB_PATH):
     L.fbst_nulls_create_directions.argtypes = [c_void_p, c_int, POINTER(ctypes.c_double),
                                                POINTER(ctypes.c_double), POINTER(c_void_p)]
     L.fbst_nulls_create_directions.restype = c_int
+    L.fbst_directions_create.argtypes = [c_void_p, c_int, POINTER(ctypes.c_double),
+                                         POINTER(ctypes.c_double), POINTER(c_void_p)]
+    L.fbst_directions_create.restype = c_int
+    L.fbst_directions_destroy.argtypes = [c_void_p]
+    L.fbst_directions_destroy.restype = None
+    L.fbst_workspace_bytes_directions.argtypes = [c_void_p, c_void_p, c_int]
+    L.fbst_workspace_bytes_directions.restype = c_size_t
+    L.fbst_execute_directions.argtypes = [c_void_p, c_void_p, c_int, c_int, c_void_p, c_void_p,
+                                          c_void_p, c_void_p]
+    L.fbst_execute_directions.restype = c_int
     L.fbst_nulls_destroy.argtypes = [c_void_p]
     L.fbst_nulls_destroy.restype = None
     L.fbst_workspace_bytes_nulled.argtypes = [c_void_p, c_void_p, c_int]
@@ -263,6 +273,28 @@ def fbst_nulls_create_directions(plan, u, v=None) -> int:
     h = c_void_p()
     _check(lib().fbst_nulls_create_directions(plan, n, ua, va, byref(h)))
     return h.value
+
+
+def fbst_directions_create(plan, u, v=None) -> int:
+    n = len(u)
+    ua = (ctypes.c_double * n)(*[float(a) for a in u])
+    va = (ctypes.c_double * n)(*[float(a) for a in v]) if v is not None else None
+    h = c_void_p()
+    _check(lib().fbst_directions_create(plan, n, ua, va, byref(h)))
+    return h.value
+
+
+def fbst_directions_destroy(dirs):
+    lib().fbst_directions_destroy(dirs)
+
+
+def fbst_workspace_bytes_directions(plan, dirs, nblocks) -> int:
+    return lib().fbst_workspace_bytes_directions(plan, dirs, nblocks)
+
+
+def fbst_execute_directions(plan, dirs, nblocks, max_chunk, x, beams, workspace, stream=0):
+    _check(lib().fbst_execute_directions(plan, dirs, nblocks, max_chunk, x, beams, workspace,
+                                         stream or None))
 
 
 def fbst_nulls_destroy(nulls):
@@ -472,6 +504,48 @@ class Nulls:
     def close(self):
         if getattr(self, "handle", None):
             fbst_nulls_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Directions:
+    """Beams at arbitrary directions (u, v) of a plan (fbst_directions_*)."""
+
+    def __init__(self, plan, u, v=None):
+        self.plan = plan
+        self.D = len(u)
+        self.handle = fbst_directions_create(plan.handle, list(u), None if v is None else list(v))
+
+    def workspace(self, nblocks=1):
+        import torch
+        n = fbst_workspace_bytes_directions(self.plan.handle, self.handle, nblocks)
+        return torch.empty(n, dtype=torch.uint8, device="cuda")
+
+    def execute(self, x, beams=None, workspace=None, max_chunk=0):
+        """x [nblocks, M, N] (or [M, N]) complex64 -> beams [nblocks, D, N] (or [D, N])."""
+        import torch
+        p = self.plan
+        single = x.dim() == 2
+        xb = x.unsqueeze(0) if single else x
+        p._check_in(xb, (p.M, p.N))
+        nb = xb.shape[0]
+        chunk = min(nb if max_chunk <= 0 else min(max_chunk, nb), MAX_LAUNCH_BLOCKS)
+        if beams is None:
+            beams = torch.empty((nb, self.D, p.N), dtype=torch.complex64, device=x.device)
+        if workspace is None:
+            workspace = self.workspace(chunk)
+        fbst_execute_directions(p.handle, self.handle, nb, chunk, xb.data_ptr(), beams.data_ptr(),
+                                workspace.data_ptr(), torch.cuda.current_stream().cuda_stream)
+        return beams[0] if single else beams
+
+    def close(self):
+        if getattr(self, "handle", None):
+            fbst_directions_destroy(self.handle)
             self.handle = None
 
     def __del__(self):
