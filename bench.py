@@ -88,7 +88,7 @@ def rocprof_summary(kt_dir, pmc_dirs, copy_dirs):
         m = re.match(r"_ZN4fbst12_GLOBAL__N_1\d+(k_\w+?)ILi(\d+)EDv8_DF16(b|_)", name)
         if m:   # names the profiler leaves mangled (16-bit vector template arguments)
             return f"{m.group(1)}<{m.group(2)}, {'bf16x8' if m.group(3) == 'b' else 'f16x8'}>"
-        n = name.replace("void fbst::(anonymous namespace)::", "").replace("void ", "")
+        n = name.replace("void ", "").replace("fbst::(anonymous namespace)::", "")
         return re.sub(r"\(.*", "", n)
 
     out = []
