@@ -181,7 +181,20 @@ fbst_status fbst_execute_batched(const fbst_plan* plan, int nblocks, int max_chu
                                  const void* x, void* beams, void* workspace,
                                  void* hip_stream);
 
-/* One stage, for per-stage parity and timing.  Element types are the plan's
+/* Streaming over one recording (Sec. III, streaming remark: contiguous and
+ * possibly overlapping batches of snapshots): x [M][T] (row-major, T samples
+ * per sensor, the plan's I/O type) is cut into windows of N samples starting
+ * every hop samples (hop < N overlaps them), nblocks = (T - N) / hop + 1, and
+ * beams [nblocks][B][N] receives the beams of each window (time origin at the
+ * window's first sample).  Launches as fbst_execute_batched (chunk =
+ * min(nblocks, max_chunk, FBST_MAX_LAUNCH_BLOCKS); workspace of
+ * fbst_workspace_bytes(plan, chunk) bytes, or NULL when chunk == 1).  Stage 1a
+ * reads the windows in place (no copy).  T >= N and hop >= 1, else
+ * FBST_E_INVALID. */
+fbst_status fbst_execute_stream(const fbst_plan* plan, long long T, int hop, const void* x,
+                                void* beams, void* workspace, int max_chunk, void* hip_stream);
+
+/* One stage, for per-stage parity and timing./* One stage, for per-stage parity and timing.  Element types are the plan's
  * stage types (complex64, or complex128 for FBST_PREC_FP64; stage 2 input is
  * the stage-1 type).
  *   stage 0 (time chirp-z, Sec. IV):   in x [nb][M][N]  -> out Yhat [nb][M][L],

@@ -551,6 +551,42 @@ fbst_status fbst_execute_batched(const fbst_plan* plan, int nblocks, int max_chu
   return FBST_OK;
 }
 
+fbst_status fbst_execute_stream(const fbst_plan* plan, long long T, int hop, const void* x,
+                                void* beams, void* workspace, int max_chunk, void* hip_stream) {
+  fbst_status s = check_exec(plan);
+  if (s != FBST_OK) return s;
+  const fbst::Params& p = plan->p;
+  if (T < p.N || hop < 1) return fail(FBST_E_INVALID, "need T >= N and hop >= 1");
+  if (!x || !beams) return fail(FBST_E_INVALID, "x and beams must not be NULL");
+  const long long nblocks_ll = (T - p.N) / hop + 1;
+  if (nblocks_ll > 0x7fffffffLL) return fail(FBST_E_INVALID, "too many windows");
+  const int nblocks = static_cast<int>(nblocks_ll);
+  int chunk = (max_chunk <= 0 || max_chunk > nblocks) ? nblocks : max_chunk;
+  if (chunk > fbst::MAX_LAUNCH_BLOCKS) chunk = fbst::MAX_LAUNCH_BLOCKS;
+  void* ws = workspace;
+  if (!ws) {
+    if (chunk != 1) return fail(FBST_E_INVALID, "workspace is NULL but chunk > 1");
+    ws = plan->own_ws;
+  }
+  const size_t e = io_elem(p);
+  const size_t out_blk = static_cast<size_t>(p.B) * p.N * e;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  for (int b0 = 0; b0 < nblocks; b0 += chunk) {
+    const int n = (nblocks - b0 < chunk) ? nblocks - b0 : chunk;
+    fbst::InPtrs xs{};
+    fbst::OutPtrs outs{};
+    xs.ld = T;
+    for (int i = 0; i < n; ++i) {
+      // window b0 + i starts at sample (b0 + i) hop of every sensor row
+      xs.p[i] = static_cast<const unsigned char*>(x) + static_cast<size_t>(b0 + i) * hop * e;
+      outs.p[i] = static_cast<unsigned char*>(beams) + (b0 + i) * out_blk;
+    }
+    const hipError_t he = fbst::run_blocks(plan, n, xs, outs, ws, st);
+    if (he != hipSuccess) return hip_fail(he, "fbst_execute_stream launch");
+  }
+  return FBST_OK;
+}
+
 fbst_status fbst_execute_stage(const fbst_plan* plan, int stage, int nblocks, const void* in,
                                void* out, void* workspace, void* hip_stream) {
   fbst_status s = check_exec(plan);

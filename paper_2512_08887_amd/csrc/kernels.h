@@ -18,6 +18,7 @@ namespace fbst {
 constexpr int MAX_LAUNCH_BLOCKS = FBST_MAX_LAUNCH_BLOCKS;
 struct InPtrs {
   const void* p[MAX_LAUNCH_BLOCKS];
+  long long ld = 0;    // elements between consecutive sensor rows of x (0: N, a [M][N] block)
 };
 struct OutPtrs {
   void* p[MAX_LAUNCH_BLOCKS];

@@ -148,7 +148,7 @@ __global__ __launch_bounds__(Shape<P>::THREADS) FBST_K12_ATTR void k_time_czt(
   cx<T> v[kE];
   const int rr = active ? row : 0;                    // inactive lanes read row 0, store nothing
   const int blk = rr / M;
-  const cx<T>* src = static_cast<const cx<T>*>(xs.p[blk]) + static_cast<size_t>(rr - blk * M) * N;
+  const cx<T>* src = static_cast<const cx<T>*>(xs.p[blk]) + (rr - blk * M) * (xs.ld > 0 ? xs.ld : N);
   // Loads at clamped indices and a select afterwards (no branch per load, so
   // the loads are issued together rather than one round trip each).
   {
@@ -234,7 +234,7 @@ __global__ __launch_bounds__(Shape<P>::THREADS) FBST_K1S_ATTR void k_time_czt_sp
   cx<T> v[kE], u[kE];
   const int rr = active ? row : 0;                    // inactive lanes read row 0, store nothing
   const int blk = rr / M;
-  const cx<T>* src = static_cast<const cx<T>*>(xs.p[blk]) + static_cast<size_t>(rr - blk * M) * N;
+  const cx<T>* src = static_cast<const cx<T>*>(xs.p[blk]) + (rr - blk * M) * (xs.ld > 0 ? xs.ld : N);
   {
     cx<T> xa[SI], pa[SI];
 #pragma unroll

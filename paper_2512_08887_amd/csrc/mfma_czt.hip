@@ -170,7 +170,7 @@ __global__ __launch_bounds__(P / FFT_E) void k_time_czt_mfma(
   const int lane = t & 63, wave = t >> 6;
   const int row = blockIdx.x;
   const int blk = row / M;
-  const c32* src = static_cast<const c32*>(xs.p[blk]) + static_cast<size_t>(row - blk * M) * N;
+  const c32* src = static_cast<const c32*>(xs.p[blk]) + (row - blk * M) * (xs.ld > 0 ? xs.ld : N);
   const DftA<V8> Af = make_dft_a<-1, V8>(lane);
   const DftA<V8> Ai = make_dft_a<+1, V8>(lane);
   {

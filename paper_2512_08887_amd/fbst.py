@@ -113,6 +113,9 @@ def load_library(path: str = LIB_PATH):
     L.fbst_autotune.argtypes = [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_int,
                                 POINTER(c_int), POINTER(ctypes.c_float)]
     L.fbst_autotune.restype = c_int
+    L.fbst_execute_stream.argtypes = [c_void_p, ctypes.c_longlong, c_int, c_void_p, c_void_p, c_void_p,
+                                      c_int, c_void_p]
+    L.fbst_execute_stream.restype = c_int
     L.fbst_nulls_create.argtypes = [c_void_p, c_int, POINTER(c_int), POINTER(c_void_p)]
     L.fbst_nulls_create.restype = c_int
     L.fbst_nulls_create_directions.argtypes = [c_void_p, c_int, POINTER(ctypes.c_double),
@@ -257,6 +260,11 @@ def fbst_autotune(plan, nblocks, x, beams, workspace, stream=0, force=False):
     _check(lib().fbst_autotune(plan, nblocks, x, beams, workspace, stream or None, int(force),
                                byref(c), byref(ms)))
     return c.value, ms.value
+
+
+def fbst_execute_stream(plan, T, hop, x, beams, workspace=0, max_chunk=0, stream=0):
+    _check(lib().fbst_execute_stream(plan, T, hop, x, beams, workspace or None, max_chunk,
+                                     stream or None))
 
 
 def fbst_nulls_create(plan, beams) -> int:
@@ -430,6 +438,23 @@ class Plan:
         fbst_execute_stage(self.handle, stage, nblocks, inp.data_ptr(), out.data_ptr(),
                            workspace.data_ptr() if workspace is not None else 0, self._stream())
         return out
+
+    def execute_stream(self, x, hop, beams=None, workspace=None, max_chunk=0):
+        """x [M, T] (a recording) -> beams [(T - N) // hop + 1, B, N] of windows every hop samples."""
+        import torch
+        if not x.is_cuda or not x.is_contiguous() or x.dtype != self.complex_dtype or x.dim() != 2 \
+                or x.shape[0] != self.M:
+            raise ValueError(f"expected a contiguous {self.complex_dtype} CUDA tensor [{self.M}, T]")
+        T = x.shape[1]
+        nb = (T - self.N) // hop + 1
+        chunk = min(nb if max_chunk <= 0 else min(max_chunk, nb), MAX_LAUNCH_BLOCKS)
+        if beams is None:
+            beams = torch.empty((nb, self.B, self.N), dtype=self.complex_dtype, device=x.device)
+        if workspace is None and chunk > 1:
+            workspace = self.workspace(chunk)
+        fbst_execute_stream(self.handle, T, hop, x.data_ptr(), beams.data_ptr(),
+                            workspace.data_ptr() if workspace is not None else 0, chunk, self._stream())
+        return beams
 
     def autotune(self, x, beams=None, workspace=None, force=False):
         """Fastest blocks per launch for x [nblocks, M, N]; returns (chunk, ms per batch)."""
