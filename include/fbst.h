@@ -59,7 +59,7 @@ typedef enum {
   FBST_E_DEVICE = -4       /* HIP runtime error (no device, launch or copy error) */
 } fbst_status;
 
-typedef enum { FBST_LINE = 0, FBST_GRID = 1 } fbst_geom_kind;
+typedef enum { FBST_LINE = 0, FBST_GRID = 1, FBST_ARBITRARY = 2 } fbst_geom_kind;
 
 typedef enum {
   FBST_PREC_FP32 = 0,        /* every stage in float32                                  */
@@ -74,12 +74,21 @@ typedef enum {
  * per unit direction cosine, so a beam with direction cosines (u, v) has
  * delays tau = u px + v py relative to the origin (the reference point).
  * LINE: mx = M, my = 1.  GRID: mx * my = M.  dx (dy) = 0 selects
- * half-wavelength spacing at the top band edge, 1 / (2 (f_c + Omega)) (Sec. IV). */
+ * half-wavelength spacing at the top band edge, 1 / (2 (f_c + Omega)) (Sec. IV).
+ * ARBITRARY (non-uniform array, Sec. IX, eq. DFT_non_unif): element m sits at px[m], py[m]
+ * (seconds per unit direction cosine, finite; py NULL: all zero); the host
+ * arrays are read during fbst_plan_create only and the plan keeps a copy;
+ * mx, my, dx, dy, x0, y0 are ignored.  The spatial sum of stage 1b is then a
+ * type-1 non-uniform FFT per frequency (spread onto an oversampled grid with
+ * an exponential-of-semicircle kernel, FFT, deconvolve), 1-D over u for a
+ * beam grid with bv = 1 and 2-D over (u, v) otherwise. */
 typedef struct {
   fbst_geom_kind kind;
   int mx, my;
   double dx, dy;
   double x0, y0;
+  const double* px;  /* ARBITRARY only: [M] */
+  const double* py;  /* ARBITRARY only: [M] or NULL */
 } fbst_geometry;
 
 /* Band (Sec. III): carrier f_c (Hz), baseband half-bandwidth Omega (Hz) and
@@ -145,6 +154,8 @@ typedef struct {
                         L outputs as two halves, each a convolution of
                         p1_split >= N + L/2 - 1 points sharing one forward FFT */
   int stage2_precomputed; /* 1 when stage 2 applies a precomputed K (FBST_FLAG_PRECOMPUTE) */
+  int nu_width;      /* ARBITRARY: spreading kernel width in grid points (p2x,
+                        p2y are then the oversampled grid sizes); else 0       */
 } fbst_info;
 
 typedef struct fbst_plan fbst_plan;
@@ -194,14 +205,14 @@ fbst_status fbst_execute_batched(const fbst_plan* plan, int nblocks, int max_chu
 fbst_status fbst_execute_stream(const fbst_plan* plan, long long T, int hop, const void* x,
                                 void* beams, void* workspace, int max_chunk, void* hip_stream);
 
-/* One stage, for per-stage parity and timing./* One stage, for per-stage parity and timing.  Element types are the plan's
+/* One stage, for per-stage parity and timing.  Element types are the plan's
  * stage types (complex64, or complex128 for FBST_PREC_FP64; stage 2 input is
  * the stage-1 type).
  *   stage 0 (time chirp-z, Sec. IV):   in x [nb][M][N]  -> out Yhat [nb][M][L],
  *            Yhat[m][l-1] = sum_n x[m][n] exp(-j omega_l t_n);
  *   stage 1 (space chirp-z, eq. DFT_1 / App. B): in Yhat -> out W [nb][B][L],
- *            W[b][l-1] = [F_b^H x]_l; a grid needs workspace of
- *            fbst_workspace_bytes(plan, nb) bytes (else may be NULL);
+ *            W[b][l-1] = [F_b^H x]_l; a grid or an arbitrary array needs
+ *            workspace of fbst_workspace_bytes(plan, nb) bytes (else may be NULL);
  *   stage 2 (Sec. V):                  in W -> out beams [nb][B][N].          */
 fbst_status fbst_execute_stage(const fbst_plan* plan, int stage, int nblocks,
                                const void* in, void* out, void* workspace,

@@ -41,9 +41,20 @@ bool stage2_double(const fbst::Params& p) {
 size_t s1_elem(const fbst::Params& p) { return stage1_double(p) ? 16 : 8; }
 size_t s2_elem(const fbst::Params& p) { return stage2_double(p) ? 16 : 8; }
 
+// Elements per block of stage 1b's scratch z: a grid's x-axis output
+// [bu][my][L]; for arbitrary positions the oversampled grid [nfx][nfy][L]
+// and, in 2-D, the x-axis output [bu][nfy][L].
+size_t z_elems(const fbst::Params& p) {
+  if (p.kind == FBST_GRID) return static_cast<size_t>(p.bu) * p.my * p.L;
+  if (p.kind == FBST_ARBITRARY) {
+    const size_t nfy = p.p2y ? p.p2y : 1;
+    return (static_cast<size_t>(p.p2x) * nfy + (p.p2y ? static_cast<size_t>(p.bu) * nfy : 0)) * p.L;
+  }
+  return 0;
+}
+
 size_t ws_per_block(const fbst::Params& p) {
-  size_t elems = (static_cast<size_t>(p.M) + p.B) * p.L;
-  if (p.kind == FBST_GRID) elems += static_cast<size_t>(p.bu) * p.my * p.L;
+  const size_t elems = (static_cast<size_t>(p.M) + p.B) * p.L + z_elems(p);
   return elems * s1_elem(p);
 }
 
@@ -109,6 +120,9 @@ fbst_status upload(fbst_plan* pl) {
     o_ayH = up.add(h.ay.H, d1);
     o_ayq = up.add(h.ay.post, d1);
   }
+  const size_t o_nup = up.add(h.nu_pre, d1), o_nux = up.add(h.nu_posx, d1),
+               o_nuy = up.add(h.nu_posy, d1), o_nucx = up.add(h.nu_cx, d1),
+               o_nucy = up.add(h.nu_cy, d1);
   const size_t o_G1 = up.add(h.G1, d2), o_G2 = up.add(h.G2, d2);
   const size_t o_pre3 = up.add(h.pre3, d2), o_H3 = up.add(h.H3, d2), o_post3 = up.add(h.post3, d2);
   const size_t tables = align_up(up.blob.size());
@@ -147,6 +161,15 @@ fbst_status upload(fbst_plan* pl) {
     pl->ayH = b + o_ayH;
     pl->ayq = b + o_ayq;
   }
+  if (p.kind == FBST_ARBITRARY) {
+    pl->nu_pre = b + o_nup;
+    pl->nu_posx = b + o_nux;
+    pl->nu_cx = b + o_nucx;
+    if (p.p2y) {
+      pl->nu_posy = b + o_nuy;
+      pl->nu_cy = b + o_nucy;
+    }
+  }
   pl->G1 = b + o_G1;
   pl->G2 = b + o_G2;
   pl->pre3 = b + o_pre3;
@@ -179,6 +202,22 @@ hipError_t run_stage1(const fbst_plan* pl, int nb, const void* yhat, void* w, vo
   if (p.kind == FBST_LINE) {
     return fbst::launch_axis_czt<T1>(p.p2x, yhat, w, pl->axp, pl->axH, pl->axq, pl->tw1, p.M, p.B,
                                      1, 1, p.L, nb, st);
+  }
+  if (p.kind == FBST_ARBITRARY) {
+    // spread yhat onto the oversampled grid z [nb][nfx][nfy][L]; 1-D: the x
+    // axis straight to w; 2-D: x axis to z2 [nb][1][bu][nfy][L], then the y
+    // axis on [nb][bu][nfy][1][L] -> w [nb][bu][bv][1][L]
+    const int nfy = p.p2y ? p.p2y : 1;
+    hipError_t e = fbst::launch_nu_spread<T1>(p.nuw, yhat, z, pl->nu_pre, pl->nu_posx, pl->nu_posy,
+                                              p.M, p.p2x, nfy, p.nu_beta, p.L, nb, st);
+    if (e != hipSuccess) return e;
+    if (!p.p2y)
+      return fbst::launch_axis_dft<T1>(p.p2x, z, w, pl->nu_cx, pl->tw1, p.bu, 1, 1, p.L, nb, st);
+    void* z2 = static_cast<unsigned char*>(z) +
+               static_cast<size_t>(nb) * p.p2x * nfy * p.L * sizeof(T1) * 2;
+    e = fbst::launch_axis_dft<T1>(p.p2x, z, z2, pl->nu_cx, pl->tw1, p.bu, 1, nfy, p.L, nb, st);
+    if (e != hipSuccess) return e;
+    return fbst::launch_axis_dft<T1>(nfy, z2, w, pl->nu_cy, pl->tw1, p.bv, p.bu, 1, p.L, nb, st);
   }
   // grid: x axis on [nb][1][mx][my][L] -> z [nb][1][bu][my][L], then the
   // y axis on [nb][bu][my][1][L] -> w [nb][bu][bv][1][L]
@@ -600,9 +639,10 @@ fbst_status fbst_execute_stage(const fbst_plan* plan, int stage, int nblocks, co
   hipError_t e = hipSuccess;
   if (stage == 1) {
     void* z = nullptr;
-    if (p.kind == FBST_GRID) {
+    if (p.kind != FBST_LINE) {
       if (!workspace) {
-        if (nblocks != 1) return fail(FBST_E_INVALID, "a grid stage 1 over several blocks needs a workspace");
+        if (nblocks != 1)
+          return fail(FBST_E_INVALID, "stage 1 of a grid or arbitrary array over several blocks needs a workspace");
         workspace = plan->own_ws;
       }
       z = workspace;
@@ -933,6 +973,7 @@ fbst_status fbst_plan_info(const fbst_plan* plan, fbst_info* info) {
   info->workspace_per_block = plan->ws_bytes_per_block;
   info->p1_split = p.p1s;
   info->stage2_precomputed = plan->K ? 1 : 0;
+  info->nu_width = p.nuw;
   return FBST_OK;
 }
 

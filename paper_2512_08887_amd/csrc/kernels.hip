@@ -18,6 +18,8 @@
 // of K3 are then fetched into one L2 and reused there.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "fft_lds.h"
 #include "kernels.h"
 
@@ -363,6 +365,149 @@ __global__ __launch_bounds__(ShapeK2<P>::THREADS) FBST_K12_ATTR void k_axis_czt(
 }
 
 // ---------------------------------------------------------------------------
+// Stage 1b for arbitrary element positions (Sec. IX, eq. DFT_non_unif): per
+// frequency l a type-1 non-uniform FFT over the modes of the beam grid.
+//   k_nu_spread: c_m = Yhat[m][l] pre[m][l] is spread onto an oversampled
+//     grid (nfx x nfy, l-fastest cells) with a W-point exponential-of-
+//     semicircle kernel per axis, accumulated with LDS atomics, and the grid
+//     is written out as [blk][nfx][nfy][L];
+//   k_axis_dft: per axis, an nf-point FFT (exp(+j)) of the grid and the output
+//     modes a - a_out/2, each scaled by the deconvolution factor corr[a].
+// A workgroup of the spread takes G consecutive frequencies of one block, in
+// min(G, 4) waves; each wave owns Gw = G / waves of them (lane = r Gw + g'),
+// so every update of one frequency's grid comes from one wave: LDS atomics of
+// one instruction and of successive instructions of a wave apply in a fixed
+// order, and the grid is the same bit for bit on every run.
+// ---------------------------------------------------------------------------
+constexpr int kSpreadThreads = 256;
+
+// Kernel values at the W grid points j0 + t of a point f grid cells beyond
+// j0 + W/2 - 1: phi(z_t), z_t = (t - W/2 + 1 - f) 2 / W,
+// phi(z) = exp(beta (sqrt(1 - z^2) - 1)).
+template <typename T, int W>
+__device__ __forceinline__ void es_taps(T f, T beta, T (&k)[W]) {
+#pragma unroll
+  for (int t = 0; t < W; ++t) {
+    const T z = (static_cast<T>(t - W / 2 + 1) - f) * static_cast<T>(2.0 / W);
+    const T q = static_cast<T>(1) - z * z;
+    const T qc = q > static_cast<T>(0) ? q : static_cast<T>(0);
+    if constexpr (sizeof(T) == 4) k[t] = expf(beta * (sqrtf(qc) - 1.0f));
+    else k[t] = ::exp(beta * (::sqrt(qc) - 1.0));
+  }
+}
+
+template <typename T, int W, bool TWO_D, int LDS_BYTES>
+__global__ __launch_bounds__(kSpreadThreads) void k_nu_spread(
+    const cx<T>* __restrict__ in, cx<T>* __restrict__ out, const cx<T>* __restrict__ pre,
+    const cx<T>* __restrict__ posx, const cx<T>* __restrict__ posy, int M, int nfx, int nfy, int G,
+    T beta, int L, int nblocks) {
+  __shared__ T grid_lds[LDS_BYTES / sizeof(T)];
+  const int cells = nfx * nfy;
+  T* re = grid_lds;
+  T* im = grid_lds + cells * G;
+  const int wl = xcd_linear(gridDim.x);
+  const int blk = wl % nblocks;
+  const int tile = wl / nblocks;
+  const int nthreads = blockDim.x;                 // 64 min(G, 4)
+  const int Gw = G / (nthreads / 64);              // frequencies per wave
+  const int lane = threadIdx.x % 64;
+  const int g = (threadIdx.x / 64) * Gw + lane % Gw, R = 64 / Gw;
+  const int l = tile * G + g;
+  for (int i = threadIdx.x; i < 2 * cells * G; i += nthreads) grid_lds[i] = static_cast<T>(0);
+  __syncthreads();
+  if (l < L) {
+    const cx<T>* src = in + static_cast<size_t>(blk) * M * L + l;
+    for (int m = lane / Gw; m < M; m += R) {
+      const size_t i = static_cast<size_t>(m) * L + l;
+      const cx<T> y = ldg(src + static_cast<size_t>(m) * L);
+      const cx<T> pr = ldg(pre + i);
+      const cx<T> px = ldg(posx + i);
+      cx<T> py{0, 0};
+      if constexpr (TWO_D) py = ldg(posy + i);
+      issue_fence();
+      const cx<T> c = cmul(y, pr);
+      T kx[W];
+      es_taps<T, W>(px.re, beta, kx);
+      const int jx0 = static_cast<int>(px.im);
+      if constexpr (!TWO_D) {
+#pragma unroll
+        for (int t = 0; t < W; ++t) {
+          const int cell = ((jx0 + t) & (nfx - 1)) * G + g;
+          atomicAdd(re + cell, c.re * kx[t]);
+          atomicAdd(im + cell, c.im * kx[t]);
+        }
+      } else {
+        T ky[W];
+        es_taps<T, W>(py.re, beta, ky);
+        const int jy0 = static_cast<int>(py.im);
+#pragma unroll
+        for (int tx = 0; tx < W; ++tx) {
+          const int row = ((jx0 + tx) & (nfx - 1)) * nfy;
+          const T cr = c.re * kx[tx], ci = c.im * kx[tx];
+#pragma unroll
+          for (int ty = 0; ty < W; ++ty) {
+            const int cell = (row + ((jy0 + ty) & (nfy - 1))) * G + g;
+            atomicAdd(re + cell, cr * ky[ty]);
+            atomicAdd(im + cell, ci * ky[ty]);
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+  cx<T>* dst = out + static_cast<size_t>(blk) * cells * L + static_cast<size_t>(tile) * G;
+  for (int i = threadIdx.x; i < cells * G; i += nthreads) {
+    const int gg = i % G, j = i / G;
+    if (tile * G + gg < L) dst[static_cast<size_t>(j) * L + gg] = cx<T>{re[i], im[i]};
+  }
+}
+
+// One axis of the non-uniform stage 1b: layout [blk][pre_n][P][post_n][L] in,
+// [blk][pre_n][a_out][post_n][L] out; lane mapping and work order as K2.
+// out[a] = corr[a].re * sum_j in[j] exp(+j 2 pi (a - a_out/2) j / P).
+template <typename T, int P>
+__global__ __launch_bounds__(ShapeK2<P>::THREADS) FBST_K12_ATTR void k_axis_dft(
+    const cx<T>* __restrict__ in, cx<T>* __restrict__ out, const cx<T>* __restrict__ corr,
+    const cx<T>* __restrict__ tw, int a_out, int pre_n, int post_n, int L, int nblocks) {
+  using SH = ShapeK2<P>;
+  __shared__ cx<T> lds[SH::G * SH::S];
+  const int g = threadIdx.x % SH::G;
+  const int t = threadIdx.x / SH::G;
+  int w = xcd_linear(gridDim.x);
+  const int q = w % post_n;
+  w /= post_n;
+  const int p = w % pre_n;
+  w /= pre_n;
+  const int blk = w % nblocks;
+  const int tile = w / nblocks;
+  const int l = tile * SH::G + g;
+  const bool active = l < L;
+  cx<T>* buf = lds + g * SH::S;
+  const int lc = active ? l : L - 1;
+  const size_t stride = static_cast<size_t>(post_n) * L;
+  const cx<T>* src = in + ((static_cast<size_t>(blk) * pre_n + p) * P * post_n + q) * L + lc;
+  cx<T> v[kE];
+#pragma unroll
+  for (int s = 0; s < kE; ++s) v[s] = ldg(src + (t + s * SH::TT) * stride);
+  issue_fence();
+  fft<T, P, kE, +1, kE, FBST_K12_TW>(v, buf, tw, t);
+  const int ka = a_out / 2;
+  cx<T>* dst = out + ((static_cast<size_t>(blk) * pre_n + p) * a_out * post_n + q) * L + l;
+  T cs[kE];
+#pragma unroll
+  for (int s = 0; s < kE; ++s) {
+    const int a = (t + s * SH::TT + ka) & (P - 1);
+    cs[s] = ldg(corr + (a < a_out ? a : 0)).re;
+  }
+  issue_fence();
+#pragma unroll
+  for (int s = 0; s < kE; ++s) {
+    const int a = (t + s * SH::TT + ka) & (P - 1);
+    if (active && a < a_out) dst[a * stride] = cx<T>{v[s].re * cs[s], v[s].im * cs[s]};
+  }
+}
+
+// ---------------------------------------------------------------------------
 // K3: per beam, beta = A_b^{-1} w_b by the Gohberg-Semencul form
 //   A^{-1} = (1/x0) [L(x) L(x)^H - L(y~) L(y~)^H],  y~ = (0, conj x_{L-1}, ..., conj x_1)
 // with each triangular Toeplitz product done by circulant embedding in P
@@ -594,6 +739,78 @@ hipError_t launch_axis_czt(int P, const void* in, void* out, const void* pre, co
   return hipErrorInvalidValue;
 }
 
+// Frequencies per spreading workgroup: up to 16 within 64 KiB of LDS, else
+// fewer within 128 KiB; 0 if one grid does not fit.
+template <typename T>
+int spread_group(int cells, int* lds_bytes) {
+  const int per = static_cast<int>(2 * sizeof(T)) * cells;
+  for (int bytes : {64 * 1024, 128 * 1024}) {
+    int G = 16;
+    while (G > 1 && G * per > bytes) G /= 2;
+    if (G * per <= bytes && (G >= 4 || bytes == 128 * 1024 || 4 * per > 128 * 1024)) {
+      *lds_bytes = bytes;
+      return G;
+    }
+  }
+  return 0;
+}
+
+template <typename T>
+hipError_t launch_nu_spread(int width, const void* in, void* out, const void* pre, const void* posx,
+                            const void* posy, int M, int nfx, int nfy, double beta, int L,
+                            int nblocks, hipStream_t st) {
+  constexpr int W = sizeof(T) == 4 ? 8 : 16;
+  if (width != W || M < 1 || L < 1 || nblocks < 1 || nfx < 1 || nfy < 1 || (nfx & (nfx - 1)) ||
+      (nfy & (nfy - 1)) || (nfy > 1 && !posy))
+    return hipErrorInvalidValue;
+  int bytes = 0;
+  const int G = spread_group<T>(nfx * nfy, &bytes);
+  if (G < 1) return hipErrorInvalidValue;
+  const long long ng = 1LL * nblocks * ((L + G - 1) / G);
+  if (ng > 0x7fffffffLL) return hipErrorInvalidValue;
+  const dim3 grid(static_cast<unsigned>(ng)), block(64 * std::min(G, 4));
+  const T b = static_cast<T>(beta);
+  auto go = [&](auto kern) {
+    hipLaunchKernelGGL(kern, grid, block, 0, st, static_cast<const cx<T>*>(in), static_cast<cx<T>*>(out),
+                       static_cast<const cx<T>*>(pre), static_cast<const cx<T>*>(posx),
+                       static_cast<const cx<T>*>(posy), M, nfx, nfy, G, b, L, nblocks);
+  };
+  if (nfy > 1) {
+    if (bytes == 64 * 1024) go(k_nu_spread<T, W, true, 64 * 1024>);
+    else go(k_nu_spread<T, W, true, 128 * 1024>);
+  } else {
+    if (bytes == 64 * 1024) go(k_nu_spread<T, W, false, 64 * 1024>);
+    else go(k_nu_spread<T, W, false, 128 * 1024>);
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_axis_dft(int P, const void* in, void* out, const void* corr, const void* tw,
+                           int a_out, int pre_n, int post_n, int L, int nblocks, hipStream_t st) {
+  if (a_out < 1 || 2 * a_out > P || pre_n < 1 || post_n < 1 || L < 1 || nblocks < 1)
+    return hipErrorInvalidValue;
+  switch (P) {
+#define CASE(PP)                                                                               \
+  case PP:                                                                                     \
+    if constexpr ((sizeof(T) * 2 * lds_stride(PP) * ShapeK2<PP>::G <= 160 * 1024)) {          \
+      const int n_tiles = (L + ShapeK2<PP>::G - 1) / ShapeK2<PP>::G;                           \
+      const long long ng = 1LL * nblocks * pre_n * post_n * n_tiles;                           \
+      if (ng > 0x7fffffffLL) return hipErrorInvalidValue;                                      \
+      hipLaunchKernelGGL((k_axis_dft<T, PP>), dim3((unsigned)ng), dim3(ShapeK2<PP>::THREADS), \
+                         0, st, (const cx<T>*)in, (cx<T>*)out, (const cx<T>*)corr,             \
+                         (const cx<T>*)tw, a_out, pre_n, post_n, L, nblocks);                  \
+      return hipGetLastError();                                                                \
+    }                                                                                          \
+    break;
+    FBST_FOR_EACH_P(CASE)
+#undef CASE
+    default:
+      break;
+  }
+  return hipErrorInvalidValue;
+}
+
 template <typename T, typename TIN, typename TOUT>
 hipError_t launch_toeplitz_fu(int P, const void* w, const OutPtrs& outs, const void* G1,
                               const void* G2, const void* pre3, const void* H3, const void* post3,
@@ -650,6 +867,14 @@ template hipError_t launch_axis_czt<float>(int, const void*, void*, const void*,
 template hipError_t launch_axis_czt<double>(int, const void*, void*, const void*, const void*,
                                             const void*, const void*, int, int, int, int, int, int,
                                             hipStream_t);
+template hipError_t launch_nu_spread<float>(int, const void*, void*, const void*, const void*,
+                                            const void*, int, int, int, double, int, int, hipStream_t);
+template hipError_t launch_nu_spread<double>(int, const void*, void*, const void*, const void*,
+                                             const void*, int, int, int, double, int, int, hipStream_t);
+template hipError_t launch_axis_dft<float>(int, const void*, void*, const void*, const void*, int,
+                                           int, int, int, int, hipStream_t);
+template hipError_t launch_axis_dft<double>(int, const void*, void*, const void*, const void*, int,
+                                            int, int, int, int, hipStream_t);
 template hipError_t launch_toeplitz_fu<float, float, float>(
     int, const void*, const OutPtrs&, const void*, const void*, const void*, const void*, const void*,
     const void*, int, int, int, int, hipStream_t);

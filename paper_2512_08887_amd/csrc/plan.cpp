@@ -189,7 +189,137 @@ void parallel_for(int n, long long cost, F&& fn) {
   for (auto& x : th) x.join();
 }
 
+// sum_m exp(j (ax xs_m + ay ys_m)) over the elements, positions in samples of
+// delay per unit direction cosine and ax, ay in rad per sample: closed-form
+// geometric sums per axis for a line or grid, the direct sum otherwise.
+zd sensor_sum(const Params& p, double ax, double ay) {
+  if (p.kind == FBST_ARBITRARY) {
+    double re = 0.0, im = 0.0;
+    for (int m = 0; m < p.M; ++m) {
+      const double ph = ax * (p.px[m] / p.ts) + ay * (p.py[m] / p.ts);
+      re += std::cos(ph);
+      im += std::sin(ph);
+    }
+    return zd(re, im);
+  }
+  const double thx = ax * (p.dx / p.ts);
+  zd s = geometric_sum(p.mx, thx * p.x0, thx);
+  if (p.kind == FBST_GRID) {
+    const double thy = ay * (p.dy / p.ts);
+    s *= geometric_sum(p.my, thy * p.y0, thy);
+  }
+  return s;
+}
+
+// Gauss-Legendre nodes and weights on [-1, 1] (Newton iteration on P_n).
+void gauss_legendre(int n, std::vector<double>* x, std::vector<double>* w) {
+  x->assign(n, 0.0);
+  w->assign(n, 0.0);
+  for (int i = 0; i < (n + 1) / 2; ++i) {
+    double z = std::cos(kPi * (i + 0.75) / (n + 0.5)), dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;                 // P_0, P_1
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (z * p1 - p0) / (z * z - 1.0);  // P_n'(z)
+      const double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    (*x)[i] = -z;
+    (*x)[n - 1 - i] = z;
+    (*w)[i] = (*w)[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+// Exponential-of-semicircle spreading kernel phi(z) = exp(beta (sqrt(1 - z^2) - 1))
+// on |z| <= 1 (Barnett, Magland, af Klinteberg, SIAM J. Sci. Comput. 2019).
+double es_kernel(double beta, double z) {
+  const double q = 1.0 - z * z;
+  return q > 0.0 ? std::exp(beta * (std::sqrt(q) - 1.0)) : (q == 0.0 ? std::exp(-beta) : 0.0);
+}
+
+// Deconvolution factors of one axis: mode k = a - a_out/2 of an nf-point grid
+// spread with a w-point kernel is divided by (nf / 2 pi) psi^(k), psi^ the
+// Fourier transform of the kernel in radians: psi^(k) = (pi w / nf)
+// int_{-1}^{1} phi(z) cos(k pi w z / nf) dz (Gauss-Legendre, 4w + 32 nodes).
+std::vector<zd> nu_deconvolution(int a_out, int nf, int w, double beta) {
+  std::vector<double> zq, wq;
+  gauss_legendre(4 * w + 32, &zq, &wq);
+  std::vector<zd> c(a_out);
+  for (int a = 0; a < a_out; ++a) {
+    const double k = a - a_out / 2;
+    double s = 0.0;
+    for (size_t i = 0; i < zq.size(); ++i)
+      s += wq[i] * es_kernel(beta, zq[i]) * std::cos(k * kPi * w * zq[i] / nf);
+    c[a] = zd(1.0 / (0.5 * w * s), 0.0);
+  }
+  return c;
+}
+
+// Type-1 non-uniform FFT tables of stage 1b (Sec. IX, eq. DFT_non_unif).  With
+// centre mode a_c = bu / 2 (c_c = bv / 2) and f_l = f_c T_s + eps l' / L
+// (cycles per sample of delay), the phase f_l 2 pi (u_a xs_m + v_c ys_m) of
+// beam (a, c) splits into the centre-direction phase (nu_pre) and
+// (a - a_c) s_x + (c - c_c) s_y with s_x = 2 pi f_l du xs_m,
+// s_y = 2 pi f_l dv ys_m: one type-1 NUFFT per l over the modes of the
+// beam grid, with the points at s_x / 2 pi mod 1 of the oversampled grid.
+// Phases and positions are reduced in long double.
+void build_nonuniform(const Params& p, HostTables* t) {
+  const int M = p.M, L = p.L, w = p.nuw;
+  const int nfx = p.p2x, nfy = p.p2y;
+  const bool two_d = nfy > 0;
+  const long double lp0 = 1.0L - 0.5L * L;
+  const long double uc = static_cast<long double>(p.u0) + static_cast<long double>(p.bu / 2) * p.du;
+  const long double vc = two_d ? static_cast<long double>(p.v0) + static_cast<long double>(p.bv / 2) * p.dv
+                               : static_cast<long double>(p.v0);
+  t->nu_pre.assign(static_cast<size_t>(M) * L, zd());
+  t->nu_posx.assign(static_cast<size_t>(M) * L, zd());
+  if (two_d) t->nu_posy.assign(static_cast<size_t>(M) * L, zd());
+  auto frac = [](long double v) { return v - std::floor(v); };
+  auto position = [&](long double cyc, int nf) {
+    const long double g = frac(cyc) * nf;
+    long double jf = std::floor(g);
+    long double f = g - jf;
+    if (f >= 1.0L) { f = 0.0L; jf += 1.0L; }
+    long long j0 = (static_cast<long long>(jf) - w / 2 + 1) % nf;
+    if (j0 < 0) j0 += nf;
+    return zd(static_cast<double>(f), static_cast<double>(j0));
+  };
+  parallel_for(M, 1LL * M * L * 64, [&](int m0, int m1) {
+    for (int m = m0; m < m1; ++m) {
+      const long double xs = static_cast<long double>(p.px[m]) / p.ts;
+      const long double ys = static_cast<long double>(p.py[m]) / p.ts;
+      for (int l = 0; l < L; ++l) {
+        const long double fl = static_cast<long double>(p.fc) * p.ts +
+                               static_cast<long double>(p.eps) * (l + lp0) / L;
+        const size_t i = static_cast<size_t>(m) * L + l;
+        t->nu_pre[i] = cis(2.0 * kPi * static_cast<double>(frac(fl * (uc * xs + vc * ys))));
+        t->nu_posx[i] = position(fl * static_cast<long double>(p.du) * xs, nfx);
+        if (two_d) t->nu_posy[i] = position(fl * static_cast<long double>(p.dv) * ys, nfy);
+      }
+    }
+  });
+  t->nu_cx = nu_deconvolution(p.bu, nfx, w, p.nu_beta);
+  if (two_d) t->nu_cy = nu_deconvolution(p.bv, nfy, w, p.nu_beta);
+}
+
 }  // namespace
+
+double pos_x(const Params& p, int m) {
+  if (p.kind == FBST_ARBITRARY) return p.px[m] / p.ts;
+  const int k = (p.kind == FBST_GRID) ? m / p.my : m;
+  return (p.x0 + k) * (p.dx / p.ts);
+}
+
+double pos_y(const Params& p, int m) {
+  if (p.kind == FBST_ARBITRARY) return p.py[m] / p.ts;
+  if (p.kind != FBST_GRID) return 0.0;
+  return (p.y0 + m % p.my) * (p.dy / p.ts);
+}
 
 void fft64(zd* a, int n, int sign) {
   // iterative radix-2, bit-reversed input order, twiddles from direct cos/sin
@@ -330,11 +460,27 @@ fbst_status resolve_params(int M, int N, int B, const fbst_geometry* geom, const
     p.dy = geom->dy != 0.0 ? geom->dy : dflt;
     p.x0 = geom->x0;
     p.y0 = geom->y0;
-    if (p.kind != FBST_LINE && p.kind != FBST_GRID) {
+    if (p.kind != FBST_LINE && p.kind != FBST_GRID && p.kind != FBST_ARBITRARY) {
       *msg = "unknown geometry kind";
       return FBST_E_INVALID;
     }
-    if (p.kind == FBST_LINE) {
+    if (p.kind == FBST_ARBITRARY) {
+      if (!geom->px) {
+        *msg = "an arbitrary array needs px (M element coordinates)";
+        return FBST_E_INVALID;
+      }
+      p.px.assign(geom->px, geom->px + M);
+      if (geom->py) p.py.assign(geom->py, geom->py + M);
+      else p.py.assign(M, 0.0);
+      for (int m = 0; m < M; ++m)
+        if (!std::isfinite(p.px[m]) || !std::isfinite(p.py[m])) {
+          *msg = "element coordinates must be finite";
+          return FBST_E_INVALID;
+        }
+      p.mx = M;
+      p.my = 1;
+      p.dx = p.dy = p.x0 = p.y0 = 0.0;
+    } else if (p.kind == FBST_LINE) {
       if (p.mx != M || p.my != 1) {
         *msg = "a line needs mx == M and my == 1";
         return FBST_E_INVALID;
@@ -371,7 +517,7 @@ fbst_status resolve_params(int M, int N, int B, const fbst_geometry* geom, const
     }
     if (grid->du == 0.0) default_grid(p.bu, &p.u0, &p.du);
     else { p.u0 = grid->u0; p.du = grid->du; }
-    if (p.kind == FBST_GRID) {
+    if (p.kind != FBST_LINE) {
       if (grid->dv == 0.0) default_grid(p.bv, &p.v0, &p.dv);
       else { p.v0 = grid->v0; p.dv = grid->dv; }
     }
@@ -386,6 +532,24 @@ fbst_status resolve_params(int M, int N, int B, const fbst_geometry* geom, const
   p.p3 = next_pow2(std::max(2LL * p.L - 1, static_cast<long long>(p.L) + p.N - 1));
   p.p2x = std::max(p.p2x, 32);
   if (p.kind == FBST_GRID) p.p2y = std::max(p.p2y, 32);
+  if (p.kind == FBST_ARBITRARY) {
+    // oversampled grids of at least twice the modes per axis; kernel width for
+    // about float32 (8 points) or float64 (16 points) accuracy; shape
+    // parameter beta = 0.98 pi (1 - 1/(2 sigma)) w for oversampling sigma
+    p.p2x = std::max(next_pow2(2LL * p.bu), 32);
+    p.p2y = p.bv > 1 ? std::max(next_pow2(2LL * p.bv), 32) : 0;
+    p.nuw = (p.prec == FBST_PREC_FP64) ? 16 : 8;
+    double sigma = static_cast<double>(p.p2x) / p.bu;
+    if (p.p2y) sigma = std::min(sigma, static_cast<double>(p.p2y) / p.bv);
+    p.nu_beta = 0.98 * kPi * (1.0 - 0.5 / sigma) * p.nuw;
+    const double grid_bytes = static_cast<double>(p.p2x) * std::max(p.p2y, 1) *
+                              (p.prec == FBST_PREC_FP64 ? 16.0 : 8.0);
+    if (grid_bytes > 128.0 * 1024) {
+      *msg = "the oversampled grid of one frequency (" + std::to_string(p.p2x) + " x " +
+             std::to_string(std::max(p.p2y, 1)) + ") exceeds 128 KiB of LDS";
+      return FBST_E_UNSUPPORTED;
+    }
+  }
   p.p1 = std::max(p.p1, 32);
   p.p3 = std::max(p.p3, 32);
   if ((p.prec == FBST_PREC_BF16_SPLIT || p.prec == FBST_PREC_FP16_SPLIT) && p.p1 < 1024) {
@@ -458,8 +622,12 @@ fbst_status build_tables(const Params& p, bool keep_gram_gen, HostTables* t, std
   }
 
   // --- stage 1b: spatial chirp-z per axis ------------------------------------
-  build_axis(p, p.mx, p.bu, p.x0, p.dx / p.ts, p.u0, p.du, p.p2x, &t->ax);
-  if (p.kind == FBST_GRID) build_axis(p, p.my, p.bv, p.y0, p.dy / p.ts, p.v0, p.dv, p.p2y, &t->ay);
+  if (p.kind == FBST_ARBITRARY) {
+    build_nonuniform(p, t);
+  } else {
+    build_axis(p, p.mx, p.bu, p.x0, p.dx / p.ts, p.u0, p.du, p.p2x, &t->ax);
+    if (p.kind == FBST_GRID) build_axis(p, p.my, p.bv, p.y0, p.dy / p.ts, p.v0, p.dv, p.p2y, &t->ay);
+  }
 
   // --- beams ---------------------------------------------------------------
   t->u.resize(B);
@@ -467,7 +635,7 @@ fbst_status build_tables(const Params& p, bool keep_gram_gen, HostTables* t, std
   for (int a = 0; a < p.bu; ++a)
     for (int c = 0; c < p.bv; ++c) {
       t->u[a * p.bv + c] = p.u0 + a * p.du;
-      t->v[a * p.bv + c] = (p.kind == FBST_GRID) ? p.v0 + c * p.dv : 0.0;
+      t->v[a * p.bv + c] = (p.kind != FBST_LINE) ? p.v0 + c * p.dv : 0.0;
     }
 
   // --- stage 2 F_u chirp-z: b[n] = post3[n] sum_i (beta[i] pre3[i]) h3[n - i] -----
@@ -510,7 +678,7 @@ fbst_status build_tables(const Params& p, bool keep_gram_gen, HostTables* t, std
   for (int d = 0; d < L; ++d) rt[d] = dirichlet(N, 2.0 * kPi * p.eps * d / L);
   std::vector<int> key_of(B);
   std::vector<std::pair<double, double>> keys;
-  {
+  if (p.kind != FBST_ARBITRARY) {
     std::vector<std::pair<std::pair<double, double>, int>> seen;
     for (int b = 0; b < B; ++b) {
       const std::pair<double, double> k(std::fabs(t->u[b]), std::fabs(t->v[b]));
@@ -555,19 +723,34 @@ fbst_status build_tables(const Params& p, bool keep_gram_gen, HostTables* t, std
   const bool refine = 2.0 * p.M * p.N / p.delta > 1e6;
   auto work = [&](int b0, int b1) {
     std::vector<zd> col(L), x(L), buf(P3);
-    for (int b = b0; b < b1; ++b) {
+    for (int b = b0; b < b1 && ok.load(); ++b) {
       const double ub = t->u[b], vb = t->v[b];
-      const double sb = 0.5 * (N - 1) - ub * dxs * (p.x0 + 0.5 * (p.mx - 1)) -
-                        ((p.kind == FBST_GRID) ? vb * dys * (p.y0 + 0.5 * (p.my - 1)) : 0.0);
-      const std::vector<double>& r = rcol[key_of[b]];
-      const std::vector<double>& xk = xr[key_of[b]];
-      for (int d = 0; d < L; ++d) {
-        const zd ph = cis(-2.0 * kPi * p.eps * d / L * sb);
-        col[d] = ph * r[d];
-        x[d] = ph * xk[d];
+      if (p.kind == FBST_ARBITRARY) {
+        // no closed form: the sensor sum directly, then complex Levinson
+        for (int d = 0; d < L; ++d) {
+          const double kd = 2.0 * kPi * p.eps * d / L;
+          col[d] = geometric_sum(N, 0.0, -kd) * sensor_sum(p, kd * ub, kd * vb);
+        }
+        col[0] = zd(col[0].real() + p.delta, 0.0);
+        if (!levinson_first_column(col.data(), L, x.data())) {
+          std::lock_guard<std::mutex> lk(fail_mu);
+          ok = false;
+          fail = "Toeplitz system not positive definite in float64 (delta too small?)";
+          break;
+        }
+      } else {
+        const double sb = 0.5 * (N - 1) - ub * dxs * (p.x0 + 0.5 * (p.mx - 1)) -
+                          ((p.kind == FBST_GRID) ? vb * dys * (p.y0 + 0.5 * (p.my - 1)) : 0.0);
+        const std::vector<double>& r = rcol[key_of[b]];
+        const std::vector<double>& xk = xr[key_of[b]];
+        for (int d = 0; d < L; ++d) {
+          const zd ph = cis(-2.0 * kPi * p.eps * d / L * sb);
+          col[d] = ph * r[d];
+          x[d] = ph * xk[d];
+        }
+        col[0] = zd(r[0], 0.0);
+        x[0] = zd(xk[0], 0.0);
       }
-      col[0] = zd(r[0], 0.0);
-      x[0] = zd(xk[0], 0.0);
       if (keep_gram_gen) std::copy(col.begin(), col.end(), t->gram.begin() + static_cast<size_t>(b) * L);
       if (refine) refine_generator(col.data(), L, P3, &x);
       if (keep_gram_gen) std::copy(x.begin(), x.end(), t->gen.begin() + static_cast<size_t>(b) * L);
@@ -590,7 +773,12 @@ fbst_status build_tables(const Params& p, bool keep_gram_gen, HostTables* t, std
     *msg = fail;
     return FBST_E_INVALID;
   }
-  parallel_for(B, 1LL * B * P3 * 64, work);
+  parallel_for(B, 1LL * B * P3 * 64 + (p.kind == FBST_ARBITRARY ? 1LL * B * L * (L + p.M) * 8 : 0),
+               work);
+  if (!ok) {
+    *msg = fail;
+    return FBST_E_INVALID;
+  }
   return FBST_OK;
 }
 
@@ -615,10 +803,7 @@ fbst_status build_direction_tables(const Params& p, const std::vector<double>& u
     std::vector<zd> col(L), x(L);
     for (int d = 0; d < L; ++d) {
       const double kd = kap * d;
-      zd c = geometric_sum(N, 0.0, -kd) * geometric_sum(p.mx, kd * ud[di] * dxs * p.x0,
-                                                        kd * ud[di] * dxs);
-      if (p.kind == FBST_GRID) c *= geometric_sum(p.my, kd * vd[di] * dys * p.y0, kd * vd[di] * dys);
-      col[d] = c;
+      col[d] = geometric_sum(N, 0.0, -kd) * sensor_sum(p, kd * ud[di], kd * vd[di]);
     }
     col[0] += p.delta;
     if (!levinson_first_column(col.data(), L, x.data())) {
@@ -636,9 +821,7 @@ fbst_status build_direction_tables(const Params& p, const std::vector<double>& u
       }
     });
     for (int m = 0; m < M; ++m) {
-      const int k1 = (p.kind == FBST_GRID) ? m / p.my : m, k2 = (p.kind == FBST_GRID) ? m % p.my : 0;
-      const double tau = ud[di] * dxs * (p.x0 + k1) +
-                         ((p.kind == FBST_GRID) ? vd[di] * dys * (p.y0 + k2) : 0.0);
+      const double tau = ud[di] * pos_x(p, m) + vd[di] * pos_y(p, m);
       for (int l = 0; l < L; ++l) (*E)[(static_cast<size_t>(di) * M + m) * L + l] = cis(a_of(l) * tau);
     }
   }
@@ -664,7 +847,7 @@ fbst_status build_null_tables(const Params& p, const std::vector<double>& uq,
   const double kap = 2.0 * kPi * p.eps / L;                     // rad per sample per unit l'
   const double dxs = p.dx / p.ts, dys = p.dy / p.ts;
   auto beam_u = [&](int b) { return p.u0 + (b / p.bv) * p.du; };
-  auto beam_v = [&](int b) { return p.kind == FBST_GRID ? p.v0 + (b % p.bv) * p.dv : 0.0; };
+  auto beam_v = [&](int b) { return p.kind != FBST_LINE ? p.v0 + (b % p.bv) * p.dv : 0.0; };
   // time factor sum_n exp(-j kappa d n), d = l - k in (-L, L)
   std::vector<zd> tf(2 * L - 1);
   for (int d = -(L - 1); d <= L - 1; ++d) tf[d + L - 1] = geometric_sum(N, 0.0, -kap * d);
@@ -672,13 +855,7 @@ fbst_status build_null_tables(const Params& p, const std::vector<double>& uq,
   // (ub, vb) and (uq, vq), tau in samples, a_l = 2 pi (f_c T_s) + kappa l'
   // (rad per sample of delay), separable per axis
   auto sensor2 = [&](double an, double ak, double ub, double vb, double u2, double v2) {
-    const double thx = (an * ub - ak * u2) * dxs;
-    zd s = geometric_sum(p.mx, thx * p.x0, thx);
-    if (p.kind == FBST_GRID) {
-      const double thy = (an * vb - ak * v2) * dys;
-      s *= geometric_sum(p.my, thy * p.y0, thy);
-    }
-    return s;
+    return sensor_sum(p, an * ub - ak * u2, an * vb - ak * v2);
   };
   auto a_of = [&](int l) { return 2.0 * kPi * p.fc * p.ts + kap * (l + lp0); };
   // generators x_q = A_q^{-1} e_0 of A_q = F_q^H F_q + delta I (Sec. V), refined
@@ -717,9 +894,7 @@ fbst_status build_null_tables(const Params& p, const std::vector<double>& uq,
     E->assign(static_cast<size_t>(P) * M * L, zd());
     for (int qi = 0; qi < P; ++qi)
       for (int m = 0; m < M; ++m) {
-        const int k1 = (p.kind == FBST_GRID) ? m / p.my : m, k2 = (p.kind == FBST_GRID) ? m % p.my : 0;
-        const double tau = uq[qi] * dxs * (p.x0 + k1) +
-                           ((p.kind == FBST_GRID) ? vq[qi] * dys * (p.y0 + k2) : 0.0);
+        const double tau = uq[qi] * pos_x(p, m) + vq[qi] * pos_y(p, m);
         for (int l = 0; l < L; ++l)
           (*E)[(static_cast<size_t>(qi) * M + m) * L + l] = cis(a_of(l) * tau);
       }

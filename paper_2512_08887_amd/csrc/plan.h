@@ -30,6 +30,12 @@ struct HostTables {
   std::vector<zd> pre3, H3, post3;        // F_u chirp-z: [L], [P3], [N]
   std::vector<double> u, v;               // beam direction cosines [B]
   std::vector<zd> gram, gen;              // [B][L] (kept on request)
+  // non-uniform stage 1b (arbitrary positions): centre-direction phases
+  // nu_pre [M][L]; per axis the spreading position of element m at frequency l
+  // as (f, j0) [M][L] (first grid point j0 of the kernel support, fractional
+  // offset f in [0, 1) of the point beyond grid point j0 + w/2 - 1); and the
+  // deconvolution factors per output mode, nu_cx [bu], nu_cy [bv] (real).
+  std::vector<zd> nu_pre, nu_posx, nu_posy, nu_cx, nu_cy;
 };
 
 struct Params {
@@ -44,7 +50,17 @@ struct Params {
   unsigned flags = 0;
   int p1 = 0, p2x = 0, p2y = 0, p3 = 0;
   int p1s = 0, ls1 = 0;                   // split-output stage 1a: FFT size, first-half length
+  // arbitrary positions: element coordinates (seconds per unit direction
+  // cosine), oversampled grid sizes (p2x, p2y hold them too; nfy = 1 for a
+  // line of beams), spreading kernel width and shape parameter
+  std::vector<double> px, py;
+  int nuw = 0;
+  double nu_beta = 0;
 };
+
+// Element m's position in samples of delay per unit direction cosine.
+double pos_x(const Params& p, int m);
+double pos_y(const Params& p, int m);
 
 // Validate and complete the user parameters (defaults, FFT sizes).  Returns
 // FBST_OK or an error with *msg set.
@@ -132,6 +148,9 @@ struct fbst_plan {
   const void *axp = nullptr, *axH = nullptr, *axq = nullptr;
   const void *ayp = nullptr, *ayH = nullptr, *ayq = nullptr;
   const void *G1 = nullptr, *G2 = nullptr, *pre3 = nullptr, *H3 = nullptr, *post3 = nullptr;
+  // non-uniform stage 1b (arbitrary positions)
+  const void *nu_pre = nullptr, *nu_posx = nullptr, *nu_posy = nullptr, *nu_cx = nullptr,
+             *nu_cy = nullptr;
   // stage 2 in precomputed form: K [L][B][N] complex64 (own allocation), or null
   void* K = nullptr;
   size_t K_bytes = 0;

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libfbst.so"
 HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "fbst.h")
 
 FBST_OK, FBST_E_INVALID, FBST_E_UNSUPPORTED, FBST_E_NOMEM, FBST_E_DEVICE = 0, -1, -2, -3, -4
-FBST_LINE, FBST_GRID = 0, 1
+FBST_LINE, FBST_GRID, FBST_ARBITRARY = 0, 1, 2
 FBST_PREC_FP32, FBST_PREC_FP64_STAGE2, FBST_PREC_FP64, FBST_PREC_BF16_SPLIT, FBST_PREC_FP16_SPLIT = range(5)
 FBST_FLAG_HOST_ONLY, FBST_FLAG_KEEP_HOST_TABLES, FBST_FLAG_NO_SPLIT, FBST_FLAG_PRECOMPUTE = 1, 2, 4, 8
 FBST_TABLE_BEAM_U, FBST_TABLE_BEAM_V, FBST_TABLE_GRAM, FBST_TABLE_GENERATOR = 0, 1, 2, 3
@@ -31,7 +31,8 @@ PRECISIONS = {"fp32": FBST_PREC_FP32, "fp64_stage2": FBST_PREC_FP64_STAGE2, "fp6
 
 class fbst_geometry(ctypes.Structure):
     _fields_ = [("kind", c_int), ("mx", c_int), ("my", c_int), ("dx", c_double), ("dy", c_double),
-                ("x0", c_double), ("y0", c_double)]
+                ("x0", c_double), ("y0", c_double), ("px", POINTER(c_double)),
+                ("py", POINTER(c_double))]
 
 
 class fbst_band(ctypes.Structure):
@@ -53,7 +54,7 @@ class fbst_info(ctypes.Structure):
                 ("bu", c_int), ("bv", c_int), ("p1", c_int), ("p2x", c_int), ("p2y", c_int),
                 ("p3", c_int), ("precision", c_int), ("io_elem_bytes", c_size_t),
                 ("device_bytes", c_size_t), ("workspace_per_block", c_size_t), ("p1_split", c_int),
-                ("stage2_precomputed", c_int)]
+                ("stage2_precomputed", c_int), ("nu_width", c_int)]
 
 
 class fbst_server_options(ctypes.Structure):
@@ -364,6 +365,22 @@ def make_grid_geometry(mx, my, dx=0.0, dy=0.0, x0=0.0, y0=0.0):
     return fbst_geometry(FBST_GRID, mx, my, dx, dy, x0, y0)
 
 
+def make_arbitrary(px, py=None):
+    """Non-uniform array: element coordinates px, py in seconds per unit
+    direction cosine (py None: a line along x).  The returned struct keeps
+    the float64 copies it points to alive."""
+    import numpy as np
+    x = np.ascontiguousarray(px, dtype=np.float64)
+    y = None if py is None else np.ascontiguousarray(py, dtype=np.float64)
+    if y is not None and y.shape != x.shape:
+        raise ValueError("px and py must have the same length")
+    g = fbst_geometry(FBST_ARBITRARY, len(x), 1, 0.0, 0.0, 0.0, 0.0,
+                      x.ctypes.data_as(POINTER(c_double)),
+                      y.ctypes.data_as(POINTER(c_double)) if y is not None else None)
+    g._keep = (x, y)
+    return g
+
+
 def make_beam_grid(bu, bv=1, u0=0.0, du=0.0, v0=0.0, dv=0.0):
     return fbst_grid(bu, bv, u0, du, v0, dv)
 
@@ -433,7 +450,8 @@ class Plan:
         odt = self.complex_dtype if stage == 2 else self.stage1_dtype
         if out is None:
             out = torch.empty((nblocks,) + shapes[stage], dtype=odt, device=inp.device)
-        if workspace is None and stage == 1 and self.info.bv > 1:
+        if workspace is None and stage == 1 and (self.info.bv > 1 or self.info.my > 1
+                                                 or self.info.nu_width > 0):
             workspace = self.workspace(nblocks)
         fbst_execute_stage(self.handle, stage, nblocks, inp.data_ptr(), out.data_ptr(),
                            workspace.data_ptr() if workspace is not None else 0, self._stream())
@@ -640,6 +658,11 @@ def plan_for_config(cfg, *, delta=None, precision="fp32", eps=None, flags=0):
     band = make_band(cfg.band.fc, cfg.band.omega, cfg.band.ts)
     d = cfg.delta_noise if delta is None else delta
     opts = make_options(d, eps=cfg.eps if eps is None else eps, L=cfg.L, precision=precision, flags=flags)
+    if cfg.perturb > 0.0:
+        px, py = cfg.array.positions()
+        geom = make_arbitrary(px, py if cfg.kind == "ura" else None)
+        grid = make_beam_grid(cfg.bu, cfg.bv) if cfg.kind == "ura" else None
+        return Plan(cfg.M, cfg.N, cfg.B, band=band, geometry=geom, grid=grid, options=opts)
     if cfg.kind == "ura":
         geom = make_grid_geometry(cfg.mx, cfg.my)
         grid = make_beam_grid(cfg.bu, cfg.bv)

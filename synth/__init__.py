@@ -57,12 +57,17 @@ def band_from_fb(fb: float) -> Band:
 
 @dataclass(frozen=True)
 class Array:
-    """Uniform linear (my == 1) or rectangular array.
+    """Uniform linear (my == 1) or rectangular array, optionally perturbed.
 
     Element (k, k2), flattened as m = k * my + k2, sits at delay-per-direction-
     cosine coordinates px = (x0 + k) * dx and py = (y0 + k2) * dy (seconds),
     so a plane wave with direction cosines (u, v) reaches it with delay
     tau = u * px + v * py relative to the reference point (the origin).
+
+    perturb > 0 makes the array non-uniform as in Sec. IX's experiments:
+    every coordinate is moved by an independent offset uniform in
+    [-perturb, perturb] times its spacing (a line moves along x only), drawn
+    from PCG64 seeded with perturb_seed (x offsets first, then y).
     """
     mx: int
     my: int
@@ -70,6 +75,8 @@ class Array:
     dy: float
     x0: float = 0.0
     y0: float = 0.0
+    perturb: float = 0.0
+    perturb_seed: int = 0
 
     @property
     def M(self) -> int:
@@ -80,6 +87,11 @@ class Array:
         k2 = np.arange(self.my, dtype=np.float64)
         px = np.repeat((self.x0 + k) * self.dx, self.my)
         py = np.tile((self.y0 + k2) * self.dy, self.mx)
+        if self.perturb > 0.0:
+            rng = np.random.default_rng(self.perturb_seed)
+            px = px + rng.uniform(-self.perturb, self.perturb, px.shape) * self.dx
+            if self.my > 1:
+                py = py + rng.uniform(-self.perturb, self.perturb, py.shape) * self.dy
         return px, py
 
 
@@ -216,6 +228,7 @@ class Config:
     eps: float = 1.01
     gamma: int = 2
     index: int = 0
+    perturb: float = 0.0      # > 0: non-uniform array (random offsets, fraction of the spacing)
     extra: dict = field(default_factory=dict)
 
     @property
@@ -228,9 +241,11 @@ class Config:
 
     @property
     def array(self) -> Array:
-        if self.kind == "ura":
-            return ura(self.mx, self.my, self.band)
-        return ula(self.M, self.band)
+        a = ura(self.mx, self.my, self.band) if self.kind == "ura" else ula(self.M, self.band)
+        if self.perturb > 0.0:
+            a = Array(a.mx, a.my, a.dx, a.dy, a.x0, a.y0, perturb=self.perturb,
+                      perturb_seed=SEED_BASE + 1000 * self.index + 500)
+        return a
 
     @property
     def delta_noise(self) -> float:
@@ -267,6 +282,13 @@ CONFIGS = {
     # block) streamed as 1024 short blocks: 3 unit-power sources, 10 dB SNR
     "ula128n64": Config("ula128n64", "ula", M=128, N=64, B=128, fb=0.5, n_sources=3,
                         power_db_range=0.0, sigma2=0.1, n_blocks=1024, index=5),
+    # non-uniform arrays (Sec. IX): the 256-element line and a 16 x 16 grid with every
+    # element moved by up to a quarter of the spacing
+    "nula256": Config("nula256", "ula", M=256, N=1024, B=256, fb=0.5, n_sources=8,
+                      power_db_range=30.0, sigma2=0.1, n_blocks=64, index=6, perturb=0.25),
+    "nura16": Config("nura16", "ura", M=256, N=512, B=256, fb=0.5, n_sources=8,
+                     power_db_range=0.0, sigma2=0.1, mx=16, my=16, bu=16, bv=16, n_blocks=16,
+                     index=7, perturb=0.25),
 }
 
 

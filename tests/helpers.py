@@ -19,6 +19,15 @@ def oracle_problem(cfg, delta, eps=None):
     """The oracle's Problem for a synth.Config (its own geometry and grid code)."""
     band = cfg.band
     e = cfg.eps if eps is None else eps
+    if cfg.perturb > 0.0:
+        px, py = cfg.array.positions()
+        if cfg.kind == "ura":
+            u = np.repeat(od.beam_grid(cfg.bu), cfg.bv)
+            v = np.tile(od.beam_grid(cfg.bv), cfg.bu)
+        else:
+            u, v = od.beam_grid(cfg.B), None
+        return od.make_problem(N=cfg.N, L=cfg.L, eps=e, delta=delta, fc=band.fc, omega=band.omega,
+                               ts=band.ts, px=px, py=py, u=u, v=v)
     if cfg.kind == "ura":
         return od.grid_problem(cfg.mx, cfg.my, cfg.bu, cfg.bv, cfg.N, fc=band.fc, omega=band.omega,
                                ts=band.ts, eps=e, gamma=cfg.gamma, delta=delta)
@@ -35,3 +44,11 @@ def grid_cfg(mx, my, bu, bv, N, fb=0.4, sigma2=0.1, n_sources=2, index=91):
     return synth.Config(f"grid{mx}x{my}", "ura", M=mx * my, N=N, B=bu * bv, fb=fb,
                         n_sources=n_sources, power_db_range=0.0, sigma2=sigma2, mx=mx, my=my,
                         bu=bu, bv=bv, index=index)
+
+
+def perturbed_cfg(kind, M, N, B, *, mx=0, my=0, bu=0, bv=0, perturb=0.25, fb=0.5, sigma2=0.1,
+                  n_sources=2, index=92):
+    """A non-uniform array (synth's perturbed line or grid)."""
+    return synth.Config(f"n{kind}{M}x{N}x{B}", kind, M=M, N=N, B=B, fb=fb, n_sources=n_sources,
+                        power_db_range=0.0, sigma2=sigma2, mx=mx, my=my, bu=bu, bv=bv,
+                        index=index, perturb=perturb)

@@ -235,3 +235,72 @@ def test_precompute_flag_validation():
                                           F.make_options(1.0, precision=prec, flags=host))
         assert st == F.FBST_OK, prec
         F.fbst_destroy(h)
+
+
+@pytest.mark.parametrize("two_d", [False, True])
+def test_host_tables_match_oracle_arbitrary(two_d):
+    """Non-uniform arrays (Sec. IX): the plan's direct-sum Gram column and its
+    complex-Levinson generator against the oracle's dense solve."""
+    rng = np.random.default_rng(11 + two_d)
+    d = 0.2
+    if two_d:
+        M, N, bu, bv = 12, 16, 3, 2
+        px = (np.repeat(np.arange(3), 4) + rng.uniform(-0.3, 0.3, M)) * d
+        py = (np.tile(np.arange(4), 3) + rng.uniform(-0.3, 0.3, M)) * d
+        grid = F.make_beam_grid(bu, bv)
+        u, v = np.repeat(od.beam_grid(bu), bv), np.tile(od.beam_grid(bv), bu)
+    else:
+        M, N, bu, bv = 9, 16, 7, 1
+        px = (np.arange(M) + rng.uniform(-0.3, 0.3, M)) * d
+        py, grid = None, None
+        u, v = od.beam_grid(bu), None
+    B = bu * bv
+    h = host_plan(M, N, B, geometry=F.make_arbitrary(px, py), grid=grid)
+    try:
+        info = F.fbst_plan_info(h)
+        L = info.L
+        assert info.nu_width == 8
+        assert info.p2x == max(32, 1 << (2 * bu - 1).bit_length())
+        assert info.p2y == (max(32, 1 << (2 * bv - 1).bit_length()) if two_d else 0)
+        p = od.make_problem(N=N, L=L, eps=1.01, delta=1e-3, fc=2.0, omega=0.5, ts=1.0, px=px,
+                            py=py, u=u, v=v)
+        assert np.allclose(F.fbst_plan_table(h, F.FBST_TABLE_BEAM_U, np.zeros(B)), p.u)
+        assert np.allclose(F.fbst_plan_table(h, F.FBST_TABLE_BEAM_V, np.zeros(B)), p.v)
+        gram = F.fbst_plan_table(h, F.FBST_TABLE_GRAM, np.zeros((B, L), complex))
+        gen = F.fbst_plan_table(h, F.FBST_TABLE_GENERATOR, np.zeros((B, L), complex))
+        for b in range(B):
+            A = od.toeplitz_system(p, b)
+            assert np.allclose(gram[b], A[:, 0], rtol=0, atol=1e-12 * np.abs(A[0, 0]))
+            x = od.generator(p, b)
+            assert np.linalg.norm(gen[b] - x) < 1e-8 * np.linalg.norm(x)
+    finally:
+        F.fbst_destroy(h)
+
+
+def test_arbitrary_geometry_validation():
+    band = F.make_band(2.0, 0.5, 1.0)
+    host = F.make_options(1e-3, flags=F.FBST_FLAG_HOST_ONLY)
+    g = F.make_arbitrary(np.arange(4) * 0.2)
+    g.px = None                                         # no coordinates
+    with pytest.raises(F.FbstError) as e:
+        F.fbst_plan_create(4, 8, 4, g, band, None, host)
+    assert e.value.status == F.FBST_E_INVALID
+    bad = np.arange(4) * 0.2
+    bad[2] = np.nan
+    with pytest.raises(F.FbstError) as e:
+        F.fbst_plan_create(4, 8, 4, F.make_arbitrary(bad), band, None, host)
+    assert e.value.status == F.FBST_E_INVALID
+    # a 2-D oversampled grid of 256 x 256 cells does not fit one workgroup's LDS
+    xy = np.arange(16) * 0.2
+    with pytest.raises(F.FbstError) as e:
+        F.fbst_plan_create(16, 8, 128 * 128, F.make_arbitrary(xy, xy), band,
+                           F.make_beam_grid(128, 128), host)
+    assert e.value.status == F.FBST_E_UNSUPPORTED
+    # float64 plans spread with 16 points; p2x covers twice the modes
+    h = F.fbst_plan_create(4, 8, 20, F.make_arbitrary(xy[:4]), band, None,
+                           F.make_options(1e-3, precision="fp64", flags=F.FBST_FLAG_HOST_ONLY))
+    try:
+        info = F.fbst_plan_info(h)
+        assert info.nu_width == 16 and info.p2x == 64 and info.p2y == 0
+    finally:
+        F.fbst_destroy(h)

@@ -1,0 +1,200 @@
+"""GPU parity for non-uniform arrays (Sec. IX, eq. DFT_non_unif): stage 1b as
+a type-1 non-uniform FFT per frequency, through the C ABI, against the FP64
+oracle's direct sums.
+
+The non-uniform FFT approximates the fan sum to its kernel's accuracy (about
+1e-7 relative with the 8-point kernel of float32 plans, near float64 rounding
+with the 16-point kernel of float64 plans), below the float32 target, so the
+float32 tolerance is the same 1e-5 relative L2 as for uniform arrays; the
+float64 path is held to 1e-9, far below float32 and far above what float64
+leaves at delta = sigma^2 L.
+"""
+import numpy as np
+import pytest
+
+from oracle import direct as od
+from oracle import nulling as on
+import synth
+from tests.helpers import rel, crandn, oracle_problem, perturbed_cfg
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2512_08887_amd import fbst as F  # noqa: E402
+
+TOL32 = 1e-5
+TOL64 = 1e-9
+
+
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def to_gpu(y, dtype=torch.complex64):
+    x = torch.from_numpy(np.ascontiguousarray(y)).to(dtype).cuda()
+    return x, x.cpu().numpy().astype(np.complex128)
+
+
+@pytest.mark.parametrize("M,N,B,perturb", [(32, 128, 32, 0.25), (45, 100, 37, 0.4),
+                                           (7, 40, 3, 0.1), (24, 64, 64, 0.25), (1, 33, 1, 0.3)])
+def test_line_all_stages(M, N, B, perturb):
+    """Perturbed lines (even and odd counts, ragged L, more beams than
+    elements, one element and one beam): stage 1b and the beams."""
+    need_gpu()
+    cfg = perturbed_cfg("ula", M, N, B, perturb=perturb, index=94 + M)
+    plan = F.plan_for_config(cfg)
+    assert plan.info.nu_width == 8
+    p = oracle_problem(cfg, cfg.delta_noise)
+    x, y32 = to_gpu(cfg.scene().block(0))
+    out = plan.execute(x)
+    w = plan.stage(1, plan.stage(0, x[None].contiguous()))
+    torch.cuda.synchronize()
+    ew = rel(w[0].cpu().numpy(), od.project(y32, p))
+    e = rel(out.cpu().numpy(), od.beams(y32, p))
+    print(f"non-uniform line M={M} N={N} B={B}: W rel err {ew:.2e}, beams {e:.2e}")
+    assert ew < TOL32 and e < TOL32
+
+
+@pytest.mark.parametrize("mx,my,bu,bv,N", [(8, 8, 8, 8, 64), (5, 6, 7, 4, 48), (4, 4, 16, 3, 32)])
+def test_plane_all_stages(mx, my, bu, bv, N):
+    """Perturbed planar arrays: 2-D non-uniform FFT over the (u, v) beam grid."""
+    need_gpu()
+    cfg = perturbed_cfg("ura", mx * my, N, bu * bv, mx=mx, my=my, bu=bu, bv=bv, index=95)
+    plan = F.plan_for_config(cfg)
+    assert plan.info.p2y >= 2 * bv
+    p = oracle_problem(cfg, cfg.delta_noise)
+    x, y32 = to_gpu(cfg.scene().block(0))
+    out = plan.execute(x)
+    w = plan.stage(1, plan.stage(0, x[None].contiguous()))
+    torch.cuda.synchronize()
+    ew = rel(w[0].cpu().numpy(), od.project(y32, p))
+    e = rel(out.cpu().numpy(), od.beams(y32, p))
+    print(f"non-uniform plane {mx}x{my} -> {bu}x{bv}: W rel err {ew:.2e}, beams {e:.2e}")
+    assert ew < TOL32 and e < TOL32
+
+
+def test_line_fp64():
+    need_gpu()
+    cfg = perturbed_cfg("ula", 40, 96, 40, index=96)
+    plan = F.plan_for_config(cfg, precision="fp64")
+    assert plan.info.nu_width == 16
+    x, y64 = to_gpu(cfg.scene().block(0), torch.complex128)
+    out = plan.execute(x).cpu().numpy()
+    e = rel(out, od.beams(y64, oracle_problem(cfg, cfg.delta_noise)))
+    print(f"non-uniform line fp64: rel err {e:.2e}")
+    assert e < TOL64
+
+
+def test_plane_fp64():
+    need_gpu()
+    cfg = perturbed_cfg("ura", 36, 40, 30, mx=6, my=6, bu=6, bv=5, index=97)
+    plan = F.plan_for_config(cfg, precision="fp64")
+    x, y64 = to_gpu(cfg.scene().block(0), torch.complex128)
+    out = plan.execute(x).cpu().numpy()
+    e = rel(out, od.beams(y64, oracle_problem(cfg, cfg.delta_noise)))
+    print(f"non-uniform plane fp64: rel err {e:.2e}")
+    assert e < TOL64
+
+
+def test_batched_equals_single_and_is_deterministic():
+    """Blocks are independent, and the spreading's LDS accumulation is owned
+    by one wave per frequency, so every launch shape gives the same bits."""
+    need_gpu()
+    cfg = perturbed_cfg("ula", 48, 128, 40, index=98)
+    sc = cfg.scene()
+    x, _ = to_gpu(np.stack([sc.block(k) for k in range(5)]))
+    plan = F.plan_for_config(cfg)
+    a = plan.execute_batched(x)
+    b = plan.execute_batched(x, max_chunk=2)
+    c = torch.stack([plan.execute(x[k].contiguous()) for k in range(5)])
+    d = plan.execute_batched(x)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b) and torch.equal(a, c) and torch.equal(a, d)
+
+
+def test_large_line_sampled_beams():
+    """The non-uniform 256-element line (M = B = 256, N = 1024, L = 2048, every
+    element moved by up to a quarter spacing): four blocks in one launch, every
+    beam finite, a spread of beams of two blocks against the oracle."""
+    need_gpu()
+    cfg = synth.config("nula256")
+    sc = cfg.scene()
+    x, y32 = to_gpu(np.stack([sc.block(k) for k in range(4)]))
+    plan = F.plan_for_config(cfg)
+    out = plan.execute_batched(x, workspace=plan.workspace(4)).cpu().numpy()
+    assert np.isfinite(out).all()
+    p = oracle_problem(cfg, cfg.delta_noise)
+    idx = [0, 1, 77, 128, 200, 255]
+    e = max(rel(out[k][idx], od.beams(y32[k], p, idx)) for k in (0, 3))
+    print(f"nula256 sampled beams rel err {e:.2e}")
+    assert e < TOL32
+
+
+def test_large_plane_sampled_beams():
+    """The non-uniform 16 x 16 grid (16 x 16 beams, N = 512)."""
+    need_gpu()
+    cfg = synth.config("nura16")
+    x, y32 = to_gpu(cfg.scene().block(0))
+    plan = F.plan_for_config(cfg)
+    out = plan.execute(x).cpu().numpy()
+    assert np.isfinite(out).all()
+    p = oracle_problem(cfg, cfg.delta_noise)
+    idx = [0, 17, 100, 128, 255]
+    e = rel(out[idx], od.beams(y32, p, idx))
+    print(f"nura16 sampled beams rel err {e:.2e}")
+    assert e < TOL32
+
+
+def test_plane_wave_on_perturbed_line():
+    """A noise-free plane wave from a grid direction comes out of its own beam
+    at the oracle's bias level."""
+    need_gpu()
+    cfg = perturbed_cfg("ula", 64, 256, 64, index=99)
+    delta = 1e-2 * cfg.L
+    p = oracle_problem(cfg, delta)
+    b0 = 41
+    f, a = synth._draw_waveform(np.random.default_rng(5), cfg.band, 1.0, 256)
+    sc = synth.Scene(cfg.array, cfg.band, [synth.Source(u=float(p.u[b0]), v=0.0, freqs=f, amps=a)],
+                     0.0, 0, cfg.N)
+    plan = F.plan_for_config(cfg, delta=delta)
+    x, y32 = to_gpu(sc.clean_block(0))
+    out = plan.execute(x).cpu().numpy()
+    assert int(np.argmax(np.sum(np.abs(out) ** 2, axis=1))) == b0
+    s = sc.source_samples(0)
+    bias = rel(od.beams(y32, p, [b0])[0], s)
+    assert abs(rel(out[b0], s) - bias) < 1e-5
+
+
+def test_nulling_and_directions_on_perturbed_line():
+    """The beamspace applications run unchanged on a non-uniform array
+    (Sec. IX): nulling of an on-grid and an off-grid interferer, and beams at
+    off-grid directions."""
+    need_gpu()
+    cfg = perturbed_cfg("ula", 16, 48, 12, index=100)
+    plan = F.plan_for_config(cfg)
+    p = oracle_problem(cfg, cfg.delta_noise)
+    rng = np.random.default_rng(3)
+    x, y32 = to_gpu(crandn(rng, 2, cfg.M, cfg.N))
+    nl = F.Nulls(plan, [4])
+    out = nl.execute(x).cpu().numpy()
+    scale = np.linalg.norm(od.beams(y32[0], p))
+    e = max(np.linalg.norm(out[k] - on.nulled_beams(y32[k], p, [4])) / scale for k in range(2))
+    nl.close()
+    uq = 0.5 * (p.u[2] + p.u[3])
+    nd = F.Nulls(plan, u=[uq])
+    outd = nd.execute(x).cpu().numpy()
+    pe = od.make_problem(N=p.N, L=p.L, eps=p.eps, delta=p.delta, fc=p.fc, omega=p.omega, ts=p.ts,
+                         px=p.px, py=p.py, u=np.append(p.u, uq), v=np.append(p.v, 0.0))
+    ed = max(np.linalg.norm(outd[k] - on.nulled_beams(y32[k], pe, [p.B], beam_idx=np.arange(p.B)))
+             / scale for k in range(2))
+    nd.close()
+    ud = [uq, -0.71]
+    dr = F.Directions(plan, ud)
+    outs = dr.execute(x).cpu().numpy()
+    px = od.make_problem(N=p.N, L=p.L, eps=p.eps, delta=p.delta, fc=p.fc, omega=p.omega, ts=p.ts,
+                         px=p.px, py=p.py, u=np.append(p.u, ud), v=np.zeros(p.B + 2))
+    es = max(rel(outs[k], od.beams(y32[k], px, beam_idx=[p.B, p.B + 1])) for k in range(2))
+    dr.close()
+    print(f"perturbed line: nulling on-grid {e:.2e}, off-grid {ed:.2e}; directions {es:.2e}")
+    assert e < TOL32 and ed < TOL32 and es < TOL32
