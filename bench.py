@@ -173,12 +173,13 @@ def stored_traffic(kernel, grid):
     return c["FETCH_SIZE"] + c["WRITE_SIZE"]
 
 
-def precompute_bench(F, torch, *, steps=10, warmup=2, nblk=1024, chunk=256, log=print):
+def precompute_bench(F, torch, *, steps=10, warmup=2, nblk=1024, chunk=256, log=print, checks=None):
     """The paper's operating point (128-element line, N = 64, L = 128, 128
     beams; synthetic stand-in, 1024 blocks): stage 2 as the Gohberg-Semencul
-    kernel against the precomputed per-beam product on the matrix cores."""
+    kernel against the precomputed per-beam product on the matrix cores.
+    Accuracy against the oracle is appended to checks (run with the CPU
+    baseline)."""
     import synth
-    from oracle import direct as od
     cfg = synth.config("ula128n64")
     sc = cfg.scene()
     base = np.stack([sc.block(k) for k in range(64)])
@@ -233,14 +234,22 @@ def precompute_bench(F, torch, *, steps=10, warmup=2, nblk=1024, chunk=256, log=
         log(f"[bench] n64 {name}: {ms:.3f} ms per {nblk} blocks, stage 2 "
             f"{r['stage2_ms_per_launch'] * 1e3:.1f} us per {chunk}-block launch, plan {plan_s:.2f} s")
         plan.close()
-    p = od.line_problem(cfg.M, cfg.N, cfg.B, fc=cfg.band.fc, omega=cfg.band.omega, ts=cfg.band.ts,
-                        eps=cfg.eps, gamma=cfg.gamma, delta=cfg.delta_noise)
-    ref = od.beams(x[0].cpu().numpy().astype(np.complex128), p)
-    out["accuracy_vs_oracle"] = {k: float(np.linalg.norm(v - ref) / np.linalg.norm(ref))
-                                 for k, v in beams.items()}
+    x0 = x[0].cpu().numpy().astype(np.complex128)
+
+    def problem():
+        from oracle import direct as od
+        return od.line_problem(cfg.M, cfg.N, cfg.B, fc=cfg.band.fc, omega=cfg.band.omega,
+                               ts=cfg.band.ts, eps=cfg.eps, gamma=cfg.gamma, delta=cfg.delta_noise)
+
+    def accuracy():
+        from oracle import direct as od
+        ref = od.beams(x0, problem())
+        out["accuracy_vs_oracle"] = {k: float(np.linalg.norm(v - ref) / np.linalg.norm(ref))
+                                     for k, v in beams.items()}
+    if checks is not None:
+        checks.append(accuracy)
 
     # beamspace nulling of interferers at 1 and 4 beams (Sec. VIII), precomputed stage 2
-    from oracle import nulling as on
     plan = F.plan_for_config(cfg, flags=F.FBST_FLAG_PRECOMPUTE)
     nul = {}
     for qs in ([40], [20, 40, 60, 100]):
@@ -260,16 +269,120 @@ def precompute_bench(F, torch, *, steps=10, warmup=2, nblk=1024, chunk=256, log=
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / steps
         idx = [0, qs[0], 77]
-        refn = on.nulled_beams(x[0].cpu().numpy().astype(np.complex128), p, qs, beam_idx=idx)
         got = bo[0].cpu().numpy()[idx]
-        nul[f"P={len(qs)}"] = {"value": samples / (ms / 1e3), "unit": "beam-samples/s",
-                               "ms_per_step": ms, "tables_build_s": build_s,
-                               "rel_l2_vs_oracle": float(np.linalg.norm(got - refn) / np.linalg.norm(refn))}
+        r = {"value": samples / (ms / 1e3), "unit": "beam-samples/s", "ms_per_step": ms,
+             "tables_build_s": build_s}
+        nul[f"P={len(qs)}"] = r
+
+        def nulling_accuracy(r=r, qs=qs, idx=idx, got=got):
+            from oracle import nulling as on
+            refn = on.nulled_beams(x0, problem(), qs, beam_idx=idx)
+            r["rel_l2_vs_oracle"] = float(np.linalg.norm(got - refn) / np.linalg.norm(refn))
+        if checks is not None:
+            checks.append(nulling_accuracy)
         log(f"[bench] n64 nulling P={len(qs)}: {ms:.3f} ms per {nblk} blocks, tables {build_s:.2f} s")
         nl.close()
     plan.close()
     out["nulling"] = nul
     return out
+
+
+def nonuniform_bench(F, torch, *, steps=10, warmup=2, log=print, checks=None):
+    """Non-uniform arrays (Sec. IX): the 256-element line with every element
+    moved by up to a quarter spacing (same band, blocks and delta as the
+    uniform line) and the perturbed 16 x 16 grid.  Stage 1b is the type-1
+    non-uniform FFT per frequency (spread kernel, then one FFT pass per axis);
+    its roofline is HBM bandwidth over the algorithmic bytes of the two
+    kernels."""
+    import synth
+    stream = torch.cuda.current_stream()
+    out = {}
+    for name in ("nula256", "nura16"):
+        cfg = synth.config(name)
+        nblk = cfg.n_blocks
+        sc = cfg.scene()
+        x = torch.from_numpy(np.stack([sc.block(k) for k in range(nblk)])).to(torch.complex64).cuda()
+        t0 = time.perf_counter()
+        plan = F.plan_for_config(cfg)
+        plan_s = time.perf_counter() - t0
+        info = plan.info
+        ws = plan.workspace(nblk)
+        bo = torch.empty((nblk, cfg.B, cfg.N), dtype=torch.complex64, device="cuda")
+        for _ in range(warmup):
+            plan.execute_batched(x, beams=bo, workspace=ws)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(steps):
+            plan.execute_batched(x, beams=bo, workspace=ws)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        # stage 1b alone over the step's blocks (one launch of each kernel)
+        yhat = plan.stage(0, x, nblocks=nblk)
+        zws = plan.workspace(nblk)
+        w = plan.stage(1, yhat, nblocks=nblk, workspace=zws)
+        a0 = torch.cuda.Event(enable_timing=True)
+        a1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a0.record(stream)
+        for _ in range(20):
+            plan.stage(1, yhat, nblocks=nblk, out=w, workspace=zws)
+        a1.record(stream)
+        torch.cuda.synchronize()
+        s1b = a0.elapsed_time(a1) / 20
+        nfx, nfy = info.p2x, max(info.p2y, 1)
+        cells, L, M, B = nfx * nfy, info.L, cfg.M, cfg.B
+        # spread: Yhat in, tables (pre + positions per axis) once, grid out;
+        # per axis pass: its input in, its output out
+        tables = M * L * 8 * (2 + (1 if info.p2y else 0))
+        byts = nblk * (M * L * 8 + cells * L * 8) + tables
+        if info.p2y:
+            byts += nblk * (cells * L * 8 + cfg.bu * nfy * L * 8) + nblk * (cfg.bu * nfy * L * 8 + B * L * 8)
+        else:
+            byts += nblk * (cells * L * 8 + B * L * 8)
+        ach = byts / (s1b / 1e3)
+        idx = [0, 37, B // 2, B - 1]
+        got = bo[0].cpu().numpy()[idx]
+        x0 = x[0].cpu().numpy().astype(np.complex128)
+        out[name] = {
+            "workload": f"{name}: {'grid %dx%d' % (cfg.mx, cfg.my) if cfg.kind == 'ura' else 'line'} "
+                        f"M={M}, B={B}, N={cfg.N}, L={L}, elements moved by up to {cfg.perturb} spacing, "
+                        f"{nblk} blocks per step",
+            "value": nblk * B * cfg.N / (ms / 1e3), "unit": "beam-samples/s", "ms_per_step": ms,
+            "plan_s": plan_s, "oversampled_grid": [nfx, nfy], "kernel_width": info.nu_width,
+            "stage1b_ms_per_launch": s1b,
+            "stage1b_roofline": {"kernels": "k_nu_spread + k_axis_dft", "bound": "hbm",
+                                 "achieved": ach / 1e9, "peak": 8000.0, "unit": "GB/s",
+                                 "frac": ach / 8e12, "bytes_per_launch": byts},
+        }
+
+        def accuracy(r=out[name], cfg=cfg, idx=idx, got=got, x0=x0):
+            from oracle import direct as od
+            ref = od.beams(x0, _oracle_problem(cfg), idx)
+            r["rel_l2_vs_oracle"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        if checks is not None:
+            checks.append(accuracy)
+        log(f"[bench] {name}: {ms:.3f} ms per {nblk} blocks, stage 1b {s1b * 1e3:.1f} us "
+            f"({ach / 1e9:.0f} GB/s), plan {plan_s:.2f} s")
+        plan.close()
+        del x, ws, zws, yhat, w, bo
+    return out
+
+
+def _oracle_problem(cfg):
+    """The oracle's Problem of a perturbed synthetic array (positions from the
+    input generator, beam grid of eq. (thetab))."""
+    from oracle import direct as od
+    px, py = cfg.array.positions()
+    if cfg.kind == "ura":
+        u, v = np.repeat(od.beam_grid(cfg.bu), cfg.bv), np.tile(od.beam_grid(cfg.bv), cfg.bu)
+    else:
+        u, v = od.beam_grid(cfg.B), None
+    b = cfg.band
+    return od.make_problem(N=cfg.N, L=cfg.L, eps=cfg.eps, delta=cfg.delta_noise, fc=b.fc,
+                           omega=b.omega, ts=b.ts, px=px, py=py, u=u, v=v)
 
 
 def serve_bench(F, torch, configs, *, seconds=2.0, loads=(0.5, 0.8, 0.95), burst=768,
@@ -381,6 +494,7 @@ def main():
     ap.add_argument("--no-n64", action="store_true",
                     help="skip the N = 64 Gohberg-Semencul vs precomputed stage-2 comparison")
     ap.add_argument("--no-variants", action="store_true", help="skip the bf16/fp16 split variants")
+    ap.add_argument("--no-nu", action="store_true", help="skip the non-uniform array measurement")
     ap.add_argument("--serve-only", action="store_true", help="only the serving-mix measurement")
     ap.add_argument("--serve-seconds", type=float, default=2.0)
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
@@ -609,10 +723,14 @@ def main():
     torch.cuda.synchronize()
     result["stage1a_ms_per_launch"] = s1a.elapsed_time(s1b)
 
+    oracle_checks = []          # oracle comparisons, run with the CPU baseline leg only
     if not args.no_n64:
         result["precompute_n64"] = precompute_bench(
             F, torch, steps=max(2, min(args.steps, 10)), warmup=1,
-            log=lambda m: print(m, file=sys.stderr, flush=True))
+            log=lambda m: print(m, file=sys.stderr, flush=True), checks=oracle_checks)
+    if not args.no_nu:
+        result["nonuniform"] = nonuniform_bench(
+            F, torch, log=lambda m: print(m, file=sys.stderr, flush=True), checks=oracle_checks)
     if not args.no_serve:
         print("[bench] serving mix", file=sys.stderr, flush=True)
         log = lambda m: print(m, file=sys.stderr, flush=True)
@@ -632,6 +750,10 @@ def main():
         for k, v in variants.items():
             acc[k] = float(np.linalg.norm(v["beams0"][idx] - ref) / np.linalg.norm(ref))
         result["accuracy_vs_oracle"] = {"rel_l2": acc, "sample": "block 0, the 16 oracle beams"}
+        print(f"[bench] oracle accuracy checks of the other measurements ({len(oracle_checks)})",
+              file=sys.stderr, flush=True)
+        for check in oracle_checks:
+            check()
     if variants:
         result["variants"] = {k: {kk: vv for kk, vv in v.items() if kk != "beams0"}
                               for k, v in variants.items()}

@@ -156,6 +156,8 @@ typedef struct {
   int stage2_precomputed; /* 1 when stage 2 applies a precomputed K (FBST_FLAG_PRECOMPUTE) */
   int nu_width;      /* ARBITRARY: spreading kernel width in grid points (p2x,
                         p2y are then the oversampled grid sizes); else 0       */
+  int nu_lanes;      /* ARBITRARY with bv = 1: elements spread at once per
+                        frequency (1..16, chosen by the plan); else 0          */
 } fbst_info;
 
 typedef struct fbst_plan fbst_plan;

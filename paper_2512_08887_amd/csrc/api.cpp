@@ -63,6 +63,12 @@ size_t align_up(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 // Staging of host tables into one device allocation.
 struct Upload {
   std::vector<unsigned char> blob;
+  size_t add_ints(const std::vector<int>& v) {
+    const size_t off = align_up(blob.size());
+    blob.resize(off + v.size() * sizeof(int));
+    if (!v.empty()) std::memcpy(blob.data() + off, v.data(), v.size() * sizeof(int));
+    return off;
+  }
   size_t add(const std::vector<fbst::zd>& v, bool as_double) {
     const size_t off = align_up(blob.size());
     const size_t bytes = v.size() * (as_double ? 16 : 8);
@@ -122,7 +128,7 @@ fbst_status upload(fbst_plan* pl) {
   }
   const size_t o_nup = up.add(h.nu_pre, d1), o_nux = up.add(h.nu_posx, d1),
                o_nuy = up.add(h.nu_posy, d1), o_nucx = up.add(h.nu_cx, d1),
-               o_nucy = up.add(h.nu_cy, d1);
+               o_nucy = up.add(h.nu_cy, d1), o_nuo = up.add_ints(h.nu_order);
   const size_t o_G1 = up.add(h.G1, d2), o_G2 = up.add(h.G2, d2);
   const size_t o_pre3 = up.add(h.pre3, d2), o_H3 = up.add(h.H3, d2), o_post3 = up.add(h.post3, d2);
   const size_t tables = align_up(up.blob.size());
@@ -165,6 +171,7 @@ fbst_status upload(fbst_plan* pl) {
     pl->nu_pre = b + o_nup;
     pl->nu_posx = b + o_nux;
     pl->nu_cx = b + o_nucx;
+    pl->nu_order = reinterpret_cast<const int*>(b + o_nuo);
     if (p.p2y) {
       pl->nu_posy = b + o_nuy;
       pl->nu_cy = b + o_nucy;
@@ -209,7 +216,8 @@ hipError_t run_stage1(const fbst_plan* pl, int nb, const void* yhat, void* w, vo
     // axis on [nb][bu][nfy][1][L] -> w [nb][bu][bv][1][L]
     const int nfy = p.p2y ? p.p2y : 1;
     hipError_t e = fbst::launch_nu_spread<T1>(p.nuw, yhat, z, pl->nu_pre, pl->nu_posx, pl->nu_posy,
-                                              p.M, p.p2x, nfy, p.nu_beta, p.L, nb, st);
+                                              pl->nu_order, pl->nu_lanes, p.M, p.p2x, nfy,
+                                              p.nu_beta, p.L, nb, st);
     if (e != hipSuccess) return e;
     if (!p.p2y)
       return fbst::launch_axis_dft<T1>(p.p2x, z, w, pl->nu_cx, pl->tw1, p.bu, 1, 1, p.L, nb, st);
@@ -538,6 +546,7 @@ fbst_status fbst_plan_create(int M, int N, int B, const fbst_geometry* geometry,
     delete pl;
     return fail(st, msg);
   }
+  pl->nu_lanes = pl->host.nu_lanes;
   if (!pl->host_only) {
     st = upload(pl);
     if (st != FBST_OK) {
@@ -974,6 +983,7 @@ fbst_status fbst_plan_info(const fbst_plan* plan, fbst_info* info) {
   info->p1_split = p.p1s;
   info->stage2_precomputed = plan->K ? 1 : 0;
   info->nu_width = p.nuw;
+  info->nu_lanes = (p.kind == FBST_ARBITRARY && !p.p2y) ? plan->nu_lanes : 0;
   return FBST_OK;
 }
 

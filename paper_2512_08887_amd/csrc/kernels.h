@@ -53,13 +53,15 @@ hipError_t launch_axis_czt(int P, const void* in, void* out, const void* pre, co
 
 // Stage 1b for arbitrary positions (type-1 non-uniform FFT per frequency):
 // spread yhat [nb][M][L] onto the oversampled grid out [nb][nfx][nfy][L]
-// (width W = 8 for float, 16 for double; tables [M][L]; posy only when nfy > 1),
+// (width W = 8 for float, 16 for double; tables [M][L]; posy only when
+// nfy > 1; for nfy = 1, lanes elements per frequency at once in the element
+// order given, whose supports the caller has checked to be disjoint),
 // then per axis an nf-point FFT and the modes a - a_out/2 scaled by corr[a]
 // (layout [nb][pre_n][P][post_n][L] -> [nb][pre_n][a_out][post_n][L]).
 template <typename T>
 hipError_t launch_nu_spread(int width, const void* in, void* out, const void* pre, const void* posx,
-                            const void* posy, int M, int nfx, int nfy, double beta, int L,
-                            int nblocks, hipStream_t st);
+                            const void* posy, const int* order, int lanes, int M, int nfx, int nfy,
+                            double beta, int L, int nblocks, hipStream_t st);
 template <typename T>
 hipError_t launch_axis_dft(int P, const void* in, void* out, const void* corr, const void* tw,
                            int a_out, int pre_n, int post_n, int L, int nblocks, hipStream_t st);

@@ -367,99 +367,238 @@ __global__ __launch_bounds__(ShapeK2<P>::THREADS) FBST_K12_ATTR void k_axis_czt(
 // ---------------------------------------------------------------------------
 // Stage 1b for arbitrary element positions (Sec. IX, eq. DFT_non_unif): per
 // frequency l a type-1 non-uniform FFT over the modes of the beam grid.
-//   k_nu_spread: c_m = Yhat[m][l] pre[m][l] is spread onto an oversampled
-//     grid (nfx x nfy, l-fastest cells) with a W-point exponential-of-
-//     semicircle kernel per axis, accumulated with LDS atomics, and the grid
-//     is written out as [blk][nfx][nfy][L];
+//   spread: c_m = Yhat[m][l] pre[m][l] is spread onto an oversampled grid
+//     (nfx x nfy cells per frequency, in LDS) with a W-point exponential-of-
+//     semicircle kernel per axis, and the grid is written out as
+//     [blk][nfx][nfy][L];
 //   k_axis_dft: per axis, an nf-point FFT (exp(+j)) of the grid and the output
 //     modes a - a_out/2, each scaled by the deconvolution factor corr[a].
-// A workgroup of the spread takes G consecutive frequencies of one block, in
-// min(G, 4) waves; each wave owns Gw = G / waves of them (lane = r Gw + g'),
-// so every update of one frequency's grid comes from one wave: LDS atomics of
-// one instruction and of successive instructions of a wave apply in a fixed
-// order, and the grid is the same bit for bit on every run.
+// The spread needs no atomics: every cell update is a read and a write of LDS
+// by the one lane that owns it at that moment, and a wave's LDS operations
+// complete in program order, so the grid is the same bit for bit on every run.
 // ---------------------------------------------------------------------------
-constexpr int kSpreadThreads = 256;
 
-// Kernel values at the W grid points j0 + t of a point f grid cells beyond
-// j0 + W/2 - 1: phi(z_t), z_t = (t - W/2 + 1 - f) 2 / W,
-// phi(z) = exp(beta (sqrt(1 - z^2) - 1)).
+// Kernel value of tap t (grid cell j0 + t) for a point f cells beyond cell
+// j0 + W/2 - 1: phi(z), z = (t - W/2 + 1 - f) 2 / W,
+// phi(z) = exp(beta (sqrt(1 - z^2) - 1)) = 2^(b2 sqrt(1 - z^2) - b2) with
+// b2 = beta log2(e) (the caller passes b2).  float: the hardware square root
+// and base-2 exponential (about 1 ulp each, far below the kernel's own
+// accuracy); double: the library functions.
 template <typename T, int W>
-__device__ __forceinline__ void es_taps(T f, T beta, T (&k)[W]) {
-#pragma unroll
-  for (int t = 0; t < W; ++t) {
-    const T z = (static_cast<T>(t - W / 2 + 1) - f) * static_cast<T>(2.0 / W);
-    const T q = static_cast<T>(1) - z * z;
-    const T qc = q > static_cast<T>(0) ? q : static_cast<T>(0);
-    if constexpr (sizeof(T) == 4) k[t] = expf(beta * (sqrtf(qc) - 1.0f));
-    else k[t] = ::exp(beta * (::sqrt(qc) - 1.0));
+__device__ __forceinline__ T es_tap(int t, T f, T b2) {
+  constexpr T s = static_cast<T>(2.0 / W);
+  const T z = static_cast<T>(t - W / 2 + 1) * s - f * s;
+  const T q = static_cast<T>(1) - z * z;
+  const T qc = q > static_cast<T>(0) ? q : static_cast<T>(0);
+  if constexpr (sizeof(T) == 4) return __builtin_amdgcn_exp2f(b2 * __builtin_amdgcn_sqrtf(qc) - b2);
+  else return ::exp2(b2 * ::sqrt(qc) - b2);
+}
+
+// LDS layout of the grids.  Line: cell c at word c + c / 16 (one pad word per
+// 16 cells, so cells 16, 32 or 64 apart -- the spacing of elements spread at
+// once -- fall in different banks).  Plane: cell (jx, jy) at word
+// jx (nfy + 8) + jy, so the W x W taps of one element spread over the banks.
+// Consecutive frequencies' grids start 8 banks apart (stride = 8 mod 32).
+__device__ __forceinline__ int swz(int c) { return c + (c >> 4); }
+__host__ __device__ constexpr int spread_words(int nfx, int nfy) {
+  return nfy > 1 ? nfx * (nfy + 8) : nfx + nfx / 16;
+}
+__host__ __device__ constexpr int spread_stride(int nfx, int nfy) {
+  return spread_words(nfx, nfy) + ((40 - spread_words(nfx, nfy) % 32) % 32);
+}
+
+// Zero the G padded grids, or write them out to [blk][cells][L] at l = l0 + g.
+template <typename T>
+__device__ __forceinline__ void spread_zero(T* lds, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) lds[i] = static_cast<T>(0);
+}
+template <typename T, typename Word>
+__device__ __forceinline__ void spread_store(const T* re, const T* im, int S, int cells, int G,
+                                             cx<T>* dst, int l0, int L, Word&& word) {
+  for (int i = threadIdx.x; i < cells * G; i += blockDim.x) {
+    const int g = i % G, j = i / G;
+    if (l0 + g < L) dst[static_cast<size_t>(j) * L + g] = cx<T>{re[g * S + word(j)], im[g * S + word(j)]};
   }
 }
 
-template <typename T, int W, bool TWO_D, int LDS_BYTES>
-__global__ __launch_bounds__(kSpreadThreads) void k_nu_spread(
+constexpr int kSpreadGroup = 8;               // elements whose loads are in flight together
+
+// Line of beams (nfy = 1).  A workgroup takes G consecutive frequencies of one
+// block with R lanes each (lane = r Gw + g' inside a wave of Gw frequencies,
+// so the Gw lanes of one r read Gw consecutive l).  Lane r takes the elements
+// order[r C + s], s < C = ceil(M / R), in turn: W cells read, updated, written.
+// The plan chooses R such that the supports of the R elements of one step are
+// disjoint at every frequency, so no cell is touched by two lanes at once.
+// Element data are loaded a group ahead (row indices two groups ahead).
+template <typename T, int W, int LDS_BYTES>
+__global__ __launch_bounds__(256) void k_nu_spread_line(
     const cx<T>* __restrict__ in, cx<T>* __restrict__ out, const cx<T>* __restrict__ pre,
-    const cx<T>* __restrict__ posx, const cx<T>* __restrict__ posy, int M, int nfx, int nfy, int G,
-    T beta, int L, int nblocks) {
+    const cx<T>* __restrict__ pos, const int* __restrict__ order, int M, int nf, int G, int R,
+    T b2, int L, int nblocks) {
+  constexpr int D = kSpreadGroup;
   __shared__ T grid_lds[LDS_BYTES / sizeof(T)];
-  const int cells = nfx * nfy;
+  const int S = spread_stride(nf, 1);
   T* re = grid_lds;
-  T* im = grid_lds + cells * G;
+  T* im = grid_lds + S * G;
   const int wl = xcd_linear(gridDim.x);
   const int blk = wl % nblocks;
   const int tile = wl / nblocks;
-  const int nthreads = blockDim.x;                 // 64 min(G, 4)
-  const int Gw = G / (nthreads / 64);              // frequencies per wave
-  const int lane = threadIdx.x % 64;
-  const int g = (threadIdx.x / 64) * Gw + lane % Gw, R = 64 / Gw;
-  const int l = tile * G + g;
-  for (int i = threadIdx.x; i < 2 * cells * G; i += nthreads) grid_lds[i] = static_cast<T>(0);
+  const int Gw = (G * R > 64) ? 64 / R : G;
+  const int i = threadIdx.x, per_wave = Gw * R;
+  const int g = (i / per_wave) * Gw + i % Gw;
+  const int r = (i % per_wave) / Gw;
+  spread_zero(grid_lds, 2 * S * G);
   __syncthreads();
-  if (l < L) {
+  const int l = tile * G + g;
+  const int C = (M + R - 1) / R;
+  const int k0 = r * C, k1 = min(M, k0 + C);
+  if (l < L && k0 < k1) {
     const cx<T>* src = in + static_cast<size_t>(blk) * M * L + l;
-    for (int m = lane / Gw; m < M; m += R) {
-      const size_t i = static_cast<size_t>(m) * L + l;
-      const cx<T> y = ldg(src + static_cast<size_t>(m) * L);
-      const cx<T> pr = ldg(pre + i);
-      const cx<T> px = ldg(posx + i);
-      cx<T> py{0, 0};
-      if constexpr (TWO_D) py = ldg(posy + i);
-      issue_fence();
-      const cx<T> c = cmul(y, pr);
-      T kx[W];
-      es_taps<T, W>(px.re, beta, kx);
-      const int jx0 = static_cast<int>(px.im);
-      if constexpr (!TWO_D) {
+    T* gre = re + g * S;
+    T* gim = im + g * S;
+    auto rows = [&](int base, int (&mm)[D]) {
 #pragma unroll
-        for (int t = 0; t < W; ++t) {
-          const int cell = ((jx0 + t) & (nfx - 1)) * G + g;
-          atomicAdd(re + cell, c.re * kx[t]);
-          atomicAdd(im + cell, c.im * kx[t]);
-        }
-      } else {
-        T ky[W];
-        es_taps<T, W>(py.re, beta, ky);
-        const int jy0 = static_cast<int>(py.im);
+      for (int d = 0; d < D; ++d) mm[d] = order[base + d < k1 ? base + d : k0];
+    };
+    auto fetch = [&](const int (&mm)[D], cx<T> (&y)[D], cx<T> (&pr)[D], cx<T> (&ps)[D]) {
 #pragma unroll
-        for (int tx = 0; tx < W; ++tx) {
-          const int row = ((jx0 + tx) & (nfx - 1)) * nfy;
-          const T cr = c.re * kx[tx], ci = c.im * kx[tx];
+      for (int d = 0; d < D; ++d) {
+        const size_t idx = static_cast<size_t>(mm[d]) * L;
+        y[d] = ldg(src + idx);
+        pr[d] = ldg(pre + idx + l);
+        ps[d] = ldg(pos + idx + l);
+      }
+    };
+    int mm[D], mn[D];
+    cx<T> y[D], pr[D], ps[D];
+    rows(k0, mm);
+    fetch(mm, y, pr, ps);
+    rows(k0 + D, mn);
+    for (int base = k0; base < k1; base += D) {
+      cx<T> y2[D], pr2[D], ps2[D];
+      const bool more = base + D < k1;
+      if (more) {
+        fetch(mn, y2, pr2, ps2);
+        rows(base + 2 * D, mn);
+      }
 #pragma unroll
-          for (int ty = 0; ty < W; ++ty) {
-            const int cell = (row + ((jy0 + ty) & (nfy - 1))) * G + g;
-            atomicAdd(re + cell, cr * ky[ty]);
-            atomicAdd(im + cell, ci * ky[ty]);
+      for (int d = 0; d < D; ++d) {
+        if (base + d < k1) {
+          const cx<T> c = cmul(y[d], pr[d]);
+          const T f = ps[d].re;
+          const int j0 = static_cast<int>(ps[d].im);
+          int cell[W];
+          T ar[W], ai[W];
+#pragma unroll
+          for (int t = 0; t < W; ++t) {
+            cell[t] = swz((j0 + t) & (nf - 1));
+            ar[t] = gre[cell[t]];
+            ai[t] = gim[cell[t]];
           }
+#pragma unroll
+          for (int t = 0; t < W; ++t) {
+            const T kv = es_tap<T, W>(t, f, b2);
+            gre[cell[t]] = ar[t] + c.re * kv;
+            gim[cell[t]] = ai[t] + c.im * kv;
+          }
+        }
+      }
+      if (more) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          y[d] = y2[d];
+          pr[d] = pr2[d];
+          ps[d] = ps2[d];
         }
       }
     }
   }
   __syncthreads();
-  cx<T>* dst = out + static_cast<size_t>(blk) * cells * L + static_cast<size_t>(tile) * G;
-  for (int i = threadIdx.x; i < cells * G; i += nthreads) {
-    const int gg = i % G, j = i / G;
-    if (tile * G + gg < L) dst[static_cast<size_t>(j) * L + gg] = cx<T>{re[i], im[i]};
+  spread_store(re, im, S, nf, G, out + static_cast<size_t>(blk) * nf * L + static_cast<size_t>(tile) * G,
+               tile * G, L, [](int j) { return swz(j); });
+}
+
+// 2-D beam grid.  One wave per frequency (G waves); lane q takes the taps
+// q + 64 i, i < TPL, as (tx, ty) = (tap / W, tap % W), of every element in
+// turn: the W x W cells of one element are distinct, so each cell update of a
+// step has one owner.  Element data are loaded a group ahead.
+template <typename T, int W, int LDS_BYTES>
+__global__ __launch_bounds__(256) void k_nu_spread_plane(
+    const cx<T>* __restrict__ in, cx<T>* __restrict__ out, const cx<T>* __restrict__ pre,
+    const cx<T>* __restrict__ posx, const cx<T>* __restrict__ posy, int M, int nfx, int nfy, int G,
+    T b2, int L, int nblocks) {
+  constexpr int TPL = (W * W + 63) / 64;
+  constexpr int D = kSpreadGroup;
+  static_assert(TPL * 64 == W * W, "W * W must be a multiple of 64");
+  __shared__ T grid_lds[LDS_BYTES / sizeof(T)];
+  const int cells = nfx * nfy, S = spread_stride(nfx, nfy), row = nfy + 8;
+  T* re = grid_lds;
+  T* im = grid_lds + S * G;
+  const int wl = xcd_linear(gridDim.x);
+  const int blk = wl % nblocks;
+  const int tile = wl / nblocks;
+  const int g = threadIdx.x / 64, q = threadIdx.x % 64;
+  spread_zero(grid_lds, 2 * S * G);
+  __syncthreads();
+  const int l = tile * G + g;
+  if (l < L) {
+    const cx<T>* src = in + static_cast<size_t>(blk) * M * L + l;
+    T* gre = re + g * S;
+    T* gim = im + g * S;
+    auto fetch = [&](int base, cx<T> (&y)[D], cx<T> (&pr)[D], cx<T> (&px)[D], cx<T> (&py)[D]) {
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        const size_t idx = static_cast<size_t>(base + d < M ? base + d : 0) * L;
+        y[d] = ldg(src + idx);
+        pr[d] = ldg(pre + idx + l);
+        px[d] = ldg(posx + idx + l);
+        py[d] = ldg(posy + idx + l);
+      }
+    };
+    cx<T> y[D], pr[D], px[D], py[D];
+    fetch(0, y, pr, px, py);
+    for (int base = 0; base < M; base += D) {
+      cx<T> y2[D], pr2[D], px2[D], py2[D];
+      const bool more = base + D < M;
+      if (more) fetch(base + D, y2, pr2, px2, py2);
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        if (base + d < M) {
+          const cx<T> c = cmul(y[d], pr[d]);
+          const int jx0 = static_cast<int>(px[d].im), jy0 = static_cast<int>(py[d].im);
+          int cell[TPL];
+          T ar[TPL], ai[TPL];
+#pragma unroll
+          for (int u = 0; u < TPL; ++u) {
+            const int tap = q + 64 * u, tx = tap / W, ty = tap % W;
+            cell[u] = ((jx0 + tx) & (nfx - 1)) * row + ((jy0 + ty) & (nfy - 1));
+            ar[u] = gre[cell[u]];
+            ai[u] = gim[cell[u]];
+          }
+#pragma unroll
+          for (int u = 0; u < TPL; ++u) {
+            const int tap = q + 64 * u, tx = tap / W, ty = tap % W;
+            const T kv = es_tap<T, W>(tx, px[d].re, b2) * es_tap<T, W>(ty, py[d].re, b2);
+            gre[cell[u]] = ar[u] + c.re * kv;
+            gim[cell[u]] = ai[u] + c.im * kv;
+          }
+        }
+      }
+      if (more) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          y[d] = y2[d];
+          pr[d] = pr2[d];
+          px[d] = px2[d];
+          py[d] = py2[d];
+        }
+      }
+    }
   }
+  __syncthreads();
+  spread_store(re, im, S, cells, G,
+               out + static_cast<size_t>(blk) * cells * L + static_cast<size_t>(tile) * G, tile * G, L,
+               [nfy, row](int j) { return (j / nfy) * row + j % nfy; });
 }
 
 // One axis of the non-uniform stage 1b: layout [blk][pre_n][P][post_n][L] in,
@@ -739,48 +878,58 @@ hipError_t launch_axis_czt(int P, const void* in, void* out, const void* pre, co
   return hipErrorInvalidValue;
 }
 
-// Frequencies per spreading workgroup: up to 16 within 64 KiB of LDS, else
-// fewer within 128 KiB; 0 if one grid does not fit.
-template <typename T>
-int spread_group(int cells, int* lds_bytes) {
-  const int per = static_cast<int>(2 * sizeof(T)) * cells;
-  for (int bytes : {64 * 1024, 128 * 1024}) {
-    int G = 16;
-    while (G > 1 && G * per > bytes) G /= 2;
-    if (G * per <= bytes && (G >= 4 || bytes == 128 * 1024 || 4 * per > 128 * 1024)) {
-      *lds_bytes = bytes;
-      return G;
-    }
-  }
-  return 0;
-}
+// LDS of a spreading workgroup: the smallest of these that holds its grids.
+constexpr int kSpreadTiers[3] = {36 * 1024, 72 * 1024, 144 * 1024};
 
 template <typename T>
 hipError_t launch_nu_spread(int width, const void* in, void* out, const void* pre, const void* posx,
-                            const void* posy, int M, int nfx, int nfy, double beta, int L,
-                            int nblocks, hipStream_t st) {
+                            const void* posy, const int* order, int lanes, int M, int nfx, int nfy,
+                            double beta, int L, int nblocks, hipStream_t st) {
   constexpr int W = sizeof(T) == 4 ? 8 : 16;
-  if (width != W || M < 1 || L < 1 || nblocks < 1 || nfx < 1 || nfy < 1 || (nfx & (nfx - 1)) ||
-      (nfy & (nfy - 1)) || (nfy > 1 && !posy))
+  if (width != W || M < 1 || L < 1 || nblocks < 1 || nfx < 2 * W || nfy < 1 || (nfx & (nfx - 1)) ||
+      (nfy & (nfy - 1)) || (nfy > 1 && (!posy || nfy < 2 * W)) || (nfy == 1 && !order) ||
+      lanes < 1 || lanes > 16 || (lanes & (lanes - 1)))
     return hipErrorInvalidValue;
-  int bytes = 0;
-  const int G = spread_group<T>(nfx * nfy, &bytes);
+  const bool plane = nfy > 1;
+  const int per = static_cast<int>(2 * sizeof(T)) * spread_stride(nfx, nfy);
+  // frequencies per workgroup: lines up to 16 (a power of two, for the lane
+  // mapping); planes 1..4 waves, whichever keeps the most waves resident
+  int G = 0, tier = 0, best = 0;
+  for (int c = plane ? 4 : 16; c >= 1; c = plane ? c - 1 : c / 2) {
+    int t = 0;
+    while (t < 3 && c * per > kSpreadTiers[t]) ++t;
+    if (t == 3) continue;
+    const int waves = (160 * 1024 / kSpreadTiers[t]) * (plane ? c : (c * lanes + 63) / 64);
+    if (waves > best) {
+      best = waves;
+      G = c;
+      tier = t;
+    }
+  }
   if (G < 1) return hipErrorInvalidValue;
   const long long ng = 1LL * nblocks * ((L + G - 1) / G);
   if (ng > 0x7fffffffLL) return hipErrorInvalidValue;
-  const dim3 grid(static_cast<unsigned>(ng)), block(64 * std::min(G, 4));
-  const T b = static_cast<T>(beta);
-  auto go = [&](auto kern) {
-    hipLaunchKernelGGL(kern, grid, block, 0, st, static_cast<const cx<T>*>(in), static_cast<cx<T>*>(out),
-                       static_cast<const cx<T>*>(pre), static_cast<const cx<T>*>(posx),
-                       static_cast<const cx<T>*>(posy), M, nfx, nfy, G, b, L, nblocks);
+  const dim3 grid(static_cast<unsigned>(ng)), block(plane ? 64 * G : G * lanes);
+  const T b = static_cast<T>(beta * 1.4426950408889634);   // beta log2(e)
+  auto go_line = [&](auto kern) {
+    hipLaunchKernelGGL(kern, grid, block, 0, st, static_cast<const cx<T>*>(in),
+                       static_cast<cx<T>*>(out), static_cast<const cx<T>*>(pre),
+                       static_cast<const cx<T>*>(posx), order, M, nfx, G, lanes, b, L, nblocks);
   };
-  if (nfy > 1) {
-    if (bytes == 64 * 1024) go(k_nu_spread<T, W, true, 64 * 1024>);
-    else go(k_nu_spread<T, W, true, 128 * 1024>);
+  auto go_plane = [&](auto kern) {
+    hipLaunchKernelGGL(kern, grid, block, 0, st, static_cast<const cx<T>*>(in),
+                       static_cast<cx<T>*>(out), static_cast<const cx<T>*>(pre),
+                       static_cast<const cx<T>*>(posx), static_cast<const cx<T>*>(posy), M, nfx,
+                       nfy, G, b, L, nblocks);
+  };
+  if (plane) {
+    if (tier == 0) go_plane(k_nu_spread_plane<T, W, kSpreadTiers[0]>);
+    else if (tier == 1) go_plane(k_nu_spread_plane<T, W, kSpreadTiers[1]>);
+    else go_plane(k_nu_spread_plane<T, W, kSpreadTiers[2]>);
   } else {
-    if (bytes == 64 * 1024) go(k_nu_spread<T, W, false, 64 * 1024>);
-    else go(k_nu_spread<T, W, false, 128 * 1024>);
+    if (tier == 0) go_line(k_nu_spread_line<T, W, kSpreadTiers[0]>);
+    else if (tier == 1) go_line(k_nu_spread_line<T, W, kSpreadTiers[1]>);
+    else go_line(k_nu_spread_line<T, W, kSpreadTiers[2]>);
   }
   return hipGetLastError();
 }
@@ -868,9 +1017,11 @@ template hipError_t launch_axis_czt<double>(int, const void*, void*, const void*
                                             const void*, const void*, int, int, int, int, int, int,
                                             hipStream_t);
 template hipError_t launch_nu_spread<float>(int, const void*, void*, const void*, const void*,
-                                            const void*, int, int, int, double, int, int, hipStream_t);
+                                            const void*, const int*, int, int, int, int, double,
+                                            int, int, hipStream_t);
 template hipError_t launch_nu_spread<double>(int, const void*, void*, const void*, const void*,
-                                             const void*, int, int, int, double, int, int, hipStream_t);
+                                             const void*, const int*, int, int, int, int, double,
+                                             int, int, hipStream_t);
 template hipError_t launch_axis_dft<float>(int, const void*, void*, const void*, const void*, int,
                                            int, int, int, int, hipStream_t);
 template hipError_t launch_axis_dft<double>(int, const void*, void*, const void*, const void*, int,

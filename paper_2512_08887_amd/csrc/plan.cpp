@@ -289,6 +289,7 @@ void build_nonuniform(const Params& p, HostTables* t) {
     if (j0 < 0) j0 += nf;
     return zd(static_cast<double>(f), static_cast<double>(j0));
   };
+  std::vector<int> j0x(two_d ? 0 : static_cast<size_t>(M) * L);
   parallel_for(M, 1LL * M * L * 64, [&](int m0, int m1) {
     for (int m = m0; m < m1; ++m) {
       const long double xs = static_cast<long double>(p.px[m]) / p.ts;
@@ -300,9 +301,46 @@ void build_nonuniform(const Params& p, HostTables* t) {
         t->nu_pre[i] = cis(2.0 * kPi * static_cast<double>(frac(fl * (uc * xs + vc * ys))));
         t->nu_posx[i] = position(fl * static_cast<long double>(p.du) * xs, nfx);
         if (two_d) t->nu_posy[i] = position(fl * static_cast<long double>(p.dv) * ys, nfy);
+        else j0x[i] = static_cast<int>(t->nu_posx[i].imag());
       }
     }
   });
+  // Line of beams: lanes per frequency of the spread.  Lane r takes the
+  // elements order[r C + s] (C = ceil(M / R)) for s = 0, 1, ...; R is the
+  // largest of 16, 8, 4, 2 for which, at every frequency and step s, the
+  // w-cell supports of those elements are pairwise disjoint on the periodic
+  // grid (else 1: one lane per frequency).
+  t->nu_order.assign(M, 0);
+  t->nu_lanes = 1;
+  if (!two_d) {
+    for (int m = 0; m < M; ++m) t->nu_order[m] = m;
+    std::stable_sort(t->nu_order.begin(), t->nu_order.end(),
+                     [&](int a, int b) { return p.px[a] < p.px[b]; });
+    for (int R = 16; R > 1 && t->nu_lanes == 1; R /= 2) {
+      const int C = (M + R - 1) / R;
+      if (C * (R - 1) >= M) continue;             // a lane would have no elements at all
+      std::atomic<bool> good{true};
+      parallel_for(L, 1LL * L * C * R * 4, [&](int l0, int l1) {
+        std::vector<int> v(R);
+        for (int l = l0; l < l1 && good.load(); ++l)
+          for (int st = 0; st < C; ++st) {
+            int n = 0;
+            for (int r = 0; r < R; ++r) {
+              const int k = r * C + st;
+              if (k < M) v[n++] = j0x[static_cast<size_t>(t->nu_order[k]) * L + l];
+            }
+            std::sort(v.begin(), v.begin() + n);
+            bool ok = n < 2 || v[0] + nfx - v[n - 1] >= w;
+            for (int a = 1; a < n && ok; ++a) ok = v[a] - v[a - 1] >= w;
+            if (!ok) {
+              good = false;
+              break;
+            }
+          }
+      });
+      if (good) t->nu_lanes = R;
+    }
+  }
   t->nu_cx = nu_deconvolution(p.bu, nfx, w, p.nu_beta);
   if (two_d) t->nu_cy = nu_deconvolution(p.bv, nfy, w, p.nu_beta);
 }
@@ -542,11 +580,13 @@ fbst_status resolve_params(int M, int N, int B, const fbst_geometry* geom, const
     double sigma = static_cast<double>(p.p2x) / p.bu;
     if (p.p2y) sigma = std::min(sigma, static_cast<double>(p.p2y) / p.bv);
     p.nu_beta = 0.98 * kPi * (1.0 - 0.5 / sigma) * p.nuw;
-    const double grid_bytes = static_cast<double>(p.p2x) * std::max(p.p2y, 1) *
-                              (p.prec == FBST_PREC_FP64 ? 16.0 : 8.0);
-    if (grid_bytes > 128.0 * 1024) {
+    // LDS words of one frequency's grid (padded layout of the spread kernels)
+    const double words = p.p2y ? static_cast<double>(p.p2x) * (p.p2y + 8) + 32.0
+                               : static_cast<double>(p.p2x) * 17.0 / 16.0 + 32.0;
+    const double grid_bytes = words * (p.prec == FBST_PREC_FP64 ? 16.0 : 8.0);
+    if (grid_bytes > 144.0 * 1024) {
       *msg = "the oversampled grid of one frequency (" + std::to_string(p.p2x) + " x " +
-             std::to_string(std::max(p.p2y, 1)) + ") exceeds 128 KiB of LDS";
+             std::to_string(std::max(p.p2y, 1)) + ") exceeds 144 KiB of LDS";
       return FBST_E_UNSUPPORTED;
     }
   }

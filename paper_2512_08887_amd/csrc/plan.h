@@ -36,6 +36,11 @@ struct HostTables {
   // offset f in [0, 1) of the point beyond grid point j0 + w/2 - 1); and the
   // deconvolution factors per output mode, nu_cx [bu], nu_cy [bv] (real).
   std::vector<zd> nu_pre, nu_posx, nu_posy, nu_cx, nu_cy;
+  // line of beams: elements in increasing x (nu_order [M]) and the lanes per
+  // frequency of the spread (each lane takes a contiguous run of that order;
+  // the runs' elements taken together never share a grid cell)
+  std::vector<int> nu_order;
+  int nu_lanes = 1;
 };
 
 struct Params {
@@ -151,6 +156,8 @@ struct fbst_plan {
   // non-uniform stage 1b (arbitrary positions)
   const void *nu_pre = nullptr, *nu_posx = nullptr, *nu_posy = nullptr, *nu_cx = nullptr,
              *nu_cy = nullptr;
+  const int* nu_order = nullptr;
+  int nu_lanes = 1;
   // stage 2 in precomputed form: K [L][B][N] complex64 (own allocation), or null
   void* K = nullptr;
   size_t K_bytes = 0;

@@ -54,7 +54,8 @@ class fbst_info(ctypes.Structure):
                 ("bu", c_int), ("bv", c_int), ("p1", c_int), ("p2x", c_int), ("p2y", c_int),
                 ("p3", c_int), ("precision", c_int), ("io_elem_bytes", c_size_t),
                 ("device_bytes", c_size_t), ("workspace_per_block", c_size_t), ("p1_split", c_int),
-                ("stage2_precomputed", c_int), ("nu_width", c_int)]
+                ("stage2_precomputed", c_int), ("nu_width", c_int),
+                ("nu_lanes", c_int)]
 
 
 class fbst_server_options(ctypes.Structure):

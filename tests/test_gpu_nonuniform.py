@@ -198,3 +198,34 @@ def test_nulling_and_directions_on_perturbed_line():
     dr.close()
     print(f"perturbed line: nulling on-grid {e:.2e}, off-grid {ed:.2e}; directions {es:.2e}")
     assert e < TOL32 and ed < TOL32 and es < TOL32
+
+
+@pytest.mark.parametrize("spread", ["wide", "clustered"])
+def test_unordered_random_lines(spread):
+    """Elements in random order at random positions: a wide aperture (the
+    points wrap the oversampled grid many times, so the plan spreads one
+    element per frequency at a time) and a clustered one."""
+    need_gpu()
+    rng = np.random.default_rng(21 if spread == "wide" else 22)
+    M, N, B = 40, 64, 24
+    px = rng.uniform(0.0, 30.0, M) if spread == "wide" else rng.normal(0.0, 0.6, M)
+    delta = 0.1 * 2 * N
+    plan = F.Plan(M, N, B, band=F.make_band(2.0, 0.5, 1.0), geometry=F.make_arbitrary(px),
+                  options=F.make_options(delta))
+    if spread == "wide":
+        assert plan.info.nu_lanes == 1
+    p = od.make_problem(N=N, L=2 * N, eps=1.01, delta=delta, fc=2.0, omega=0.5, ts=1.0, px=px,
+                        u=od.beam_grid(B))
+    x, y32 = to_gpu(crandn(rng, M, N))
+    out = plan.execute(x).cpu().numpy()
+    e = rel(out, od.beams(y32, p))
+    print(f"random line ({spread}, {plan.info.nu_lanes} lanes): rel err {e:.2e}")
+    assert e < TOL32
+
+
+def test_workload_spread_lanes():
+    """The perturbed 256-element line keeps its elements in order, so its
+    spread runs 16 elements per frequency at once."""
+    need_gpu()
+    plan = F.plan_for_config(synth.config("nula256"))
+    assert plan.info.nu_lanes == 16
