@@ -334,14 +334,16 @@ def nonuniform_bench(F, torch, *, steps=10, warmup=2, log=print, checks=None):
         s1b = a0.elapsed_time(a1) / 20
         nfx, nfy = info.p2x, max(info.p2y, 1)
         cells, L, M, B = nfx * nfy, info.L, cfg.M, cfg.B
-        # spread: Yhat in, tables (pre + positions per axis) once, grid out;
-        # per axis pass: its input in, its output out
+        fused = info.p2y == 0 and 256 <= nfx <= 4096
+        # Yhat in, tables (pre + positions per axis) once per launch, W out; the
+        # two-kernel form also writes the oversampled grid and reads it back
+        # (and, in 2-D, the x pass's output)
         tables = M * L * 8 * (2 + (1 if info.p2y else 0))
-        byts = nblk * (M * L * 8 + cells * L * 8) + tables
-        if info.p2y:
-            byts += nblk * (cells * L * 8 + cfg.bu * nfy * L * 8) + nblk * (cfg.bu * nfy * L * 8 + B * L * 8)
-        else:
-            byts += nblk * (cells * L * 8 + B * L * 8)
+        byts = nblk * (M * L * 8 + B * L * 8) + tables
+        if not fused:
+            byts += nblk * 2 * cells * L * 8
+            if info.p2y:
+                byts += nblk * 2 * cfg.bu * nfy * L * 8
         ach = byts / (s1b / 1e3)
         idx = [0, 37, B // 2, B - 1]
         got = bo[0].cpu().numpy()[idx]
@@ -353,15 +355,21 @@ def nonuniform_bench(F, torch, *, steps=10, warmup=2, log=print, checks=None):
             "value": nblk * B * cfg.N / (ms / 1e3), "unit": "beam-samples/s", "ms_per_step": ms,
             "plan_s": plan_s, "oversampled_grid": [nfx, nfy], "kernel_width": info.nu_width,
             "stage1b_ms_per_launch": s1b,
-            "stage1b_roofline": {"kernels": "k_nu_spread + k_axis_dft", "bound": "hbm",
+            "stage1b_roofline": {"kernels": "k_nu_line_fused" if fused else
+                                 ("k_nu_spread_plane + 2 x k_axis_dft" if info.p2y else
+                                  "k_nu_spread_line + k_axis_dft"), "bound": "hbm",
                                  "achieved": ach / 1e9, "peak": 8000.0, "unit": "GB/s",
                                  "frac": ach / 8e12, "bytes_per_launch": byts},
         }
 
         def accuracy(r=out[name], cfg=cfg, idx=idx, got=got, x0=x0):
             from oracle import direct as od
+            t0 = time.perf_counter()
             ref = od.beams(x0, _oracle_problem(cfg), idx)
+            dt = time.perf_counter() - t0
             r["rel_l2_vs_oracle"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+            r["oracle"] = {"value": len(idx) * cfg.N / dt, "unit": "beam-samples/s",
+                           "sample": f"FP64 oracle, one block, {len(idx)} beams, {dt:.1f} s"}
         if checks is not None:
             checks.append(accuracy)
         log(f"[bench] {name}: {ms:.3f} ms per {nblk} blocks, stage 1b {s1b * 1e3:.1f} us "

@@ -123,6 +123,10 @@ typedef struct {
                                          8 B N L bytes of device memory (at most 16 GiB)
                                          and needs P3 <= 8192; not with FBST_PREC_FP64
                                          (otherwise FBST_E_UNSUPPORTED)                   */
+#define FBST_FLAG_NU_UNFUSED 16u      /* arbitrary positions with a line of beams: stage 1b
+                                         as two kernels (the oversampled grid through
+                                         device memory) even where the fused kernel
+                                         (grids of 256..4096 points) applies             */
 
 /* Basis and solver options.  eps: band expansion epsilon > 0 (0 selects 1.01).
  * L: number of basis frequencies, even and >= 2 (0 selects 2N, i.e.

@@ -215,6 +215,10 @@ hipError_t run_stage1(const fbst_plan* pl, int nb, const void* yhat, void* w, vo
     // axis straight to w; 2-D: x axis to z2 [nb][1][bu][nfy][L], then the y
     // axis on [nb][bu][nfy][1][L] -> w [nb][bu][bv][1][L]
     const int nfy = p.p2y ? p.p2y : 1;
+    if (!p.p2y && p.p2x >= 256 && p.p2x <= 4096 && !(p.flags & FBST_FLAG_NU_UNFUSED))
+      return fbst::launch_nu_line_fused<T1>(p.nuw, p.p2x, yhat, w, pl->nu_pre, pl->nu_posx,
+                                            pl->nu_order, pl->nu_lanes, pl->nu_cx, pl->tw1, p.M,
+                                            p.bu, p.nu_beta, p.L, nb, st);
     hipError_t e = fbst::launch_nu_spread<T1>(p.nuw, yhat, z, pl->nu_pre, pl->nu_posx, pl->nu_posy,
                                               pl->nu_order, pl->nu_lanes, p.M, p.p2x, nfy,
                                               p.nu_beta, p.L, nb, st);

@@ -62,6 +62,14 @@ template <typename T>
 hipError_t launch_nu_spread(int width, const void* in, void* out, const void* pre, const void* posx,
                             const void* posy, const int* order, int lanes, int M, int nfx, int nfy,
                             double beta, int L, int nblocks, hipStream_t st);
+// Line of beams, spread + FFT + modes in one kernel (oversampled grid of
+// P = 256..4096 points kept in LDS): yhat [nb][M][L] -> w [nb][a_out][L].
+// hipErrorInvalidValue for other P (the caller then uses the two-kernel path).
+template <typename T>
+hipError_t launch_nu_line_fused(int width, int P, const void* in, void* w, const void* pre,
+                                const void* pos, const int* order, int lanes, const void* corr,
+                                const void* tw, int M, int a_out, double beta, int L, int nblocks,
+                                hipStream_t st);
 template <typename T>
 hipError_t launch_axis_dft(int P, const void* in, void* out, const void* corr, const void* tw,
                            int a_out, int pre_n, int post_n, int L, int nblocks, hipStream_t st);

@@ -430,12 +430,86 @@ constexpr int kSpreadGroup = 8;               // elements whose loads are in fli
 // The plan chooses R such that the supports of the R elements of one step are
 // disjoint at every frequency, so no cell is touched by two lanes at once.
 // Element data are loaded a group ahead (row indices two groups ahead).
+struct LineLane {
+  int g, r;        // frequency within the workgroup, lane within the frequency
+};
+__device__ __forceinline__ LineLane line_lane(int G, int R) {
+  const int Gw = (G * R > 64) ? 64 / R : G;
+  const int i = threadIdx.x, per_wave = Gw * R;
+  return {(i / per_wave) * Gw + i % Gw, (i % per_wave) / Gw};
+}
+
+// Lane r's run of elements spread into the grid (gre, gim) of frequency l.
+template <typename T, int W>
+__device__ __forceinline__ void spread_line_run(const cx<T>* __restrict__ src,
+                                                const cx<T>* __restrict__ pre,
+                                                const cx<T>* __restrict__ pos,
+                                                const int* __restrict__ order, int k0, int k1,
+                                                int nf, int l, int L, T b2, T* gre, T* gim) {
+  constexpr int D = kSpreadGroup;
+  auto rows = [&](int base, int (&mm)[D]) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) mm[d] = order[base + d < k1 ? base + d : k0];
+  };
+  auto fetch = [&](const int (&mm)[D], cx<T> (&y)[D], cx<T> (&pr)[D], cx<T> (&ps)[D]) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const size_t idx = static_cast<size_t>(mm[d]) * L;
+      y[d] = ldg(src + idx);
+      pr[d] = ldg(pre + idx + l);
+      ps[d] = ldg(pos + idx + l);
+    }
+  };
+  int mm[D], mn[D];
+  cx<T> y[D], pr[D], ps[D];
+  rows(k0, mm);
+  fetch(mm, y, pr, ps);
+  rows(k0 + D, mn);
+  for (int base = k0; base < k1; base += D) {
+    cx<T> y2[D], pr2[D], ps2[D];
+    const bool more = base + D < k1;
+    if (more) {
+      fetch(mn, y2, pr2, ps2);
+      rows(base + 2 * D, mn);
+    }
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      if (base + d < k1) {
+        const cx<T> c = cmul(y[d], pr[d]);
+        const T f = ps[d].re;
+        const int j0 = static_cast<int>(ps[d].im);
+        int cell[W];
+        T ar[W], ai[W];
+#pragma unroll
+        for (int t = 0; t < W; ++t) {
+          cell[t] = swz((j0 + t) & (nf - 1));
+          ar[t] = gre[cell[t]];
+          ai[t] = gim[cell[t]];
+        }
+#pragma unroll
+        for (int t = 0; t < W; ++t) {
+          const T kv = es_tap<T, W>(t, f, b2);
+          gre[cell[t]] = ar[t] + c.re * kv;
+          gim[cell[t]] = ai[t] + c.im * kv;
+        }
+      }
+    }
+    if (more) {
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        y[d] = y2[d];
+        pr[d] = pr2[d];
+        ps[d] = ps2[d];
+      }
+    }
+  }
+}
+
 template <typename T, int W, int LDS_BYTES>
 __global__ __launch_bounds__(256) void k_nu_spread_line(
     const cx<T>* __restrict__ in, cx<T>* __restrict__ out, const cx<T>* __restrict__ pre,
     const cx<T>* __restrict__ pos, const int* __restrict__ order, int M, int nf, int G, int R,
     T b2, int L, int nblocks) {
-  constexpr int D = kSpreadGroup;
   __shared__ T grid_lds[LDS_BYTES / sizeof(T)];
   const int S = spread_stride(nf, 1);
   T* re = grid_lds;
@@ -443,79 +517,80 @@ __global__ __launch_bounds__(256) void k_nu_spread_line(
   const int wl = xcd_linear(gridDim.x);
   const int blk = wl % nblocks;
   const int tile = wl / nblocks;
-  const int Gw = (G * R > 64) ? 64 / R : G;
-  const int i = threadIdx.x, per_wave = Gw * R;
-  const int g = (i / per_wave) * Gw + i % Gw;
-  const int r = (i % per_wave) / Gw;
+  const LineLane ln = line_lane(G, R);
   spread_zero(grid_lds, 2 * S * G);
   __syncthreads();
-  const int l = tile * G + g;
+  const int l = tile * G + ln.g;
   const int C = (M + R - 1) / R;
-  const int k0 = r * C, k1 = min(M, k0 + C);
-  if (l < L && k0 < k1) {
-    const cx<T>* src = in + static_cast<size_t>(blk) * M * L + l;
-    T* gre = re + g * S;
-    T* gim = im + g * S;
-    auto rows = [&](int base, int (&mm)[D]) {
-#pragma unroll
-      for (int d = 0; d < D; ++d) mm[d] = order[base + d < k1 ? base + d : k0];
-    };
-    auto fetch = [&](const int (&mm)[D], cx<T> (&y)[D], cx<T> (&pr)[D], cx<T> (&ps)[D]) {
-#pragma unroll
-      for (int d = 0; d < D; ++d) {
-        const size_t idx = static_cast<size_t>(mm[d]) * L;
-        y[d] = ldg(src + idx);
-        pr[d] = ldg(pre + idx + l);
-        ps[d] = ldg(pos + idx + l);
-      }
-    };
-    int mm[D], mn[D];
-    cx<T> y[D], pr[D], ps[D];
-    rows(k0, mm);
-    fetch(mm, y, pr, ps);
-    rows(k0 + D, mn);
-    for (int base = k0; base < k1; base += D) {
-      cx<T> y2[D], pr2[D], ps2[D];
-      const bool more = base + D < k1;
-      if (more) {
-        fetch(mn, y2, pr2, ps2);
-        rows(base + 2 * D, mn);
-      }
-#pragma unroll
-      for (int d = 0; d < D; ++d) {
-        if (base + d < k1) {
-          const cx<T> c = cmul(y[d], pr[d]);
-          const T f = ps[d].re;
-          const int j0 = static_cast<int>(ps[d].im);
-          int cell[W];
-          T ar[W], ai[W];
-#pragma unroll
-          for (int t = 0; t < W; ++t) {
-            cell[t] = swz((j0 + t) & (nf - 1));
-            ar[t] = gre[cell[t]];
-            ai[t] = gim[cell[t]];
-          }
-#pragma unroll
-          for (int t = 0; t < W; ++t) {
-            const T kv = es_tap<T, W>(t, f, b2);
-            gre[cell[t]] = ar[t] + c.re * kv;
-            gim[cell[t]] = ai[t] + c.im * kv;
-          }
-        }
-      }
-      if (more) {
-#pragma unroll
-        for (int d = 0; d < D; ++d) {
-          y[d] = y2[d];
-          pr[d] = pr2[d];
-          ps[d] = ps2[d];
-        }
-      }
-    }
-  }
+  const int k0 = ln.r * C, k1 = min(M, k0 + C);
+  if (l < L && k0 < k1)
+    spread_line_run<T, W>(in + static_cast<size_t>(blk) * M * L + l, pre, pos, order, k0, k1, nf,
+                          l, L, b2, re + ln.g * S, im + ln.g * S);
   __syncthreads();
   spread_store(re, im, S, nf, G, out + static_cast<size_t>(blk) * nf * L + static_cast<size_t>(tile) * G,
                tile * G, L, [](int j) { return swz(j); });
+}
+
+// Line of beams, fused: the spread as above into per-frequency regions of 2 Sf
+// words (re at 0, im at Sf), then in rounds of NT = 256 / TT frequencies the
+// P-point FFT (exp(+j)) of each grid, its scratch laid over the grid's own
+// region once the grid is in registers, and the modes a - a_out/2 scaled by
+// corr[a] stored to w [blk][a][l]: the oversampled grid never leaves LDS.
+// FFT lanes: lane = t NT + g' (the NT lanes of one t store NT consecutive l).
+__host__ __device__ constexpr int fused_stride(int P) {
+  return P + P / 16 + (((4 - (P + P / 16) % 32) + 32) % 32 == 0 ? 32 : ((4 - (P + P / 16) % 32) + 32) % 32);
+}
+
+template <typename T, int W, int P, int LDS_BYTES>
+__global__ __launch_bounds__(256) void k_nu_line_fused(
+    const cx<T>* __restrict__ in, cx<T>* __restrict__ wout, const cx<T>* __restrict__ pre,
+    const cx<T>* __restrict__ pos, const int* __restrict__ order, const cx<T>* __restrict__ corr,
+    const cx<T>* __restrict__ tw, int M, int G, int R, T b2, int L, int nblocks, int a_out) {
+  constexpr int TT = P / kE, NT = 256 / TT;
+  constexpr int Sf = fused_stride(P);
+  static_assert(Sf >= lds_stride(P), "a grid region must hold the FFT scratch");
+  __shared__ alignas(16) T grid_lds[LDS_BYTES / sizeof(T)];
+  const int wl = xcd_linear(gridDim.x);
+  const int blk = wl % nblocks;
+  const int tile = wl / nblocks;
+  spread_zero(grid_lds, 2 * Sf * G);
+  __syncthreads();
+  {
+    const LineLane ln = line_lane(G, R);
+    const int l = tile * G + ln.g;
+    const int C = (M + R - 1) / R;
+    const int k0 = ln.r * C, k1 = min(M, k0 + C);
+    if (threadIdx.x < G * R && l < L && k0 < k1)
+      spread_line_run<T, W>(in + static_cast<size_t>(blk) * M * L + l, pre, pos, order, k0, k1, P,
+                            l, L, b2, grid_lds + 2 * Sf * ln.g, grid_lds + 2 * Sf * ln.g + Sf);
+  }
+  __syncthreads();
+  const int gi = threadIdx.x % NT, t = threadIdx.x / NT, ka = a_out / 2;
+  for (int g0 = 0; g0 < G; g0 += NT) {
+    const int g = g0 + gi, l = tile * G + g;
+    const T* gre = grid_lds + 2 * Sf * g;
+    cx<T> v[kE];
+#pragma unroll
+    for (int s = 0; s < kE; ++s) {
+      const int c = swz(t + s * TT);
+      v[s] = cx<T>{gre[c], gre[Sf + c]};
+    }
+    // the FFT's first write to its scratch follows a workgroup barrier, after
+    // which every lane holds its grid values in registers
+    fft<T, P, kE, +1, kE, FBST_K12_TW>(v, reinterpret_cast<cx<T>*>(grid_lds + 2 * Sf * g), tw, t);
+    T cs[kE];
+#pragma unroll
+    for (int s = 0; s < kE; ++s) {
+      const int a = (t + s * TT + ka) & (P - 1);
+      cs[s] = ldg(corr + (a < a_out ? a : 0)).re;
+    }
+    cx<T>* dst = wout + static_cast<size_t>(blk) * a_out * L + l;
+#pragma unroll
+    for (int s = 0; s < kE; ++s) {
+      const int a = (t + s * TT + ka) & (P - 1);
+      if (l < L && a < a_out) dst[static_cast<size_t>(a) * L] = cx<T>{v[s].re * cs[s], v[s].im * cs[s]};
+    }
+  }
 }
 
 // 2-D beam grid.  One wave per frequency (G waves); lane q takes the taps
@@ -934,6 +1009,51 @@ hipError_t launch_nu_spread(int width, const void* in, void* out, const void* pr
   return hipGetLastError();
 }
 
+// Fused line stage 1b for oversampled grids of 256..4096 points: G
+// frequencies per workgroup (a multiple of the FFT round, within 72 KiB of LDS
+// if possible, else 144 KiB); returns hipErrorInvalidValue for other sizes.
+template <typename T>
+hipError_t launch_nu_line_fused(int width, int P, const void* in, void* w, const void* pre,
+                                const void* pos, const int* order, int lanes, const void* corr,
+                                const void* tw, int M, int a_out, double beta, int L, int nblocks,
+                                hipStream_t st) {
+  constexpr int W = sizeof(T) == 4 ? 8 : 16;
+  if (width != W || M < 1 || L < 1 || nblocks < 1 || !order || lanes < 1 || lanes > 16 ||
+      (lanes & (lanes - 1)) || a_out < 1 || 2 * a_out > P)
+    return hipErrorInvalidValue;
+  const T b = static_cast<T>(beta * 1.4426950408889634);   // beta log2(e)
+  switch (P) {
+#define CASE(PP)                                                                                 \
+  case PP: {                                                                                     \
+    constexpr int NT = 256 / (PP / kE);                                                          \
+    const int per = static_cast<int>(2 * sizeof(T)) * fused_stride(PP);                          \
+    int G = 16, bytes = 72 * 1024;                                                               \
+    while (G > NT && G * per > bytes) G /= 2;                                                    \
+    if (G * per > bytes) {                                                                       \
+      bytes = 144 * 1024;                                                                        \
+      G = 16;                                                                                    \
+      while (G > NT && G * per > bytes) G /= 2;                                                  \
+    }                                                                                            \
+    if (G * per > bytes || G % NT) return hipErrorInvalidValue;                                  \
+    const long long ng = 1LL * nblocks * ((L + G - 1) / G);                                      \
+    if (ng > 0x7fffffffLL) return hipErrorInvalidValue;                                          \
+    auto kern = bytes == 72 * 1024 ? k_nu_line_fused<T, W, PP, 72 * 1024>                        \
+                                   : k_nu_line_fused<T, W, PP, 144 * 1024>;                      \
+    hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(ng)), dim3(256), 0, st,                  \
+                       static_cast<const cx<T>*>(in), static_cast<cx<T>*>(w),                    \
+                       static_cast<const cx<T>*>(pre), static_cast<const cx<T>*>(pos), order,    \
+                       static_cast<const cx<T>*>(corr), static_cast<const cx<T>*>(tw), M, G,     \
+                       lanes, b, L, nblocks, a_out);                                             \
+    return hipGetLastError();                                                                    \
+  }
+    CASE(256) CASE(512) CASE(1024) CASE(2048) CASE(4096)
+#undef CASE
+    default:
+      break;
+  }
+  return hipErrorInvalidValue;
+}
+
 template <typename T>
 hipError_t launch_axis_dft(int P, const void* in, void* out, const void* corr, const void* tw,
                            int a_out, int pre_n, int post_n, int L, int nblocks, hipStream_t st) {
@@ -1022,6 +1142,12 @@ template hipError_t launch_nu_spread<float>(int, const void*, void*, const void*
 template hipError_t launch_nu_spread<double>(int, const void*, void*, const void*, const void*,
                                              const void*, const int*, int, int, int, int, double,
                                              int, int, hipStream_t);
+template hipError_t launch_nu_line_fused<float>(int, int, const void*, void*, const void*,
+                                                const void*, const int*, int, const void*,
+                                                const void*, int, int, double, int, int, hipStream_t);
+template hipError_t launch_nu_line_fused<double>(int, int, const void*, void*, const void*,
+                                                 const void*, const int*, int, const void*,
+                                                 const void*, int, int, double, int, int, hipStream_t);
 template hipError_t launch_axis_dft<float>(int, const void*, void*, const void*, const void*, int,
                                            int, int, int, int, hipStream_t);
 template hipError_t launch_axis_dft<double>(int, const void*, void*, const void*, const void*, int,

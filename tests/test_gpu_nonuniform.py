@@ -229,3 +229,27 @@ def test_workload_spread_lanes():
     need_gpu()
     plan = F.plan_for_config(synth.config("nula256"))
     assert plan.info.nu_lanes == 16
+
+
+@pytest.mark.parametrize("B,prec", [(100, "fp32"), (256, "fp32"), (300, "fp32"), (700, "fp32"),
+                                    (1500, "fp32"), (200, "fp64")])
+def test_fused_line_against_two_kernel_form(B, prec):
+    """Lines of beams whose oversampled grid is 256..4096 points run stage 1b
+    as one fused kernel (spread, FFT and modes in LDS); the same plan with
+    FBST_FLAG_NU_UNFUSED takes the grid through device memory.  Both against
+    the oracle."""
+    need_gpu()
+    M, N = 24, 32
+    cfg = perturbed_cfg("ula", M, N, B, index=101)
+    p = oracle_problem(cfg, cfg.delta_noise)
+    dt = torch.complex128 if prec == "fp64" else torch.complex64
+    x, y = to_gpu(cfg.scene().block(0), dt)
+    ref = od.beams(y, p)
+    tol = TOL64 if prec == "fp64" else TOL32
+    errs = []
+    for flags in (0, F.FBST_FLAG_NU_UNFUSED):
+        plan = F.plan_for_config(cfg, precision=prec, flags=flags)
+        assert plan.info.p2x == max(32, 1 << (2 * B - 1).bit_length())
+        errs.append(rel(plan.execute(x).cpu().numpy(), ref))
+    print(f"line B={B} {prec} (grid {plan.info.p2x}): fused {errs[0]:.2e}, two kernels {errs[1]:.2e}")
+    assert max(errs) < tol
