@@ -123,6 +123,13 @@ typedef struct {
                                          8 B N L bytes of device memory (at most 16 GiB)
                                          and needs P3 <= 8192; not with FBST_PREC_FP64
                                          (otherwise FBST_E_UNSUPPORTED)                   */
+#define FBST_FLAG_DEVICE_GENERATORS 32u /* solve the B Toeplitz systems for the generators
+                                         x_b = A_b^{-1} e_0 (Sec. V) on the GPU during
+                                         fbst_plan_create (Levinson recursion in float64,
+                                         one workgroup per beam, L <= 8192), for fast
+                                         plan rebuilds when the beam set changes; the
+                                         columns, refinement and spectra stay on the
+                                         host.  Not with FBST_FLAG_HOST_ONLY. */
 #define FBST_FLAG_NU_UNFUSED 16u      /* arbitrary positions with a line of beams: stage 1b
                                          as two kernels (the oversampled grid through
                                          device memory) even where the fused kernel

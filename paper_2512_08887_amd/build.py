@@ -21,7 +21,8 @@ LIB = os.path.join(PKG, "libfbst.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["kernels.hip", "mfma_czt.hip", "precompute.hip", "plan.cpp", "api.cpp", "server.cpp"]
+SOURCES = ["kernels.hip", "mfma_czt.hip", "precompute.hip", "levinson.hip", "plan.cpp", "api.cpp",
+           "server.cpp"]
 
 CFLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",

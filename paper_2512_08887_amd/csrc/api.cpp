@@ -521,6 +521,39 @@ fbst_status make_nulls(const fbst_plan* plan, int n, const int* qs, const double
   return FBST_OK;
 }
 
+// FBST_FLAG_DEVICE_GENERATORS: the Levinson solves of build_tables' columns
+// on the GPU (float64), then the host completes the stage-2 tables.
+fbst_status solve_generators_on_device(fbst_plan* pl) {
+  const fbst::Params& p = pl->p;
+  const size_t n = static_cast<size_t>(p.B) * p.L;
+  void *dc = nullptr, *dx = nullptr, *ds = nullptr;
+  auto release = [&] {
+    if (dc) (void)hipFree(dc);
+    if (dx) (void)hipFree(dx);
+    if (ds) (void)hipFree(ds);
+  };
+  if (hipMalloc(&dc, n * 16) != hipSuccess || hipMalloc(&dx, n * 16) != hipSuccess ||
+      hipMalloc(&ds, sizeof(int) * p.B) != hipSuccess) {
+    (void)hipGetLastError();
+    release();
+    return fail(FBST_E_NOMEM, "hipMalloc for the device generator solve failed");
+  }
+  std::vector<fbst::zd> x(n);
+  std::vector<int> status(p.B, 1);
+  hipError_t e = hipMemcpy(dc, pl->host.cols.data(), n * 16, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = fbst::launch_levinson(dc, dx, static_cast<int*>(ds), p.B, p.L, nullptr);
+  if (e == hipSuccess) e = hipMemcpy(x.data(), dx, n * 16, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(status.data(), ds, sizeof(int) * p.B, hipMemcpyDeviceToHost);
+  release();
+  if (e != hipSuccess) return hip_fail(e, "device generator solve");
+  for (int b = 0; b < p.B; ++b)
+    if (status[b])
+      return fail(FBST_E_INVALID, "Toeplitz system not positive definite in float64 (delta too small?)");
+  if (fbst::finish_generators(p, x, pl->kept, &pl->host) != FBST_OK)
+    return fail(FBST_E_INVALID, "device generator solve: inconsistent tables");
+  return FBST_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -551,6 +584,17 @@ fbst_status fbst_plan_create(int M, int N, int B, const fbst_geometry* geometry,
     return fail(st, msg);
   }
   pl->nu_lanes = pl->host.nu_lanes;
+  if (!pl->host_only && (p.flags & FBST_FLAG_DEVICE_GENERATORS)) {
+    try {
+      st = solve_generators_on_device(pl);
+    } catch (const std::bad_alloc&) {
+      st = fail(FBST_E_NOMEM, "host allocation of the generator tables failed");
+    }
+    if (st != FBST_OK) {
+      delete pl;
+      return st;
+    }
+  }
   if (!pl->host_only) {
     st = upload(pl);
     if (st != FBST_OK) {

@@ -113,6 +113,11 @@ hipError_t launch_gather_rows(const void* w, const int* map, void* out, int B, i
 hipError_t launch_project_dirs(const void* yhat, const void* E, void* out, int M, int P, int L,
                                int nblocks, hipStream_t st);
 
+// x [B][L] = first columns of the inverses of the Hermitian Toeplitz matrices
+// with first columns cols [B][L] (complex128), Levinson recursion in float64,
+// L <= 8192; status [B] (device ints): 0, or 1 if a pivot is not positive.
+hipError_t launch_levinson(const void* cols, void* x, int* status, int B, int L, hipStream_t st);
+
 // w[j][b][l] = (l == l0 + j) for j < rows (complex64, [rows][B][L]).
 hipError_t launch_unit_rows(void* w, int B, int L, int l0, int rows, hipStream_t st);
 

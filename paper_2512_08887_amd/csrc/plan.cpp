@@ -609,6 +609,16 @@ fbst_status resolve_params(int M, int N, int B, const fbst_geometry* geom, const
       p.ls1 = ls;
     }
   }
+  if (p.flags & FBST_FLAG_DEVICE_GENERATORS) {
+    if (p.flags & FBST_FLAG_HOST_ONLY) {
+      *msg = "FBST_FLAG_DEVICE_GENERATORS needs a device plan (not FBST_FLAG_HOST_ONLY)";
+      return FBST_E_INVALID;
+    }
+    if (p.L > 8192) {
+      *msg = "the device generator solve holds L <= 8192 coefficients in LDS";
+      return FBST_E_UNSUPPORTED;
+    }
+  }
   if (p.flags & FBST_FLAG_PRECOMPUTE) {
     if (p.prec == FBST_PREC_FP64) {
       *msg = "the precomputed stage 2 takes complex64 data (any precision but FBST_PREC_FP64)";
@@ -632,6 +642,55 @@ fbst_status resolve_params(int M, int N, int B, const fbst_geometry* geom, const
     return FBST_E_UNSUPPORTED;
   }
   *out = p;
+  return FBST_OK;
+}
+
+namespace {
+
+// The tail of one beam's stage-2 tables from its Toeplitz column col (with
+// delta) and generator x: refinement when cond(A) is large, the kept copies,
+// and the Gohberg-Semencul spectra G1 = FFT(x), G2 = FFT(y~), both scaled by
+// 1 / (P3 sqrt(x0)).
+void finish_beam(const Params& p, int b, const zd* col, std::vector<zd>* xv, bool keep_gram_gen,
+                 HostTables* t, std::vector<zd>* bufv) {
+  const int L = p.L, P3 = p.p3;
+  std::vector<zd>& x = *xv;
+  std::vector<zd>& buf = *bufv;
+  // refine the generators when cond(A) ~ 2MN/delta makes their float64
+  // forward error visible (above ~1e6)
+  const bool refine = 2.0 * p.M * p.N / p.delta > 1e6;
+  if (keep_gram_gen) std::copy(col, col + L, t->gram.begin() + static_cast<size_t>(b) * L);
+  if (refine) refine_generator(col, L, P3, &x);
+  if (keep_gram_gen) std::copy(x.begin(), x.end(), t->gen.begin() + static_cast<size_t>(b) * L);
+  const double scale = 1.0 / (P3 * std::sqrt(x[0].real()));
+  std::fill(buf.begin(), buf.end(), zd());
+  std::copy(x.begin(), x.end(), buf.begin());
+  fft64(buf.data(), P3, -1);
+  for (int i = 0; i < P3; ++i) t->G1[static_cast<size_t>(b) * P3 + i] = buf[i] * scale;
+  // y~ = (0, conj x_{L-1}, ..., conj x_1)
+  std::fill(buf.begin(), buf.end(), zd());
+  for (int i = 1; i < L; ++i) buf[i] = std::conj(x[L - i]);
+  fft64(buf.data(), P3, -1);
+  for (int i = 0; i < P3; ++i) t->G2[static_cast<size_t>(b) * P3 + i] = buf[i] * scale;
+}
+
+}  // namespace
+
+fbst_status finish_generators(const Params& p, const std::vector<zd>& x, bool keep_gram_gen,
+                              HostTables* t) {
+  const int L = p.L, B = p.B;
+  if (t->cols.size() != static_cast<size_t>(B) * L || x.size() != t->cols.size())
+    return FBST_E_INVALID;
+  parallel_for(B, 1LL * B * p.p3 * 64, [&](int b0, int b1) {
+    std::vector<zd> xb(L), buf(p.p3);
+    for (int b = b0; b < b1; ++b) {
+      std::copy(x.begin() + static_cast<size_t>(b) * L, x.begin() + static_cast<size_t>(b + 1) * L,
+                xb.begin());
+      finish_beam(p, b, t->cols.data() + static_cast<size_t>(b) * L, &xb, keep_gram_gen, t, &buf);
+    }
+  });
+  t->cols.clear();
+  t->cols.shrink_to_fit();
   return FBST_OK;
 }
 
@@ -734,6 +793,10 @@ fbst_status build_tables(const Params& p, bool keep_gram_gen, HostTables* t, std
     }
   }
   const int K = static_cast<int>(keys.size());
+  // generators solved on the device (FBST_FLAG_DEVICE_GENERATORS): keep the
+  // columns only; finish_generators completes the tables
+  const bool device = (p.flags & FBST_FLAG_DEVICE_GENERATORS) != 0;
+  if (device) t->cols.assign(static_cast<size_t>(B) * L, zd());
   std::vector<std::vector<double>> rcol(K), xr(K);
   std::atomic<bool> ok{true};
   std::mutex fail_mu;
@@ -750,6 +813,7 @@ fbst_status build_tables(const Params& p, bool keep_gram_gen, HostTables* t, std
         r[d] = v;
       }
       r[0] += p.delta;
+      if (device) continue;
       xr[k].resize(L);
       if (!levinson_real(r.data(), L, xr[k].data())) {
         std::lock_guard<std::mutex> lk(fail_mu);
@@ -758,9 +822,6 @@ fbst_status build_tables(const Params& p, bool keep_gram_gen, HostTables* t, std
       }
     }
   };
-  // refine the generators when cond(A) ~ 2MN/delta makes their float64
-  // forward error visible (above ~1e6)
-  const bool refine = 2.0 * p.M * p.N / p.delta > 1e6;
   auto work = [&](int b0, int b1) {
     std::vector<zd> col(L), x(L), buf(P3);
     for (int b = b0; b < b1 && ok.load(); ++b) {
@@ -772,7 +833,7 @@ fbst_status build_tables(const Params& p, bool keep_gram_gen, HostTables* t, std
           col[d] = geometric_sum(N, 0.0, -kd) * sensor_sum(p, kd * ub, kd * vb);
         }
         col[0] = zd(col[0].real() + p.delta, 0.0);
-        if (!levinson_first_column(col.data(), L, x.data())) {
+        if (!device && !levinson_first_column(col.data(), L, x.data())) {
           std::lock_guard<std::mutex> lk(fail_mu);
           ok = false;
           fail = "Toeplitz system not positive definite in float64 (delta too small?)";
@@ -782,30 +843,19 @@ fbst_status build_tables(const Params& p, bool keep_gram_gen, HostTables* t, std
         const double sb = 0.5 * (N - 1) - ub * dxs * (p.x0 + 0.5 * (p.mx - 1)) -
                           ((p.kind == FBST_GRID) ? vb * dys * (p.y0 + 0.5 * (p.my - 1)) : 0.0);
         const std::vector<double>& r = rcol[key_of[b]];
-        const std::vector<double>& xk = xr[key_of[b]];
-        for (int d = 0; d < L; ++d) {
-          const zd ph = cis(-2.0 * kPi * p.eps * d / L * sb);
-          col[d] = ph * r[d];
-          x[d] = ph * xk[d];
-        }
+        for (int d = 0; d < L; ++d) col[d] = cis(-2.0 * kPi * p.eps * d / L * sb) * r[d];
         col[0] = zd(r[0], 0.0);
-        x[0] = zd(xk[0], 0.0);
+        if (!device) {
+          const std::vector<double>& xk = xr[key_of[b]];
+          for (int d = 0; d < L; ++d) x[d] = cis(-2.0 * kPi * p.eps * d / L * sb) * xk[d];
+          x[0] = zd(xk[0], 0.0);
+        }
       }
-      if (keep_gram_gen) std::copy(col.begin(), col.end(), t->gram.begin() + static_cast<size_t>(b) * L);
-      if (refine) refine_generator(col.data(), L, P3, &x);
-      if (keep_gram_gen) std::copy(x.begin(), x.end(), t->gen.begin() + static_cast<size_t>(b) * L);
-      const double x0r = x[0].real();
-      const double scale = 1.0 / (P3 * std::sqrt(x0r));
-      // G1 = FFT(x zero-padded)
-      std::fill(buf.begin(), buf.end(), zd());
-      std::copy(x.begin(), x.end(), buf.begin());
-      fft64(buf.data(), P3, -1);
-      for (int i = 0; i < P3; ++i) t->G1[static_cast<size_t>(b) * P3 + i] = buf[i] * scale;
-      // G2 = FFT(y~ zero-padded), y~ = (0, conj x_{L-1}, ..., conj x_1)
-      std::fill(buf.begin(), buf.end(), zd());
-      for (int i = 1; i < L; ++i) buf[i] = std::conj(x[L - i]);
-      fft64(buf.data(), P3, -1);
-      for (int i = 0; i < P3; ++i) t->G2[static_cast<size_t>(b) * P3 + i] = buf[i] * scale;
+      if (device) {
+        std::copy(col.begin(), col.end(), t->cols.begin() + static_cast<size_t>(b) * L);
+        continue;
+      }
+      finish_beam(p, b, col.data(), &x, keep_gram_gen, t, &buf);
     }
   };
   parallel_for(K, 1LL * K * L * L, real_work);

@@ -41,6 +41,9 @@ struct HostTables {
   // the runs' elements taken together never share a grid cell)
   std::vector<int> nu_order;
   int nu_lanes = 1;
+  // FBST_FLAG_DEVICE_GENERATORS: Toeplitz first columns [B][L] (with delta)
+  // awaiting the device solve; emptied by finish_generators
+  std::vector<zd> cols;
 };
 
 struct Params {
@@ -75,6 +78,12 @@ fbst_status resolve_params(int M, int N, int B, const fbst_geometry* geom, const
 
 // Build every table in float64.  keep_gram_gen: also fill gram/gen.
 fbst_status build_tables(const Params& p, bool keep_gram_gen, HostTables* t, std::string* msg);
+
+// With FBST_FLAG_DEVICE_GENERATORS, build_tables leaves G1/G2 (and gen/gram)
+// empty and t->cols filled; given x = A_b^{-1} e_0 [B][L] from the device
+// solve, this completes them (refinement, spectra) as the host path would.
+fbst_status finish_generators(const Params& p, const std::vector<zd>& x, bool keep_gram_gen,
+                              HostTables* t);
 
 // Beams at directions (ud, vd): K [l][d][n] = (F_u A_d^{-1})[n][l] and the
 // projection phases E [d][m][l] = exp(j a_l tau_{d,m}); float64.

@@ -304,3 +304,15 @@ def test_arbitrary_geometry_validation():
         assert info.nu_width == 16 and info.p2x == 64 and info.p2y == 0
     finally:
         F.fbst_destroy(h)
+
+
+def test_device_generator_flag_validation():
+    band = F.make_band(2.0, 0.5, 1.0)
+    with pytest.raises(F.FbstError) as e:
+        F.fbst_plan_create(8, 32, 8, None, band, None,
+                           F.make_options(1.0, flags=F.FBST_FLAG_DEVICE_GENERATORS | F.FBST_FLAG_HOST_ONLY))
+    assert e.value.status == F.FBST_E_INVALID
+    with pytest.raises(F.FbstError) as e:
+        F.fbst_plan_create(8, 5000, 8, None, band, None,
+                           F.make_options(1.0, flags=F.FBST_FLAG_DEVICE_GENERATORS))
+    assert e.value.status == F.FBST_E_UNSUPPORTED

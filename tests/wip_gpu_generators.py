@@ -1,0 +1,91 @@
+"""Generators solved on the GPU (FBST_FLAG_DEVICE_GENERATORS): the Levinson
+recursion for x_b = A_b^{-1} e_0 (Sec. V) in float64, one workgroup per beam,
+against the host's float64 solve of the same matrices and, through the beams,
+against the oracle.
+
+Both solves are backward stable, so their generators agree to about
+cond(A_b) u (cond ~ 2MN/delta); with refinement (2MN/delta > 1e6) both are
+refined on the host from their own solves and agree to a few u of cond."""
+import time
+
+import numpy as np
+import pytest
+
+from oracle import direct as od
+import synth
+from tests.helpers import rel, crandn, oracle_problem, grid_cfg, perturbed_cfg
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2512_08887_amd import fbst as F  # noqa: E402
+
+TOL32 = 1e-5
+
+
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def generators(plan):
+    return F.fbst_plan_table(plan.handle, F.FBST_TABLE_GENERATOR,
+                             np.zeros((plan.B, plan.L), complex))
+
+
+@pytest.mark.parametrize("name", ["ula16", "grid", "perturbed", "ula256"])
+def test_device_generators_match_host(name):
+    need_gpu()
+    cfg = {"ula16": synth.config("ula16"), "grid": grid_cfg(4, 6, 5, 4, 64),
+           "perturbed": perturbed_cfg("ula", 48, 128, 40, index=102),
+           "ula256": synth.config("ula256")}[name]
+    keep = F.FBST_FLAG_KEEP_HOST_TABLES
+    host = F.plan_for_config(cfg, flags=keep)
+    dev = F.plan_for_config(cfg, flags=keep | F.FBST_FLAG_DEVICE_GENERATORS)
+    gh, gd = generators(host), generators(dev)
+    cond = 2.0 * cfg.M * cfg.N / cfg.delta_noise
+    d = max(rel(gd[b], gh[b]) for b in range(cfg.B))
+    x, y32 = None, None
+    y = cfg.scene().block(0)
+    x = torch.from_numpy(y).to(torch.complex64).cuda()
+    out = dev.execute(x).cpu().numpy()
+    y32 = x.cpu().numpy().astype(np.complex128)
+    idx = list(range(cfg.B)) if cfg.B <= 64 else [0, 1, 100, 200, 255]
+    e = rel(out[idx], od.beams(y32, oracle_problem(cfg, cfg.delta_noise), idx))
+    print(f"{name}: device vs host generators {d:.2e} (cond ~ {cond:.1e}); beams vs oracle {e:.2e}")
+    assert d < 100 * cond * np.finfo(np.float64).eps
+    assert e < TOL32
+
+
+def test_device_generators_refined_at_paper_delta():
+    """delta = 1e-5 (cond ~ 2MN/delta = 8e8): the device solve, refined on the
+    host, gives float64 beams at the oracle's accuracy bound."""
+    need_gpu()
+    cfg = synth.config("ula16")
+    plan = F.plan_for_config(cfg, delta=1e-5, precision="fp64",
+                             flags=F.FBST_FLAG_DEVICE_GENERATORS)
+    y = cfg.scene().block(0)
+    x = torch.from_numpy(y).to(torch.complex128).cuda()
+    out = plan.execute(x).cpu().numpy()
+    e = rel(out, od.beams(x.cpu().numpy(), oracle_problem(cfg, 1e-5)))
+    print(f"ula16 fp64 delta=1e-5 device generators: rel err {e:.2e}")
+    assert e < 2.0 * cfg.M * cfg.N / 1e-5 * np.finfo(np.float64).eps
+
+
+def test_device_generators_largest_L():
+    """L = 8192 (the 1024-element line, N = 4096): the largest system the
+    device solve holds; generators against the host solve."""
+    need_gpu()
+    cfg = synth.config("ula1024")
+    keep = F.FBST_FLAG_KEEP_HOST_TABLES
+    t0 = time.perf_counter()
+    host = F.plan_for_config(cfg, flags=keep)
+    t1 = time.perf_counter()
+    dev = F.plan_for_config(cfg, flags=keep | F.FBST_FLAG_DEVICE_GENERATORS)
+    t2 = time.perf_counter()
+    gh, gd = generators(host), generators(dev)
+    cond = 2.0 * cfg.M * cfg.N / cfg.delta_noise
+    d = max(rel(gd[b], gh[b]) for b in range(0, cfg.B, 37))
+    print(f"ula1024: device vs host generators {d:.2e} (cond ~ {cond:.1e}); plan build "
+          f"{t1 - t0:.2f} s host, {t2 - t1:.2f} s with device generators")
+    assert d < 100 * cond * np.finfo(np.float64).eps
