@@ -18,8 +18,6 @@
 // of K3 are then fetched into one L2 and reused there.
 #include <hip/hip_runtime.h>
 
-#include <algorithm>
-
 #include "fft_lds.h"
 #include "kernels.h"
 

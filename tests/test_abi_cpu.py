@@ -316,3 +316,36 @@ def test_device_generator_flag_validation():
         F.fbst_plan_create(8, 5000, 8, None, band, None,
                            F.make_options(1.0, flags=F.FBST_FLAG_DEVICE_GENERATORS))
     assert e.value.status == F.FBST_E_UNSUPPORTED
+
+
+def test_nonuniform_spread_lanes_choice():
+    """The plan spreads R elements per frequency at once only where their
+    kernel supports are disjoint at every frequency: 16 for the perturbed
+    256-element line (elements in order, about 25 grid cells between the
+    elements taken together), 1 for an unordered aperture that wraps the
+    oversampled grid many times, and 0 (not used) for a 2-D beam grid."""
+    import synth
+    band = F.make_band(2.0, 0.5, 1.0)
+    cfg = synth.config("nula256")
+    px, _ = cfg.array.positions()
+    host = F.FBST_FLAG_HOST_ONLY
+    h = F.fbst_plan_create(cfg.M, cfg.N, cfg.B, F.make_arbitrary(px), band, None,
+                           F.make_options(cfg.delta_noise, L=cfg.L, flags=host))
+    try:
+        assert F.fbst_plan_info(h).nu_lanes == 16
+    finally:
+        F.fbst_destroy(h)
+    rng = np.random.default_rng(0)
+    h = F.fbst_plan_create(64, 128, 64, F.make_arbitrary(rng.uniform(0.0, 40.0, 64)), band, None,
+                           F.make_options(25.6, flags=host))
+    try:
+        assert F.fbst_plan_info(h).nu_lanes == 1
+    finally:
+        F.fbst_destroy(h)
+    xy = np.arange(16) * 0.2
+    h = F.fbst_plan_create(16, 32, 16, F.make_arbitrary(xy, xy[::-1]), band, F.make_beam_grid(4, 4),
+                           F.make_options(6.4, flags=host))
+    try:
+        assert F.fbst_plan_info(h).nu_lanes == 0
+    finally:
+        F.fbst_destroy(h)
