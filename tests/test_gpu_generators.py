@@ -3,9 +3,13 @@ recursion for x_b = A_b^{-1} e_0 (Sec. V) in float64, one workgroup per beam,
 against the host's float64 solve of the same matrices and, through the beams,
 against the oracle.
 
-Both solves are backward stable, so their generators agree to about
-cond(A_b) u (cond ~ 2MN/delta); with refinement (2MN/delta > 1e6) both are
-refined on the host from their own solves and agree to a few u of cond."""
+The Levinson recursion on a positive definite Toeplitz matrix is weakly
+stable: its forward error is bounded by a modest multiple of L cond(A_b) u
+(cond ~ 2MN/delta), and the host solves a real, centred form of the same
+matrix while the device solves the complex one, so the two generators are
+held to L cond u of each other.  Each device generator is also checked on its
+own: its residual |A x - e_0| relative to |A| |x| stays at float64 rounding
+times L.  With refinement (2MN/delta > 1e6) both are refined on the host."""
 import time
 
 import numpy as np
@@ -26,6 +30,15 @@ TOL32 = 1e-5
 def need_gpu():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
+
+
+def residual(col, x):
+    """|A x - e_0| / (|A|_1 |x|) for the Hermitian Toeplitz A with first column col."""
+    import scipy.linalg as sla
+    A = sla.toeplitz(col, np.conj(col))
+    r = A @ x
+    r[0] -= 1.0
+    return float(np.linalg.norm(r) / (np.abs(A).sum(axis=0).max() * np.linalg.norm(x)))
 
 
 def generators(plan):
@@ -52,8 +65,12 @@ def test_device_generators_match_host(name):
     y32 = x.cpu().numpy().astype(np.complex128)
     idx = list(range(cfg.B)) if cfg.B <= 64 else [0, 1, 100, 200, 255]
     e = rel(out[idx], od.beams(y32, oracle_problem(cfg, cfg.delta_noise), idx))
-    print(f"{name}: device vs host generators {d:.2e} (cond ~ {cond:.1e}); beams vs oracle {e:.2e}")
-    assert d < 100 * cond * np.finfo(np.float64).eps
+    gram = F.fbst_plan_table(dev.handle, F.FBST_TABLE_GRAM, np.zeros((cfg.B, dev.L), complex))
+    res = max(residual(gram[b], gd[b]) for b in (0, cfg.B // 3, cfg.B - 1))
+    print(f"{name}: device vs host generators {d:.2e} (cond ~ {cond:.1e}); residual {res:.1e}; "
+          f"beams vs oracle {e:.2e}")
+    assert d < dev.L * cond * np.finfo(np.float64).eps
+    assert res < dev.L * np.finfo(np.float64).eps
     assert e < TOL32
 
 
@@ -88,4 +105,4 @@ def test_device_generators_largest_L():
     d = max(rel(gd[b], gh[b]) for b in range(0, cfg.B, 37))
     print(f"ula1024: device vs host generators {d:.2e} (cond ~ {cond:.1e}); plan build "
           f"{t1 - t0:.2f} s host, {t2 - t1:.2f} s with device generators")
-    assert d < 100 * cond * np.finfo(np.float64).eps
+    assert d < dev.L * cond * np.finfo(np.float64).eps
