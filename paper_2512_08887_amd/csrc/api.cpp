@@ -471,10 +471,10 @@ fbst_status make_nulls(const fbst_plan* plan, int n, const int* qs, const double
   for (int i = 0; i < n; ++i) {
     if (qs) {
       uq[i] = p.u0 + (qs[i] / p.bv) * p.du;
-      vq[i] = (p.kind == FBST_GRID) ? p.v0 + (qs[i] % p.bv) * p.dv : 0.0;
+      vq[i] = (p.kind != FBST_LINE) ? p.v0 + (qs[i] % p.bv) * p.dv : 0.0;
     } else {
       uq[i] = u[i];
-      vq[i] = (v && p.kind == FBST_GRID) ? v[i] : 0.0;
+      vq[i] = (v && p.kind != FBST_LINE) ? v[i] : 0.0;
     }
   }
   std::vector<fbst::zd> G, E;
@@ -883,7 +883,7 @@ fbst_status fbst_directions_create(const fbst_plan* plan, int n_directions, cons
     return fail(FBST_E_UNSUPPORTED, "beams at directions take complex64 data (not FBST_PREC_FP64)");
   std::vector<double> ud(u, u + n_directions), vd(n_directions, 0.0);
   for (int i = 0; i < n_directions; ++i) {
-    if (v && p.kind == FBST_GRID) vd[i] = v[i];
+    if (v && p.kind != FBST_LINE) vd[i] = v[i];
     if (!std::isfinite(ud[i]) || !std::isfinite(vd[i]))
       return fail(FBST_E_INVALID, "directions must be finite");
   }

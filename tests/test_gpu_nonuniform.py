@@ -253,3 +253,44 @@ def test_fused_line_against_two_kernel_form(B, prec):
         errs.append(rel(plan.execute(x).cpu().numpy(), ref))
     print(f"line B={B} {prec} (grid {plan.info.p2x}): fused {errs[0]:.2e}, two kernels {errs[1]:.2e}")
     assert max(errs) < tol
+
+
+def test_nulling_and_directions_on_perturbed_plane():
+    """Beamspace applications on a non-uniform planar array with a (u, v) beam
+    grid: nulling of an on-grid interferer, and beams at off-grid (u, v)."""
+    need_gpu()
+    cfg = perturbed_cfg("ura", 20, 40, 12, mx=5, my=4, bu=4, bv=3, index=103)
+    plan = F.plan_for_config(cfg)
+    p = oracle_problem(cfg, cfg.delta_noise)
+    rng = np.random.default_rng(8)
+    x, y32 = to_gpu(crandn(rng, 2, cfg.M, cfg.N))
+    nl = F.Nulls(plan, [5])
+    out = nl.execute(x).cpu().numpy()
+    nl.close()
+    scale = np.linalg.norm(od.beams(y32[0], p))
+    e = max(np.linalg.norm(out[k] - on.nulled_beams(y32[k], p, [5])) / scale for k in range(2))
+    ud, vd = [0.13, -0.41], [0.27, 0.05]
+    dr = F.Directions(plan, ud, vd)
+    outs = dr.execute(x).cpu().numpy()
+    dr.close()
+    pe = od.make_problem(N=p.N, L=p.L, eps=p.eps, delta=p.delta, fc=p.fc, omega=p.omega, ts=p.ts,
+                         px=p.px, py=p.py, u=np.append(p.u, ud), v=np.append(p.v, vd))
+    es = max(rel(outs[k], od.beams(y32[k], pe, beam_idx=[p.B, p.B + 1])) for k in range(2))
+    print(f"perturbed plane: nulling {e:.2e}; directions {es:.2e}")
+    assert e < TOL32 and es < TOL32
+
+
+def test_stream_windows_on_perturbed_line():
+    """Overlapping windows of one recording on a non-uniform line: each window's
+    beams equal those of the same samples run as a separate block."""
+    need_gpu()
+    cfg = perturbed_cfg("ula", 16, 64, 12, index=104)
+    plan = F.plan_for_config(cfg)
+    rng = np.random.default_rng(9)
+    T, hop = 64 + 5 * 24, 24
+    rec, _ = to_gpu(crandn(rng, cfg.M, T))
+    out = plan.execute_stream(rec, hop).cpu().numpy()
+    wins = torch.stack([rec[:, k * hop:k * hop + cfg.N] for k in range(out.shape[0])]).contiguous()
+    ref = plan.execute_batched(wins).cpu().numpy()
+    assert out.shape[0] == (T - cfg.N) // hop + 1
+    assert np.array_equal(out, ref)
