@@ -294,3 +294,31 @@ def test_stream_windows_on_perturbed_line():
     ref = plan.execute_batched(wins).cpu().numpy()
     assert out.shape[0] == (T - cfg.N) // hop + 1
     assert np.array_equal(out, ref)
+
+
+def test_precomputed_stage2_and_graph_on_perturbed_line():
+    """A non-uniform line with the precomputed stage 2 (K_b = F_u A_b^{-1} built
+    from the direct-sum generators) against the oracle, and a captured graph
+    of the non-uniform path replayed between eager work, equal to eager."""
+    need_gpu()
+    cfg = perturbed_cfg("ula", 32, 64, 24, index=105)
+    p = oracle_problem(cfg, cfg.delta_noise)
+    sc = cfg.scene()
+    x, y32 = to_gpu(np.stack([sc.block(k) for k in range(3)]))
+    pre = F.plan_for_config(cfg, flags=F.FBST_FLAG_PRECOMPUTE)
+    out = pre.execute_batched(x).cpu().numpy()
+    e = max(rel(out[k], od.beams(y32[k], p)) for k in range(3))
+    plan = F.plan_for_config(cfg)
+    eager = plan.execute_batched(x)
+    beams = torch.empty_like(eager)
+    g = plan.graph(x, beams)
+    same = True
+    for _ in range(3):
+        beams.zero_()
+        g.launch()
+        plan.execute_batched(x[:1].contiguous())          # eager work between replays
+        torch.cuda.synchronize()
+        same = same and torch.equal(beams, eager)
+    g.close()
+    print(f"perturbed line precomputed stage 2: rel err {e:.2e}; graph replays equal eager: {same}")
+    assert e < TOL32 and same
