@@ -334,7 +334,7 @@ def nonuniform_bench(F, torch, *, steps=10, warmup=2, log=print, checks=None):
         s1b = a0.elapsed_time(a1) / 20
         nfx, nfy = info.p2x, max(info.p2y, 1)
         cells, L, M, B = nfx * nfy, info.L, cfg.M, cfg.B
-        fused = info.p2y == 0 and 256 <= nfx <= 4096
+        fused = (info.p2y == 0 and 256 <= nfx <= 4096) or (nfx == 32 and info.p2y == 32)
         # Yhat in, tables (pre + positions per axis) once per launch, W out; the
         # two-kernel form also writes the oversampled grid and reads it back
         # (and, in 2-D, the x pass's output)
@@ -355,7 +355,7 @@ def nonuniform_bench(F, torch, *, steps=10, warmup=2, log=print, checks=None):
             "value": nblk * B * cfg.N / (ms / 1e3), "unit": "beam-samples/s", "ms_per_step": ms,
             "plan_s": plan_s, "oversampled_grid": [nfx, nfy], "kernel_width": info.nu_width,
             "stage1b_ms_per_launch": s1b,
-            "stage1b_roofline": {"kernels": "k_nu_line_fused" if fused else
+            "stage1b_roofline": {"kernels": ("k_nu_plane_fused" if info.p2y else "k_nu_line_fused") if fused else
                                  ("k_nu_spread_plane + 2 x k_axis_dft" if info.p2y else
                                   "k_nu_spread_line + k_axis_dft"), "bound": "hbm",
                                  "achieved": ach / 1e9, "peak": 8000.0, "unit": "GB/s",

@@ -130,10 +130,11 @@ typedef struct {
                                          plan rebuilds when the beam set changes; the
                                          columns, refinement and spectra stay on the
                                          host.  Not with FBST_FLAG_HOST_ONLY. */
-#define FBST_FLAG_NU_UNFUSED 16u      /* arbitrary positions with a line of beams: stage 1b
-                                         as two kernels (the oversampled grid through
-                                         device memory) even where the fused kernel
-                                         (grids of 256..4096 points) applies             */
+#define FBST_FLAG_NU_UNFUSED 16u      /* arbitrary positions: stage 1b with the
+                                         oversampled grid through device memory (spread,
+                                         then one FFT pass per axis) even where a fused
+                                         kernel applies (a line of beams on a grid of
+                                         256..4096 points; a 2-D beam grid on 32 x 32)   */
 
 /* Basis and solver options.  eps: band expansion epsilon > 0 (0 selects 1.01).
  * L: number of basis frequencies, even and >= 2 (0 selects 2N, i.e.

@@ -219,6 +219,10 @@ hipError_t run_stage1(const fbst_plan* pl, int nb, const void* yhat, void* w, vo
       return fbst::launch_nu_line_fused<T1>(p.nuw, p.p2x, yhat, w, pl->nu_pre, pl->nu_posx,
                                             pl->nu_order, pl->nu_lanes, pl->nu_cx, pl->tw1, p.M,
                                             p.bu, p.nu_beta, p.L, nb, st);
+    if (p.p2x == 32 && p.p2y == 32 && !(p.flags & FBST_FLAG_NU_UNFUSED))
+      return fbst::launch_nu_plane_fused<T1>(p.nuw, p.p2x, p.p2y, yhat, w, pl->nu_pre, pl->nu_posx,
+                                             pl->nu_posy, pl->nu_cx, pl->nu_cy, pl->tw1, p.M, p.bu,
+                                             p.bv, p.nu_beta, p.L, nb, st);
     hipError_t e = fbst::launch_nu_spread<T1>(p.nuw, yhat, z, pl->nu_pre, pl->nu_posx, pl->nu_posy,
                                               pl->nu_order, pl->nu_lanes, p.M, p.p2x, nfy,
                                               p.nu_beta, p.L, nb, st);

@@ -70,6 +70,13 @@ hipError_t launch_nu_line_fused(int width, int P, const void* in, void* w, const
                                 const void* pos, const int* order, int lanes, const void* corr,
                                 const void* tw, int M, int a_out, double beta, int L, int nblocks,
                                 hipStream_t st);
+// 2-D beam grid, spread + row and column FFTs + modes in one kernel (32 x 32
+// oversampled grid, beam grids up to 16 x 16): yhat -> w [nb][bu bv][L].
+template <typename T>
+hipError_t launch_nu_plane_fused(int width, int nfx, int nfy, const void* in, void* w,
+                                 const void* pre, const void* posx, const void* posy,
+                                 const void* cxs, const void* cys, const void* tw, int M, int bu,
+                                 int bv, double beta, int L, int nblocks, hipStream_t st);
 template <typename T>
 hipError_t launch_axis_dft(int P, const void* in, void* out, const void* corr, const void* tw,
                            int a_out, int pre_n, int post_n, int L, int nblocks, hipStream_t st);

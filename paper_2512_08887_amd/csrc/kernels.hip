@@ -595,14 +595,73 @@ __global__ __launch_bounds__(256) void k_nu_line_fused(
 // q + 64 i, i < TPL, as (tx, ty) = (tap / W, tap % W), of every element in
 // turn: the W x W cells of one element are distinct, so each cell update of a
 // step has one owner.  Element data are loaded a group ahead.
+template <typename T, int W>
+__device__ __forceinline__ void spread_plane_run(const cx<T>* __restrict__ src,
+                                                 const cx<T>* __restrict__ pre,
+                                                 const cx<T>* __restrict__ posx,
+                                                 const cx<T>* __restrict__ posy, int M, int nfx,
+                                                 int nfy, int row, int l, int L, T b2, T* gre,
+                                                 T* gim) {
+  constexpr int TPL = (W * W + 63) / 64;
+  constexpr int D = kSpreadGroup;
+  static_assert(TPL * 64 == W * W, "W * W must be a multiple of 64");
+  const int q = threadIdx.x % 64;
+  auto fetch = [&](int base, cx<T> (&y)[D], cx<T> (&pr)[D], cx<T> (&px)[D], cx<T> (&py)[D]) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const size_t idx = static_cast<size_t>(base + d < M ? base + d : 0) * L;
+      y[d] = ldg(src + idx);
+      pr[d] = ldg(pre + idx + l);
+      px[d] = ldg(posx + idx + l);
+      py[d] = ldg(posy + idx + l);
+    }
+  };
+  cx<T> y[D], pr[D], px[D], py[D];
+  fetch(0, y, pr, px, py);
+  for (int base = 0; base < M; base += D) {
+    cx<T> y2[D], pr2[D], px2[D], py2[D];
+    const bool more = base + D < M;
+    if (more) fetch(base + D, y2, pr2, px2, py2);
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      if (base + d < M) {
+        const cx<T> c = cmul(y[d], pr[d]);
+        const int jx0 = static_cast<int>(px[d].im), jy0 = static_cast<int>(py[d].im);
+        int cell[TPL];
+        T ar[TPL], ai[TPL];
+#pragma unroll
+        for (int u = 0; u < TPL; ++u) {
+          const int tap = q + 64 * u, tx = tap / W, ty = tap % W;
+          cell[u] = ((jx0 + tx) & (nfx - 1)) * row + ((jy0 + ty) & (nfy - 1));
+          ar[u] = gre[cell[u]];
+          ai[u] = gim[cell[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < TPL; ++u) {
+          const int tap = q + 64 * u, tx = tap / W, ty = tap % W;
+          const T kv = es_tap<T, W>(tx, px[d].re, b2) * es_tap<T, W>(ty, py[d].re, b2);
+          gre[cell[u]] = ar[u] + c.re * kv;
+          gim[cell[u]] = ai[u] + c.im * kv;
+        }
+      }
+    }
+    if (more) {
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        y[d] = y2[d];
+        pr[d] = pr2[d];
+        px[d] = px2[d];
+        py[d] = py2[d];
+      }
+    }
+  }
+}
+
 template <typename T, int W, int LDS_BYTES>
 __global__ __launch_bounds__(256) void k_nu_spread_plane(
     const cx<T>* __restrict__ in, cx<T>* __restrict__ out, const cx<T>* __restrict__ pre,
     const cx<T>* __restrict__ posx, const cx<T>* __restrict__ posy, int M, int nfx, int nfy, int G,
     T b2, int L, int nblocks) {
-  constexpr int TPL = (W * W + 63) / 64;
-  constexpr int D = kSpreadGroup;
-  static_assert(TPL * 64 == W * W, "W * W must be a multiple of 64");
   __shared__ T grid_lds[LDS_BYTES / sizeof(T)];
   const int cells = nfx * nfy, S = spread_stride(nfx, nfy), row = nfy + 8;
   T* re = grid_lds;
@@ -610,68 +669,89 @@ __global__ __launch_bounds__(256) void k_nu_spread_plane(
   const int wl = xcd_linear(gridDim.x);
   const int blk = wl % nblocks;
   const int tile = wl / nblocks;
-  const int g = threadIdx.x / 64, q = threadIdx.x % 64;
+  const int g = threadIdx.x / 64;
   spread_zero(grid_lds, 2 * S * G);
   __syncthreads();
   const int l = tile * G + g;
-  if (l < L) {
-    const cx<T>* src = in + static_cast<size_t>(blk) * M * L + l;
-    T* gre = re + g * S;
-    T* gim = im + g * S;
-    auto fetch = [&](int base, cx<T> (&y)[D], cx<T> (&pr)[D], cx<T> (&px)[D], cx<T> (&py)[D]) {
-#pragma unroll
-      for (int d = 0; d < D; ++d) {
-        const size_t idx = static_cast<size_t>(base + d < M ? base + d : 0) * L;
-        y[d] = ldg(src + idx);
-        pr[d] = ldg(pre + idx + l);
-        px[d] = ldg(posx + idx + l);
-        py[d] = ldg(posy + idx + l);
-      }
-    };
-    cx<T> y[D], pr[D], px[D], py[D];
-    fetch(0, y, pr, px, py);
-    for (int base = 0; base < M; base += D) {
-      cx<T> y2[D], pr2[D], px2[D], py2[D];
-      const bool more = base + D < M;
-      if (more) fetch(base + D, y2, pr2, px2, py2);
-#pragma unroll
-      for (int d = 0; d < D; ++d) {
-        if (base + d < M) {
-          const cx<T> c = cmul(y[d], pr[d]);
-          const int jx0 = static_cast<int>(px[d].im), jy0 = static_cast<int>(py[d].im);
-          int cell[TPL];
-          T ar[TPL], ai[TPL];
-#pragma unroll
-          for (int u = 0; u < TPL; ++u) {
-            const int tap = q + 64 * u, tx = tap / W, ty = tap % W;
-            cell[u] = ((jx0 + tx) & (nfx - 1)) * row + ((jy0 + ty) & (nfy - 1));
-            ar[u] = gre[cell[u]];
-            ai[u] = gim[cell[u]];
-          }
-#pragma unroll
-          for (int u = 0; u < TPL; ++u) {
-            const int tap = q + 64 * u, tx = tap / W, ty = tap % W;
-            const T kv = es_tap<T, W>(tx, px[d].re, b2) * es_tap<T, W>(ty, py[d].re, b2);
-            gre[cell[u]] = ar[u] + c.re * kv;
-            gim[cell[u]] = ai[u] + c.im * kv;
-          }
-        }
-      }
-      if (more) {
-#pragma unroll
-        for (int d = 0; d < D; ++d) {
-          y[d] = y2[d];
-          pr[d] = pr2[d];
-          px[d] = px2[d];
-          py[d] = py2[d];
-        }
-      }
-    }
-  }
+  if (l < L)
+    spread_plane_run<T, W>(in + static_cast<size_t>(blk) * M * L + l, pre, posx, posy, M, nfx, nfy,
+                           row, l, L, b2, re + g * S, im + g * S);
   __syncthreads();
   spread_store(re, im, S, cells, G,
                out + static_cast<size_t>(blk) * cells * L + static_cast<size_t>(tile) * G, tile * G, L,
                [nfy, row](int j) { return (j / nfy) * row + j % nfy; });
+}
+
+// 2-D beam grid on a 32 x 32 oversampled grid, fused: the spread as above
+// into per-frequency regions of 2 S32 words (re at 0, im at S32, rows of 40
+// words), then per frequency (one wave) the 32 row FFTs and the 32 column FFTs
+// (exp(+j); 2 lanes per transform, the scratch laid over the region once the
+// grid is in registers) and the modes (a - bu/2, c - bv/2) scaled by
+// cx[a] cy[c] stored to w [blk][a bv + c][l]: the grid never leaves LDS.
+constexpr int kPlaneRow = 40;
+constexpr int kPlaneS = 32 * kPlaneRow + 8;
+
+template <typename T, int W, int LDS_BYTES>
+__global__ __launch_bounds__(256) void k_nu_plane_fused(
+    const cx<T>* __restrict__ in, cx<T>* __restrict__ wout, const cx<T>* __restrict__ pre,
+    const cx<T>* __restrict__ posx, const cx<T>* __restrict__ posy, const cx<T>* __restrict__ cxs,
+    const cx<T>* __restrict__ cys, const cx<T>* __restrict__ tw, int M, int G, int bu, int bv,
+    T b2, int L, int nblocks) {
+  constexpr int P = 32, TT = P / kE;                 // 2 lanes per 32-point transform
+  static_assert(32 * lds_stride(P) <= kPlaneS, "a region must hold 32 transforms' scratch");
+  __shared__ alignas(16) T grid_lds[LDS_BYTES / sizeof(T)];
+  const int wl = xcd_linear(gridDim.x);
+  const int blk = wl % nblocks;
+  const int tile = wl / nblocks;
+  const int g = threadIdx.x / 64, q = threadIdx.x % 64;
+  const int l = tile * G + g;
+  T* gre = grid_lds + 2 * kPlaneS * g;
+  T* gim = gre + kPlaneS;
+  cx<T>* scratch = reinterpret_cast<cx<T>*>(gre);
+  spread_zero(grid_lds, 2 * kPlaneS * G);
+  __syncthreads();
+  if (l < L)
+    spread_plane_run<T, W>(in + static_cast<size_t>(blk) * M * L + l, pre, posx, posy, M, P, P,
+                           kPlaneRow, l, L, b2, gre, gim);
+  __syncthreads();
+  const int r = q / TT, t = q % TT;                  // transform (row, then column) and its lane
+  cx<T> v[kE];
+  // rows: v[s] = cell (r, t + TT s)
+#pragma unroll
+  for (int s = 0; s < kE; ++s) {
+    const int c = r * kPlaneRow + t + TT * s;
+    v[s] = cx<T>{gre[c], gim[c]};
+  }
+  fft<T, P, kE, +1, kE, FBST_K12_TW>(v, scratch + r * lds_stride(P), tw, t);
+  __syncthreads();                                   // every lane is done with the scratch
+#pragma unroll
+  for (int s = 0; s < kE; ++s) {
+    const int c = r * kPlaneRow + t + TT * s;
+    gre[c] = v[s].re;
+    gim[c] = v[s].im;
+  }
+  __syncthreads();
+  // columns: v[s] = cell (t + TT s, r)
+#pragma unroll
+  for (int s = 0; s < kE; ++s) {
+    const int c = (t + TT * s) * kPlaneRow + r;
+    v[s] = cx<T>{gre[c], gim[c]};
+  }
+  fft<T, P, kE, +1, kE, FBST_K12_TW>(v, scratch + r * lds_stride(P), tw, t);
+  // v[s] is the spectrum at (kx, ky) = (t + TT s, r)
+  const int cy_i = (r + bv / 2) & (P - 1);
+  if (l < L && cy_i < bv) {
+    const T sy = ldg(cys + cy_i).re;
+    cx<T>* dst = wout + static_cast<size_t>(blk) * bu * bv * L + l;
+#pragma unroll
+    for (int s = 0; s < kE; ++s) {
+      const int a = (t + TT * s + bu / 2) & (P - 1);
+      if (a < bu) {
+        const T sc = ldg(cxs + a).re * sy;
+        dst[(static_cast<size_t>(a) * bv + cy_i) * L] = cx<T>{v[s].re * sc, v[s].im * sc};
+      }
+    }
+  }
 }
 
 // One axis of the non-uniform stage 1b: layout [blk][pre_n][P][post_n][L] in,
@@ -1052,6 +1132,49 @@ hipError_t launch_nu_line_fused(int width, int P, const void* in, void* w, const
   return hipErrorInvalidValue;
 }
 
+// Fused 2-D stage 1b for a 32 x 32 oversampled grid (beam grids up to 16 x 16):
+// G = 1..4 frequencies (waves) per workgroup, whichever keeps the most waves
+// resident; hipErrorInvalidValue for other grids.
+template <typename T>
+hipError_t launch_nu_plane_fused(int width, int nfx, int nfy, const void* in, void* w,
+                                 const void* pre, const void* posx, const void* posy,
+                                 const void* cxs, const void* cys, const void* tw, int M, int bu,
+                                 int bv, double beta, int L, int nblocks, hipStream_t st) {
+  constexpr int W = sizeof(T) == 4 ? 8 : 16;
+  if (width != W || nfx != 32 || nfy != 32 || M < 1 || L < 1 || nblocks < 1 || bu < 1 || bv < 1 ||
+      2 * bu > 32 || 2 * bv > 32 || !posy || !cys)
+    return hipErrorInvalidValue;
+  const int per = static_cast<int>(2 * sizeof(T)) * kPlaneS;
+  int G = 0, tier = 0, best = 0;
+  for (int c = 4; c >= 1; --c) {
+    int tr = 0;
+    while (tr < 3 && c * per > kSpreadTiers[tr]) ++tr;
+    if (tr == 3) continue;
+    const int waves = (160 * 1024 / kSpreadTiers[tr]) * c;
+    if (waves > best) {
+      best = waves;
+      G = c;
+      tier = tr;
+    }
+  }
+  if (G < 1) return hipErrorInvalidValue;
+  const long long ng = 1LL * nblocks * ((L + G - 1) / G);
+  if (ng > 0x7fffffffLL) return hipErrorInvalidValue;
+  const T b = static_cast<T>(beta * 1.4426950408889634);   // beta log2(e)
+  auto go = [&](auto kern) {
+    hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(ng)), dim3(64 * G), 0, st,
+                       static_cast<const cx<T>*>(in), static_cast<cx<T>*>(w),
+                       static_cast<const cx<T>*>(pre), static_cast<const cx<T>*>(posx),
+                       static_cast<const cx<T>*>(posy), static_cast<const cx<T>*>(cxs),
+                       static_cast<const cx<T>*>(cys), static_cast<const cx<T>*>(tw), M, G, bu, bv,
+                       b, L, nblocks);
+  };
+  if (tier == 0) go(k_nu_plane_fused<T, W, kSpreadTiers[0]>);
+  else if (tier == 1) go(k_nu_plane_fused<T, W, kSpreadTiers[1]>);
+  else go(k_nu_plane_fused<T, W, kSpreadTiers[2]>);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_axis_dft(int P, const void* in, void* out, const void* corr, const void* tw,
                            int a_out, int pre_n, int post_n, int L, int nblocks, hipStream_t st) {
@@ -1146,6 +1269,14 @@ template hipError_t launch_nu_line_fused<float>(int, int, const void*, void*, co
 template hipError_t launch_nu_line_fused<double>(int, int, const void*, void*, const void*,
                                                  const void*, const int*, int, const void*,
                                                  const void*, int, int, double, int, int, hipStream_t);
+template hipError_t launch_nu_plane_fused<float>(int, int, int, const void*, void*, const void*,
+                                                 const void*, const void*, const void*,
+                                                 const void*, const void*, int, int, int, double,
+                                                 int, int, hipStream_t);
+template hipError_t launch_nu_plane_fused<double>(int, int, int, const void*, void*, const void*,
+                                                  const void*, const void*, const void*,
+                                                  const void*, const void*, int, int, int, double,
+                                                  int, int, hipStream_t);
 template hipError_t launch_axis_dft<float>(int, const void*, void*, const void*, const void*, int,
                                            int, int, int, int, hipStream_t);
 template hipError_t launch_axis_dft<double>(int, const void*, void*, const void*, const void*, int,

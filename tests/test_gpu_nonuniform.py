@@ -322,3 +322,24 @@ def test_precomputed_stage2_and_graph_on_perturbed_line():
     g.close()
     print(f"perturbed line precomputed stage 2: rel err {e:.2e}; graph replays equal eager: {same}")
     assert e < TOL32 and same
+
+
+@pytest.mark.parametrize("mx,my,bu,bv,prec", [(8, 8, 8, 8, "fp32"), (5, 6, 7, 4, "fp32"),
+                                              (6, 6, 16, 16, "fp32"), (6, 6, 6, 5, "fp64")])
+def test_fused_plane_against_two_kernel_form(mx, my, bu, bv, prec):
+    """2-D beam grids on a 32 x 32 oversampled grid run stage 1b as one fused
+    kernel (spread, row and column FFTs, modes); FBST_FLAG_NU_UNFUSED takes the
+    grid through device memory.  Both against the oracle."""
+    need_gpu()
+    cfg = perturbed_cfg("ura", mx * my, 40, bu * bv, mx=mx, my=my, bu=bu, bv=bv, index=106)
+    p = oracle_problem(cfg, cfg.delta_noise)
+    dt = torch.complex128 if prec == "fp64" else torch.complex64
+    x, y = to_gpu(cfg.scene().block(0), dt)
+    ref = od.beams(y, p)
+    errs = []
+    for flags in (0, F.FBST_FLAG_NU_UNFUSED):
+        plan = F.plan_for_config(cfg, precision=prec, flags=flags)
+        assert (plan.info.p2x, plan.info.p2y) == (32, 32)
+        errs.append(rel(plan.execute(x).cpu().numpy(), ref))
+    print(f"plane {mx}x{my} -> {bu}x{bv} {prec}: fused {errs[0]:.2e}, two kernels {errs[1]:.2e}")
+    assert max(errs) < (TOL64 if prec == "fp64" else TOL32)
