@@ -98,3 +98,40 @@ def test_admission_limits_batch_to_budget():
     assert max(c.batch for c in comps) <= 2
     for x, o in zip(xs, outs):
         assert torch.equal(p.execute(x), o)
+
+
+def test_mix_with_nonuniform_plans():
+    """Non-uniform line and planar plans served in a mix with a uniform one:
+    each block bitwise equal to the same block run alone."""
+    need_gpu()
+    rng = np.random.default_rng(5)
+    band = synth.band_from_fb(0.5)
+    d = 1.0 / (2.0 * band.f_top)
+    px = (np.arange(40) + rng.uniform(-0.25, 0.25, 40)) * d
+    gx = (np.repeat(np.arange(6), 6) + rng.uniform(-0.25, 0.25, 36)) * d
+    gy = (np.tile(np.arange(6), 6) + rng.uniform(-0.25, 0.25, 36)) * d
+    b = F.make_band(band.fc, band.omega)
+    plans = [F.Plan(40, 128, 40, band=b, geometry=F.make_arbitrary(px), options=F.make_options(25.6)),
+             F.Plan(36, 64, 36, band=b, geometry=F.make_arbitrary(gx, gy),
+                    grid=F.make_beam_grid(6, 6), options=F.make_options(12.8)),
+             F.Plan(16, 256, 16, band=b, options=F.make_options(51.2))]
+    reqs = []
+    for i in range(30):
+        k = int(rng.integers(0, len(plans)))
+        p = plans[k]
+        x = torch.from_numpy(crandn(rng, p.M, p.N)).to(torch.complex64).cuda()
+        reqs.append((k, x, torch.empty((p.B, p.N), dtype=torch.complex64, device="cuda")))
+    torch.cuda.synchronize()
+    srv = F.Server(workspace_bytes=64 << 20, streams=3, max_batch=8)
+    for tag, (k, x, out) in enumerate(reqs):
+        srv.submit(plans[k], x, out, tag)
+    srv.drain(timeout_s=60)
+    comps = srv.poll(1000)
+    srv.close()
+    assert sorted(c.tag for c in comps) == list(range(len(reqs)))
+    assert all(c.status == F.FBST_OK for c in comps)
+    torch.cuda.synchronize()
+    for k, x, out in reqs:
+        alone = plans[k].execute(x)
+        torch.cuda.synchronize()
+        assert torch.equal(alone, out)
