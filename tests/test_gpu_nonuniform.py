@@ -343,3 +343,21 @@ def test_fused_plane_against_two_kernel_form(mx, my, bu, bv, prec):
         errs.append(rel(plan.execute(x).cpu().numpy(), ref))
     print(f"plane {mx}x{my} -> {bu}x{bv} {prec}: fused {errs[0]:.2e}, two kernels {errs[1]:.2e}")
     assert max(errs) < (TOL64 if prec == "fp64" else TOL32)
+
+
+@pytest.mark.parametrize("bu,bv,prec", [(20, 5, "fp32"), (24, 24, "fp32"), (18, 3, "fp64")])
+def test_wide_plane_grids(bu, bv, prec):
+    """2-D beam grids wider than 16 beams per axis: oversampled grids of 64
+    points on that axis, stage 1b as spread + FFT passes (the 2-D fused kernel
+    covers 32 x 32 only), larger LDS tiers."""
+    need_gpu()
+    mx, my = 6, 5
+    cfg = perturbed_cfg("ura", mx * my, 40, bu * bv, mx=mx, my=my, bu=bu, bv=bv, index=107)
+    plan = F.plan_for_config(cfg, precision=prec)
+    assert plan.info.p2x == 64
+    p = oracle_problem(cfg, cfg.delta_noise)
+    dt = torch.complex128 if prec == "fp64" else torch.complex64
+    x, y = to_gpu(cfg.scene().block(0), dt)
+    e = rel(plan.execute(x).cpu().numpy(), od.beams(y, p))
+    print(f"plane {mx}x{my} -> {bu}x{bv} {prec} (grid {plan.info.p2x}x{plan.info.p2y}): rel err {e:.2e}")
+    assert e < (TOL64 if prec == "fp64" else TOL32)
