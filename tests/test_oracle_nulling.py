@@ -59,3 +59,24 @@ def test_interferer_removed_source_kept():
     assert after < 1e-4 * before
     out = on.nulled_beams(y, p, [q], beam_idx=[s])[0]
     assert rel(out, sc.source_samples(1)) < 1e-2
+
+
+def test_nulling_on_random_positions():
+    """Non-uniform arrays (Sec. IX: the beamspace applications are unchanged):
+    on a random planar layout the cross-Gram equals the explicit product and
+    the beamspace form equals the array-space projection, for interferers at a
+    grid beam and at an off-grid direction."""
+    rng = np.random.default_rng(12)
+    px = rng.uniform(0.0, 1.0, 7)
+    py = rng.uniform(0.0, 0.8, 7)
+    u = np.array([-0.6, -0.1, 0.3, 0.75, 0.2])
+    v = np.array([0.1, -0.4, 0.25, 0.0, 0.55])
+    p = od.make_problem(N=8, L=16, eps=1.01, delta=0.05, fc=2.0, omega=0.5, ts=1.0, px=px, py=py,
+                        u=u, v=v)
+    for b, q in [(0, 3), (4, 1), (2, 2)]:
+        C = on.cross_gram(p, b, q)
+        E = od.F_matrix(p, b).conj().T @ od.F_matrix(p, q)
+        assert np.abs(C - E).max() < 1e-10 * np.abs(E).max()
+    y = crandn(rng, p.M, p.N)
+    for qs in ([1], [0, 4]):
+        assert rel(on.nulled_beams(y, p, qs), on.nulled_beams_dense(y, p, qs)) < 1e-9, qs
