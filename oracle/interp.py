@@ -1,0 +1,138 @@
+"""Off-grid beams by spline interpolation of grid beams (Sec. VIII, "Off-grid
+angle interpolation") in float64 on the CPU.  Test infrastructure only: the
+product path never imports this package.
+
+The paper forms the beam at an off-grid direction theta* by interpolating the
+beams of the few grid directions around it (8 of the 256 beams of its 128-
+element line) with a spline, for every time sample.  Readings taken here
+(the paper names neither the spline nor the coordinate):
+
+* the interpolation variable is the direction cosine u = sin(theta), in
+  which the beam grid of eq. (thetab) is uniform;
+* the 8 neighbours are the grid beams j-3 .. j+4, where u_j <= u* < u_{j+1}
+  (so u* lies in the middle interval), the window shifted inward where it
+  would leave the grid; u* outside [u_0, u_{B-1}] is rejected (no
+  extrapolation);
+* the spline is the cubic interpolating spline with not-a-knot end
+  conditions (the third derivative is continuous at the second and the
+  second-to-last node), applied to the real and imaginary parts alike, so
+  the interpolated beam is a real-weighted sum of the 8 beams.
+
+``spline_weights`` writes that spline out from its definition: one cubic per
+interval, 4 (n - 1) unknown coefficients, fixed by interpolation at both
+ends of every interval, continuity of the first and second derivatives at
+the interior nodes and the two not-a-knot conditions, solved as one dense
+linear system.  Since the spline is linear in the node values, the weight
+of node i is the spline through the unit vector e_i, evaluated at u*.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+__all__ = ["NEIGHBOURS", "neighbour_window", "spline_coefficients", "spline_eval",
+           "spline_weights", "interp_weights", "interp_beams"]
+
+NEIGHBOURS = 8
+
+
+def neighbour_window(grid_u: np.ndarray, u: float, k: int = NEIGHBOURS) -> int:
+    """First index of the k grid beams used for direction u (grid_u ascending)."""
+    g = np.asarray(grid_u, dtype=np.float64)
+    if len(g) < k:
+        raise ValueError(f"need at least {k} grid beams")
+    if not (g[0] <= u <= g[-1]):
+        raise ValueError("direction outside the beam grid (no extrapolation)")
+    j = int(np.searchsorted(g, u, side="right")) - 1          # g[j] <= u < g[j+1]
+    j = min(j, len(g) - 1)
+    return int(min(max(j - (k // 2 - 1), 0), len(g) - k))
+
+
+def spline_coefficients(x: np.ndarray, y: np.ndarray) -> np.ndarray:
+    """Coefficients [n-1, 4] (a, b, c, d) of the not-a-knot cubic spline through
+    (x_i, y_i): on [x_k, x_{k+1}], S(t) = a + b s + c s^2 + d s^3 with s = t - x_k.
+    Needs n >= 4 strictly increasing nodes."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    n = len(x)
+    if n < 4 or np.any(np.diff(x) <= 0):
+        raise ValueError("need >= 4 strictly increasing nodes")
+    m = n - 1                                   # intervals
+    A = np.zeros((4 * m, 4 * m))
+    r = np.zeros(4 * m)
+    row = 0
+
+    def col(k, p):                              # coefficient p of interval k
+        return 4 * k + p
+
+    for k in range(m):
+        h = x[k + 1] - x[k]
+        A[row, col(k, 0)] = 1.0                 # S_k(x_k) = y_k
+        r[row] = y[k]
+        row += 1
+        for p in range(4):                      # S_k(x_{k+1}) = y_{k+1}
+            A[row, col(k, p)] = h ** p
+        r[row] = y[k + 1]
+        row += 1
+    for k in range(m - 1):                      # interior node x_{k+1}
+        h = x[k + 1] - x[k]
+        # S_k'(x_{k+1}) - S_{k+1}'(x_{k+1}) = 0
+        A[row, col(k, 1)] = 1.0
+        A[row, col(k, 2)] = 2.0 * h
+        A[row, col(k, 3)] = 3.0 * h * h
+        A[row, col(k + 1, 1)] = -1.0
+        row += 1
+        # S_k''(x_{k+1}) - S_{k+1}''(x_{k+1}) = 0
+        A[row, col(k, 2)] = 2.0
+        A[row, col(k, 3)] = 6.0 * h
+        A[row, col(k + 1, 2)] = -2.0
+        row += 1
+    # not-a-knot: S''' continuous at x_1 and x_{n-2}
+    A[row, col(0, 3)] = 1.0
+    A[row, col(1, 3)] = -1.0
+    row += 1
+    A[row, col(m - 2, 3)] = 1.0
+    A[row, col(m - 1, 3)] = -1.0
+    row += 1
+    assert row == 4 * m
+    return np.linalg.solve(A, r).reshape(m, 4)
+
+
+def spline_eval(x: np.ndarray, coef: np.ndarray, t: float) -> float:
+    """Value of the spline (nodes x, coefficients from spline_coefficients) at t
+    in [x_0, x_{n-1}]."""
+    x = np.asarray(x, dtype=np.float64)
+    k = int(np.searchsorted(x, t, side="right")) - 1
+    k = min(max(k, 0), len(x) - 2)
+    s = t - x[k]
+    a, b, c, d = coef[k]
+    return float(a + b * s + c * s * s + d * s ** 3)
+
+
+def spline_weights(x: np.ndarray, t: float) -> np.ndarray:
+    """w with S(t) = sum_i w_i y_i for every data vector y: w_i is the spline
+    through the unit vector e_i evaluated at t."""
+    n = len(x)
+    w = np.empty(n)
+    for i in range(n):
+        e = np.zeros(n)
+        e[i] = 1.0
+        w[i] = spline_eval(x, spline_coefficients(x, e), t)
+    return w
+
+
+def interp_weights(grid_u: np.ndarray, u: float, k: int = NEIGHBOURS):
+    """(first neighbour index, k weights) for direction u on beam grid grid_u."""
+    g = np.asarray(grid_u, dtype=np.float64)
+    j0 = neighbour_window(g, u, k)
+    return j0, spline_weights(g[j0:j0 + k], u)
+
+
+def interp_beams(beams: np.ndarray, grid_u: np.ndarray, us) -> np.ndarray:
+    """Interpolated beams at directions us from grid beams [..., B, N]:
+    out[..., d, :] = sum_i w_{d,i} beams[..., j0_d + i, :]."""
+    bm = np.asarray(beams)
+    out = np.empty(bm.shape[:-2] + (len(us), bm.shape[-1]), dtype=np.complex128)
+    for d, u in enumerate(us):
+        j0, w = interp_weights(grid_u, float(u))
+        out[..., d, :] = np.tensordot(w, bm[..., j0:j0 + len(w), :], axes=([0], [-2]))
+    return out
