@@ -141,7 +141,7 @@ def rocprof_summary(kt_dir, pmc_dirs, copy_dirs):
 
 
 # Sources whose change invalidates stored HBM counter readings of the kernels.
-KERNEL_SOURCES = ["cx.h", "fft_lds.h", "kernels.h", "kernels.hip", "mfma_czt.hip"]
+KERNEL_SOURCES = ["cx.h", "fft_lds.h", "kernels.h", "kernels.hip", "mfma_czt.hip", "precompute.hip"]
 COUNTERS_JSON = os.path.join(ROOT, "profiles", "hbm_counters_ula256.json")
 
 
@@ -379,6 +379,56 @@ def nonuniform_bench(F, torch, *, steps=10, warmup=2, log=print, checks=None):
     return out
 
 
+def interp_bench(F, torch, plan, cfg, beams, *, reps=20, log=print, checks=None):
+    """Off-grid beams by spline interpolation of 8 grid beams (Sec. VIII) on
+    the step's own beams: one launch over 16 blocks at B directions
+    drawn across the grid (seeded).  Algorithmic HBM bytes per launch: each
+    grid beam read once and each interpolated beam written once,
+    8 nb N (B + D); the kernel is bound by HBM."""
+    # the default beam grid of a line (eq. thetab): u_b = (2b - B + 1) / B for
+    # even B, (2b - B + 1) / (B - 1) for odd B, b = 0..B-1
+    den = cfg.B if cfg.B % 2 == 0 else cfg.B - 1
+    g = (2.0 * np.arange(cfg.B) - cfg.B + 1.0) / den
+    us = np.sort(np.random.default_rng(7).uniform(g[0], g[-1], cfg.B))
+    it = F.Interp(plan, us)
+    D, nb = len(us), min(16, beams.shape[0])   # fixed launch size: comparable counter runs
+    src = beams[:nb]
+    out = torch.empty((nb, D, cfg.N), dtype=torch.complex64, device="cuda")
+    stream = torch.cuda.current_stream()
+    for _ in range(3):
+        it.execute(src, out)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        it.execute(src, out)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    nbytes = 8 * nb * cfg.N * (cfg.B + D)
+    ach = nbytes / (ms / 1e3) / 1e9
+    r = {"workload": f"{cfg.name}: {D} directions drawn across the beam grid, {nb} blocks per "
+                     f"launch, 8 grid beams each (not-a-knot cubic spline in u)",
+         "value": nb * D * cfg.N / (ms / 1e3), "unit": "beam-samples/s", "ms_per_launch": ms,
+         "roofline": {"kernel": "k_interp_beams", "bound": "hbm", "achieved": ach, "peak": 8000.0,
+                      "unit": "GB/s", "frac": ach / 8000.0, "bytes_per_launch": nbytes,
+                      "traffic": stored_traffic("k_interp_beams<float>",
+                                                nb * D * ((cfg.N + 255) // 256) * 256)}}
+    got = out[0].cpu().numpy().astype(np.complex128)
+    b0 = src[0].cpu().numpy().astype(np.complex128)
+
+    def accuracy():
+        from oracle import interp as oi
+        ref = oi.interp_beams(b0, g, us)
+        r["rel_l2_vs_oracle"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    if checks is not None:
+        checks.append(accuracy)
+    log(f"[bench] interp: {ms * 1e3:.1f} us per {nb}-block launch ({ach:.0f} GB/s)")
+    it.close()
+    return r
+
+
 def _oracle_problem(cfg):
     """The oracle's Problem of a perturbed synthetic array (positions from the
     input generator, beam grid of eq. (thetab))."""
@@ -503,6 +553,8 @@ def main():
                     help="skip the N = 64 Gohberg-Semencul vs precomputed stage-2 comparison")
     ap.add_argument("--no-variants", action="store_true", help="skip the bf16/fp16 split variants")
     ap.add_argument("--no-nu", action="store_true", help="skip the non-uniform array measurement")
+    ap.add_argument("--no-interp", action="store_true",
+                    help="skip the spline-interpolated off-grid beams measurement")
     ap.add_argument("--serve-only", action="store_true", help="only the serving-mix measurement")
     ap.add_argument("--serve-seconds", type=float, default=2.0)
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
@@ -736,6 +788,10 @@ def main():
         result["precompute_n64"] = precompute_bench(
             F, torch, steps=max(2, min(args.steps, 10)), warmup=1,
             log=lambda m: print(m, file=sys.stderr, flush=True), checks=oracle_checks)
+    if not args.no_interp:
+        result["interp"] = interp_bench(F, torch, plan, cfg, beams,
+                                        log=lambda m: print(m, file=sys.stderr, flush=True),
+                                        checks=oracle_checks)
     if not args.no_nu:
         result["nonuniform"] = nonuniform_bench(
             F, torch, log=lambda m: print(m, file=sys.stderr, flush=True), checks=oracle_checks)

@@ -967,6 +967,86 @@ fbst_status fbst_execute_directions(const fbst_plan* plan, const fbst_directions
   return FBST_OK;
 }
 
+fbst_status fbst_interp_create(const fbst_plan* plan, int n_directions, const double* u,
+                               fbst_interp** out) {
+  if (!out) return fail(FBST_E_INVALID, "out is NULL");
+  *out = nullptr;
+  fbst_status s = check_exec(plan);
+  if (s != FBST_OK) return s;
+  if (n_directions < 1 || n_directions > 65536 || !u)
+    return fail(FBST_E_INVALID, "need 1..65536 directions");
+  std::vector<double> ud(u, u + n_directions);
+  for (double x : ud)
+    if (!std::isfinite(x)) return fail(FBST_E_INVALID, "directions must be finite");
+  fbst_interp* it = new (std::nothrow) fbst_interp();
+  if (!it) return fail(FBST_E_NOMEM, "host allocation failed");
+  std::string msg;
+  try {
+    s = fbst::build_interp_table(plan->p, ud, &it->host_first, &it->host_w, &msg);
+  } catch (const std::bad_alloc&) {
+    s = FBST_E_NOMEM;
+    msg = "host allocation of the interpolation table failed";
+  }
+  if (s != FBST_OK) {
+    delete it;
+    return fail(s, msg);
+  }
+  const size_t o_w = (static_cast<size_t>(n_directions) * sizeof(int) + 255) / 256 * 256;
+  const size_t bytes = o_w + it->host_w.size() * sizeof(double);
+  hipError_t e = hipMalloc(&it->dev, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    delete it;
+    return fail(FBST_E_NOMEM, "hipMalloc of the interpolation table failed");
+  }
+  unsigned char* b = static_cast<unsigned char*>(it->dev);
+  e = hipMemcpy(b, it->host_first.data(), n_directions * sizeof(int), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(b + o_w, it->host_w.data(), it->host_w.size() * sizeof(double),
+                  hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(it->dev);
+    delete it;
+    return hip_fail(e, "hipMemcpy of the interpolation table");
+  }
+  it->plan = plan;
+  it->D = n_directions;
+  it->first = reinterpret_cast<const int*>(b);
+  it->w = reinterpret_cast<const double*>(b + o_w);
+  *out = it;
+  return FBST_OK;
+}
+
+void fbst_interp_destroy(fbst_interp* interp) {
+  if (!interp) return;
+  if (interp->dev) (void)hipFree(interp->dev);
+  delete interp;
+}
+
+fbst_status fbst_interp_table(const fbst_interp* interp, int* first, double* w) {
+  if (!interp) return fail(FBST_E_INVALID, "interp is NULL");
+  if (first) std::copy(interp->host_first.begin(), interp->host_first.end(), first);
+  if (w) std::copy(interp->host_w.begin(), interp->host_w.end(), w);
+  return FBST_OK;
+}
+
+fbst_status fbst_execute_interp(const fbst_interp* interp, int nblocks, const void* beams,
+                                void* out, void* hip_stream) {
+  if (!interp) return fail(FBST_E_INVALID, "interp is NULL");
+  fbst_status s = check_exec(interp->plan);
+  if (s != FBST_OK) return s;
+  if (nblocks < 0) return fail(FBST_E_INVALID, "nblocks must be >= 0");
+  if (nblocks == 0) return FBST_OK;
+  if (!beams || !out) return fail(FBST_E_INVALID, "beams and out are required");
+  const fbst::Params& p = interp->plan->p;
+  const hipError_t e = fbst::launch_interp_beams(beams, interp->first, interp->w, out, p.B,
+                                                 interp->D, p.N, nblocks,
+                                                 p.prec == FBST_PREC_FP64,
+                                                 static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return hip_fail(e, "fbst_execute_interp launch");
+  return FBST_OK;
+}
+
 void fbst_nulls_destroy(fbst_nulls* nulls) {
   if (!nulls) return;
   if (nulls->dev) (void)hipFree(nulls->dev);

@@ -992,4 +992,82 @@ fbst_status build_null_tables(const Params& p, const std::vector<double>& uq,
   return FBST_OK;
 }
 
+// Off-grid beams by spline interpolation (Sec. VIII).  In the grid index
+// s = (u - u0) / du the beams sit at the integers, and an affine change of
+// variable maps a cubic spline to a cubic spline with the same end
+// conditions, so the weights follow from unit-spaced nodes 0..7.  With
+// moments M_k = S''(k), the spline through node values y is
+//   S(x) = M_k a^3 / 6 + M_{k+1} b^3 / 6 + (y_k - M_k / 6) a + (y_{k+1} - M_{k+1} / 6) b,
+//   a = k + 1 - x, b = x - k on [k, k + 1],
+// where the interior nodes give M_{k-1} + 4 M_k + M_{k+1} = 6 (y_{k-1} - 2 y_k + y_{k+1})
+// and the not-a-knot ends M_0 - 2 M_1 + M_2 = 0 = M_5 - 2 M_6 + M_7 (equal
+// third derivatives on the first two and on the last two intervals).  The
+// weight of node i is the spline through the unit vector e_i.
+namespace {
+void spline_unit_weights(double x, double* w) {
+  constexpr int n = INTERP_TAPS;
+  for (int i = 0; i < n; ++i) {
+    double A[n][n + 1] = {};
+    A[0][0] = 1.0; A[0][1] = -2.0; A[0][2] = 1.0;
+    A[n - 1][n - 3] = 1.0; A[n - 1][n - 2] = -2.0; A[n - 1][n - 1] = 1.0;
+    for (int k = 1; k < n - 1; ++k) {
+      A[k][k - 1] = 1.0; A[k][k] = 4.0; A[k][k + 1] = 1.0;
+      A[k][n] = 6.0 * ((k - 1 == i) - 2.0 * (k == i) + (k + 1 == i));
+    }
+    // Gaussian elimination with partial pivoting, then back substitution
+    for (int c = 0; c < n; ++c) {
+      int piv = c;
+      for (int r = c + 1; r < n; ++r)
+        if (std::fabs(A[r][c]) > std::fabs(A[piv][c])) piv = r;
+      if (piv != c)
+        for (int k = 0; k <= n; ++k) std::swap(A[c][k], A[piv][k]);
+      for (int r = c + 1; r < n; ++r) {
+        const double f = A[r][c] / A[c][c];
+        for (int k = c; k <= n; ++k) A[r][k] -= f * A[c][k];
+      }
+    }
+    double Mo[n];
+    for (int r = n - 1; r >= 0; --r) {
+      double acc = A[r][n];
+      for (int k = r + 1; k < n; ++k) acc -= A[r][k] * Mo[k];
+      Mo[r] = acc / A[r][r];
+    }
+    int k = static_cast<int>(std::floor(x));
+    if (k < 0) k = 0;
+    if (k > n - 2) k = n - 2;
+    const double a = k + 1 - x, b = x - k;
+    const double yk = (k == i), yk1 = (k + 1 == i);
+    w[i] = Mo[k] * a * a * a / 6.0 + Mo[k + 1] * b * b * b / 6.0 + (yk - Mo[k] / 6.0) * a +
+           (yk1 - Mo[k + 1] / 6.0) * b;
+  }
+}
+}  // namespace
+
+fbst_status build_interp_table(const Params& p, const std::vector<double>& ud,
+                               std::vector<int>* first, std::vector<double>* w,
+                               std::string* msg) {
+  if (p.bv != 1 || p.bu < INTERP_TAPS || p.du == 0.0) {
+    *msg = "spline interpolation needs a line of at least 8 distinct beams (bv == 1)";
+    return FBST_E_UNSUPPORTED;
+  }
+  const size_t D = ud.size();
+  first->assign(D, 0);
+  w->assign(D * INTERP_TAPS, 0.0);
+  const double last = p.bu - 1;
+  for (size_t d = 0; d < D; ++d) {
+    double s = (ud[d] - p.u0) / p.du;
+    const double tol = 1e-9 * (last + 1);
+    if (!(s >= -tol && s <= last + tol)) {
+      *msg = "interpolation directions must lie within the beam grid (no extrapolation)";
+      return FBST_E_INVALID;
+    }
+    s = std::min(std::max(s, 0.0), last);
+    const int j = std::min(static_cast<int>(std::floor(s)), p.bu - 1);   // u_j <= u < u_{j+1}
+    const int j0 = std::min(std::max(j - (INTERP_TAPS / 2 - 1), 0), p.bu - INTERP_TAPS);
+    (*first)[d] = j0;
+    spline_unit_weights(s - j0, w->data() + d * INTERP_TAPS);
+  }
+  return FBST_OK;
+}
+
 }  // namespace fbst

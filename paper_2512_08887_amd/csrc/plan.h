@@ -91,6 +91,16 @@ fbst_status build_direction_tables(const Params& p, const std::vector<double>& u
                                    const std::vector<double>& vd, std::vector<zd>* K,
                                    std::vector<zd>* E, std::string* msg);
 
+// Off-grid beams by spline interpolation (Sec. VIII, off-grid angles), for a
+// line of beams u_b = u0 + b du (bv = 1, bu >= INTERP_TAPS): for each
+// direction, the first of the INTERP_TAPS consecutive grid beams around it and
+// the weights of the not-a-knot cubic spline through them evaluated at the
+// direction, first [D], w [D][INTERP_TAPS]; float64.
+constexpr int INTERP_TAPS = 8;
+fbst_status build_interp_table(const Params& p, const std::vector<double>& ud,
+                               std::vector<int>* first, std::vector<double>* w,
+                               std::string* msg);
+
 // Beamspace nulling tables for interferer directions (uq, vq) (Sec. VIII):
 // G [q L + k][b][n] = (F_b^H F_q A_q^{-1})[n][k] and, when E is given, the
 // projection phases E [q][m][l] = exp(j a_l tau_{q,m}); float64.
@@ -137,6 +147,18 @@ struct fbst_directions {
   size_t dev_bytes = 0;
   const void* E = nullptr;
   const void* K = nullptr;
+};
+
+// Spline-interpolated off-grid beams of one plan (device: first [D] ints,
+// then the weights [D][INTERP_TAPS] as float64; host copies kept for queries).
+struct fbst_interp {
+  const fbst_plan* plan = nullptr;
+  int D = 0;
+  void* dev = nullptr;
+  const int* first = nullptr;
+  const double* w = nullptr;
+  std::vector<int> host_first;
+  std::vector<double> host_w;
 };
 
 // A captured and instantiated launch sequence of one plan.

@@ -266,4 +266,56 @@ hipError_t launch_unit_rows(void* w, int B, int L, int l0, int rows, hipStream_t
   return hipGetLastError();
 }
 
+namespace {
+
+// Off-grid beams by spline interpolation (Sec. VIII):
+//   out[blk][d][n] = sum_i w[d][i] beams[blk][first[d] + i][n]   (i < 8)
+// One workgroup per 256 consecutive n of one (block, direction) row, so the
+// window and its weights are uniform over the workgroup; the 8 input rows are
+// read coalesced in n.  Each XCD takes a contiguous range of rows, so the
+// directions that share grid beams read them through one L2.
+template <typename T>
+__global__ __launch_bounds__(256) void k_interp_beams(const cx<T>* __restrict__ beams,
+                                                      const int* __restrict__ first,
+                                                      const double* __restrict__ w,
+                                                      cx<T>* __restrict__ out, int B, int D,
+                                                      int N, int ntile) {
+  const int wg = xcd_linear(gridDim.x);          // contiguous logical range per XCD
+  const int row = wg / ntile;                    // blk * D + d
+  const int n = (wg - row * ntile) * 256 + threadIdx.x;
+  if (n >= N) return;
+  const int d = row % D;
+  const size_t blk = static_cast<size_t>(row / D);
+  const cx<T>* src = beams + (blk * B + first[d]) * N + n;
+  const double* wd = w + static_cast<size_t>(d) * 8;
+  T re = 0, im = 0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const cx<T> a = src[static_cast<size_t>(i) * N];
+    const T c = static_cast<T>(wd[i]);
+    re += c * a.re;
+    im += c * a.im;
+  }
+  out[static_cast<size_t>(row) * N + n] = cx<T>{re, im};
+}
+
+}  // namespace
+
+hipError_t launch_interp_beams(const void* beams, const int* first, const double* w, void* out,
+                               int B, int D, int N, int nblocks, bool fp64, hipStream_t st) {
+  if (nblocks < 1 || B < 8 || D < 1 || N < 1) return hipErrorInvalidValue;
+  const long long ntile = (N + 255) / 256;
+  const long long grid = 1LL * nblocks * D * ntile;
+  if (grid > 0x7fffffffLL) return hipErrorInvalidValue;
+  if (fp64)
+    hipLaunchKernelGGL(k_interp_beams<double>, dim3(static_cast<unsigned>(grid)), dim3(256), 0, st,
+                       static_cast<const cx<double>*>(beams), first, w,
+                       static_cast<cx<double>*>(out), B, D, N, static_cast<int>(ntile));
+  else
+    hipLaunchKernelGGL(k_interp_beams<float>, dim3(static_cast<unsigned>(grid)), dim3(256), 0, st,
+                       static_cast<const cx<float>*>(beams), first, w,
+                       static_cast<cx<float>*>(out), B, D, N, static_cast<int>(ntile));
+  return hipGetLastError();
+}
+
 }  // namespace fbst

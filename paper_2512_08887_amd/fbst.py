@@ -135,6 +135,15 @@ def load_library(path: str = LIB_PATH):
     L.fbst_execute_directions.argtypes = [c_void_p, c_void_p, c_int, c_int, c_void_p, c_void_p,
                                           c_void_p, c_void_p]
     L.fbst_execute_directions.restype = c_int
+    L.fbst_interp_create.argtypes = [c_void_p, c_int, POINTER(ctypes.c_double),
+                                     POINTER(c_void_p)]
+    L.fbst_interp_create.restype = c_int
+    L.fbst_interp_destroy.argtypes = [c_void_p]
+    L.fbst_interp_destroy.restype = None
+    L.fbst_interp_table.argtypes = [c_void_p, POINTER(c_int), POINTER(ctypes.c_double)]
+    L.fbst_interp_table.restype = c_int
+    L.fbst_execute_interp.argtypes = [c_void_p, c_int, c_void_p, c_void_p, c_void_p]
+    L.fbst_execute_interp.restype = c_int
     L.fbst_nulls_destroy.argtypes = [c_void_p]
     L.fbst_nulls_destroy.restype = None
     L.fbst_workspace_bytes_nulled.argtypes = [c_void_p, c_void_p, c_int]
@@ -307,6 +316,30 @@ def fbst_workspace_bytes_directions(plan, dirs, nblocks) -> int:
 def fbst_execute_directions(plan, dirs, nblocks, max_chunk, x, beams, workspace, stream=0):
     _check(lib().fbst_execute_directions(plan, dirs, nblocks, max_chunk, x, beams, workspace,
                                          stream or None))
+
+
+def fbst_interp_create(plan, u) -> int:
+    n = len(u)
+    ua = (ctypes.c_double * n)(*[float(a) for a in u])
+    h = c_void_p()
+    _check(lib().fbst_interp_create(plan, n, ua, byref(h)))
+    return h.value
+
+
+def fbst_interp_destroy(interp):
+    lib().fbst_interp_destroy(interp)
+
+
+def fbst_interp_table(interp, D):
+    """(first [D] ints, weights [D][8] float64) as lists."""
+    fa = (c_int * D)()
+    wa = (ctypes.c_double * (8 * D))()
+    _check(lib().fbst_interp_table(interp, fa, wa))
+    return list(fa), [list(wa[8 * d:8 * d + 8]) for d in range(D)]
+
+
+def fbst_execute_interp(interp, nblocks, beams, out, stream=0):
+    _check(lib().fbst_execute_interp(interp, nblocks, beams, out, stream or None))
 
 
 def fbst_nulls_destroy(nulls):
@@ -550,6 +583,46 @@ class Nulls:
     def close(self):
         if getattr(self, "handle", None):
             fbst_nulls_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Interp:
+    """Off-grid beams interpolated from grid beams with a spline (fbst_interp_*)."""
+
+    def __init__(self, plan, u):
+        self.plan = plan
+        self.D = len(u)
+        self.handle = fbst_interp_create(plan.handle, list(u))
+
+    def table(self):
+        return fbst_interp_table(self.handle, self.D)
+
+    def execute(self, beams, out=None):
+        """beams [nblocks, B, N] (or [B, N]) -> out [nblocks, D, N] (or [D, N])."""
+        import torch
+        p = self.plan
+        single = beams.dim() == 2
+        bb = beams.unsqueeze(0) if single else beams
+        p._check_in(bb, (p.B, p.N))
+        nb = bb.shape[0]
+        if out is None:
+            out = torch.empty((nb, self.D, p.N), dtype=bb.dtype, device=bb.device)
+        elif (not out.is_cuda or not out.is_contiguous() or out.dtype != bb.dtype
+              or out.numel() != nb * self.D * p.N):
+            raise ValueError("out must be a contiguous CUDA tensor of [nblocks, D, N] elements")
+        fbst_execute_interp(self.handle, nb, bb.data_ptr(), out.data_ptr(),
+                            torch.cuda.current_stream().cuda_stream)
+        return out.reshape(self.D, p.N) if single else out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            fbst_interp_destroy(self.handle)
             self.handle = None
 
     def __del__(self):
