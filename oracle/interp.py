@@ -18,6 +18,11 @@ element line) with a spline, for every time sample.  Readings taken here
   second-to-last node), applied to the real and imaginary parts alike, so
   the interpolated beam is a real-weighted sum of the 8 beams.
 
+For a planar (u, v) beam grid (beam b = a * bv + c at (u_a, v_c)) the same
+reading is applied per axis: the tensor-product spline over the 8 x 8 grid
+beams around (u*, v*), i.e. the 1-D spline along u of the 1-D splines along
+v, whose weights are the products of the two axes' weights.
+
 ``spline_weights`` writes that spline out from its definition: one cubic per
 interval, 4 (n - 1) unknown coefficients, fixed by interpolation at both
 ends of every interval, continuity of the first and second derivatives at
@@ -30,7 +35,8 @@ from __future__ import annotations
 import numpy as np
 
 __all__ = ["NEIGHBOURS", "neighbour_window", "spline_coefficients", "spline_eval",
-           "spline_weights", "interp_weights", "interp_beams"]
+           "spline_weights", "interp_weights", "interp_beams", "interp_weights_2d",
+           "interp_beams_2d"]
 
 NEIGHBOURS = 8
 
@@ -136,3 +142,23 @@ def interp_beams(beams: np.ndarray, grid_u: np.ndarray, us) -> np.ndarray:
         j0, w = interp_weights(grid_u, float(u))
         out[..., d, :] = np.tensordot(w, bm[..., j0:j0 + len(w), :], axes=([0], [-2]))
     return out
+
+
+def interp_weights_2d(grid_u: np.ndarray, grid_v: np.ndarray, u: float, v: float,
+                      k: int = NEIGHBOURS) -> np.ndarray:
+    """Weights over all bu * bv grid beams (beam b = a * bv + c) of the
+    tensor-product spline at (u, v): W[a, c] = w_u[a - a0] w_v[c - c0] inside
+    the two windows, zero elsewhere; returned flattened to [bu * bv]."""
+    a0, wu = interp_weights(grid_u, u, k)
+    c0, wv = interp_weights(grid_v, v, k)
+    W = np.zeros((len(grid_u), len(grid_v)))
+    W[a0:a0 + k, c0:c0 + k] = np.outer(wu, wv)
+    return W.reshape(-1)
+
+
+def interp_beams_2d(beams: np.ndarray, grid_u: np.ndarray, grid_v: np.ndarray, us, vs) -> np.ndarray:
+    """Interpolated beams at directions (us[d], vs[d]) from planar-grid beams
+    [..., bu * bv, N]."""
+    bm = np.asarray(beams)
+    W = np.stack([interp_weights_2d(grid_u, grid_v, float(u), float(v)) for u, v in zip(us, vs)])
+    return np.moveaxis(np.tensordot(W, bm, axes=([1], [-2])), 0, -2)

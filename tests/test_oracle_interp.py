@@ -6,7 +6,7 @@ setting (a 128-element line, 256 beams, theta* = pi/3), where the beam
 interpolated from 8 grid beams must be close to the beam formed at theta*."""
 import numpy as np
 import pytest
-from scipy.interpolate import CubicSpline
+from scipy.interpolate import CubicSpline, RectBivariateSpline
 
 from oracle import direct as od
 from oracle import interp as oi
@@ -106,3 +106,42 @@ def test_fig3d_interpolated_beam_close_to_true_beam():
     # and far better than the nearest grid beam alone
     nearest = near[int(np.argmin(np.abs(grid[j0:j0 + 8] - u_star)))]
     assert err < 0.5 * np.linalg.norm(nearest - true) / np.linalg.norm(true)
+
+
+def test_2d_matches_scipy_bivariate_interpolating_spline():
+    """FITPACK's interpolating bicubic spline (s = 0) keeps the interior knots
+    at all but the second and second-to-last nodes of each axis: the
+    tensor-product not-a-knot spline."""
+    rng = np.random.default_rng(15)
+    gu = od.beam_grid(12)
+    gv = od.beam_grid(9)
+    Z = rng.standard_normal((12, 9))
+    for _ in range(10):
+        u = rng.uniform(gu[0], gu[-1])
+        v = rng.uniform(gv[0], gv[-1])
+        a0 = oi.neighbour_window(gu, u)
+        c0 = oi.neighbour_window(gv, v)
+        ref = RectBivariateSpline(gu[a0:a0 + 8], gv[c0:c0 + 8], Z[a0:a0 + 8, c0:c0 + 8],
+                                  kx=3, ky=3, s=0)(u, v)[0, 0]
+        assert abs(oi.interp_weights_2d(gu, gv, u, v) @ Z.reshape(-1) - ref) < 1e-12
+
+
+def test_2d_reproduces_bicubics_and_nodes():
+    rng = np.random.default_rng(16)
+    gu = od.beam_grid(10)
+    gv = od.beam_grid(8)
+    c = rng.standard_normal((4, 4))
+    f = lambda u, v: sum(c[p, q] * u ** p * v ** q for p in range(4) for q in range(4))
+    vals = np.array([[f(a, b) for b in gv] for a in gu]).reshape(-1)
+    for _ in range(10):
+        u = rng.uniform(gu[0], gu[-1])
+        v = rng.uniform(gv[0], gv[-1])
+        assert abs(oi.interp_weights_2d(gu, gv, u, v) @ vals - f(u, v)) < 1e-11
+    W = oi.interp_weights_2d(gu, gv, gu[3], gv[5])
+    assert np.allclose(W, np.eye(80)[3 * 8 + 5], atol=1e-13)
+    bm = rng.standard_normal((2, 80, 4)) + 1j * rng.standard_normal((2, 80, 4))
+    out = oi.interp_beams_2d(bm, gu, gv, [gu[3], 0.1], [gv[5], -0.2])
+    assert out.shape == (2, 2, 4)
+    assert np.allclose(out[:, 0], bm[:, 3 * 8 + 5], atol=1e-13)
+    ref = np.tensordot(oi.interp_weights_2d(gu, gv, 0.1, -0.2), bm, axes=([0], [1]))
+    assert np.allclose(out[:, 1], ref, atol=1e-14)
