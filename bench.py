@@ -413,7 +413,7 @@ def interp_bench(F, torch, plan, cfg, beams, *, reps=20, log=print, checks=None)
          "value": nb * D * cfg.N / (ms / 1e3), "unit": "beam-samples/s", "ms_per_launch": ms,
          "roofline": {"kernel": "k_interp_beams", "bound": "hbm", "achieved": ach, "peak": 8000.0,
                       "unit": "GB/s", "frac": ach / 8000.0, "bytes_per_launch": nbytes,
-                      "traffic": stored_traffic("k_interp_beams<float>",
+                      "traffic": stored_traffic("k_interp_beams<float, 1>",
                                                 nb * D * ((cfg.N + 255) // 256) * 256)}}
     got = out[0].cpu().numpy().astype(np.complex128)
     b0 = src[0].cpu().numpy().astype(np.complex128)

@@ -333,29 +333,36 @@ fbst_status fbst_execute_directions(const fbst_plan* plan, const fbst_directions
 /* ---- Off-grid beams by spline interpolation (Sec. VIII, off-grid angles) --- */
 typedef struct fbst_interp fbst_interp;
 
-/* The paper's interpolated off-grid beam: for each direction u[d] (direction
- * cosine) on a line of beams u_b = u0 + b du (bv == 1, B >= 8), the 8
- * consecutive grid beams j-3 .. j+4 with u_j <= u[d] < u_{j+1} (the window
- * shifted inward at the ends of the grid) and the real weights of the cubic
- * spline with not-a-knot ends through them, evaluated at u[d] (computed in
- * float64 on the host, kept there and uploaded: 68 bytes per direction).
- * u[d] must lie within [u_0, u_{B-1}] (FBST_E_INVALID otherwise: no
- * extrapolation); other beam grids give FBST_E_UNSUPPORTED.  1..65536
- * directions.  The plan must outlive it. */
+/* The paper's interpolated off-grid beam: for each direction (u[d], v[d])
+ * (direction cosines) and each axis of the beam grid u_a = u0 + a du,
+ * v_c = v0 + c dv (beam b = a bv + c), the 8 consecutive grid beams
+ * j-3 .. j+4 with x_j <= x < x_{j+1} (the window shifted inward at the ends of
+ * the axis) and the real weights of the cubic spline with not-a-knot ends
+ * through them, evaluated at the direction (computed in float64 on the host,
+ * kept there and uploaded: 136 bytes per direction).  A line of beams
+ * (bv == 1, v NULL or ignored) interpolates 8 beams along u; a planar grid
+ * (bv > 1, v required) takes the tensor-product spline over 8 x 8 beams.
+ * Each axis with more than one beam needs at least 8 distinct beams
+ * (FBST_E_UNSUPPORTED otherwise); directions must lie within the grid
+ * (FBST_E_INVALID otherwise: no extrapolation).  1..65536 directions.  The
+ * plan must outlive it. */
 fbst_status fbst_interp_create(const fbst_plan* plan, int n_directions, const double* u,
-                               fbst_interp** out);
+                               const double* v, fbst_interp** out);
 
 /* Free interpolation tables (after their launches finished); NULL is a no-op. */
 void fbst_interp_destroy(fbst_interp* interp);
 
-/* Host copy of the table: first [D] (first grid beam of each window) and
- * w [D][8] (float64 weights); either may be NULL.  FBST_E_INVALID on NULL interp. */
+/* Host copy of the table: first [D][2] (first grid index of the u and the v
+ * window; v is 0 for a line) and w [D][2][8] (float64 weights along u, then
+ * along v; a line has (1, 0, ..., 0) along v); either may be NULL.
+ * FBST_E_INVALID on NULL interp. */
 fbst_status fbst_interp_table(const fbst_interp* interp, int* first, double* w);
 
 /* beams [nblocks][B][N] (device; complex64, complex128 for FBST_PREC_FP64
  * plans; the output of fbst_execute*) -> out [nblocks][D][N] (device, same
- * type): out[blk][d][n] = sum_i w[d][i] beams[blk][first[d] + i][n], one
- * launch on hip_stream, no workspace.  nblocks == 0 is a no-op. */
+ * type): out[blk][d][n] = sum_{i,j} wu[d][i] wv[d][j]
+ * beams[blk][(a0 + i) bv + c0 + j][n] with (a0, c0) = first[d], one launch on
+ * hip_stream, no workspace.  nblocks == 0 is a no-op. */
 fbst_status fbst_execute_interp(const fbst_interp* interp, int nblocks, const void* beams,
                                 void* out, void* hip_stream);
 

@@ -968,21 +968,25 @@ fbst_status fbst_execute_directions(const fbst_plan* plan, const fbst_directions
 }
 
 fbst_status fbst_interp_create(const fbst_plan* plan, int n_directions, const double* u,
-                               fbst_interp** out) {
+                               const double* v, fbst_interp** out) {
   if (!out) return fail(FBST_E_INVALID, "out is NULL");
   *out = nullptr;
   fbst_status s = check_exec(plan);
   if (s != FBST_OK) return s;
   if (n_directions < 1 || n_directions > 65536 || !u)
     return fail(FBST_E_INVALID, "need 1..65536 directions");
-  std::vector<double> ud(u, u + n_directions);
-  for (double x : ud)
-    if (!std::isfinite(x)) return fail(FBST_E_INVALID, "directions must be finite");
+  const bool plane = plan->p.bv > 1;
+  if (plane && !v) return fail(FBST_E_INVALID, "a planar beam grid needs v");
+  std::vector<double> ud(u, u + n_directions), vd(n_directions, 0.0);
+  if (plane) vd.assign(v, v + n_directions);
+  for (int i = 0; i < n_directions; ++i)
+    if (!std::isfinite(ud[i]) || !std::isfinite(vd[i]))
+      return fail(FBST_E_INVALID, "directions must be finite");
   fbst_interp* it = new (std::nothrow) fbst_interp();
   if (!it) return fail(FBST_E_NOMEM, "host allocation failed");
   std::string msg;
   try {
-    s = fbst::build_interp_table(plan->p, ud, &it->host_first, &it->host_w, &msg);
+    s = fbst::build_interp_table(plan->p, ud, vd, &it->host_first, &it->host_w, &msg);
   } catch (const std::bad_alloc&) {
     s = FBST_E_NOMEM;
     msg = "host allocation of the interpolation table failed";
@@ -991,7 +995,7 @@ fbst_status fbst_interp_create(const fbst_plan* plan, int n_directions, const do
     delete it;
     return fail(s, msg);
   }
-  const size_t o_w = (static_cast<size_t>(n_directions) * sizeof(int) + 255) / 256 * 256;
+  const size_t o_w = (it->host_first.size() * sizeof(int) + 255) / 256 * 256;
   const size_t bytes = o_w + it->host_w.size() * sizeof(double);
   hipError_t e = hipMalloc(&it->dev, bytes);
   if (e != hipSuccess) {
@@ -1000,7 +1004,8 @@ fbst_status fbst_interp_create(const fbst_plan* plan, int n_directions, const do
     return fail(FBST_E_NOMEM, "hipMalloc of the interpolation table failed");
   }
   unsigned char* b = static_cast<unsigned char*>(it->dev);
-  e = hipMemcpy(b, it->host_first.data(), n_directions * sizeof(int), hipMemcpyHostToDevice);
+  e = hipMemcpy(b, it->host_first.data(), it->host_first.size() * sizeof(int),
+                hipMemcpyHostToDevice);
   if (e == hipSuccess)
     e = hipMemcpy(b + o_w, it->host_w.data(), it->host_w.size() * sizeof(double),
                   hipMemcpyHostToDevice);
@@ -1040,7 +1045,7 @@ fbst_status fbst_execute_interp(const fbst_interp* interp, int nblocks, const vo
   if (!beams || !out) return fail(FBST_E_INVALID, "beams and out are required");
   const fbst::Params& p = interp->plan->p;
   const hipError_t e = fbst::launch_interp_beams(beams, interp->first, interp->w, out, p.B,
-                                                 interp->D, p.N, nblocks,
+                                                 p.bv, interp->D, p.N, nblocks,
                                                  p.prec == FBST_PREC_FP64,
                                                  static_cast<hipStream_t>(hip_stream));
   if (e != hipSuccess) return hip_fail(e, "fbst_execute_interp launch");

@@ -125,11 +125,13 @@ hipError_t launch_project_dirs(const void* yhat, const void* E, void* out, int M
 // L <= 8192; status [B] (device ints): 0, or 1 if a pivot is not positive.
 hipError_t launch_levinson(const void* cols, void* x, int* status, int B, int L, hipStream_t st);
 
-// out[blk][d][n] = sum_i w[d][i] beams[blk][first[d] + i][n] for i < 8
-// (complex64, or complex128 when fp64; beams [nb][B][N], out [nb][D][N];
-// first and w are device arrays [D] and [D][8]).
+// out[blk][d][n] = sum_{i<8, j<TV} wu[d][i] wv[d][j] beams[blk][(a0 + i) bv + c0 + j][n]
+// with (a0, c0) = first[d] and (wu, wv) = w[d] (TV = 8 if bv > 1, else 1);
+// complex64, or complex128 when fp64; beams [nb][B][N], out [nb][D][N];
+// first and w are device arrays [D][2] and [D][2][8].
 hipError_t launch_interp_beams(const void* beams, const int* first, const double* w, void* out,
-                               int B, int D, int N, int nblocks, bool fp64, hipStream_t st);
+                               int B, int bv, int D, int N, int nblocks, bool fp64,
+                               hipStream_t st);
 
 // w[j][b][l] = (l == l0 + j) for j < rows (complex64, [rows][B][L]).
 hipError_t launch_unit_rows(void* w, int B, int L, int l0, int rows, hipStream_t st);

@@ -1044,28 +1044,39 @@ void spline_unit_weights(double x, double* w) {
 }  // namespace
 
 fbst_status build_interp_table(const Params& p, const std::vector<double>& ud,
-                               std::vector<int>* first, std::vector<double>* w,
-                               std::string* msg) {
-  if (p.bv != 1 || p.bu < INTERP_TAPS || p.du == 0.0) {
-    *msg = "spline interpolation needs a line of at least 8 distinct beams (bv == 1)";
+                               const std::vector<double>& vd, std::vector<int>* first,
+                               std::vector<double>* w, std::string* msg) {
+  const bool plane = p.bv > 1;
+  if (p.bu < INTERP_TAPS || p.du == 0.0 || (plane && (p.bv < INTERP_TAPS || p.dv == 0.0))) {
+    *msg = "spline interpolation needs at least 8 distinct grid beams along each axis";
     return FBST_E_UNSUPPORTED;
   }
+  // window and weights along one axis with n beams at x0 + k dx
+  auto axis = [](double x, double x0, double dx, int n, int* f, double* ww) {
+    const double last = n - 1;
+    double s = (x - x0) / dx;
+    const double tol = 1e-9 * n;
+    if (!(s >= -tol && s <= last + tol)) return false;
+    s = std::min(std::max(s, 0.0), last);
+    const int j = std::min(static_cast<int>(std::floor(s)), n - 1);   // x_j <= x < x_{j+1}
+    const int j0 = std::min(std::max(j - (INTERP_TAPS / 2 - 1), 0), n - INTERP_TAPS);
+    *f = j0;
+    spline_unit_weights(s - j0, ww);
+    return true;
+  };
   const size_t D = ud.size();
-  first->assign(D, 0);
-  w->assign(D * INTERP_TAPS, 0.0);
-  const double last = p.bu - 1;
+  first->assign(2 * D, 0);
+  w->assign(2 * D * INTERP_TAPS, 0.0);
   for (size_t d = 0; d < D; ++d) {
-    double s = (ud[d] - p.u0) / p.du;
-    const double tol = 1e-9 * (last + 1);
-    if (!(s >= -tol && s <= last + tol)) {
+    int* f = first->data() + 2 * d;
+    double* ww = w->data() + 2 * d * INTERP_TAPS;
+    bool ok = axis(ud[d], p.u0, p.du, p.bu, f, ww);
+    if (plane) ok = ok && axis(vd[d], p.v0, p.dv, p.bv, f + 1, ww + INTERP_TAPS);
+    else ww[INTERP_TAPS] = 1.0;                 // one beam along v, weight 1
+    if (!ok) {
       *msg = "interpolation directions must lie within the beam grid (no extrapolation)";
       return FBST_E_INVALID;
     }
-    s = std::min(std::max(s, 0.0), last);
-    const int j = std::min(static_cast<int>(std::floor(s)), p.bu - 1);   // u_j <= u < u_{j+1}
-    const int j0 = std::min(std::max(j - (INTERP_TAPS / 2 - 1), 0), p.bu - INTERP_TAPS);
-    (*first)[d] = j0;
-    spline_unit_weights(s - j0, w->data() + d * INTERP_TAPS);
   }
   return FBST_OK;
 }

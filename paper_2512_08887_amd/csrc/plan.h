@@ -91,15 +91,18 @@ fbst_status build_direction_tables(const Params& p, const std::vector<double>& u
                                    const std::vector<double>& vd, std::vector<zd>* K,
                                    std::vector<zd>* E, std::string* msg);
 
-// Off-grid beams by spline interpolation (Sec. VIII, off-grid angles), for a
-// line of beams u_b = u0 + b du (bv = 1, bu >= INTERP_TAPS): for each
-// direction, the first of the INTERP_TAPS consecutive grid beams around it and
-// the weights of the not-a-knot cubic spline through them evaluated at the
-// direction, first [D], w [D][INTERP_TAPS]; float64.
+// Off-grid beams by spline interpolation (Sec. VIII, off-grid angles) on the
+// beam grid u_a = u0 + a du, v_c = v0 + c dv (beam b = a bv + c; at least
+// INTERP_TAPS distinct beams along each axis that has more than one): per
+// direction and axis, the first of the INTERP_TAPS consecutive grid beams
+// around it and the weights of the not-a-knot cubic spline through them
+// evaluated at the direction (the tensor-product spline on a plane; a line
+// gets the window 0 and the weights (1, 0, ...) along v).
+// first [D][2] (u, v), w [D][2][INTERP_TAPS]; float64.
 constexpr int INTERP_TAPS = 8;
 fbst_status build_interp_table(const Params& p, const std::vector<double>& ud,
-                               std::vector<int>* first, std::vector<double>* w,
-                               std::string* msg);
+                               const std::vector<double>& vd, std::vector<int>* first,
+                               std::vector<double>* w, std::string* msg);
 
 // Beamspace nulling tables for interferer directions (uq, vq) (Sec. VIII):
 // G [q L + k][b][n] = (F_b^H F_q A_q^{-1})[n][k] and, when E is given, the
@@ -149,8 +152,9 @@ struct fbst_directions {
   const void* K = nullptr;
 };
 
-// Spline-interpolated off-grid beams of one plan (device: first [D] ints,
-// then the weights [D][INTERP_TAPS] as float64; host copies kept for queries).
+// Spline-interpolated off-grid beams of one plan (device: first [D][2] ints,
+// then the weights [D][2][INTERP_TAPS] as float64; host copies kept for
+// queries).
 struct fbst_interp {
   const fbst_plan* plan = nullptr;
   int D = 0;

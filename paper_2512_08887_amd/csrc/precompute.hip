@@ -268,33 +268,40 @@ hipError_t launch_unit_rows(void* w, int B, int L, int l0, int rows, hipStream_t
 
 namespace {
 
-// Off-grid beams by spline interpolation (Sec. VIII):
-//   out[blk][d][n] = sum_i w[d][i] beams[blk][first[d] + i][n]   (i < 8)
+// Off-grid beams by spline interpolation (Sec. VIII), tensor product over the
+// beam grid (beam b = a bv + c):
+//   out[blk][d][n] = sum_{i < 8, j < TV} wu[d][i] wv[d][j] beams[blk][(a0 + i) bv + c0 + j][n]
+// with (a0, c0) = first[d] and (wu, wv) = w[d]; TV = 1 for a line of beams
+// (bv = 1, wv = 1), 8 for a plane.
 // One workgroup per 256 consecutive n of one (block, direction) row, so the
 // window and its weights are uniform over the workgroup; the 8 input rows are
 // read coalesced in n.  Each XCD takes a contiguous range of rows, so the
 // directions that share grid beams read them through one L2.
-template <typename T>
+template <typename T, int TV>
 __global__ __launch_bounds__(256) void k_interp_beams(const cx<T>* __restrict__ beams,
                                                       const int* __restrict__ first,
                                                       const double* __restrict__ w,
-                                                      cx<T>* __restrict__ out, int B, int D,
-                                                      int N, int ntile) {
+                                                      cx<T>* __restrict__ out, int B, int bv,
+                                                      int D, int N, int ntile) {
   const int wg = xcd_linear(gridDim.x);          // contiguous logical range per XCD
   const int row = wg / ntile;                    // blk * D + d
   const int n = (wg - row * ntile) * 256 + threadIdx.x;
   if (n >= N) return;
   const int d = row % D;
   const size_t blk = static_cast<size_t>(row / D);
-  const cx<T>* src = beams + (blk * B + first[d]) * N + n;
-  const double* wd = w + static_cast<size_t>(d) * 8;
+  const int a0 = first[2 * d], c0 = first[2 * d + 1];
+  const cx<T>* src = beams + (blk * B + static_cast<size_t>(a0) * bv + c0) * N + n;
+  const double* wd = w + static_cast<size_t>(d) * 16;
   T re = 0, im = 0;
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
-    const cx<T> a = src[static_cast<size_t>(i) * N];
-    const T c = static_cast<T>(wd[i]);
-    re += c * a.re;
-    im += c * a.im;
+#pragma unroll
+    for (int j = 0; j < TV; ++j) {
+      const cx<T> a = src[(static_cast<size_t>(i) * bv + j) * N];
+      const T c = static_cast<T>(wd[i] * wd[8 + j]);
+      re += c * a.re;
+      im += c * a.im;
+    }
   }
   out[static_cast<size_t>(row) * N + n] = cx<T>{re, im};
 }
@@ -302,19 +309,26 @@ __global__ __launch_bounds__(256) void k_interp_beams(const cx<T>* __restrict__ 
 }  // namespace
 
 hipError_t launch_interp_beams(const void* beams, const int* first, const double* w, void* out,
-                               int B, int D, int N, int nblocks, bool fp64, hipStream_t st) {
-  if (nblocks < 1 || B < 8 || D < 1 || N < 1) return hipErrorInvalidValue;
+                               int B, int bv, int D, int N, int nblocks, bool fp64,
+                               hipStream_t st) {
+  if (nblocks < 1 || bv < 1 || B % bv != 0 || B / bv < 8 || (bv > 1 && bv < 8) || D < 1 || N < 1)
+    return hipErrorInvalidValue;
   const long long ntile = (N + 255) / 256;
   const long long grid = 1LL * nblocks * D * ntile;
   if (grid > 0x7fffffffLL) return hipErrorInvalidValue;
-  if (fp64)
-    hipLaunchKernelGGL(k_interp_beams<double>, dim3(static_cast<unsigned>(grid)), dim3(256), 0, st,
-                       static_cast<const cx<double>*>(beams), first, w,
-                       static_cast<cx<double>*>(out), B, D, N, static_cast<int>(ntile));
-  else
-    hipLaunchKernelGGL(k_interp_beams<float>, dim3(static_cast<unsigned>(grid)), dim3(256), 0, st,
-                       static_cast<const cx<float>*>(beams), first, w,
-                       static_cast<cx<float>*>(out), B, D, N, static_cast<int>(ntile));
+  const dim3 g(static_cast<unsigned>(grid)), b(256);
+  const int nt = static_cast<int>(ntile);
+  if (fp64) {
+    auto in = static_cast<const cx<double>*>(beams);
+    auto o = static_cast<cx<double>*>(out);
+    if (bv > 1) hipLaunchKernelGGL((k_interp_beams<double, 8>), g, b, 0, st, in, first, w, o, B, bv, D, N, nt);
+    else hipLaunchKernelGGL((k_interp_beams<double, 1>), g, b, 0, st, in, first, w, o, B, bv, D, N, nt);
+  } else {
+    auto in = static_cast<const cx<float>*>(beams);
+    auto o = static_cast<cx<float>*>(out);
+    if (bv > 1) hipLaunchKernelGGL((k_interp_beams<float, 8>), g, b, 0, st, in, first, w, o, B, bv, D, N, nt);
+    else hipLaunchKernelGGL((k_interp_beams<float, 1>), g, b, 0, st, in, first, w, o, B, bv, D, N, nt);
+  }
   return hipGetLastError();
 }
 

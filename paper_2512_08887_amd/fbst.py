@@ -136,7 +136,7 @@ def load_library(path: str = LIB_PATH):
                                           c_void_p, c_void_p]
     L.fbst_execute_directions.restype = c_int
     L.fbst_interp_create.argtypes = [c_void_p, c_int, POINTER(ctypes.c_double),
-                                     POINTER(c_void_p)]
+                                     POINTER(ctypes.c_double), POINTER(c_void_p)]
     L.fbst_interp_create.restype = c_int
     L.fbst_interp_destroy.argtypes = [c_void_p]
     L.fbst_interp_destroy.restype = None
@@ -318,11 +318,12 @@ def fbst_execute_directions(plan, dirs, nblocks, max_chunk, x, beams, workspace,
                                          stream or None))
 
 
-def fbst_interp_create(plan, u) -> int:
+def fbst_interp_create(plan, u, v=None) -> int:
     n = len(u)
     ua = (ctypes.c_double * n)(*[float(a) for a in u])
+    va = (ctypes.c_double * n)(*[float(a) for a in v]) if v is not None else None
     h = c_void_p()
-    _check(lib().fbst_interp_create(plan, n, ua, byref(h)))
+    _check(lib().fbst_interp_create(plan, n, ua, va, byref(h)))
     return h.value
 
 
@@ -331,11 +332,12 @@ def fbst_interp_destroy(interp):
 
 
 def fbst_interp_table(interp, D):
-    """(first [D] ints, weights [D][8] float64) as lists."""
-    fa = (c_int * D)()
-    wa = (ctypes.c_double * (8 * D))()
+    """(first [D][2] ints (u, v windows), weights [D][2][8] float64) as lists."""
+    fa = (c_int * (2 * D))()
+    wa = (ctypes.c_double * (16 * D))()
     _check(lib().fbst_interp_table(interp, fa, wa))
-    return list(fa), [list(wa[8 * d:8 * d + 8]) for d in range(D)]
+    return ([(fa[2 * d], fa[2 * d + 1]) for d in range(D)],
+            [(list(wa[16 * d:16 * d + 8]), list(wa[16 * d + 8:16 * d + 16])) for d in range(D)])
 
 
 def fbst_execute_interp(interp, nblocks, beams, out, stream=0):
@@ -595,10 +597,10 @@ class Nulls:
 class Interp:
     """Off-grid beams interpolated from grid beams with a spline (fbst_interp_*)."""
 
-    def __init__(self, plan, u):
+    def __init__(self, plan, u, v=None):
         self.plan = plan
         self.D = len(u)
-        self.handle = fbst_interp_create(plan.handle, list(u))
+        self.handle = fbst_interp_create(plan.handle, list(u), None if v is None else list(v))
 
     def table(self):
         return fbst_interp_table(self.handle, self.D)

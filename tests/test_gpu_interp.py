@@ -25,16 +25,22 @@ def need_gpu():
         pytest.skip("no GPU")
 
 
-def dense(first, w, B):
-    """Weights of each direction over all B grid beams."""
-    out = np.zeros((len(first), B))
-    for d, (j0, wd) in enumerate(zip(first, w)):
-        out[d, j0:j0 + len(wd)] = wd
-    return out
+def dense(first, w, bu, bv=1):
+    """Weights of each direction over all bu * bv grid beams (b = a bv + c) from
+    the table (first [D] of (a0, c0), w [D] of (wu, wv))."""
+    out = np.zeros((len(first), bu, bv))
+    for d, ((a0, c0), (wu, wv)) in enumerate(zip(first, w)):
+        tv = 8 if bv > 1 else 1
+        out[d, a0:a0 + 8, c0:c0 + tv] = np.outer(wu, wv[:tv])
+    return out.reshape(len(first), -1)
 
 
 def oracle_dense(grid_u, us):
-    return dense(*zip(*[oi.interp_weights(grid_u, float(u)) for u in us]), len(grid_u))
+    out = np.zeros((len(us), len(grid_u)))
+    for d, u in enumerate(us):
+        j0, w = oi.interp_weights(grid_u, float(u))
+        out[d, j0:j0 + 8] = w
+    return out
 
 
 def line_directions(g):
@@ -53,6 +59,7 @@ def test_interp_line():
     us = line_directions(p.u)
     it = F.Interp(plan, us)
     first, w = it.table()
+    assert all(c0 == 0 for _, c0 in first) and all(wv == [1.0] + [0.0] * 7 for _, wv in w)
     et = np.abs(dense(first, w, B) - oracle_dense(p.u, us)).max()
     y = crandn(rng, 3, M, N)
     x = torch.from_numpy(y.astype(np.complex64)).cuda()
@@ -111,10 +118,50 @@ def test_interp_errors_and_empty():
     grid2 = F.Plan(12, N, 12, band=band, geometry=F.make_grid_geometry(4, 3),
                    grid=F.make_beam_grid(4, 3), options=F.make_options(6.4))
     with pytest.raises(F.FbstError) as ei:
-        F.Interp(grid2, [0.0])
+        F.Interp(grid2, [0.0], [0.0])                 # axes of 4 and 3 beams
     assert ei.value.status == F.FBST_E_UNSUPPORTED
     it = F.Interp(plan, [0.1])
     F.fbst_execute_interp(it.handle, 0, 0, 0)          # no blocks: nothing launched
+    it.close()
+    plane = F.Plan(16, N, 64, band=band, geometry=F.make_grid_geometry(4, 4),
+                   grid=F.make_beam_grid(8, 8), options=F.make_options(6.4))
+    for u, v in (([0.0], None), ([0.0], [g[-1] + 1e-3]), ([0.0], [float("inf")])):
+        with pytest.raises(F.FbstError) as ei:
+            F.Interp(plane, u, v)
+        assert ei.value.status == F.FBST_E_INVALID
+
+
+def test_interp_plane():
+    """A 4 x 4 planar array with a 12 x 10 beam grid: the tensor-product spline
+    over 8 x 8 grid beams at off-grid (u, v), the grid's corners and a node."""
+    need_gpu()
+    mx, my, bu, bv, N = 4, 4, 12, 10, 32
+    M, B = mx * my, bu * bv
+    delta = 0.1 * 2 * N
+    rng = np.random.default_rng(44)
+    plan = F.Plan(M, N, B, band=F.make_band(2.0, 0.5, 1.0), geometry=F.make_grid_geometry(mx, my),
+                  grid=F.make_beam_grid(bu, bv), options=F.make_options(delta))
+    pg = od.grid_problem(mx, my, bu, bv, N, fc=2.0, delta=delta)
+    gu, gv = od.beam_grid(bu), od.beam_grid(bv)
+    us = list(rng.uniform(gu[0], gu[-1], 6)) + [gu[0], gu[-1], gu[2]]
+    vs = list(rng.uniform(gv[0], gv[-1], 6)) + [gv[-1], gv[0], gv[5]]
+    it = F.Interp(plan, us, vs)
+    first, w = it.table()
+    ref_w = np.stack([oi.interp_weights_2d(gu, gv, u, v) for u, v in zip(us, vs)])
+    et = np.abs(dense(first, w, bu, bv) - ref_w).max()
+    x = torch.from_numpy(crandn(rng, 2, M, N).astype(np.complex64)).cuda()
+    beams = plan.execute_batched(x)
+    out = it.execute(beams)
+    torch.cuda.synchronize()
+    bd = beams.cpu().numpy().astype(np.complex128)
+    o = out.cpu().numpy()
+    es = rel(o, oi.interp_beams_2d(bd, gu, gv, us, vs))
+    y32 = x.cpu().numpy().astype(np.complex128)
+    ref = oi.interp_beams_2d(np.stack([od.beams(y32[k], pg) for k in range(2)]), gu, gv, us, vs)
+    ee = rel(o, ref)
+    en = rel(o[:, 8], bd[:, 2 * bv + 5])
+    print(f"interp plane: table {et:.1e}  step {es:.2e}  chain {ee:.2e}  node {en:.2e}")
+    assert et < 1e-12 and es < STEP32 and ee < TOL32 and en < STEP32
     it.close()
 
 
