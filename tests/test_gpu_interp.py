@@ -9,7 +9,7 @@ import pytest
 from oracle import direct as od
 from oracle import interp as oi
 import synth
-from tests.helpers import rel, crandn
+from tests.helpers import rel, crandn, oracle_problem, perturbed_cfg
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -184,4 +184,29 @@ def test_interp_ula256_sampled():
     e = rel(out.cpu().numpy(), oi.interp_beams(beams.cpu().numpy().astype(np.complex128), g, us))
     print(f"interp ula256: step {e:.2e}")
     assert e < STEP32
+    it.close()
+
+
+def test_interp_on_perturbed_line():
+    """A non-uniform (perturbed) line (Sec. IX) has the same beam grid, so its
+    beams interpolate unchanged: the chain against the oracle's beams of the
+    perturbed array interpolated by the oracle."""
+    need_gpu()
+    cfg = perturbed_cfg("ula", 16, 48, 12, index=101)
+    plan = F.plan_for_config(cfg)
+    p = oracle_problem(cfg, cfg.delta_noise)
+    rng = np.random.default_rng(45)
+    du = p.u[1] - p.u[0]
+    us = [p.u[0] + 0.3 * du, p.u[5] + 0.61 * du, p.u[-2] + 0.9 * du]
+    it = F.Interp(plan, us)
+    x = torch.from_numpy(crandn(rng, 2, cfg.M, cfg.N).astype(np.complex64)).cuda()
+    beams = plan.execute_batched(x)
+    out = it.execute(beams)
+    torch.cuda.synchronize()
+    o = out.cpu().numpy()
+    es = rel(o, oi.interp_beams(beams.cpu().numpy().astype(np.complex128), p.u, us))
+    y32 = x.cpu().numpy().astype(np.complex128)
+    ee = rel(o, oi.interp_beams(np.stack([od.beams(y32[k], p) for k in range(2)]), p.u, us))
+    print(f"interp perturbed line: step {es:.2e}  chain {ee:.2e}")
+    assert es < STEP32 and ee < TOL32
     it.close()
