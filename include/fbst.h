@@ -344,7 +344,9 @@ typedef struct fbst_interp fbst_interp;
  * (bv > 1, v required) takes the tensor-product spline over 8 x 8 beams.
  * Each axis with more than one beam needs at least 8 distinct beams
  * (FBST_E_UNSUPPORTED otherwise); directions must lie within the grid
- * (FBST_E_INVALID otherwise: no extrapolation).  1..65536 directions.  The
+ * (FBST_E_INVALID otherwise: no extrapolation).  1..65536 directions.  For a
+ * plan created with FBST_FLAG_HOST_ONLY only the host table is built
+ * (fbst_interp_table works, fbst_execute_interp returns FBST_E_INVALID).  The
  * plan must outlive it. */
 fbst_status fbst_interp_create(const fbst_plan* plan, int n_directions, const double* u,
                                const double* v, fbst_interp** out);

@@ -971,8 +971,8 @@ fbst_status fbst_interp_create(const fbst_plan* plan, int n_directions, const do
                                const double* v, fbst_interp** out) {
   if (!out) return fail(FBST_E_INVALID, "out is NULL");
   *out = nullptr;
-  fbst_status s = check_exec(plan);
-  if (s != FBST_OK) return s;
+  if (!plan) return fail(FBST_E_INVALID, "plan is NULL");
+  fbst_status s = FBST_OK;
   if (n_directions < 1 || n_directions > 65536 || !u)
     return fail(FBST_E_INVALID, "need 1..65536 directions");
   const bool plane = plan->p.bv > 1;
@@ -995,6 +995,12 @@ fbst_status fbst_interp_create(const fbst_plan* plan, int n_directions, const do
     delete it;
     return fail(s, msg);
   }
+  it->plan = plan;
+  it->D = n_directions;
+  if (plan->host_only) {                       // the host table only (no device memory)
+    *out = it;
+    return FBST_OK;
+  }
   const size_t o_w = (it->host_first.size() * sizeof(int) + 255) / 256 * 256;
   const size_t bytes = o_w + it->host_w.size() * sizeof(double);
   hipError_t e = hipMalloc(&it->dev, bytes);
@@ -1014,8 +1020,6 @@ fbst_status fbst_interp_create(const fbst_plan* plan, int n_directions, const do
     delete it;
     return hip_fail(e, "hipMemcpy of the interpolation table");
   }
-  it->plan = plan;
-  it->D = n_directions;
   it->first = reinterpret_cast<const int*>(b);
   it->w = reinterpret_cast<const double*>(b + o_w);
   *out = it;
