@@ -411,10 +411,10 @@ def interp_bench(F, torch, plan, cfg, beams, *, reps=20, log=print, checks=None)
     r = {"workload": f"{cfg.name}: {D} directions drawn across the beam grid, {nb} blocks per "
                      f"launch, 8 grid beams each (not-a-knot cubic spline in u)",
          "value": nb * D * cfg.N / (ms / 1e3), "unit": "beam-samples/s", "ms_per_launch": ms,
-         "roofline": {"kernel": "k_interp_beams", "bound": "hbm", "achieved": ach, "peak": 8000.0,
+         "roofline": {"kernel": "k_interp_beams_x2", "bound": "hbm", "achieved": ach, "peak": 8000.0,
                       "unit": "GB/s", "frac": ach / 8000.0, "bytes_per_launch": nbytes,
-                      "traffic": stored_traffic("k_interp_beams<float, 1>",
-                                                nb * D * ((cfg.N + 255) // 256) * 256)}}
+                      "traffic": stored_traffic("k_interp_beams_x2<1>",
+                                                nb * D * ((cfg.N // 2 + 255) // 256) * 256)}}
     got = out[0].cpu().numpy().astype(np.complex128)
     b0 = src[0].cpu().numpy().astype(np.complex128)
 

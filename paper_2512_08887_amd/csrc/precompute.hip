@@ -16,6 +16,8 @@
 // n.
 #include <hip/hip_runtime.h>
 
+#include <cstdint>
+
 #include "cx.h"
 #include "kernels.h"
 
@@ -306,6 +308,41 @@ __global__ __launch_bounds__(256) void k_interp_beams(const cx<T>* __restrict__ 
   out[static_cast<size_t>(row) * N + n] = cx<T>{re, im};
 }
 
+// The same sum in float32 with two consecutive samples per lane (16-byte
+// loads and stores; N even and both buffers 16-byte aligned).  Each sample
+// takes the same operations in the same order as above, so the results are
+// identical.
+template <int TV>
+__global__ __launch_bounds__(256) void k_interp_beams_x2(const float4* __restrict__ beams,
+                                                         const int* __restrict__ first,
+                                                         const double* __restrict__ w,
+                                                         float4* __restrict__ out, int B, int bv,
+                                                         int D, int N2, int ntile) {
+  const int wg = xcd_linear(gridDim.x);
+  const int row = wg / ntile;                    // blk * D + d
+  const int q = (wg - row * ntile) * 256 + threadIdx.x;   // sample pair: n = 2 q, 2 q + 1
+  if (q >= N2) return;
+  const int d = row % D;
+  const size_t blk = static_cast<size_t>(row / D);
+  const int a0 = first[2 * d], c0 = first[2 * d + 1];
+  const float4* src = beams + (blk * B + static_cast<size_t>(a0) * bv + c0) * N2 + q;
+  const double* wd = w + static_cast<size_t>(d) * 16;
+  float r0 = 0, i0 = 0, r1 = 0, i1 = 0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+#pragma unroll
+    for (int j = 0; j < TV; ++j) {
+      const float4 a = src[(static_cast<size_t>(i) * bv + j) * N2];
+      const float c = static_cast<float>(wd[i] * wd[8 + j]);
+      r0 += c * a.x;
+      i0 += c * a.y;
+      r1 += c * a.z;
+      i1 += c * a.w;
+    }
+  }
+  out[static_cast<size_t>(row) * N2 + q] = make_float4(r0, i0, r1, i1);
+}
+
 }  // namespace
 
 hipError_t launch_interp_beams(const void* beams, const int* first, const double* w, void* out,
@@ -323,6 +360,19 @@ hipError_t launch_interp_beams(const void* beams, const int* first, const double
     auto o = static_cast<cx<double>*>(out);
     if (bv > 1) hipLaunchKernelGGL((k_interp_beams<double, 8>), g, b, 0, st, in, first, w, o, B, bv, D, N, nt);
     else hipLaunchKernelGGL((k_interp_beams<double, 1>), g, b, 0, st, in, first, w, o, B, bv, D, N, nt);
+  } else if (N % 2 == 0 && reinterpret_cast<uintptr_t>(beams) % 16 == 0 &&
+             reinterpret_cast<uintptr_t>(out) % 16 == 0) {
+    const int n2 = N / 2;
+    const long long nt2 = (n2 + 255) / 256;
+    const dim3 g2(static_cast<unsigned>(1LL * nblocks * D * nt2));
+    auto in = static_cast<const float4*>(beams);
+    auto o = static_cast<float4*>(out);
+    if (bv > 1)
+      hipLaunchKernelGGL((k_interp_beams_x2<8>), g2, b, 0, st, in, first, w, o, B, bv, D, n2,
+                         static_cast<int>(nt2));
+    else
+      hipLaunchKernelGGL((k_interp_beams_x2<1>), g2, b, 0, st, in, first, w, o, B, bv, D, n2,
+                         static_cast<int>(nt2));
   } else {
     auto in = static_cast<const cx<float>*>(beams);
     auto o = static_cast<cx<float>*>(out);

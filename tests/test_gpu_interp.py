@@ -210,3 +210,33 @@ def test_interp_on_perturbed_line():
     print(f"interp perturbed line: step {es:.2e}  chain {ee:.2e}")
     assert es < STEP32 and ee < TOL32
     it.close()
+
+
+def test_interp_odd_n_and_offset_buffers():
+    """Odd N and buffers that are not 16-byte aligned take the one-sample-per-
+    lane form; its results equal the oracle's interpolation of the same beams,
+    and for even N the paired form equals the single form bit for bit."""
+    need_gpu()
+    M, B = 8, 16
+    rng = np.random.default_rng(46)
+    g = od.beam_grid(B)
+    us = [g[2] + 0.4 * (g[3] - g[2]), g[-1], 0.03]
+    for N in (41, 40):
+        plan = F.Plan(M, N, B, band=F.make_band(2.0, 0.5, 1.0), options=F.make_options(0.2 * N))
+        it = F.Interp(plan, us)
+        x = torch.from_numpy(crandn(rng, 2, M, N).astype(np.complex64)).cuda()
+        beams = plan.execute_batched(x)
+        out = it.execute(beams)
+        # the same beams one complex64 element into a larger buffer: 8-byte aligned only
+        big = torch.zeros(beams.numel() + 1, dtype=torch.complex64, device="cuda")
+        big[1:] = beams.reshape(-1)
+        shifted = big[1:].view(2, B, N)
+        obig = torch.zeros(2 * len(us) * N + 1, dtype=torch.complex64, device="cuda")
+        o1 = it.execute(shifted, obig[1:].view(2, len(us), N))
+        torch.cuda.synchronize()
+        o = out.cpu().numpy()
+        e = rel(o, oi.interp_beams(beams.cpu().numpy().astype(np.complex128), g, us))
+        print(f"interp N={N}: step {e:.2e}")
+        assert e < STEP32
+        assert np.array_equal(o1.cpu().numpy(), o)
+        it.close()
