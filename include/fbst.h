@@ -139,10 +139,16 @@ typedef struct {
 /* Basis and solver options.  eps: band expansion epsilon > 0 (0 selects 1.01).
  * L: number of basis frequencies, even and >= 2 (0 selects 2N, i.e.
  * gamma = 2; Sec. III-A).  delta: ridge of eq. (betahatls), > 0, absolute.
- * The condition number of F^H F + delta I is about 2MN/delta, so float32
- * stage 2 needs delta of the order of the noise level (e.g. sigma^2 L); the
- * paper's delta = 1e-5 needs FBST_PREC_FP64.  A NULL options pointer selects
- * eps = 1.01, L = 2N, delta = 1e-5, FBST_PREC_FP32, flags 0. */
+ * The condition number of A_b = F_b^H F_b + delta I is about 2MN/delta (at
+ * most cond_bound = 1 + M lambda_max(T)/delta, T the time Gram, reported by
+ * fbst_plan_info), so float32 stage 2 needs delta of the order of the noise
+ * level (e.g. sigma^2 L); the paper's delta = 1e-5 needs FBST_PREC_FP64.
+ * fbst_plan_create refuses (FBST_E_UNSUPPORTED, with a message) a plan whose
+ * cond_bound times the stage-2 unit roundoff (2^-24 for a float32 stage 2:
+ * FBST_PREC_FP32 and the two split precisions; 2^-53 for FBST_PREC_FP64 and
+ * FBST_PREC_FP64_STAGE2) exceeds 1e-2, since its beams could be off by O(1).
+ * A NULL options pointer selects eps = 1.01, L = 2N, delta = 1e-5 (the
+ * paper's), FBST_PREC_FP64 (complex128 input and output), flags 0. */
 typedef struct {
   double eps;
   int L;
@@ -170,6 +176,8 @@ typedef struct {
                         p2y are then the oversampled grid sizes); else 0       */
   int nu_lanes;      /* ARBITRARY with bv = 1: elements spread at once per
                         frequency (1..16, chosen by the plan); else 0          */
+  double cond_bound; /* upper bound on cond(F_b^H F_b + delta I) over the beams:
+                        1 + M lambda_max(T) / delta, T the time Gram (Sec. V) */
 } fbst_info;
 
 typedef struct fbst_plan fbst_plan;

@@ -47,22 +47,46 @@ def _run(cmd, verbose):
     return r
 
 
-def build(verbose: bool = False, defines=(), out: str = LIB, build_dir: str = BUILD) -> str:
+def _stale(obj, src, defines_file, defines):
+    """True when obj is missing, older than its source or any header, or was
+    built with other definitions."""
+    if not os.path.exists(obj) or not os.path.exists(defines_file):
+        return True
+    with open(defines_file) as f:
+        if f.read() != repr(sorted(defines)):
+            return True
+    t = os.path.getmtime(obj)
+    deps = [src] + [os.path.join(CSRC, h) for h in os.listdir(CSRC) if h.endswith(".h")]
+    deps.append(os.path.join(ROOT, "include", "fbst.h"))
+    return any(os.path.getmtime(d) > t for d in deps)
+
+
+def build(verbose: bool = False, defines=(), out: str = LIB, build_dir: str = BUILD,
+          incremental: bool = False) -> str:
     """Compile every source for gfx950 and link libfbst.so; returns its path.
 
     defines: extra preprocessor definitions ("NAME=VALUE") for tuning builds;
-    out / build_dir: where the library and objects go."""
+    out / build_dir: where the library and objects go; incremental: recompile
+    only objects older than their source or a header (a development aid; the
+    default recompiles everything)."""
     os.makedirs(build_dir, exist_ok=True)
     objs = []
     cmds = []
+    defines_file = os.path.join(build_dir, "defines.txt")
     for src in SOURCES:
         obj = os.path.join(build_dir, os.path.splitext(src)[0] + ".o")
         objs.append(obj)
+        path = os.path.join(CSRC, src)
+        if incremental and not _stale(obj, path, defines_file, defines):
+            continue
         lang = ["-x", "hip"]
         dflags = [f"-D{d}" for d in defines]
-        cmds.append([HIPCC, *lang, *CFLAGS, *dflags, "-c", os.path.join(CSRC, src), "-o", obj])
-    with ThreadPoolExecutor(max_workers=len(cmds)) as ex:
-        list(ex.map(lambda c: _run(c, verbose), cmds))
+        cmds.append([HIPCC, *lang, *CFLAGS, *dflags, "-c", path, "-o", obj])
+    if cmds:
+        with ThreadPoolExecutor(max_workers=len(cmds)) as ex:
+            list(ex.map(lambda c: _run(c, verbose), cmds))
+    with open(defines_file, "w") as f:
+        f.write(repr(sorted(defines)))
     tmp = out + ".tmp"
     _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp,
           "-Wl,-soname,libfbst.so"], verbose)
@@ -71,4 +95,4 @@ def build(verbose: bool = False, defines=(), out: str = LIB, build_dir: str = BU
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, incremental="--incremental" in sys.argv))

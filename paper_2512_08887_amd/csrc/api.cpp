@@ -1125,6 +1125,7 @@ fbst_status fbst_plan_info(const fbst_plan* plan, fbst_info* info) {
   info->stage2_precomputed = plan->K ? 1 : 0;
   info->nu_width = p.nuw;
   info->nu_lanes = (p.kind == FBST_ARBITRARY && !p.p2y) ? plan->nu_lanes : 0;
+  info->cond_bound = p.cond_bound;
   return FBST_OK;
 }
 

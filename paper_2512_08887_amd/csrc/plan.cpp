@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <cstdio>
 #include <mutex>
 #include <thread>
 
@@ -434,6 +435,47 @@ bool levinson_real(const double* col, int L, double* x) {
   return true;
 }
 
+// Largest eigenvalue of the L x L time Gram T[l][k] = sum_{n<N} exp(-j kappa
+// (l - k) n), kappa = 2 pi eps / L (the Gram of Sec. V with a single element
+// at the origin), by power iteration with circulant-embedded products of
+// P >= 2L - 1 points; the Rayleigh quotient of the last iterate.
+double time_gram_lmax(int N, int L, double eps) {
+  const int P = next_pow2(2LL * L - 1);
+  const double kappa = 2.0 * kPi * eps / L;
+  std::vector<zd> spec(P, zd()), v(L), buf(P);
+  for (int d = 0; d < L; ++d) {
+    const zd c = geometric_sum(N, 0.0, -kappa * d);
+    spec[d] = c;
+    if (d > 0) spec[P - d] = std::conj(c);
+  }
+  fft64(spec.data(), P, -1);
+  // deterministic start with components along every eigenvector
+  unsigned long long s = 0x9e3779b97f4a7c15ULL;
+  for (int l = 0; l < L; ++l) {
+    s = s * 6364136223846793005ULL + 1442695040888963407ULL;
+    v[l] = zd(0.5 + static_cast<double>(s >> 11) * 0x1.0p-53, 0.0);
+  }
+  double lam = 0.0;
+  for (int it = 0; it < 40; ++it) {
+    double nv = 0.0;
+    for (int l = 0; l < L; ++l) nv += std::norm(v[l]);
+    nv = std::sqrt(nv);
+    std::fill(buf.begin(), buf.end(), zd());
+    for (int l = 0; l < L; ++l) buf[l] = v[l] / nv;
+    fft64(buf.data(), P, -1);
+    for (int i = 0; i < P; ++i) buf[i] *= spec[i];
+    fft64(buf.data(), P, +1);
+    double rq = 0.0;
+    for (int l = 0; l < L; ++l) {
+      const zd tv = buf[l] / static_cast<double>(P);
+      rq += (std::conj(v[l] / nv) * tv).real();
+      v[l] = tv;
+    }
+    lam = rq;
+  }
+  return lam;
+}
+
 fbst_status resolve_params(int M, int N, int B, const fbst_geometry* geom, const fbst_band* band,
                            const fbst_grid* grid, const fbst_options* opt, Params* out,
                            std::string* msg) {
@@ -460,7 +502,7 @@ fbst_status resolve_params(int M, int N, int B, const fbst_geometry* geom, const
   p.eps = 1.01;
   p.L = 2 * N;
   p.delta = 1e-5;
-  p.prec = FBST_PREC_FP32;
+  p.prec = FBST_PREC_FP64;     // the paper's delta needs float64 (cond(A_b) ~ 2MN / delta)
   if (opt) {
     if (opt->eps != 0.0) p.eps = opt->eps;
     if (opt->L != 0) p.L = opt->L;
@@ -640,6 +682,30 @@ fbst_status resolve_params(int M, int N, int B, const fbst_geometry* geom, const
   if (p.p1 > lim1 || p.p2x > lim1 || p.p2y > lim1 || p.p3 > lim2) {
     *msg = "an FFT size exceeds what one workgroup holds in LDS for this precision";
     return FBST_E_UNSUPPORTED;
+  }
+  // Conditioning guard (Sec. V).  F_b^H F_b = sum_m D_m T D_m^H with T the
+  // time Gram and D_m = diag(exp(j omega_l tau_{b,m})) unitary, so for every
+  // beam and any geometry cond(A_b) <= 1 + M lambda_max(T) / delta.  A solve in
+  // a precision of unit roundoff u can lose up to cond * u of relative
+  // accuracy; plans whose bound exceeds 1e-2 (float32 stage 2: cond > 1.7e5,
+  // about 1e-4 of measured beam error; float64: cond > 9e13) are refused
+  // rather than built to return beams off by O(1).
+  {
+    const double lam = time_gram_lmax(p.N, p.L, p.eps);
+    p.cond_bound = 1.0 + p.M * lam / p.delta;
+    const bool s2_double = p.prec == FBST_PREC_FP64 || p.prec == FBST_PREC_FP64_STAGE2;
+    const double u2 = s2_double ? 0x1.0p-53 : 0x1.0p-24;
+    if (!(p.cond_bound * u2 <= 1e-2)) {
+      char buf[320];
+      std::snprintf(buf, sizeof buf,
+                    "delta = %.3g is too small for a %s stage 2: cond(F^H F + delta I) can reach "
+                    "%.3g (1 + M lambda_max(T)/delta), beyond the %.3g this precision holds; "
+                    "raise delta towards the noise level (e.g. sigma^2 L) or use %s",
+                    p.delta, s2_double ? "float64" : "float32", p.cond_bound, 1e-2 / u2,
+                    s2_double ? "a larger delta" : "FBST_PREC_FP64");
+      *msg = buf;
+      return FBST_E_UNSUPPORTED;
+    }
   }
   *out = p;
   return FBST_OK;

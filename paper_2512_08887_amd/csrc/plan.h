@@ -64,6 +64,7 @@ struct Params {
   std::vector<double> px, py;
   int nuw = 0;
   double nu_beta = 0;
+  double cond_bound = 0;                  // upper bound on cond(A_b) over the beams (Sec. V)
 };
 
 // Element m's position in samples of delay per unit direction cosine.

@@ -57,7 +57,7 @@ class fbst_info(ctypes.Structure):
                 ("p3", c_int), ("precision", c_int), ("io_elem_bytes", c_size_t),
                 ("device_bytes", c_size_t), ("workspace_per_block", c_size_t), ("p1_split", c_int),
                 ("stage2_precomputed", c_int), ("nu_width", c_int),
-                ("nu_lanes", c_int)]
+                ("nu_lanes", c_int), ("cond_bound", c_double)]
 
 
 class fbst_server_options(ctypes.Structure):

@@ -21,9 +21,10 @@ def test_library_exports_every_declared_symbol():
     assert F.fbst_version().startswith("fbst")
 
 
-def host_plan(M, N, B, *, fc=2.0, omega=0.5, delta=1e-3, eps=1.01, L=0, geometry=None, grid=None):
+def host_plan(M, N, B, *, fc=2.0, omega=0.5, delta=1e-3, eps=1.01, L=0, geometry=None, grid=None,
+              precision="fp64"):
     band = F.make_band(fc, omega, 1.0)
-    opts = F.make_options(delta, eps=eps, L=L, flags=F.FBST_FLAG_HOST_ONLY)
+    opts = F.make_options(delta, eps=eps, L=L, precision=precision, flags=F.FBST_FLAG_HOST_ONLY)
     return F.fbst_plan_create(M, N, B, geometry, band, grid, opts)
 
 
@@ -142,7 +143,7 @@ def test_null_and_host_only_plan_calls():
                                  None, 0, ctypes.byref(c), ctypes.byref(ms)) == F.FBST_E_INVALID
         info = F.fbst_plan_info(h)
         assert (info.p1, info.p2x, info.p3) == (64, 32, 64)
-        assert F.fbst_workspace_bytes(h, 3) == 3 * (8 + 4) * 32 * 8
+        assert F.fbst_workspace_bytes(h, 3) == 3 * (8 + 4) * 32 * 16     # complex128 (FBST_PREC_FP64)
     finally:
         F.fbst_destroy(h)
 
@@ -259,7 +260,7 @@ def test_host_tables_match_oracle_arbitrary(two_d):
     try:
         info = F.fbst_plan_info(h)
         L = info.L
-        assert info.nu_width == 8
+        assert info.nu_width == 16            # float64 plan (float32 plans take 8)
         assert info.p2x == max(32, 1 << (2 * bu - 1).bit_length())
         assert info.p2y == (max(32, 1 << (2 * bv - 1).bit_length()) if two_d else 0)
         p = od.make_problem(N=N, L=L, eps=1.01, delta=1e-3, fc=2.0, omega=0.5, ts=1.0, px=px,
@@ -349,3 +350,56 @@ def test_nonuniform_spread_lanes_choice():
         assert F.fbst_plan_info(h).nu_lanes == 0
     finally:
         F.fbst_destroy(h)
+
+
+def test_conditioning_guard():
+    """fbst_plan_create refuses a plan whose stage-2 precision cannot hold
+    cond(A_b) (Sec. V: A_b = F_b^H F_b + delta I): float32 at the paper's
+    delta = 1e-5 would return beams off by O(1).  The reported bound
+    1 + M lambda_max(T)/delta must cover every beam's condition number (the
+    oracle's Gram, dense eigenvalues) and be tight at broadside."""
+    M, N, B = 16, 64, 16
+    for prec in ("fp32", "bf16_split", "fp16_split"):
+        st, hnd = F.fbst_plan_create_status(M, N, B, None, F.make_band(2.0, 0.5, 1.0), None,
+                                            F.make_options(1e-5, precision=prec,
+                                                           flags=F.FBST_FLAG_HOST_ONLY))
+        if prec != "fp32" and st == F.FBST_E_UNSUPPORTED and "1024 points" in F.fbst_last_error():
+            continue          # the matrix-core stage 1a needs larger FFTs: refused earlier
+        assert st == F.FBST_E_UNSUPPORTED and hnd is None, (prec, st)
+        assert "too small" in F.fbst_last_error()
+    # float64 at the same delta is accepted and reports its bound
+    h = host_plan(M, N, B, delta=1e-5, precision="fp64")
+    try:
+        bound = F.fbst_plan_info(h).cond_bound
+    finally:
+        F.fbst_destroy(h)
+    p = od.line_problem(M, N, B, fc=2.0, omega=0.5, delta=1e-5)
+    conds = []
+    for b in range(B):
+        ev = np.linalg.eigvalsh(od.toeplitz_system(p, b))
+        conds.append(ev[-1] / ev[0])
+    assert max(conds) <= bound * (1 + 1e-6), (max(conds), bound)
+    assert max(conds) >= 0.9 * bound, (max(conds), bound)
+    # float32 at a noise-level delta (sigma^2 L) is accepted; float64 at an
+    # absurdly small delta is not
+    h = host_plan(M, N, B, delta=0.01 * 2 * N, precision="fp32")
+    F.fbst_destroy(h)
+    st, hnd = F.fbst_plan_create_status(M, N, B, None, F.make_band(2.0, 0.5, 1.0), None,
+                                        F.make_options(1e-12, precision="fp64",
+                                                       flags=F.FBST_FLAG_HOST_ONLY))
+    assert st == F.FBST_E_UNSUPPORTED and hnd is None
+
+
+def test_null_options_default_is_float64():
+    """NULL options select the paper's delta = 1e-5 with FBST_PREC_FP64, a
+    combination whose conditioning bound passes the guard: without a GPU the
+    call gets past validation and the tables and fails only at the device."""
+    st, hnd = F.fbst_plan_create_status(16, 64, 16, None, F.make_band(2.0, 0.5, 1.0), None, None)
+    if hnd is not None:                      # a GPU is present
+        try:
+            info = F.fbst_plan_info(hnd)
+            assert info.precision == F.PRECISIONS["fp64"] and info.io_elem_bytes == 16
+        finally:
+            F.fbst_destroy(hnd)
+    else:
+        assert st == F.FBST_E_DEVICE, (st, F.fbst_last_error())
