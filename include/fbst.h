@@ -376,6 +376,30 @@ fbst_status fbst_interp_table(const fbst_interp* interp, int* first, double* w);
 fbst_status fbst_execute_interp(const fbst_interp* interp, int nblocks, const void* beams,
                                 void* out, void* hip_stream);
 
+/* ---- Allocation-free execution ------------------------------------------
+ * For callers that cannot allocate device memory while they run: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * fbst_execute_static is fbst_execute_batched with its workspace taken from
+ * a fixed device array inside libfbst.so (FBST_STATIC_SCRATCH_BYTES per GPU,
+ * held by every GPU the library runs on until the process ends) instead of
+ * caller or plan memory: it calls no allocating routine.  Blocks are
+ * processed min(nblocks, FBST_MAX_LAUNCH_BLOCKS, scratch / workspace per
+ * block) per launch.  The plan's device must be the current device.  Every
+ * call on a GPU shares that GPU's array, so calls that overlap in time on one
+ * GPU (on different streams or threads) race and must be serialised by the
+ * caller; the array's contents from earlier calls are never read.  Errors:
+ * FBST_E_INVALID on a NULL plan, x or beams, a host-only plan or another
+ * current device; FBST_E_UNSUPPORTED when one block's workspace
+ * (fbst_workspace_bytes(plan, 1)) exceeds the array.  nblocks == 0 is a
+ * no-op.  Layouts as fbst_execute_batched.
+ * ------------------------------------------------------------------------ */
+#define FBST_STATIC_SCRATCH_BYTES (64u * 1024u * 1024u)
+fbst_status fbst_execute_static(const fbst_plan* plan, int nblocks, const void* x, void* beams,
+                                void* hip_stream);
+
+/* Size of that array in bytes (FBST_STATIC_SCRATCH_BYTES). */
+size_t fbst_static_scratch_bytes(void);
+
 /* Workspace bytes for nblocks blocks processed in one launch (0 on NULL plan). */
 size_t fbst_workspace_bytes(const fbst_plan* plan, int nblocks);
 

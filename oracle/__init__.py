@@ -21,6 +21,13 @@ analysis
 nulling
     Beamspace interference nulling of Sec. VIII (eq. interfer_beam_space) and
     the array-space projection it is derived from (explicit matrices).
+fbst64
+    The FBST itself in float64 with numpy FFTs (Secs. IV and V: chirp-z
+    stages by Bluestein, closed-form Gram column, Levinson generator,
+    Gohberg-Semencul product by circulant embedding, F_u as a chirp-z): the
+    fast all-beam check at full size, pinned to ``direct``.
+interp
+    Off-grid interpolation of Sec. VIII (not-a-knot cubic spline weights).
 
 Pins (tests/test_oracle_*.py, run with ``-m "not gpu"``)
 ------------------------------------------------------
@@ -40,4 +47,4 @@ Readings of the paper that the oracle takes (where it is silent or garbled)
 are listed in the project design notes; each function cites the passage it
 follows.
 """
-from . import direct, analysis, nulling  # noqa: F401
+from . import direct, analysis, nulling, fbst64  # noqa: F401

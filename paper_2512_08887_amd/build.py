@@ -22,7 +22,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 SOURCES = ["kernels.hip", "mfma_czt.hip", "precompute.hip", "levinson.hip", "plan.cpp", "api.cpp",
-           "server.cpp"]
+           "server.cpp", "noalloc.cpp"]
 
 CFLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",

@@ -199,3 +199,16 @@ struct fbst_plan {
   size_t K_bytes = 0;
   int device = 0;
 };
+
+namespace fbst {
+struct InPtrs;
+struct OutPtrs;
+// Whole path of nb <= MAX_LAUNCH_BLOCKS blocks (inputs xs, outputs outs) with
+// the workspace [yhat | w | z] of nb blocks at ws (api.cpp).
+hipError_t run_blocks(const fbst_plan* pl, int nb, const InPtrs& xs, const OutPtrs& outs, void* ws,
+                      hipStream_t st);
+// Whole path of nb contiguous blocks, at most chunk (<= MAX_LAUNCH_BLOCKS) per
+// launch, all launches sharing the workspace of chunk blocks at ws.
+hipError_t run_contiguous(const fbst_plan* pl, int nb, int chunk, const void* x, void* beams,
+                          void* ws, hipStream_t st);
+}  // namespace fbst

@@ -27,11 +27,6 @@
 #include "kernels.h"
 #include "plan.h"
 
-namespace fbst {
-hipError_t run_blocks(const fbst_plan* pl, int nb, const InPtrs& xs, const OutPtrs& outs, void* ws,
-                      hipStream_t st);
-}  // namespace fbst
-
 namespace {
 
 using clk = std::chrono::steady_clock;

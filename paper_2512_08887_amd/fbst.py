@@ -92,6 +92,10 @@ def load_library(path: str = LIB_PATH):
     L.fbst_execute.restype = c_int
     L.fbst_execute_batched.argtypes = [c_void_p, c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p]
     L.fbst_execute_batched.restype = c_int
+    L.fbst_execute_static.argtypes = [c_void_p, c_int, c_void_p, c_void_p, c_void_p]
+    L.fbst_execute_static.restype = c_int
+    L.fbst_static_scratch_bytes.argtypes = []
+    L.fbst_static_scratch_bytes.restype = c_size_t
     L.fbst_execute_stage.argtypes = [c_void_p, c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p]
     L.fbst_execute_stage.restype = c_int
     L.fbst_workspace_bytes.argtypes = [c_void_p, c_int]
@@ -222,6 +226,14 @@ def fbst_execute(plan, x, beams, workspace=0, stream=0):
 def fbst_execute_batched(plan, nblocks, max_chunk, x, beams, workspace=0, stream=0):
     _check(lib().fbst_execute_batched(plan, nblocks, max_chunk, x, beams, workspace or None,
                                       stream or None))
+
+
+def fbst_execute_static(plan, nblocks, x, beams, stream=0):
+    _check(lib().fbst_execute_static(plan, nblocks, x, beams, stream or None))
+
+
+def fbst_static_scratch_bytes() -> int:
+    return int(lib().fbst_static_scratch_bytes())
 
 
 def fbst_execute_stage(plan, stage, nblocks, inp, out, workspace=0, stream=0):
@@ -480,6 +492,15 @@ class Plan:
             workspace = self.workspace(chunk)
         fbst_execute_batched(self.handle, nb, chunk, x.data_ptr(), beams.data_ptr(),
                              workspace.data_ptr() if workspace is not None else 0, self._stream())
+        return beams
+
+    def execute_static(self, x, beams):
+        """x [nb][M][N] -> beams [nb][B][N] (both preallocated) through
+        fbst_execute_static: no workspace, no allocation in the library."""
+        self._check_in(x, (self.M, self.N))
+        self._check_in(beams, (self.B, self.N))
+        nb = x.shape[0] if x.dim() == 3 else 1
+        fbst_execute_static(self.handle, nb, x.data_ptr(), beams.data_ptr(), self._stream())
         return beams
 
     def stage(self, stage, inp, nblocks=1, out=None, workspace=None):

@@ -1,0 +1,76 @@
+"""Allocation-free execution, fbst_execute_static (include/fbst.h): the path of
+fbst_execute_batched with its workspace in the library's fixed device array.
+Its beams must equal fbst_execute_batched's bit for bit (the same kernels on
+the same inputs), on two calls in a row, the second with a smaller input; a
+plan whose one-block workspace exceeds the array is refused."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from paper_2512_08887_amd import fbst as F
+
+pytestmark = pytest.mark.gpu
+
+
+def _seeded(shape, seed):
+    g = np.random.default_rng(seed)
+    a = g.standard_normal(shape) + 1j * g.standard_normal(shape)
+    return torch.from_numpy(a.astype(np.complex64)).cuda()
+
+
+def _reference(plan, x):
+    nb = x.shape[0]
+    return plan.execute_batched(x, workspace=plan.workspace(nb))
+
+
+def test_static_equals_batched_two_calls():
+    scratch = F.fbst_static_scratch_bytes()
+    assert scratch == 64 * 1024 * 1024
+    big = F.plan_for_config(synth.config("ula256"))
+    small = F.plan_for_config(synth.config("ula16"))
+    try:
+        per_block = F.fbst_workspace_bytes(big.handle, 1)
+        nb = scratch // per_block + 2            # more blocks than one launch holds
+        print(f"static scratch {scratch} B, ula256 block workspace {per_block} B, {nb} blocks", flush=True)
+        x = _seeded((nb, big.M, big.N), 1)
+        ref = _reference(big, x)
+        out = torch.full_like(ref, float("nan"))
+        big.execute_static(x, out)
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref)
+        # second call, smaller input (another plan, fewer blocks): the array
+        # holds the first call's contents, which must not leak into the result
+        cfg = synth.config("ula16")
+        y = np.stack([cfg.scene().block(k) for k in range(3)]).astype(np.complex64)
+        xs = torch.from_numpy(y).cuda()
+        ref2 = _reference(small, xs)
+        out2 = torch.full_like(ref2, float("nan"))
+        small.execute_static(xs, out2)
+        torch.cuda.synchronize()
+        assert torch.equal(out2, ref2)
+        # and one block of the large plan again
+        out3 = torch.full_like(ref[:1], float("nan"))
+        big.execute_static(x[:1].contiguous(), out3)
+        torch.cuda.synchronize()
+        assert torch.equal(out3, ref[:1])
+    finally:
+        big.close()
+        small.close()
+
+
+def test_static_refuses_blocks_beyond_the_array():
+    # a 4096-element line with one beam: (M + B) L 8 bytes = 67.1 MB > 64 MiB
+    M, N, B = 4096, 1024, 1
+    plan = F.Plan(M, N, B, band=F.make_band(2.0, 0.5, 1.0), options=F.make_options(0.1 * 2 * N))
+    try:
+        assert F.fbst_workspace_bytes(plan.handle, 1) > F.fbst_static_scratch_bytes()
+        x = torch.zeros((1, M, N), dtype=torch.complex64, device="cuda")
+        out = torch.zeros((1, B, N), dtype=torch.complex64, device="cuda")
+        st = F.lib().fbst_execute_static(plan.handle, 1, x.data_ptr(), out.data_ptr(), None)
+        assert st == F.FBST_E_UNSUPPORTED
+        assert "static scratch" in F.fbst_last_error()
+        assert F.lib().fbst_execute_static(plan.handle, 0, None, None, None) == F.FBST_OK
+        assert F.lib().fbst_execute_static(None, 1, x.data_ptr(), out.data_ptr(), None) == F.FBST_E_INVALID
+    finally:
+        plan.close()
