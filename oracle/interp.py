@@ -23,6 +23,17 @@ reading is applied per axis: the tensor-product spline over the 8 x 8 grid
 beams around (u*, v*), i.e. the 1-D spline along u of the 1-D splines along
 v, whose weights are the products of the two axes' weights.
 
+Two forms are written out.  ``interp_beams`` interpolates the finished
+time-domain beams b_b.  The paper's own text (Sec. VIII) interpolates the
+beamspace vectors instead: the stage-1 outputs w_b = F_b^H y of the grid
+beams around theta* give an estimate of w* = F_*^H y, and the beam at theta*
+is then formed from it like any grid beam, b* = F_u A_*^{-1} w*, with A_* the
+Toeplitz system of theta* itself (``vector_interp_beams``).  The two differ
+because A_b changes from beam to beam; at a grid node both return the grid
+beam, and both approach the beam formed at theta* as the grid is refined.
+The vectors are interpolated with their reference point at the centre of
+the array (``interp_vectors``), a reading: the paper does not say where.
+
 ``spline_weights`` writes that spline out from its definition: one cubic per
 interval, 4 (n - 1) unknown coefficients, fixed by interpolation at both
 ends of every interval, continuity of the first and second derivatives at
@@ -32,11 +43,16 @@ of node i is the spline through the unit vector e_i, evaluated at u*.
 """
 from __future__ import annotations
 
+import dataclasses
+
 import numpy as np
+
+from . import direct as od
 
 __all__ = ["NEIGHBOURS", "neighbour_window", "spline_coefficients", "spline_eval",
            "spline_weights", "interp_weights", "interp_beams", "interp_weights_2d",
-           "interp_beams_2d"]
+           "interp_beams_2d", "array_centre", "interp_vectors", "direction_problem",
+           "vector_interp_beams"]
 
 NEIGHBOURS = 8
 
@@ -162,3 +178,79 @@ def interp_beams_2d(beams: np.ndarray, grid_u: np.ndarray, grid_v: np.ndarray, u
     bm = np.asarray(beams)
     W = np.stack([interp_weights_2d(grid_u, grid_v, float(u), float(v)) for u, v in zip(us, vs)])
     return np.moveaxis(np.tensordot(W, bm, axes=([1], [-2])), 0, -2)
+
+
+def array_centre(p: od.Problem):
+    """Centre of the array's extent (delay coordinates, seconds per unit
+    direction cosine): the midpoints of px and of py."""
+    return (0.5 * (float(np.min(p.px)) + float(np.max(p.px))),
+            0.5 * (float(np.min(p.py)) + float(np.max(p.py))))
+
+
+def _reference_phase(p: od.Problem, u, v, centre) -> np.ndarray:
+    """exp(j (2 pi f_c + omega_l) (u c_x + v c_y)) for directions (u, v),
+    shape [D, L]: the phase that moves a beamspace vector's reference point
+    from the origin to the point c (eq. FthetaH: w_b[l] carries
+    exp(j (2 pi f_c + omega_l) tau_{b,m}) for element m)."""
+    a = 2.0 * np.pi * p.fc + od.omegas(p.L, p.eps, p.ts)
+    arg = np.asarray(u, dtype=np.float64) * centre[0] + np.asarray(v, dtype=np.float64) * centre[1]
+    return np.exp(1j * np.multiply.outer(arg, a))
+
+
+def interp_vectors(W: np.ndarray, grid_u: np.ndarray, us, grid_v=None, vs=None,
+                   p: od.Problem | None = None, centre=None) -> np.ndarray:
+    """Spline estimates of beamspace vectors at directions from the grid ones
+    (Sec. VIII): W [B, L] (grid beam b = a * bv + c on a plane, at p.u[b],
+    p.v[b]) -> [D, L].
+
+    Reading: the vectors are interpolated with their reference point moved
+    to `centre` (p required; default None keeps the origin): w_b[l] is
+    multiplied by conj(_reference_phase) of its grid direction, interpolated
+    with the real spline weights, and the result multiplied by the phase of
+    the target direction.  Referred to the array's centre the vectors vary
+    more slowly with u (their phase no longer turns with the full aperture
+    measured from one end), so the spline is more accurate; with the origin
+    it is the plain interpolation of the w_b."""
+    us = np.atleast_1d(np.asarray(us, dtype=np.float64))
+    vs = np.zeros_like(us) if vs is None else np.atleast_1d(np.asarray(vs, dtype=np.float64))
+    Wc = np.asarray(W, dtype=np.complex128)
+    if centre is not None:
+        Wc = Wc * np.conj(_reference_phase(p, p.u, p.v, centre))
+    if grid_v is None or len(grid_v) == 1:
+        out = interp_beams(Wc, grid_u, us)
+    else:
+        out = interp_beams_2d(Wc, grid_u, grid_v, us, vs)
+    if centre is not None:
+        out = out * _reference_phase(p, us, vs, centre)
+    return out
+
+
+def direction_problem(p: od.Problem, us, vs=None) -> od.Problem:
+    """The problem of p with its beam set replaced by the directions (us, vs)."""
+    u = np.atleast_1d(np.asarray(us, dtype=np.float64))
+    v = np.zeros_like(u) if vs is None else np.atleast_1d(np.asarray(vs, dtype=np.float64))
+    return dataclasses.replace(p, u=u, v=v)
+
+
+def vector_interp_beams(y: np.ndarray, p: od.Problem, grid_u: np.ndarray, us, grid_v=None,
+                        vs=None, W=None, centre="array", return_parts: bool = False):
+    """The paper's off-grid beam (Sec. VIII): w* spline-interpolated from the
+    beamspace vectors of the 8 (8 x 8 on a plane) grid beams around each
+    direction (``interp_vectors``), then beta* = A_*^{-1} w* (A_* = F_*^H F_*
+    + delta I, the Toeplitz system of the direction itself, Sec. V) and
+    b* = F_u beta* (eq. bhatls).  W: the grid's beamspace vectors [B, L]
+    (default: projected from y by the oracle).  centre: "array" (reference
+    point of the interpolation at the array's centre), "origin", or a pair
+    (c_x, c_y).  Returns [D, N] (and w*, beta* on request)."""
+    if W is None:
+        W = od.project(y, p)
+    c = array_centre(p) if centre == "array" else (None if centre == "origin" else centre)
+    ws = interp_vectors(W, grid_u, us, grid_v, vs, p=p, centre=c)
+    pd = direction_problem(p, us, vs)
+    beta = np.empty_like(ws)
+    for d in range(pd.B):
+        beta[d] = od.solve(od.toeplitz_system(pd, d), ws[d])
+    out = od.reconstruct(beta, pd)
+    if return_parts:
+        return out, ws, beta
+    return out

@@ -145,3 +145,114 @@ def test_2d_reproduces_bicubics_and_nodes():
     assert np.allclose(out[:, 0], bm[:, 3 * 8 + 5], atol=1e-13)
     ref = np.tensordot(oi.interp_weights_2d(gu, gv, 0.1, -0.2), bm, axes=([0], [1]))
     assert np.allclose(out[:, 1], ref, atol=1e-14)
+
+
+# ---- the paper's form: interpolate the beamspace vectors w, then solve at the
+# ---- direction itself (Sec. VIII)
+
+def _plane_wave_line(p, u, fc, omega, rng, tones=12):
+    y = np.zeros((p.M, p.N), dtype=np.complex128)
+    tau = u * p.px
+    for f, a in zip(rng.uniform(-omega, omega, tones),
+                    rng.standard_normal(tones) + 1j * rng.standard_normal(tones)):
+        y += a * np.exp(-2j * np.pi * fc * tau)[:, None] * np.exp(
+            2j * np.pi * f * (p.t[None, :] - tau[:, None]))
+    return y
+
+
+@pytest.mark.parametrize("centre", ["array", "origin"])
+def test_vector_interp_at_nodes_is_the_grid_beam(centre):
+    rng = np.random.default_rng(40)
+    M, N, B = 8, 32, 16
+    p = od.line_problem(M, N, B, fc=2.0, delta=1.0)
+    y = rng.standard_normal((M, N)) + 1j * rng.standard_normal((M, N))
+    g = od.beam_grid(B)
+    nodes = [0, 5, 11, 15]
+    out = oi.vector_interp_beams(y, p, g, g[nodes], centre=centre)
+    ref = od.beams(y, p, beam_idx=nodes)
+    assert np.linalg.norm(out - ref) / np.linalg.norm(ref) < 1e-12
+
+
+@pytest.mark.parametrize("centre", ["array", "origin"])
+def test_vector_interp_converges_at_fourth_order(centre):
+    """Refining the beam grid moves the interpolated w* to F_*^H y at the
+    rate of a cubic spline, h^4, and the beam with it, since A_* is the
+    direction's own system; solving with a neighbouring grid beam's system
+    instead would leave an O(h) error."""
+    rng = np.random.default_rng(41)
+    M, N = 8, 32
+    y = rng.standard_normal((M, N)) + 1j * rng.standard_normal((M, N))
+    us = 0.3137
+    true = od.beams(y, oi.direction_problem(od.line_problem(M, N, 1, fc=1.0, delta=1e-2), [us]))[0]
+    errs = []
+    for B in (32, 64, 128):
+        p = od.line_problem(M, N, B, fc=1.0, delta=1e-2)
+        out = oi.vector_interp_beams(y, p, od.beam_grid(B), [us], centre=centre)[0]
+        errs.append(np.linalg.norm(out - true) / np.linalg.norm(true))
+    assert errs[0] / errs[1] > 10 and errs[1] / errs[2] > 10, errs
+
+
+def test_vectors_reproduce_referenced_cubics():
+    """Beamspace vectors whose reference-moved form is a cubic in u come out
+    exactly: pins the sign and size of the reference phase, which a plain
+    cubic (centre at the origin) would not see."""
+    rng = np.random.default_rng(42)
+    M, N, B = 6, 16, 12
+    p = od.line_problem(M, N, B, fc=2.0, delta=1.0)
+    g = od.beam_grid(B)
+    c = oi.array_centre(p)
+    a = 2 * np.pi * p.fc + od.omegas(p.L, p.eps, p.ts)
+    coef = rng.standard_normal((4, p.L)) + 1j * rng.standard_normal((4, p.L))
+    cubic = lambda u: sum(coef[k] * u ** k for k in range(4))
+    W = np.stack([cubic(u) * np.exp(1j * a * u * c[0]) for u in g])
+    us = [g[2] + 0.41 * (g[3] - g[2]), g[9] + 0.77 * (g[10] - g[9])]
+    got = oi.interp_vectors(W, g, us, p=p, centre=c)
+    for d, u in enumerate(us):
+        want = cubic(u) * np.exp(1j * a * u * c[0])
+        assert np.max(np.abs(got[d] - want)) < 1e-11 * np.max(np.abs(want))
+    # the same vectors interpolated without moving the reference are not exact
+    plain = oi.interp_vectors(W, g, us)
+    assert np.max(np.abs(plain[0] - cubic(us[0]) * np.exp(1j * a * us[0] * c[0]))) > 1e-6
+
+
+def test_vectors_reproduce_referenced_bicubics_on_a_plane():
+    rng = np.random.default_rng(43)
+    mx, my, bu, bv, N = 3, 4, 9, 10, 8
+    p = od.grid_problem(mx, my, bu, bv, N, fc=2.0, delta=1.0)
+    gu, gv = od.beam_grid(bu), od.beam_grid(bv)
+    c = oi.array_centre(p)
+    a = 2 * np.pi * p.fc + od.omegas(p.L, p.eps, p.ts)
+    coef = rng.standard_normal((4, 4, p.L))
+    f = lambda u, v: sum(coef[i, k] * u ** i * v ** k for i in range(4) for k in range(4))
+    W = np.stack([f(u, v) * np.exp(1j * a * (u * c[0] + v * c[1])) for u, v in zip(p.u, p.v)])
+    us, vs = [0.13, -0.61], [0.27, 0.05]
+    got = oi.interp_vectors(W, gu, us, gv, vs, p=p, centre=c)
+    for d, (u, v) in enumerate(zip(us, vs)):
+        want = f(u, v) * np.exp(1j * a * (u * c[0] + v * c[1]))
+        assert np.max(np.abs(got[d] - want)) < 1e-10 * np.max(np.abs(want))
+    # nodes of the plane give the grid beams
+    y = rng.standard_normal((p.M, N)) + 1j * rng.standard_normal((p.M, N))
+    b = [3 * bv + 4, 8 * bv + 9]
+    out = oi.vector_interp_beams(y, p, gu, p.u[b], gv, p.v[b])
+    ref = od.beams(y, p, beam_idx=b)
+    assert np.linalg.norm(out - ref) / np.linalg.norm(ref) < 1e-12
+
+
+def test_fig3d_vector_interp_close_to_true_beam():
+    """The Fig. 3(d) setting (128 elements, 256 beams, theta* = pi/3) in the
+    paper's form: 1.6e-3 relative L2 from the beam formed at theta* with the
+    reference at the array's centre (6.4e-2 with the reference at element 0,
+    25 % for the nearest grid beam alone)."""
+    M, N, B, fc, omega = 128, 32, 256, 1.0, 0.5
+    u_star = np.sin(np.pi / 3)
+    grid = od.beam_grid(B)
+    p = od.line_problem(M, N, B, fc=fc, omega=omega, delta=1e-3)
+    y = _plane_wave_line(p, u_star, fc, omega, np.random.default_rng(14))
+    j0 = oi.neighbour_window(grid, u_star)
+    W = np.zeros((B, p.L), dtype=np.complex128)
+    W[j0:j0 + 8] = od.project(y, p, np.arange(j0, j0 + 8))
+    true = od.beams(y, oi.direction_problem(p, [u_star]))[0]
+    err = {c: np.linalg.norm(oi.vector_interp_beams(y, p, grid, [u_star], W=W, centre=c)[0] - true)
+           / np.linalg.norm(true) for c in ("array", "origin")}
+    assert err["array"] < 5e-3, err
+    assert err["origin"] < 0.1, err
