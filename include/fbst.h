@@ -291,6 +291,23 @@ fbst_status fbst_nulls_create(const fbst_plan* plan, int n_interferers, const in
 fbst_status fbst_nulls_create_directions(const fbst_plan* plan, int n_interferers, const double* u,
                                          const double* v, fbst_nulls** out);
 
+/* Interferers at arbitrary directions (u[i], v[i]) within the beam grid,
+ * with each interferer's beam vector w_q estimated the paper's way (Sec. VIII,
+ * closing paragraph of interference cancellation: off-grid beam vectors are
+ * interpolated from the surrounding grid beam vectors): stage 1 forms W for
+ * the grid, and w_q is the not-a-knot cubic spline in direction cosine
+ * through the 8 (8 x 8 on a planar grid) grid vectors around the interferer,
+ * taken with their reference point moved to the centre of the array's extent
+ * (the vectors vary more slowly with direction that way; the result is
+ * referred back to the origin).  G_{b,q} as in fbst_nulls_create_directions,
+ * at the interferer's own direction; no projection phases are stored.
+ * Needs at least 8 distinct grid beams along each axis with more than one
+ * (FBST_E_UNSUPPORTED) and directions inside the grid (FBST_E_INVALID; no
+ * extrapolation); v required for a planar grid.  Executes with
+ * fbst_execute_nulled and fbst_workspace_bytes_nulled. */
+fbst_status fbst_nulls_create_interp(const fbst_plan* plan, int n_interferers, const double* u,
+                                     const double* v, fbst_nulls** out);
+
 /* Free nulling tables (after their launches finished); NULL is a no-op. */
 void fbst_nulls_destroy(fbst_nulls* nulls);
 
@@ -315,13 +332,36 @@ typedef struct fbst_directions fbst_directions;
  * direction d, K_d = F_u (F_d^H F_d + delta I)^{-1} (N x L, Gohberg-Semencul
  * applies of the refined generator) and the projection phases of F_d^H, and
  * uploads them as complex64: 8 D L (N + M) bytes (at most 16 GiB).  The
- * paper interpolates off-grid beams from neighbouring grid beams with a
- * spline; here they are formed exactly (the regularised least-squares beam of
- * that direction) at a cost of M L + N L complex products per direction and
- * block.  Not for FBST_PREC_FP64 plans (FBST_E_UNSUPPORTED).  The plan must
+ * paper interpolates the beam vector of an off-grid direction from
+ * neighbouring grid beam vectors with a spline (fbst_directions_create_interp);
+ * here it is projected exactly, so the beam is the regularised least-squares
+ * beam of that direction, at a cost of M L + N L complex products per
+ * direction and block.  Not for FBST_PREC_FP64 plans (FBST_E_UNSUPPORTED).  The plan must
  * outlive it. */
 fbst_status fbst_directions_create(const fbst_plan* plan, int n_directions, const double* u,
                                    const double* v, fbst_directions** out);
+
+/* The paper's off-grid beams (Sec. VIII, off-grid angle interpolation): for
+ * each direction d, w_d is estimated from the beamspace vectors of the grid
+ * beams around it and the beam is formed from it like a grid beam,
+ *     b_d = K_d w_d,  K_d = F_u (F_d^H F_d + delta I)^{-1},
+ * with the direction's own Toeplitz system.  w_d is the not-a-knot cubic
+ * spline in direction cosine through the 8 grid vectors j-3 .. j+4 around the
+ * direction (window shifted inward at the ends; 8 x 8 with the tensor-product
+ * spline on a planar grid), interpolated with the reference point moved to
+ * the centre of the array's extent and referred back to the origin:
+ *     w_d[l] = sum_i c_i exp(j a_l (u_d - u_i) c_x) w_i[l]   (and along v),
+ * a_l = 2 pi f_c + omega_l.  K_d as in fbst_directions_create; no projection
+ * phases: 8 D L N bytes plus 160 bytes per direction and 16 L bytes.  Needs
+ * at least 8 distinct grid beams along each axis with more than one
+ * (FBST_E_UNSUPPORTED) and directions inside the grid (FBST_E_INVALID; no
+ * extrapolation); v required for a planar grid.  Executes with
+ * fbst_execute_directions: stage 1 for the whole grid, the interpolation,
+ * then the K_d product; its workspace (fbst_workspace_bytes_directions)
+ * holds the path's own per-block workspace plus D L complex64 per block. */
+fbst_status fbst_directions_create_interp(const fbst_plan* plan, int n_directions,
+                                          const double* u, const double* v,
+                                          fbst_directions** out);
 
 /* Free direction tables (after their launches finished); NULL is a no-op. */
 void fbst_directions_destroy(fbst_directions* dirs);

@@ -69,6 +69,12 @@ struct Upload {
     if (!v.empty()) std::memcpy(blob.data() + off, v.data(), v.size() * sizeof(int));
     return off;
   }
+  size_t add_doubles(const std::vector<double>& v) {
+    const size_t off = align_up(blob.size());
+    blob.resize(off + v.size() * sizeof(double));
+    if (!v.empty()) std::memcpy(blob.data() + off, v.data(), v.size() * sizeof(double));
+    return off;
+  }
   size_t add(const std::vector<fbst::zd>& v, bool as_double) {
     const size_t off = align_up(blob.size());
     const size_t bytes = v.size() * (as_double ? 16 : 8);
@@ -407,9 +413,15 @@ hipError_t run_blocks_nulled(const fbst_plan* pl, const fbst_nulls* nl, int nb,
   fbst::c32* wt = wq + static_cast<size_t>(nb) * nl->P * p.L;
   hipError_t e = run_stage0<float>(pl, nb, xs, yhat, st);
   if (e == hipSuccess) e = run_stage1<float>(pl, nb, yhat, w, z, st);
-  if (e == hipSuccess)
-    e = nl->map ? fbst::launch_gather_rows(w, nl->map, wq, p.B, nl->P, p.L, nb, st)
-                : fbst::launch_project_dirs(yhat, nl->E, wq, p.M, nl->P, p.L, nb, st);
+  if (e == hipSuccess) {
+    if (nl->map)
+      e = fbst::launch_gather_rows(w, nl->map, wq, p.B, nl->P, p.L, nb, st);
+    else if (nl->E)
+      e = fbst::launch_project_dirs(yhat, nl->E, wq, p.M, nl->P, p.L, nb, st);
+    else
+      e = fbst::launch_interp_vectors(w, nl->vi.first, nl->vi.w, nl->vi.frac, nl->vi.theta, wq,
+                                      p.B, p.bv, nl->P, p.L, nb, st);
+  }
   if (e != hipSuccess) return e;
   fbst::ProductArgs c{};
   c.K = static_cast<const fbst::c32*>(nl->G);
@@ -440,9 +452,20 @@ hipError_t run_blocks_directions(const fbst_plan* pl, const fbst_directions* dr,
   const fbst::Params& p = pl->p;
   unsigned char* base = static_cast<unsigned char*>(ws);
   void* yhat = base;
-  auto* wd = reinterpret_cast<fbst::c32*>(base + align_up(static_cast<size_t>(nb) * p.M * p.L * 8));
   hipError_t e = run_stage0<float>(pl, nb, xs, yhat, st);
-  if (e == hipSuccess) e = fbst::launch_project_dirs(yhat, dr->E, wd, p.M, dr->D, p.L, nb, st);
+  fbst::c32* wd = nullptr;
+  if (dr->E) {                                 // w_d projected from Yhat
+    wd = reinterpret_cast<fbst::c32*>(base + align_up(static_cast<size_t>(nb) * p.M * p.L * 8));
+    if (e == hipSuccess) e = fbst::launch_project_dirs(yhat, dr->E, wd, p.M, dr->D, p.L, nb, st);
+  } else {                                     // w_d interpolated from the grid's W
+    void* w = base + static_cast<size_t>(nb) * p.M * p.L * 8;
+    void* z = static_cast<unsigned char*>(w) + static_cast<size_t>(nb) * p.B * p.L * 8;
+    wd = reinterpret_cast<fbst::c32*>(base + align_up(pl->ws_bytes_per_block * nb));
+    if (e == hipSuccess) e = run_stage1<float>(pl, nb, yhat, w, z, st);
+    if (e == hipSuccess)
+      e = fbst::launch_interp_vectors(w, dr->vi.first, dr->vi.w, dr->vi.frac, dr->vi.theta, wd,
+                                      p.B, p.bv, dr->D, p.L, nb, st);
+  }
   if (e != hipSuccess) return e;
   fbst::ProductArgs a{};
   a.K = static_cast<const fbst::c32*>(dr->K);
@@ -458,13 +481,45 @@ hipError_t run_blocks_directions(const fbst_plan* pl, const fbst_directions* dr,
 
 size_t directions_ws_per_block(const fbst_plan* pl, const fbst_directions* dr) {
   const fbst::Params& p = pl->p;
-  return align_up(static_cast<size_t>(p.M) * p.L * 8) + static_cast<size_t>(dr->D) * p.L * 8;
+  const size_t front = dr->E ? static_cast<size_t>(p.M) * p.L * 8 : pl->ws_bytes_per_block;
+  return align_up(front) + static_cast<size_t>(dr->D) * p.L * 8;
+}
+
+// Interpolation table of beamspace vectors at directions (ud, vd) added to
+// an upload; offsets returned for set_vector_interp.
+struct VIOffsets {
+  size_t first = 0, w = 0, frac = 0, theta = 0;
+};
+
+fbst_status add_vector_interp(const fbst_plan* plan, const std::vector<double>& ud,
+                              const std::vector<double>& vd, Upload* up, VIOffsets* o) {
+  std::vector<int> first;
+  std::vector<double> w, frac, theta;
+  std::string msg;
+  const fbst_status s = fbst::build_interp_table(plan->p, ud, vd, &first, &w, &msg, &frac);
+  if (s != FBST_OK) return fail(s, msg);
+  fbst::reference_phase_rates(plan->p, &theta);
+  o->first = up->add_ints(first);
+  o->w = up->add_doubles(w);
+  o->frac = up->add_doubles(frac);
+  o->theta = up->add_doubles(theta);
+  return FBST_OK;
+}
+
+VectorInterp vector_interp_at(const void* dev, const VIOffsets& o) {
+  const unsigned char* b = static_cast<const unsigned char*>(dev);
+  VectorInterp vi;
+  vi.first = reinterpret_cast<const int*>(b + o.first);
+  vi.w = reinterpret_cast<const double*>(b + o.w);
+  vi.frac = reinterpret_cast<const double*>(b + o.frac);
+  vi.theta = reinterpret_cast<const double*>(b + o.theta);
+  return vi;
 }
 
 // Nulling tables for n on-grid interferers (beam indices qs) or for n
 // explicit directions (u, v; qs null).
 fbst_status make_nulls(const fbst_plan* plan, int n, const int* qs, const double* u,
-                       const double* v, fbst_nulls** out) {
+                       const double* v, bool interp, fbst_nulls** out) {
   const fbst::Params& p = plan->p;
   if (p.prec == FBST_PREC_FP64)
     return fail(FBST_E_UNSUPPORTED, "beamspace nulling takes complex64 data (not FBST_PREC_FP64)");
@@ -485,7 +540,7 @@ fbst_status make_nulls(const fbst_plan* plan, int n, const int* qs, const double
   std::string msg;
   fbst_status s;
   try {
-    s = fbst::build_null_tables(p, uq, vq, &G, qs ? nullptr : &E, &msg);
+    s = fbst::build_null_tables(p, uq, vq, &G, (qs || interp) ? nullptr : &E, &msg);
   } catch (const std::bad_alloc&) {
     s = FBST_E_NOMEM;
     msg = "host allocation of the nulling tables failed";
@@ -493,9 +548,13 @@ fbst_status make_nulls(const fbst_plan* plan, int n, const int* qs, const double
   if (s != FBST_OK) return fail(s, msg);
   Upload up;
   size_t o_map = 0, o_e = 0;
+  VIOffsets o_vi;
   if (qs) {
     up.blob.resize(align_up(sizeof(int) * n));
     std::memcpy(up.blob.data(), qs, sizeof(int) * n);
+  } else if (interp) {
+    s = add_vector_interp(plan, uq, vq, &up, &o_vi);
+    if (s != FBST_OK) return s;
   } else {
     o_e = up.add(E, false);
   }
@@ -518,6 +577,7 @@ fbst_status make_nulls(const fbst_plan* plan, int n, const int* qs, const double
   nl->plan = plan;
   nl->P = n;
   if (qs) nl->map = reinterpret_cast<const int*>(b + o_map);
+  else if (interp) nl->vi = vector_interp_at(nl->dev, o_vi);
   else nl->E = b + o_e;
   nl->G = b + o_g;
   nl->dev_bytes = up.blob.size();
@@ -857,7 +917,7 @@ fbst_status fbst_nulls_create(const fbst_plan* plan, int n_interferers, const in
   std::vector<int> qs(beams, beams + n_interferers);
   for (int q : qs)
     if (q < 0 || q >= p.B) return fail(FBST_E_INVALID, "interferer beam index out of range");
-  return make_nulls(plan, n_interferers, qs.data(), nullptr, nullptr, out);
+  return make_nulls(plan, n_interferers, qs.data(), nullptr, nullptr, false, out);
 }
 
 fbst_status fbst_nulls_create_directions(const fbst_plan* plan, int n_interferers, const double* u,
@@ -871,11 +931,28 @@ fbst_status fbst_nulls_create_directions(const fbst_plan* plan, int n_interferer
   for (int i = 0; i < n_interferers; ++i)
     if (!std::isfinite(u[i]) || (v && !std::isfinite(v[i])))
       return fail(FBST_E_INVALID, "interferer directions must be finite");
-  return make_nulls(plan, n_interferers, nullptr, u, v, out);
+  return make_nulls(plan, n_interferers, nullptr, u, v, false, out);
 }
 
-fbst_status fbst_directions_create(const fbst_plan* plan, int n_directions, const double* u,
-                                   const double* v, fbst_directions** out) {
+fbst_status fbst_nulls_create_interp(const fbst_plan* plan, int n_interferers, const double* u,
+                                     const double* v, fbst_nulls** out) {
+  if (!out) return fail(FBST_E_INVALID, "out is NULL");
+  *out = nullptr;
+  fbst_status s = check_exec(plan);
+  if (s != FBST_OK) return s;
+  if (n_interferers < 1 || n_interferers > 64 || !u)
+    return fail(FBST_E_INVALID, "need 1..64 interferer directions");
+  if (plan->p.bv > 1 && !v) return fail(FBST_E_INVALID, "a planar beam grid needs v");
+  for (int i = 0; i < n_interferers; ++i)
+    if (!std::isfinite(u[i]) || (v && !std::isfinite(v[i])))
+      return fail(FBST_E_INVALID, "interferer directions must be finite");
+  return make_nulls(plan, n_interferers, nullptr, u, v, true, out);
+}
+
+namespace {
+
+fbst_status make_directions(const fbst_plan* plan, int n_directions, const double* u,
+                            const double* v, bool interp, fbst_directions** out) {
   if (!out) return fail(FBST_E_INVALID, "out is NULL");
   *out = nullptr;
   fbst_status s = check_exec(plan);
@@ -885,25 +962,32 @@ fbst_status fbst_directions_create(const fbst_plan* plan, int n_directions, cons
     return fail(FBST_E_INVALID, "need 1..65536 directions");
   if (p.prec == FBST_PREC_FP64)
     return fail(FBST_E_UNSUPPORTED, "beams at directions take complex64 data (not FBST_PREC_FP64)");
+  if (interp && p.bv > 1 && !v) return fail(FBST_E_INVALID, "a planar beam grid needs v");
   std::vector<double> ud(u, u + n_directions), vd(n_directions, 0.0);
   for (int i = 0; i < n_directions; ++i) {
     if (v && p.kind != FBST_LINE) vd[i] = v[i];
     if (!std::isfinite(ud[i]) || !std::isfinite(vd[i]))
       return fail(FBST_E_INVALID, "directions must be finite");
   }
-  if (8.0 * n_directions * p.L * (static_cast<double>(p.N) + p.M) > 16.0 * (1ULL << 30))
+  const double per_dir = 8.0 * p.L * (static_cast<double>(p.N) + (interp ? 0 : p.M));
+  if (per_dir * n_directions > 16.0 * (1ULL << 30))
     return fail(FBST_E_UNSUPPORTED, "the direction tables would exceed 16 GiB");
+  Upload up;
+  VIOffsets o_vi;
+  if (interp) {                                // validate the grid window first (cheap)
+    s = add_vector_interp(plan, ud, vd, &up, &o_vi);
+    if (s != FBST_OK) return s;
+  }
   std::vector<fbst::zd> K, E;
   std::string msg;
   try {
-    s = fbst::build_direction_tables(p, ud, vd, &K, &E, &msg);
+    s = fbst::build_direction_tables(p, ud, vd, &K, interp ? nullptr : &E, &msg);
   } catch (const std::bad_alloc&) {
     s = FBST_E_NOMEM;
     msg = "host allocation of the direction tables failed";
   }
   if (s != FBST_OK) return fail(s, msg);
-  Upload up;
-  const size_t o_e = up.add(E, false), o_k = up.add(K, false);
+  const size_t o_e = interp ? 0 : up.add(E, false), o_k = up.add(K, false);
   fbst_directions* dr = new (std::nothrow) fbst_directions();
   if (!dr) return fail(FBST_E_NOMEM, "host allocation failed");
   hipError_t e = hipMalloc(&dr->dev, up.blob.size());
@@ -921,11 +1005,25 @@ fbst_status fbst_directions_create(const fbst_plan* plan, int n_directions, cons
   const unsigned char* b = static_cast<const unsigned char*>(dr->dev);
   dr->plan = plan;
   dr->D = n_directions;
-  dr->E = b + o_e;
+  if (interp) dr->vi = vector_interp_at(dr->dev, o_vi);
+  else dr->E = b + o_e;
   dr->K = b + o_k;
   dr->dev_bytes = up.blob.size();
   *out = dr;
   return FBST_OK;
+}
+
+}  // namespace
+
+fbst_status fbst_directions_create(const fbst_plan* plan, int n_directions, const double* u,
+                                   const double* v, fbst_directions** out) {
+  return make_directions(plan, n_directions, u, v, false, out);
+}
+
+fbst_status fbst_directions_create_interp(const fbst_plan* plan, int n_directions,
+                                          const double* u, const double* v,
+                                          fbst_directions** out) {
+  return make_directions(plan, n_directions, u, v, true, out);
 }
 
 void fbst_directions_destroy(fbst_directions* dirs) {

@@ -133,6 +133,16 @@ hipError_t launch_interp_beams(const void* beams, const int* first, const double
                                int B, int bv, int D, int N, int nblocks, bool fp64,
                                hipStream_t st);
 
+// Beamspace vectors interpolated at directions with the reference point at
+// the array's centre: out[blk][d][l] = sum_{i<8, j<TV} wu[d][i] wv[d][j]
+// exp(j (theta[l] (fu - i) + theta[L + l] (fv - j))) W[blk][(a0 + i) bv + c0 + j][l]
+// ((a0, c0) = first[d], (fu, fv) = frac[d]); complex64, W [nb][B][L],
+// out [nb][D][L]; first [D][2], w [D][2][8], frac [D][2], theta [2][L] on
+// the device.
+hipError_t launch_interp_vectors(const void* W, const int* first, const double* w,
+                                 const double* frac, const double* theta, void* out, int B,
+                                 int bv, int D, int L, int nblocks, hipStream_t st);
+
 // w[j][b][l] = (l == l0 + j) for j < rows (complex64, [rows][B][L]).
 hipError_t launch_unit_rows(void* w, int B, int L, int l0, int rows, hipStream_t st);
 

@@ -953,7 +953,7 @@ fbst_status build_direction_tables(const Params& p, const std::vector<double>& u
   const double dxs = p.dx / p.ts, dys = p.dy / p.ts;
   auto a_of = [&](int l) { return 2.0 * kPi * p.fc * p.ts + kap * (l + lp0); };
   K->assign(static_cast<size_t>(L) * D * N, zd());
-  E->assign(static_cast<size_t>(D) * M * L, zd());
+  if (E) E->assign(static_cast<size_t>(D) * M * L, zd());
   for (int di = 0; di < D; ++di) {
     // A_d = F_d^H F_d + delta I: c(d) = [sum_n e^{-j kappa d n}][sum_m e^{j kappa d tau_m}] + delta
     std::vector<zd> col(L), x(L);
@@ -976,7 +976,7 @@ fbst_status build_direction_tables(const Params& p, const std::vector<double>& u
         for (int l = 0; l < L; ++l) (*K)[(static_cast<size_t>(l) * D + di) * N + n] = std::conj(g[l]);
       }
     });
-    for (int m = 0; m < M; ++m) {
+    for (int m = 0; E && m < M; ++m) {
       const double tau = ud[di] * pos_x(p, m) + vd[di] * pos_y(p, m);
       for (int l = 0; l < L; ++l) (*E)[(static_cast<size_t>(di) * M + m) * L + l] = cis(a_of(l) * tau);
     }
@@ -1111,40 +1111,68 @@ void spline_unit_weights(double x, double* w) {
 
 fbst_status build_interp_table(const Params& p, const std::vector<double>& ud,
                                const std::vector<double>& vd, std::vector<int>* first,
-                               std::vector<double>* w, std::string* msg) {
+                               std::vector<double>* w, std::string* msg,
+                               std::vector<double>* frac) {
   const bool plane = p.bv > 1;
   if (p.bu < INTERP_TAPS || p.du == 0.0 || (plane && (p.bv < INTERP_TAPS || p.dv == 0.0))) {
     *msg = "spline interpolation needs at least 8 distinct grid beams along each axis";
     return FBST_E_UNSUPPORTED;
   }
   // window and weights along one axis with n beams at x0 + k dx
-  auto axis = [](double x, double x0, double dx, int n, int* f, double* ww) {
+  auto axis = [](double x, double x0, double dx, int n, int* f, double* ww, double* fr) {
     const double last = n - 1;
-    double s = (x - x0) / dx;
+    // position on the grid, x = x0 + s dx; the direction itself, not the
+    // clamped s, sets the offset from the window (a hair outside the ends)
+    const double s_raw = (x - x0) / dx;
     const double tol = 1e-9 * n;
-    if (!(s >= -tol && s <= last + tol)) return false;
-    s = std::min(std::max(s, 0.0), last);
+    if (!(s_raw >= -tol && s_raw <= last + tol)) return false;
+    const double s = std::min(std::max(s_raw, 0.0), last);
     const int j = std::min(static_cast<int>(std::floor(s)), n - 1);   // x_j <= x < x_{j+1}
     const int j0 = std::min(std::max(j - (INTERP_TAPS / 2 - 1), 0), n - INTERP_TAPS);
     *f = j0;
     spline_unit_weights(s - j0, ww);
+    *fr = s_raw - j0;
     return true;
   };
   const size_t D = ud.size();
   first->assign(2 * D, 0);
   w->assign(2 * D * INTERP_TAPS, 0.0);
+  std::vector<double> fr(2 * D, 0.0);
   for (size_t d = 0; d < D; ++d) {
     int* f = first->data() + 2 * d;
     double* ww = w->data() + 2 * d * INTERP_TAPS;
-    bool ok = axis(ud[d], p.u0, p.du, p.bu, f, ww);
-    if (plane) ok = ok && axis(vd[d], p.v0, p.dv, p.bv, f + 1, ww + INTERP_TAPS);
+    bool ok = axis(ud[d], p.u0, p.du, p.bu, f, ww, &fr[2 * d]);
+    if (plane) ok = ok && axis(vd[d], p.v0, p.dv, p.bv, f + 1, ww + INTERP_TAPS, &fr[2 * d + 1]);
     else ww[INTERP_TAPS] = 1.0;                 // one beam along v, weight 1
     if (!ok) {
       *msg = "interpolation directions must lie within the beam grid (no extrapolation)";
       return FBST_E_INVALID;
     }
   }
+  if (frac) *frac = std::move(fr);
   return FBST_OK;
+}
+
+void reference_phase_rates(const Params& p, std::vector<double>* theta) {
+  const int L = p.L;
+  const double lp0 = 1.0 - 0.5 * L;
+  const double kap = 2.0 * kPi * p.eps / L;
+  double xmin = 0, xmax = 0, ymin = 0, ymax = 0;
+  for (int m = 0; m < p.M; ++m) {
+    const double x = pos_x(p, m), y = pos_y(p, m);
+    if (m == 0 || x < xmin) xmin = x;
+    if (m == 0 || x > xmax) xmax = x;
+    if (m == 0 || y < ymin) ymin = y;
+    if (m == 0 || y > ymax) ymax = y;
+  }
+  const double cx = 0.5 * (xmin + xmax), cy = 0.5 * (ymin + ymax);
+  theta->assign(2 * static_cast<size_t>(L), 0.0);
+  for (int l = 0; l < L; ++l) {
+    // a_l = 2 pi f_c T_s + kappa l' radians per sample of delay (Sec. IV)
+    const double a = 2.0 * kPi * p.fc * p.ts + kap * (l + lp0);
+    (*theta)[l] = a * cx * p.du;
+    (*theta)[L + l] = (p.bv > 1) ? a * cy * p.dv : 0.0;
+  }
 }
 
 }  // namespace fbst

@@ -86,8 +86,8 @@ fbst_status build_tables(const Params& p, bool keep_gram_gen, HostTables* t, std
 fbst_status finish_generators(const Params& p, const std::vector<zd>& x, bool keep_gram_gen,
                               HostTables* t);
 
-// Beams at directions (ud, vd): K [l][d][n] = (F_u A_d^{-1})[n][l] and the
-// projection phases E [d][m][l] = exp(j a_l tau_{d,m}); float64.
+// Beams at directions (ud, vd): K [l][d][n] = (F_u A_d^{-1})[n][l] and, when
+// E is given, the projection phases E [d][m][l] = exp(j a_l tau_{d,m}); float64.
 fbst_status build_direction_tables(const Params& p, const std::vector<double>& ud,
                                    const std::vector<double>& vd, std::vector<zd>* K,
                                    std::vector<zd>* E, std::string* msg);
@@ -99,11 +99,23 @@ fbst_status build_direction_tables(const Params& p, const std::vector<double>& u
 // around it and the weights of the not-a-knot cubic spline through them
 // evaluated at the direction (the tensor-product spline on a plane; a line
 // gets the window 0 and the weights (1, 0, ...) along v).
-// first [D][2] (u, v), w [D][2][INTERP_TAPS]; float64.
+// first [D][2] (u, v), w [D][2][INTERP_TAPS]; float64.  frac (optional):
+// [D][2], the direction's position on each axis counted in grid steps from
+// the window's first beam ((u - u_first) / du; 0 along v for a line).
 constexpr int INTERP_TAPS = 8;
 fbst_status build_interp_table(const Params& p, const std::vector<double>& ud,
                                const std::vector<double>& vd, std::vector<int>* first,
-                               std::vector<double>* w, std::string* msg);
+                               std::vector<double>* w, std::string* msg,
+                               std::vector<double>* frac = nullptr);
+
+// Interpolation of beamspace vectors with the reference point at the centre
+// (c_x, c_y) of the array's extent (Sec. VIII, the paper's off-grid form):
+// the vector at a direction is sum_i c_i exp(j a_l (u - u_i) c_x + ...) w_i[l],
+// and u - u_i = (frac - i) du.  theta [2][L] holds the per-step phases
+// a_l c_x du and a_l c_y dv (radians; a_l = 2 pi f_c T_s + kappa l' per
+// sample of delay, c in samples per unit direction cosine; 0 along v for a
+// line).
+void reference_phase_rates(const Params& p, std::vector<double>* theta);
 
 // Beamspace nulling tables for interferer directions (uq, vq) (Sec. VIII):
 // G [q L + k][b][n] = (F_b^H F_q A_q^{-1})[n][k] and, when E is given, the
@@ -132,6 +144,15 @@ void fft64(zd* a, int n, int sign);
 // interferer beam indices [P] (int, on-grid interferers: their rows of W are
 // gathered) or the projection phases E [P][M][L] (complex64, any direction:
 // their beam vectors are projected from stage 1a's output).
+// With interferer vectors interpolated from the grid's (fbst_nulls_create_interp)
+// neither map nor E is set and vi holds the interpolation table.
+struct VectorInterp {
+  const int* first = nullptr;      // [n][2]
+  const double* w = nullptr;       // [n][2][INTERP_TAPS]
+  const double* frac = nullptr;    // [n][2]
+  const double* theta = nullptr;   // [2][L]
+};
+
 struct fbst_nulls {
   const fbst_plan* plan = nullptr;
   int P = 0;
@@ -140,10 +161,14 @@ struct fbst_nulls {
   const int* map = nullptr;
   const void* E = nullptr;
   const void* G = nullptr;
+  VectorInterp vi;
 };
 
-// Beams at arbitrary directions of one plan (one device allocation): the
-// projection phases E [D][M][L] and K_d = F_u A_d^{-1} as [L][D][N] (complex64).
+// Beams at arbitrary directions of one plan (one device allocation):
+// K_d = F_u A_d^{-1} as [L][D][N] (complex64) and either the projection
+// phases E [D][M][L] (complex64; w_d projected from stage 1a's output) or,
+// for fbst_directions_create_interp, the interpolation table vi (w_d
+// interpolated from the grid's beamspace vectors).
 struct fbst_directions {
   const fbst_plan* plan = nullptr;
   int D = 0;
@@ -151,6 +176,7 @@ struct fbst_directions {
   size_t dev_bytes = 0;
   const void* E = nullptr;
   const void* K = nullptr;
+  VectorInterp vi;
 };
 
 // Spline-interpolated off-grid beams of one plan (device: first [D][2] ints,

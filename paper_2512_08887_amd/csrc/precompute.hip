@@ -343,6 +343,69 @@ __global__ __launch_bounds__(256) void k_interp_beams_x2(const float4* __restric
   out[static_cast<size_t>(row) * N2 + q] = make_float4(r0, i0, r1, i1);
 }
 
+// Beamspace vectors at directions, spline-interpolated from the grid's
+// (Sec. VIII, the paper's off-grid form), with the reference point moved to
+// the array's centre c for the interpolation:
+//   out[blk][d][l] = sum_{i < 8, j < TV} wu[i] wv[j]
+//                    exp(j (theta_x[l] (fu - i) + theta_y[l] (fv - j)))
+//                    W[blk][(a0 + i) bv + c0 + j][l]
+// where theta_x[l] = a_l c_x du (u - u_{a0+i} = (fu - i) du) and likewise
+// along v; (a0, c0) = first[d], (fu, fv) = frac[d].  The per-tap phases are
+// formed in float64 and reduced to [-pi, pi] before the float32 sine and
+// cosine.  One workgroup per 256 consecutive l of one (block, direction)
+// row, XCD-contiguous like k_interp_beams.
+template <int TV>
+__global__ __launch_bounds__(256) void k_interp_vectors(const c32* __restrict__ W,
+                                                        const int* __restrict__ first,
+                                                        const double* __restrict__ w,
+                                                        const double* __restrict__ frac,
+                                                        const double* __restrict__ theta,
+                                                        c32* __restrict__ out, int B, int bv,
+                                                        int D, int L, int ntile) {
+  const int wg = xcd_linear(gridDim.x);
+  const int row = wg / ntile;                    // blk * D + d
+  const int l = (wg - row * ntile) * 256 + threadIdx.x;
+  if (l >= L) return;
+  const int d = row % D;
+  const size_t blk = static_cast<size_t>(row / D);
+  const int a0 = first[2 * d], c0 = first[2 * d + 1];
+  const double* wd = w + static_cast<size_t>(d) * 16;
+  const double twopi = 6.283185307179586476925;
+  auto rot = [&](double ph) {
+    ph -= twopi * rint(ph * (1.0 / twopi));
+    float sn, cs;
+    sincosf(static_cast<float>(ph), &sn, &cs);
+    return c32{cs, sn};
+  };
+  c32 rx[8], ry[TV];
+  const double fu = frac[2 * d], tx = theta[l];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) rx[i] = rot(tx * (fu - i));
+  if (TV > 1) {
+    const double fv = frac[2 * d + 1], ty = theta[L + l];
+#pragma unroll
+    for (int j = 0; j < TV; ++j) ry[j] = rot(ty * (fv - j));
+  } else {
+    ry[0] = c32{1.0f, 0.0f};
+  }
+  const c32* src = W + (blk * B + static_cast<size_t>(a0) * bv + c0) * L + l;
+  float re = 0, im = 0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+#pragma unroll
+    for (int j = 0; j < TV; ++j) {
+      const c32 a = src[(static_cast<size_t>(i) * bv + j) * L];
+      const c32 r = (TV > 1) ? c32{rx[i].re * ry[j].re - rx[i].im * ry[j].im,
+                                   rx[i].re * ry[j].im + rx[i].im * ry[j].re}
+                             : rx[i];
+      const float c = static_cast<float>(wd[i] * wd[8 + j]);
+      re += c * (r.re * a.re - r.im * a.im);
+      im += c * (r.re * a.im + r.im * a.re);
+    }
+  }
+  out[static_cast<size_t>(row) * L + l] = c32{re, im};
+}
+
 }  // namespace
 
 hipError_t launch_interp_beams(const void* beams, const int* first, const double* w, void* out,
@@ -379,6 +442,26 @@ hipError_t launch_interp_beams(const void* beams, const int* first, const double
     if (bv > 1) hipLaunchKernelGGL((k_interp_beams<float, 8>), g, b, 0, st, in, first, w, o, B, bv, D, N, nt);
     else hipLaunchKernelGGL((k_interp_beams<float, 1>), g, b, 0, st, in, first, w, o, B, bv, D, N, nt);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_interp_vectors(const void* W, const int* first, const double* w,
+                                 const double* frac, const double* theta, void* out, int B,
+                                 int bv, int D, int L, int nblocks, hipStream_t st) {
+  if (nblocks < 1 || bv < 1 || B % bv != 0 || B / bv < 8 || (bv > 1 && bv < 8) || D < 1 || L < 1)
+    return hipErrorInvalidValue;
+  const long long ntile = (L + 255) / 256;
+  const long long grid = 1LL * nblocks * D * ntile;
+  if (grid > 0x7fffffffLL) return hipErrorInvalidValue;
+  const dim3 g(static_cast<unsigned>(grid)), b(256);
+  auto in = static_cast<const c32*>(W);
+  auto o = static_cast<c32*>(out);
+  if (bv > 1)
+    hipLaunchKernelGGL((k_interp_vectors<8>), g, b, 0, st, in, first, w, frac, theta, o, B, bv, D,
+                       L, static_cast<int>(ntile));
+  else
+    hipLaunchKernelGGL((k_interp_vectors<1>), g, b, 0, st, in, first, w, frac, theta, o, B, bv, D,
+                       L, static_cast<int>(ntile));
   return hipGetLastError();
 }
 

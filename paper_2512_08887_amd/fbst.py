@@ -132,6 +132,12 @@ def load_library(path: str = LIB_PATH):
     L.fbst_directions_create.argtypes = [c_void_p, c_int, POINTER(ctypes.c_double),
                                          POINTER(ctypes.c_double), POINTER(c_void_p)]
     L.fbst_directions_create.restype = c_int
+    L.fbst_directions_create_interp.argtypes = [c_void_p, c_int, POINTER(ctypes.c_double),
+                                                POINTER(ctypes.c_double), POINTER(c_void_p)]
+    L.fbst_directions_create_interp.restype = c_int
+    L.fbst_nulls_create_interp.argtypes = [c_void_p, c_int, POINTER(ctypes.c_double),
+                                           POINTER(ctypes.c_double), POINTER(c_void_p)]
+    L.fbst_nulls_create_interp.restype = c_int
     L.fbst_directions_destroy.argtypes = [c_void_p]
     L.fbst_directions_destroy.restype = None
     L.fbst_workspace_bytes_directions.argtypes = [c_void_p, c_void_p, c_int]
@@ -308,12 +314,30 @@ def fbst_nulls_create_directions(plan, u, v=None) -> int:
     return h.value
 
 
+def fbst_nulls_create_interp(plan, u, v=None) -> int:
+    n = len(u)
+    ua = (ctypes.c_double * n)(*[float(a) for a in u])
+    va = (ctypes.c_double * n)(*[float(a) for a in v]) if v is not None else None
+    h = c_void_p()
+    _check(lib().fbst_nulls_create_interp(plan, n, ua, va, byref(h)))
+    return h.value
+
+
 def fbst_directions_create(plan, u, v=None) -> int:
     n = len(u)
     ua = (ctypes.c_double * n)(*[float(a) for a in u])
     va = (ctypes.c_double * n)(*[float(a) for a in v]) if v is not None else None
     h = c_void_p()
     _check(lib().fbst_directions_create(plan, n, ua, va, byref(h)))
+    return h.value
+
+
+def fbst_directions_create_interp(plan, u, v=None) -> int:
+    n = len(u)
+    ua = (ctypes.c_double * n)(*[float(a) for a in u])
+    va = (ctypes.c_double * n)(*[float(a) for a in v]) if v is not None else None
+    h = c_void_p()
+    _check(lib().fbst_directions_create_interp(plan, n, ua, va, byref(h)))
     return h.value
 
 
@@ -569,16 +593,18 @@ class Plan:
 class Nulls:
     """Beamspace nulling of interferers at beams of a plan (fbst_nulls_*)."""
 
-    def __init__(self, plan, beams=None, *, u=None, v=None):
-        """Interferers at beams of the plan's grid, or at directions u (and v)."""
+    def __init__(self, plan, beams=None, *, u=None, v=None, interp=False):
+        """Interferers at beams of the plan's grid, or at directions u (and v),
+        their beam vectors projected exactly or (interp=True) interpolated
+        from the grid's (fbst_nulls_create_interp)."""
         self.plan = plan
         if beams is not None:
             self.beams = [int(b) for b in beams]
             self.handle = fbst_nulls_create(plan.handle, self.beams)
         else:
             self.beams = None
-            self.handle = fbst_nulls_create_directions(plan.handle, list(u),
-                                                       None if v is None else list(v))
+            make = fbst_nulls_create_interp if interp else fbst_nulls_create_directions
+            self.handle = make(plan.handle, list(u), None if v is None else list(v))
 
     def workspace(self, nblocks=1):
         import torch
@@ -658,10 +684,13 @@ class Interp:
 class Directions:
     """Beams at arbitrary directions (u, v) of a plan (fbst_directions_*)."""
 
-    def __init__(self, plan, u, v=None):
+    def __init__(self, plan, u, v=None, interp=False):
+        """interp=True: the paper's form, beam vectors interpolated from the
+        grid's (fbst_directions_create_interp); else projected exactly."""
         self.plan = plan
         self.D = len(u)
-        self.handle = fbst_directions_create(plan.handle, list(u), None if v is None else list(v))
+        make = fbst_directions_create_interp if interp else fbst_directions_create
+        self.handle = make(plan.handle, list(u), None if v is None else list(v))
 
     def workspace(self, nblocks=1):
         import torch
