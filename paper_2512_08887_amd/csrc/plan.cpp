@@ -678,7 +678,10 @@ fbst_status resolve_params(int M, int N, int B, const fbst_geometry* geom, const
     }
   }
   const int lim1 = (p.prec == FBST_PREC_FP64) ? 8192 : PMAX;
-  const int lim2 = (p.prec == FBST_PREC_FP32) ? PMAX : 8192;
+  // stage 2 runs in float64 for FBST_PREC_FP64 and FBST_PREC_FP64_STAGE2, in
+  // float32 otherwise (the split precisions change stage 1a only)
+  const bool s2_double = p.prec == FBST_PREC_FP64 || p.prec == FBST_PREC_FP64_STAGE2;
+  const int lim2 = s2_double ? 8192 : PMAX;
   if (p.p1 > lim1 || p.p2x > lim1 || p.p2y > lim1 || p.p3 > lim2) {
     *msg = "an FFT size exceeds what one workgroup holds in LDS for this precision";
     return FBST_E_UNSUPPORTED;

@@ -52,3 +52,21 @@ def perturbed_cfg(kind, M, N, B, *, mx=0, my=0, bu=0, bv=0, perturb=0.25, fb=0.5
     return synth.Config(f"n{kind}{M}x{N}x{B}", kind, M=M, N=N, B=B, fb=fb, n_sources=n_sources,
                         power_db_range=0.0, sigma2=sigma2, mx=mx, my=my, bu=bu, bv=bv,
                         index=index, perturb=perturb)
+
+
+_FBST64_CACHE = {}
+
+
+def fbst64_beams(cfg, block=0, delta=None):
+    """Every beam of one block of a synth.Config by the second FP64 oracle
+    (oracle.fbst64) on the complex64-rounded input the GPU sees; cached for
+    the test session (the large configurations take tens of seconds)."""
+    from oracle import fbst64 as fb
+    d = cfg.delta_noise if delta is None else delta
+    key = (cfg.name, block, d)
+    if key not in _FBST64_CACHE:
+        y = cfg.scene().block(block).astype(np.complex64).astype(np.complex128)
+        p = oracle_problem(cfg, d)
+        shape = (cfg.mx, cfg.my, cfg.bu, cfg.bv) if cfg.kind == "ura" else None
+        _FBST64_CACHE[key] = fb.beams(y, p, shape=shape)
+    return _FBST64_CACHE[key]

@@ -122,6 +122,24 @@ def test_invalid_arguments():
     assert st == F.FBST_E_UNSUPPORTED and hnd is None
 
 
+def test_stage2_size_limit_follows_the_stage2_precision():
+    """The split precisions change stage 1a only: their float32 stage 2 takes
+    the float32 limit (P3 = 16384 at M = B = 1024, N = 4096), while a float64
+    stage 2 holds P3 <= 8192 in one workgroup's LDS."""
+    band = F.make_band(2.0, 0.5, 1.0)
+    delta = 1.0 * 2 * 4096
+    for prec in ("fp32", "bf16_split", "fp16_split"):
+        h = F.fbst_plan_create(1024, 4096, 1024, None, band, None,
+                               F.make_options(delta, precision=prec, flags=F.FBST_FLAG_HOST_ONLY))
+        info = F.fbst_plan_info(h)
+        F.fbst_destroy(h)
+        assert info.p3 == 16384, (prec, info.p3)
+    st, hnd = F.fbst_plan_create_status(1024, 4096, 1024, None, band, None,
+                                        F.make_options(delta, precision="fp64_stage2",
+                                                       flags=F.FBST_FLAG_HOST_ONLY))
+    assert st == F.FBST_E_UNSUPPORTED and hnd is None
+
+
 def test_null_and_host_only_plan_calls():
     lib = F.lib()
     lib.fbst_destroy(None)                                  # no-op
