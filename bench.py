@@ -140,6 +140,52 @@ def rocprof_summary(kt_dir, pmc_dirs, copy_dirs):
     return "\n".join(out), scaled
 
 
+def sq_summary(pmc_dirs, kernels=("k_toeplitz_fu", "k_time_czt", "k_axis_czt")):
+    """Per-wave SQ counters of the hot kernels from rocprofv3 --pmc runs
+    (counter_collection.csv; several runs, each with its own counter set):
+    median over dispatches of counter / SQ_WAVES, per (kernel, grid)."""
+    import csv
+    import glob
+    import re
+    from collections import defaultdict
+
+    def short(name):
+        m = re.match(r"_ZN4fbst12_GLOBAL__N_1\d+(k_\w+?)ILi(\d+)EDv8_DF16(b|_)", name)
+        if m:
+            return f"{m.group(1)}<{m.group(2)}, {'bf16x8' if m.group(3) == 'b' else 'f16x8'}>"
+        n = name.replace("void ", "").replace("fbst::(anonymous namespace)::", "")
+        return re.sub(r"\(.*", "", n)
+
+    per = defaultdict(lambda: defaultdict(list))      # (kernel, grid) -> counter -> values
+    for pdir in pmc_dirs:
+        for f in glob.glob(os.path.join(pdir, "*counter_collection.csv")):
+            rows = list(csv.DictReader(open(f)))
+            by_dispatch = defaultdict(dict)
+            for r in rows:
+                k = short(r["Kernel_Name"])
+                if not any(k.startswith(x) for x in kernels):
+                    continue
+                by_dispatch[(r.get("Dispatch_Id", ""), k, int(r["Grid_Size"]))][r["Counter_Name"]] = \
+                    float(r["Counter_Value"])
+            for (_, k, g), c in by_dispatch.items():
+                waves = c.get("SQ_WAVES")
+                for name, val in c.items():
+                    if name != "SQ_WAVES" and waves:
+                        per[(k, g)][name].append(val / waves)
+                if waves:
+                    per[(k, g)]["SQ_WAVES"].append(waves)
+    names = sorted({n for d in per.values() for n in d})
+    out = ["kernel | grid | " + " | ".join(n.replace("SQ_", "") for n in names),
+           "---|---|" + "---|" * len(names)]
+    for (k, g), d in sorted(per.items()):
+        cells = []
+        for n in names:
+            v = d.get(n)
+            cells.append(f"{np.median(v):.0f}" if v else "")
+        out.append(f"{k} | {g} | " + " | ".join(cells))
+    return "\n".join(out)
+
+
 # Sources whose change invalidates stored HBM counter readings of the kernels.
 KERNEL_SOURCES = ["cx.h", "fft_lds.h", "kernels.h", "kernels.hip", "mfma_czt.hip", "precompute.hip"]
 COUNTERS_JSON = os.path.join(ROOT, "profiles", "hbm_counters_ula256.json")
@@ -530,6 +576,10 @@ def serve_bench(F, torch, configs, *, seconds=2.0, loads=(0.5, 0.8, 0.95), burst
 
 
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "--sq-summary":
+        # bench.py --sq-summary PMC_DIR[,PMC_DIR...]: per-wave SQ counters of the hot kernels
+        print(sq_summary(sys.argv[2].split(",")))
+        return
     if len(sys.argv) > 1 and sys.argv[1] == "--rocprof-summary":
         # bench.py --rocprof-summary KT_DIR PMC_DIR[,PMC_DIR] COPY_DIR[,COPY_DIR] [COUNTERS_JSON]
         text, scaled = rocprof_summary(sys.argv[2], sys.argv[3].split(","), sys.argv[4].split(","))
