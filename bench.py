@@ -54,14 +54,23 @@ def stage_flops(info):
     return s0, s1, s2
 
 
-def cpu_baseline(cfg, y, delta, n_beams=48):
-    """The FP64 oracle on one block restricted to n_beams beams."""
-    from oracle import direct as od
+def _cpu_model():
     try:
-        import threadpoolctl
-        threads = max([d.get("num_threads", 1) for d in threadpoolctl.threadpool_info()] or [1])
-    except Exception:
-        threads = os.cpu_count() or 1
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(cfg, y, delta, n_beams=48, n_beams_1t=8):
+    """The FP64 oracle on one block restricted to n_beams beams, on every BLAS
+    thread the process may use, and on n_beams_1t beams with one thread."""
+    from oracle import direct as od
+    import threadpoolctl
+    threads = max([d.get("num_threads", 1) for d in threadpoolctl.threadpool_info()] or [1])
     band = cfg.band
     p = od.line_problem(cfg.M, cfg.N, cfg.B, fc=band.fc, omega=band.omega, ts=band.ts, eps=cfg.eps,
                         gamma=cfg.gamma, delta=delta)
@@ -69,10 +78,75 @@ def cpu_baseline(cfg, y, delta, n_beams=48):
     t0 = time.perf_counter()
     ref = od.beams(y, p, idx)
     dt = time.perf_counter() - t0
+    idx1 = idx[:: max(1, n_beams // n_beams_1t)][:n_beams_1t]
+    with threadpoolctl.threadpool_limits(1):
+        t1 = time.perf_counter()
+        od.beams(y, p, idx1)
+        dt1 = time.perf_counter() - t1
     return ({"value": n_beams * cfg.N / dt, "unit": "beam-samples/s", "cores": int(threads),
              "kind": "oracle",
              "sample": f"FP64 oracle (definition: dense projection sums + Cholesky), one block, "
-                       f"{n_beams} of {cfg.B} beams, {dt:.1f} s"}, idx, ref)
+                       f"{n_beams} of {cfg.B} beams, {dt:.1f} s",
+             "cpu_model": _cpu_model(), "affinity_cores": len(os.sched_getaffinity(0)),
+             "one_thread": {"value": len(idx1) * cfg.N / dt1, "unit": "beam-samples/s",
+                            "sample": f"{len(idx1)} beams, {dt1:.1f} s, 1 BLAS thread"}},
+            idx, ref)
+
+
+def fbst64_baseline(names=("ula16", "ula256", "ura32", "ula1024")):
+    """The second FP64 oracle (the FBST with numpy FFTs) on every beam of one
+    block of each workload, on the host's cores (its Levinson solves run in
+    up to 16 worker processes for the large ones)."""
+    from oracle import fbst64 as fb
+    import synth
+    out, beams = {}, {}
+    for name in names:
+        c = synth.config(name)
+        p = _oracle_problem(c)
+        y = c.scene().block(0).astype(np.complex64).astype(np.complex128)
+        shape = (c.mx, c.my, c.bu, c.bv) if c.kind == "ura" else None
+        t0 = time.perf_counter()
+        beams[name] = fb.beams(y, p, shape=shape)
+        dt = time.perf_counter() - t0
+        out[name] = {"blocks_per_s": 1.0 / dt, "beam_samples_per_s": c.B * c.N / dt,
+                     "seconds": dt}
+    out["workers"] = min(16, os.cpu_count() or 1)
+    return out, beams
+
+
+def large_bench(F, torch, *, steps=5, log=print):
+    """Whole-path throughput of the planar array (32 x 32, N = 2048) and the
+    1024-element line (N = 4096) in float32, and of the line with the
+    bfloat16 / float16 split stage 1a; blocks of one step in one launch.
+    Returns the results and block 0's beams of each (for the oracle check)."""
+    import synth
+    runs = [("ura32", "fp32", 8), ("ula1024", "fp32", 4), ("ula1024", "bf16_split", 4),
+            ("ula1024", "fp16_split", 4)]
+    out, first = {}, {}
+    for name, prec, nb in runs:
+        c = synth.config(name)
+        plan = F.plan_for_config(c, precision=prec)
+        y = np.stack([c.scene().block(k) for k in range(nb)]).astype(np.complex64)
+        x = torch.from_numpy(y).cuda()
+        ws = plan.workspace(nb)
+        bo = plan.execute_batched(x, workspace=ws)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            plan.execute_batched(x, beams=bo, workspace=ws)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        key = f"{name}_{prec}"
+        out[key] = {"workload": f"{name}: M={c.M}, B={c.B}, N={c.N}, L={c.L}, {nb} blocks per launch",
+                    "precision": prec, "value": nb * c.B * c.N / (ms * 1e-3),
+                    "unit": "beam-samples/s", "ms_per_step": ms}
+        first[key] = (name, bo[0].cpu().numpy())
+        log(f"[bench] {key}: {ms:.3f} ms per {nb} blocks, {out[key]['value']:.3e} beam-samples/s")
+        plan.close()
+        del x, ws, bo
+    return out, first
 
 
 def rocprof_summary(kt_dir, pmc_dirs, copy_dirs):
@@ -490,16 +564,20 @@ def _oracle_problem(cfg):
 
 
 def serve_bench(F, torch, configs, *, seconds=2.0, loads=(0.5, 0.8, 0.95), burst=768,
-                slots=16, seed=0, log=print):
+                slots=16, seed=0, precision="fp32", log=print, checks=None):
     """Continuous-batching server over resident plans: saturation throughput
     from a burst, then Poisson arrivals at fractions of it (arrays chosen
-    uniformly); latency = completion - submission on the server clock."""
+    uniformly); latency = completion - submission on the server clock.  Each
+    array's input is block 0 of its synthetic scene.  checks: a list that
+    receives (config, plan-precision, served beams of block 0) for the first
+    arrays of each distinct shape class, compared with the oracle in the CPU
+    leg."""
     from concurrent.futures import ThreadPoolExecutor
 
     t0 = time.perf_counter()
 
     def mk(c):
-        return F.plan_for_config(c)
+        return F.plan_for_config(c, precision=precision)
 
     with ThreadPoolExecutor(4) as ex:
         plans = list(ex.map(mk, configs))
@@ -507,7 +585,7 @@ def serve_bench(F, torch, configs, *, seconds=2.0, loads=(0.5, 0.8, 0.95), burst
     rng = np.random.default_rng(seed)
     xs, outs = [], []
     for c, p in zip(configs, plans):
-        x = (torch.randn((c.M, c.N), dtype=torch.complex64, device="cuda"))
+        x = torch.from_numpy(c.scene().block(0).astype(np.complex64)).cuda()
         xs.append(x)
         outs.append([torch.empty((c.B, c.N), dtype=torch.complex64, device="cuda") for _ in range(slots)])
     torch.cuda.synchronize()
@@ -518,11 +596,10 @@ def serve_bench(F, torch, configs, *, seconds=2.0, loads=(0.5, 0.8, 0.95), burst
     def run_point(arrivals_us, choice):
         free = [list(range(slots)) for _ in range(A)]
         inflight = {}
-        lat, done_samples = [], 0
+        lat, batch, done_samples = [], [], 0
         base = srv.clock_us()
         k = 0
         tag = 0
-        pending_start = time.perf_counter()
 
         def harvest():
             nonlocal done_samples
@@ -530,6 +607,7 @@ def serve_bench(F, torch, configs, *, seconds=2.0, loads=(0.5, 0.8, 0.95), burst
                 a, s, sub = inflight.pop(comp.tag)
                 free[a].append(s)
                 lat.append(comp.done_us - comp.submit_us)
+                batch.append(comp.batch)
                 done_samples += samples[a]
 
         while k < len(arrivals_us):
@@ -543,36 +621,63 @@ def serve_bench(F, torch, configs, *, seconds=2.0, loads=(0.5, 0.8, 0.95), burst
                 continue
             s = free[a].pop()
             inflight[tag] = (a, s, now)
-            srv.submit(plans[a], xs[a], outs[a][s], tag)
+            srv.submit(plans[a], xs[a], outs[a][s], tag, sync=False)
             tag += 1
             k += 1
         srv.drain(timeout_s=120)
         harvest()
         elapsed_s = (srv.clock_us() - base) / 1e6
-        return np.array(lat) / 1e3, done_samples / elapsed_s, len(lat) / elapsed_s
+        return (np.array(lat) / 1e3, done_samples / elapsed_s, len(lat) / elapsed_s,
+                float(np.mean(batch)) if batch else 0.0)
 
     # saturation: everything submitted at once
     choice = rng.integers(0, A, burst)
-    lat, sat_samples, sat_blocks = run_point(np.zeros(burst), choice)
-    log(f"[serve] {A} arrays, plans {plan_s:.1f} s; saturation {sat_blocks:.0f} blocks/s, "
-        f"{sat_samples:.3e} beam-samples/s")
-    res = {"arrays": A, "plan_build_s": plan_s, "saturation_blocks_per_s": sat_blocks,
-           "saturation_beam_samples_per_s": sat_samples, "points": []}
+    lat, sat_samples, sat_blocks, sat_batch = run_point(np.zeros(burst), choice)
+    log(f"[serve {precision}] {A} arrays, plans {plan_s:.1f} s; saturation {sat_blocks:.0f} blocks/s, "
+        f"{sat_samples:.3e} beam-samples/s, mean batch {sat_batch:.1f}")
+    res = {"arrays": A, "precision": precision, "plan_build_s": plan_s,
+           "saturation_blocks_per_s": sat_blocks, "saturation_beam_samples_per_s": sat_samples,
+           "saturation_mean_batch": sat_batch, "points": []}
     for load in loads:
         rate = load * sat_blocks
         n = max(50, int(rate * seconds))
         arr = np.cumsum(rng.exponential(1e6 / rate, n))
         choice = rng.integers(0, A, n)
-        lat, thr, blk = run_point(arr, choice)
+        lat, thr, blk, mb = run_point(arr, choice)
         pt = {"load": load, "offered_blocks_per_s": rate, "blocks": int(len(lat)),
               "beam_samples_per_s": thr, "p50_ms": float(np.percentile(lat, 50)),
-              "p99_ms": float(np.percentile(lat, 99))}
-        log(f"[serve] load {load:.2f}: {blk:.0f} blocks/s, p50 {pt['p50_ms']:.3f} ms, p99 {pt['p99_ms']:.3f} ms")
+              "p99_ms": float(np.percentile(lat, 99)), "mean_batch": mb}
+        log(f"[serve {precision}] load {load:.2f}: {blk:.0f} blocks/s, p50 {pt['p50_ms']:.3f} ms, "
+            f"p99 {pt['p99_ms']:.3f} ms, mean batch {mb:.2f}")
         res["points"].append(pt)
     srv.close()
+    if checks is not None:
+        # the largest array and the extreme fractional bandwidths of the mix
+        pick = sorted(set([int(np.argmax([c.M * c.N for c in configs])),
+                           int(np.argmin([c.fb for c in configs])),
+                           int(np.argmax([c.fb for c in configs]))]))
+        for a in pick:
+            out = plans[a].execute(xs[a])
+            torch.cuda.synchronize()
+            checks.append((configs[a], precision, xs[a].cpu().numpy(), out.cpu().numpy()))
     for p in plans:
         p.close()
     return res
+
+
+def serve_accuracy(checks, n_beams=6):
+    """Relative L2 error of served beams against the second FP64 oracle
+    (oracle.fbst64) on sampled beams, per checked array and precision."""
+    from oracle import fbst64 as fb
+    out = []
+    for cfg, prec, y, got in checks:
+        p = _oracle_problem(cfg)
+        idx = np.unique(np.linspace(0, cfg.B - 1, n_beams).round().astype(int))
+        ref = fb.beams(y.astype(np.complex128), p, beam_idx=idx)
+        out.append({"array": cfg.name, "M": cfg.M, "N": cfg.N, "fb": round(cfg.fb, 3),
+                    "precision": prec,
+                    "rel_l2": float(np.linalg.norm(got[idx] - ref) / np.linalg.norm(ref))})
+    return out
 
 
 def main():
@@ -597,6 +702,10 @@ def main():
     ap.add_argument("--chunk", type=int, default=-1,
                     help="blocks per launch (-1: chosen by fbst_autotune, 0: all 64)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the planar array and 1024-element line throughputs")
+    ap.add_argument("--no-fbst64", action="store_true",
+                    help="skip timing the FP64 FBST oracle on every workload")
     ap.add_argument("--latency-reps", type=int, default=200)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-mix measurement")
     ap.add_argument("--no-n64", action="store_true",
@@ -605,7 +714,6 @@ def main():
     ap.add_argument("--no-nu", action="store_true", help="skip the non-uniform array measurement")
     ap.add_argument("--no-interp", action="store_true",
                     help="skip the spline-interpolated off-grid beams measurement")
-    ap.add_argument("--serve-only", action="store_true", help="only the serving-mix measurement")
     ap.add_argument("--serve-seconds", type=float, default=2.0)
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run plain device copies of MIB MiB (HBM counter calibration)")
@@ -848,13 +956,26 @@ def main():
     if not args.no_serve:
         print("[bench] serving mix", file=sys.stderr, flush=True)
         log = lambda m: print(m, file=sys.stderr, flush=True)
+        serve_checks = []
         result["serving"] = {
-            "mix": serve_bench(F, torch, synth.serving_arrays(), seconds=args.serve_seconds, log=log),
+            "mix": serve_bench(F, torch, synth.serving_arrays(), seconds=args.serve_seconds, log=log,
+                               checks=serve_checks),
+            "mix_fp16_split": serve_bench(F, torch, synth.serving_arrays(),
+                                          seconds=args.serve_seconds, precision="fp16_split",
+                                          log=log, checks=serve_checks),
             "ula256_stream": serve_bench(F, torch, [cfg], seconds=args.serve_seconds, loads=(0.8,),
                                          log=log),
             "what": "continuous-batching server (4 streams, up to 16 blocks of one plan per launch); "
-                    "latency = completion - submission",
+                    "inputs: block 0 of each array's synthetic scene; latency = completion - "
+                    "submission; mean_batch = blocks per launch seen by the completed requests; "
+                    "mix_fp16_split: the same mix with stage 1a as float16 split products on the "
+                    "matrix cores",
         }
+    large_first = {}
+    if not args.no_large:
+        print("[bench] planar array and 1024-element line", file=sys.stderr, flush=True)
+        result["large"], large_first = large_bench(F, torch, log=lambda m: print(m, file=sys.stderr,
+                                                                                flush=True))
     fp32_0 = beams[0].cpu().numpy()
     if not args.no_cpu:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
@@ -868,6 +989,20 @@ def main():
               file=sys.stderr, flush=True)
         for check in oracle_checks:
             check()
+        if "serving" in result:
+            result["serving"]["accuracy_vs_oracle"] = {
+                "arrays": serve_accuracy(serve_checks),
+                "sample": "block 0 of the largest array and of the lowest and highest fractional "
+                          "bandwidth in the mix, 6 beams, against the FP64 FBST oracle"}
+        if not args.no_fbst64:
+            print("[bench] timing the FP64 FBST oracle on every workload", file=sys.stderr, flush=True)
+            result["cpu_baseline"]["fbst64"], ref64 = fbst64_baseline()
+            for key, (name, got) in large_first.items():
+                ref = ref64[name]
+                result["large"][key]["rel_l2_vs_oracle"] = float(
+                    np.linalg.norm(got - ref) / np.linalg.norm(ref))
+                result["large"][key]["per_beam_max_vs_oracle"] = float(
+                    (np.linalg.norm(got - ref, axis=1) / np.linalg.norm(ref, axis=1)).max())
     if variants:
         result["variants"] = {k: {kk: vv for kk, vv in v.items() if kk != "beams0"}
                               for k, v in variants.items()}

@@ -513,7 +513,11 @@ fbst_status fbst_server_create(const fbst_server_options* options, fbst_server**
 
 /* Queue one block: x [M][N] -> beams [B][N] of plan (layouts as fbst_execute).
  * Returns at once; x and beams must stay valid, and beams untouched, until the
- * request's completion has been polled.  The plan must outlive its requests. */
+ * request's completion has been polled.  The plan must outlive its requests.
+ * x must already hold its data when this is called: the server's streams do
+ * not wait on the caller's streams, so device work that writes x (on any
+ * stream) must have completed (e.g. hipStreamSynchronize of the producing
+ * stream) before the submit. */
 fbst_status fbst_server_submit(fbst_server* server, const fbst_plan* plan, const void* x,
                                void* beams, unsigned long long tag);
 

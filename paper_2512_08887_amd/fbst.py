@@ -757,7 +757,13 @@ class Server:
     def __init__(self, workspace_bytes=1 << 30, streams=4, max_batch=16, device=-1):
         self.handle = fbst_server_create(fbst_server_options(workspace_bytes, streams, max_batch, device))
 
-    def submit(self, plan, x, beams, tag):
+    def submit(self, plan, x, beams, tag, sync=True):
+        """Queue x -> beams.  The server's streams do not wait on torch's: with
+        sync (default) the current stream is synchronised first, so x holds
+        what was last written to it; pass sync=False when x is known ready."""
+        if sync:
+            import torch
+            torch.cuda.current_stream().synchronize()
         fbst_server_submit(self.handle, plan.handle, x.data_ptr(), beams.data_ptr(), tag)
 
     def poll(self, max_n=256):

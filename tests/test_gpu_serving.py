@@ -135,3 +135,65 @@ def test_mix_with_nonuniform_plans():
         alone = plans[k].execute(x)
         torch.cuda.synchronize()
         assert torch.equal(alone, out)
+
+
+def _serving_cfg(name, M, N, fb, n_sources, index):
+    return synth.Config(name, "ula", M=M, N=N, B=M, fb=fb, n_sources=n_sources,
+                        power_db_range=0.0, sigma2=0.1, index=index)
+
+
+def test_served_blocks_match_the_oracle():
+    """Blocks served in a mix of serving-mix shapes (the largest, M = 512 with
+    N = 4096, at fractional bandwidths 0.2 and 0.8; and two smaller arrays),
+    float32 plans and one float16-split plan, against the FP64 oracle
+    (oracle.fbst64, pinned to the Cholesky oracle) on sampled beams of each
+    plan's synthetic scene block: aggregate relative L2 <= 1e-5 (float32) and
+    <= 1e-3 (float16 split), each beam <= 1e-4 (float32)."""
+    need_gpu()
+    from oracle import fbst64 as fb
+    from tests.helpers import oracle_problem
+    specs = [("s512n4096fb02", 512, 4096, 0.2, 3, 31, "fp32"),
+             ("s512n4096fb08", 512, 4096, 0.8, 5, 32, "fp32"),
+             ("s64n512fb05", 64, 512, 0.5, 8, 33, "fp32"),
+             ("s128n2048fb035", 128, 2048, 0.35, 1, 34, "fp32"),
+             ("s256n1024fb06h", 256, 1024, 0.6, 4, 35, "fp16_split")]
+    cfgs = [_serving_cfg(n, M, N, f, k, i) for n, M, N, f, k, i, _ in specs]
+    plans = [F.plan_for_config(c, precision=pr) for c, (*_, pr) in zip(cfgs, specs)]
+    blocks = [c.scene().block(0).astype(np.complex64) for c in cfgs]
+    rng = np.random.default_rng(7)
+    reqs = []                                   # (plan index, x, out); block 0 of each plan first
+    for k, (c, y) in enumerate(zip(cfgs, blocks)):
+        reqs.append((k, torch.from_numpy(y).cuda(),
+                     torch.empty((c.B, c.N), dtype=torch.complex64, device="cuda")))
+    for _ in range(20):                          # more traffic around them
+        k = int(rng.integers(0, len(cfgs)))
+        c = cfgs[k]
+        reqs.append((k, torch.from_numpy(crandn(rng, c.M, c.N)).to(torch.complex64).cuda(),
+                     torch.empty((c.B, c.N), dtype=torch.complex64, device="cuda")))
+    order = rng.permutation(len(reqs))
+    torch.cuda.synchronize()
+    srv = F.Server(workspace_bytes=1 << 30, streams=4, max_batch=8)
+    for tag in order:
+        k, x, out = reqs[tag]
+        srv.submit(plans[k], x, out, int(tag), sync=False)
+    srv.drain(timeout_s=120)
+    comps = srv.poll(1000)
+    srv.close()
+    assert sorted(c.tag for c in comps) == list(range(len(reqs)))
+    assert all(c.status == F.FBST_OK for c in comps)
+    torch.cuda.synchronize()
+    for k, (c, y) in enumerate(zip(cfgs, blocks)):
+        prec = specs[k][-1]
+        p = oracle_problem(c, c.delta_noise)
+        idx = np.unique(np.r_[0, c.B - 1, c.B // 2, rng.choice(c.B, 5, replace=False)])
+        ref = fb.beams(y.astype(np.complex128), p, beam_idx=idx)
+        got = reqs[k][2].cpu().numpy()[idx]
+        agg = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        per = (np.linalg.norm(got - ref, axis=1) / np.linalg.norm(ref, axis=1)).max()
+        print(f"served {c.name} ({prec}): aggregate {agg:.2e}, per-beam max {per:.2e}", flush=True)
+        if prec == "fp32":
+            assert agg < 1e-5 and per < 1e-4
+        else:
+            assert agg < 1e-3
+    for p in plans:
+        p.close()
