@@ -120,12 +120,15 @@ def large_bench(F, torch, *, steps=5, log=print):
     bfloat16 / float16 split stage 1a; blocks of one step in one launch.
     Returns the results and block 0's beams of each (for the oracle check)."""
     import synth
-    runs = [("ura32", "fp32", 8), ("ula1024", "fp32", 4), ("ula1024", "bf16_split", 4),
-            ("ula1024", "fp16_split", 4)]
+    runs = [("ura32", "fp32", 8), ("ura32", "fp32_refine", 8), ("ula1024", "fp32", 4),
+            ("ula1024", "bf16_split", 4), ("ula1024", "fp16_split", 4)]
     out, first = {}, {}
     for name, prec, nb in runs:
         c = synth.config(name)
-        plan = F.plan_for_config(c, precision=prec)
+        if prec == "fp32_refine":
+            plan = F.plan_for_config(c, precision="fp32", flags=F.FBST_FLAG_STAGE2_REFINE)
+        else:
+            plan = F.plan_for_config(c, precision=prec)
         y = np.stack([c.scene().block(k) for k in range(nb)]).astype(np.complex64)
         x = torch.from_numpy(y).cuda()
         ws = plan.workspace(nb)
@@ -901,8 +904,11 @@ def main():
     # the matrix-core split-precision stage 1a: same 64 blocks, same launches
     variants = {}
     if not args.no_variants:
-        for prec in ("bf16_split", "fp16_split"):
-            vp = F.plan_for_config(cfg, precision=prec)
+        for prec in ("bf16_split", "fp16_split", "fp32_refine"):
+            if prec == "fp32_refine":   # float32 with one refinement step of the stage-2 solve
+                vp = F.plan_for_config(cfg, precision="fp32", flags=F.FBST_FLAG_STAGE2_REFINE)
+            else:
+                vp = F.plan_for_config(cfg, precision=prec)
             vb = torch.empty_like(beams)
             vws = vp.workspace(chunk)
 

@@ -130,6 +130,21 @@ typedef struct {
                                          plan rebuilds when the beam set changes; the
                                          columns, refinement and spectra stay on the
                                          host.  Not with FBST_FLAG_HOST_ONLY. */
+#define FBST_FLAG_STAGE2_REFINE 64u /* float32 stage 2 with one step of iterative
+                                         refinement (Sec. V system A_b beta = w_b):
+                                         beta_1 by the Gohberg-Semencul apply, then
+                                         beta = beta_1 + A_b^{-1} (w_b - A_b beta_1), the
+                                         residual through the circulant embedding of A_b
+                                         (its first column, a plan table of B P3 complex
+                                         values).  The two Gohberg-Semencul terms can be
+                                         ~100x larger than beta and cancel, which float32
+                                         rounding of their FFTs turns into beam errors of a
+                                         few 1e-5; the refined solve removes that.  Costs
+                                         8 more P3-point transforms per beam (16 in all)
+                                         and B L complex64 of workspace per block.  Only
+                                         with a float32 stage 2 (FBST_PREC_FP32 and the
+                                         split precisions), not with FBST_FLAG_PRECOMPUTE
+                                         (otherwise FBST_E_UNSUPPORTED)                  */
 #define FBST_FLAG_NU_UNFUSED 16u      /* arbitrary positions: stage 1b with the
                                          oversampled grid through device memory (spread,
                                          then one FFT pass per axis) even where a fused
@@ -235,7 +250,9 @@ fbst_status fbst_execute_stream(const fbst_plan* plan, long long T, int hop, con
  *   stage 1 (space chirp-z, eq. DFT_1 / App. B): in Yhat -> out W [nb][B][L],
  *            W[b][l-1] = [F_b^H x]_l; a grid or an arbitrary array needs
  *            workspace of fbst_workspace_bytes(plan, nb) bytes (else may be NULL);
- *   stage 2 (Sec. V):                  in W -> out beams [nb][B][N].          */
+ *   stage 2 (Sec. V):                  in W -> out beams [nb][B][N]; a plan
+ *            with FBST_FLAG_STAGE2_REFINE needs workspace of
+ *            fbst_workspace_bytes(plan, nb) bytes (may be NULL when nb == 1). */
 fbst_status fbst_execute_stage(const fbst_plan* plan, int stage, int nblocks,
                                const void* in, void* out, void* workspace,
                                void* hip_stream);

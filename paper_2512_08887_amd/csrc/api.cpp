@@ -53,8 +53,15 @@ size_t z_elems(const fbst::Params& p) {
   return 0;
 }
 
+// Elements per block of the refined stage 2's first solution beta_1 [B][L]
+// (float32 stage 2 only, so the stage-1 element size is the stage-2 one).
+size_t refine_elems(const fbst::Params& p) {
+  return (p.flags & FBST_FLAG_STAGE2_REFINE) ? static_cast<size_t>(p.B) * p.L : 0;
+}
+
+// Workspace of one block: [yhat M L | w B L | z | beta_1] in the stage-1 type.
 size_t ws_per_block(const fbst::Params& p) {
-  const size_t elems = (static_cast<size_t>(p.M) + p.B) * p.L + z_elems(p);
+  const size_t elems = (static_cast<size_t>(p.M) + p.B) * p.L + z_elems(p) + refine_elems(p);
   return elems * s1_elem(p);
 }
 
@@ -137,6 +144,7 @@ fbst_status upload(fbst_plan* pl) {
                o_nucy = up.add(h.nu_cy, d1), o_nuo = up.add_ints(h.nu_order);
   const size_t o_G1 = up.add(h.G1, d2), o_G2 = up.add(h.G2, d2);
   const size_t o_pre3 = up.add(h.pre3, d2), o_H3 = up.add(h.H3, d2), o_post3 = up.add(h.post3, d2);
+  const size_t o_CA = up.add(h.CA, d2);
   const size_t tables = align_up(up.blob.size());
   const size_t total = tables + align_up(pl->ws_bytes_per_block);
 
@@ -188,6 +196,7 @@ fbst_status upload(fbst_plan* pl) {
   pl->pre3 = b + o_pre3;
   pl->H3 = b + o_H3;
   pl->post3 = b + o_post3;
+  if (p.flags & FBST_FLAG_STAGE2_REFINE) pl->CA = b + o_CA;
   pl->own_ws = b + tables;
   return FBST_OK;
 }
@@ -250,10 +259,15 @@ hipError_t run_stage1(const fbst_plan* pl, int nb, const void* yhat, void* w, vo
                                    p.bu, 1, p.L, nb, st);
 }
 
+// bt: room for beta_1 of nb blocks ([nb][B][L] complex64) when the plan
+// refines its stage 2, else unused.
 hipError_t run_stage2(const fbst_plan* pl, int nb, const void* w, const fbst::OutPtrs& outs,
-                      hipStream_t st) {
+                      void* bt, hipStream_t st) {
   const fbst::Params& p = pl->p;
   if (pl->K) return fbst::launch_precomputed_apply(pl->K, w, outs, p.B, p.L, p.N, nb, st);
+  if (pl->CA)
+    return fbst::launch_toeplitz_fu_refined(p.p3, w, outs, pl->G1, pl->G2, pl->pre3, pl->H3,
+                                            pl->post3, pl->tw2, pl->CA, bt, p.B, p.L, p.N, nb, st);
   switch (p.prec) {
     case FBST_PREC_FP64:
       return fbst::launch_toeplitz_fu<double, double, double>(p.p3, w, outs, pl->G1, pl->G2,
@@ -362,7 +376,8 @@ hipError_t run_blocks(const fbst_plan* pl, int nb, const InPtrs& xs, const OutPt
   if (e != hipSuccess) return e;
   e = d1 ? run_stage1<double>(pl, nb, yhat, w, z, st) : run_stage1<float>(pl, nb, yhat, w, z, st);
   if (e != hipSuccess) return e;
-  return run_stage2(pl, nb, w, outs, st);
+  void* bt = static_cast<unsigned char*>(z) + static_cast<size_t>(nb) * z_elems(p) * e1;
+  return run_stage2(pl, nb, w, outs, bt, st);
 }
 
 // Whole path for nb contiguous blocks, at most `chunk` (<= MAX_LAUNCH_BLOCKS) per launch.
@@ -435,7 +450,8 @@ hipError_t run_blocks_nulled(const fbst_plan* pl, const fbst_nulls* nl, int nb,
   c.nb = nb;
   e = fbst::launch_beam_product(c, st);
   if (e != hipSuccess) return e;
-  return run_stage2(pl, nb, wt, outs, st);
+  void* bt = static_cast<unsigned char*>(z) + static_cast<size_t>(nb) * z_elems(p) * 8;
+  return run_stage2(pl, nb, wt, outs, bt, st);
 }
 
 fbst_status check_exec(const fbst_plan* plan) {
@@ -758,6 +774,12 @@ fbst_status fbst_execute_stage(const fbst_plan* plan, int stage, int nblocks, co
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   const size_t e1 = s1_elem(p), eio = io_elem(p);
   hipError_t e = hipSuccess;
+  if (stage == 2 && plan->CA && !workspace) {
+    // the refined stage 2 keeps beta_1 in the workspace
+    if (nblocks != 1)
+      return fail(FBST_E_INVALID, "the refined stage 2 over several blocks needs a workspace");
+    workspace = plan->own_ws;
+  }
   if (stage == 1) {
     void* z = nullptr;
     if (p.kind != FBST_LINE) {
@@ -784,7 +806,7 @@ fbst_status fbst_execute_stage(const fbst_plan* plan, int stage, int nblocks, co
         for (int i = 0; i < n; ++i)
           outs.p[i] = static_cast<unsigned char*>(out) + static_cast<size_t>(b0 + i) * p.B * p.N * eio;
         const void* w = static_cast<const unsigned char*>(in) + static_cast<size_t>(b0) * p.B * p.L * e1;
-        e = run_stage2(plan, n, w, outs, st);
+        e = run_stage2(plan, n, w, outs, workspace, st);
       }
     }
   }

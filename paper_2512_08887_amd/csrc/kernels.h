@@ -87,6 +87,15 @@ hipError_t launch_toeplitz_fu(int P, const void* w, const OutPtrs& outs, const v
                               const void* G2, const void* pre3, const void* H3, const void* post3,
                               const void* tw, int B, int L, int N, int nblocks, hipStream_t st);
 
+// Stage 2 in float32 with one step of iterative refinement: beta_1 = A^{-1} w
+// by Gohberg-Semencul (stored to bt [nblocks][B][L]), then beta = beta_1 +
+// A^{-1} (w - A beta_1) with A applied through its circulant-embedding
+// spectrum CA [B][P] (already divided by P), then F_u; two launches.
+hipError_t launch_toeplitz_fu_refined(int P, const void* w, const OutPtrs& outs, const void* G1,
+                                      const void* G2, const void* pre3, const void* H3,
+                                      const void* post3, const void* tw, const void* CA, void* bt,
+                                      int B, int L, int N, int nblocks, hipStream_t st);
+
 // Per-group complex product over the blocks of a launch (complex64):
 //   out[blk][g][n] = sum_k K[k][g][n] in[blk][row(g)][k]        (g < NG, n < NO, k < KL)
 // row(g) = in_map[g] (a device array) if given, else 0 when in_rows == 1, else g;

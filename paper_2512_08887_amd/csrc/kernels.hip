@@ -820,12 +820,20 @@ constexpr bool k3_dual() {
   return FBST_K3_DUAL && sizeof(T) * 2 * lds_stride(P) * 2 * Shape<P>::G <= 160 * 1024;
 }
 
-template <typename T, typename TIN, typename TOUT, int P, int SN>
+// Stage 2 with one step of iterative refinement (MODE 1 then MODE 2, two
+// launches): the float32 Gohberg-Semencul apply loses accuracy where its two
+// terms, each much larger than beta, cancel; a second apply to the residual
+// r = w - A beta_1 (A by circulant embedding of its first column, CA =
+// FFT(c_0 .. c_{L-1}, 0 .., conj c_{L-1} .. conj c_1) / P) recovers it:
+//   MODE 0  beta = GS(w); beams = F_u beta                       (8 transforms)
+//   MODE 1  beta_1 = GS(w) stored to bt [rows][L]                (6 transforms)
+//   MODE 2  r = w - A beta_1; beta = beta_1 + GS(r); beams = F_u beta (10 transforms)
+template <typename T, typename TIN, typename TOUT, int P, int SN, int MODE = 0>
 __global__ __launch_bounds__(Shape<P>::THREADS) FBST_K3_ATTR void k_toeplitz_fu(
     const cx<TIN>* __restrict__ w, const OutPtrs outs, const cx<T>* __restrict__ G1,
     const cx<T>* __restrict__ G2, const cx<T>* __restrict__ pre3, const cx<T>* __restrict__ H3,
     const cx<T>* __restrict__ post3, const cx<T>* __restrict__ tw, int B, int L, int N,
-    int nblocks) {
+    int nblocks, cx<T>* __restrict__ bt = nullptr, const cx<T>* __restrict__ CA = nullptr) {
   using SH = Shape<P>;
   constexpr int SL = kE / 2;
   constexpr bool DUAL = k3_dual<T, P>();
@@ -845,10 +853,30 @@ __global__ __launch_bounds__(Shape<P>::THREADS) FBST_K3_ATTR void k_toeplitz_fu(
 
   cx<T> u1[kE], u2[kE];
   const cx<TIN>* src = w + row * L;                   // row of block 0, beam 0 when inactive
+  cx<T>* brow = bt + row * L;
+  if constexpr (MODE == 2) {
+    // r = w - A beta_1, A beta_1 = IFFT(CA FFT(beta_1)) (circulant embedding)
 #pragma unroll
-  for (int s = 0; s < kE; ++s) {
-    const int i = t + s * SH::TT;
-    u1[s] = (s < SL && active && i < L) ? cvt<T>(src[i]) : cx<T>{0, 0};
+    for (int s = 0; s < kE; ++s) {
+      const int i = t + s * SH::TT;
+      u1[s] = (s < SL && active && i < L) ? brow[i] : cx<T>{0, 0};
+    }
+    fft<T, P, kE, -1, SL, FBST_K3_TW>(u1, buf, tw, t);
+    with_tables<FBST_K3_GB, kE, SH::TT>(CA + static_cast<size_t>(b) * P + t,
+                                        static_cast<const cx<T>*>(nullptr),
+                                        [&](int s, cx<T> a, cx<T>) { u1[s] = cmul(u1[s], a); });
+    fft<T, P, kE, +1, kE, FBST_K3_TW>(u1, buf, tw, t);
+#pragma unroll
+    for (int s = 0; s < kE; ++s) {
+      const int i = t + s * SH::TT;
+      u1[s] = (s < SL && active && i < L) ? cvt<T>(src[i]) - u1[s] : cx<T>{0, 0};
+    }
+  } else {
+#pragma unroll
+    for (int s = 0; s < kE; ++s) {
+      const int i = t + s * SH::TT;
+      u1[s] = (s < SL && active && i < L) ? cvt<T>(src[i]) : cx<T>{0, 0};
+    }
   }
   fft<T, P, kE, -1, SL, FBST_K3_TW>(u1, buf, tw, t);
   with_tables<FBST_K3_GB, kE, SH::TT>(g1 + t, g2 + t, [&](int s, cx<T> a, cx<T> c) {
@@ -889,6 +917,21 @@ __global__ __launch_bounds__(Shape<P>::THREADS) FBST_K3_ATTR void k_toeplitz_fu(
   }
   // beta = trunc_L(IFFT(Z)), then the F_u chirp-z
   fft<T, P, kE, +1, kE, FBST_K3_TW>(u1, buf, tw, t);
+  if constexpr (MODE == 1) {
+#pragma unroll
+    for (int s = 0; s < SL; ++s) {
+      const int i = t + s * SH::TT;
+      if (active && i < L) brow[i] = u1[s];
+    }
+    return;
+  }
+  if constexpr (MODE == 2) {
+#pragma unroll
+    for (int s = 0; s < SL; ++s) {
+      const int i = t + s * SH::TT;
+      if (i < L) u1[s] = u1[s] + brow[active ? i : 0];
+    }
+  }
 #pragma unroll
   for (int s = 0; s < kE; ++s) {
     const int i = t + s * SH::TT;
@@ -1194,6 +1237,47 @@ hipError_t launch_axis_dft(int P, const void* in, void* out, const void* corr, c
     }                                                                                          \
     break;
     FBST_FOR_EACH_P(CASE)
+#undef CASE
+    default:
+      break;
+  }
+  return hipErrorInvalidValue;
+}
+
+// Stage 2 with one refinement step (float32): MODE 1 (beta_1 to bt) then
+// MODE 2 (residual, correction, F_u), both of one launch shape.
+hipError_t launch_toeplitz_fu_refined(int P, const void* w, const OutPtrs& outs, const void* G1,
+                                      const void* G2, const void* pre3, const void* H3,
+                                      const void* post3, const void* tw, const void* CA, void* bt,
+                                      int B, int L, int N, int nblocks, hipStream_t st) {
+  if (nblocks < 1 || nblocks > MAX_LAUNCH_BLOCKS || !CA || !bt) return hipErrorInvalidValue;
+  using T = float;
+  switch (P) {
+#define CASE(PP)                                                                               \
+  case PP: {                                                                                   \
+    if (2 * L > PP) return hipErrorInvalidValue;                                               \
+    const dim3 grid(grid_for<PP>(nblocks * B)), block(Shape<PP>::THREADS);                     \
+    const int sn = slots_for<PP>(N);                                                           \
+    const auto a = (const cx<T>*)w;                                                            \
+    const auto& o = outs;                                                                      \
+    const auto g1 = (const cx<T>*)G1, g2 = (const cx<T>*)G2, p3 = (const cx<T>*)pre3;          \
+    const auto h3 = (const cx<T>*)H3, q3 = (const cx<T>*)post3, twp = (const cx<T>*)tw;        \
+    const auto ca = (const cx<T>*)CA;                                                          \
+    const auto b1 = (cx<T>*)bt;                                                                \
+    hipLaunchKernelGGL((k_toeplitz_fu<T, T, T, PP, kE / 4, 1>), grid, block, 0, st, a, o, g1, g2, \
+                       p3, h3, q3, twp, B, L, N, nblocks, b1, ca);                             \
+    if (sn <= kE / 4)                                                                          \
+      hipLaunchKernelGGL((k_toeplitz_fu<T, T, T, PP, kE / 4, 2>), grid, block, 0, st, a, o, g1,  \
+                         g2, p3, h3, q3, twp, B, L, N, nblocks, b1, ca);                       \
+    else if (sn <= kE / 2)                                                                     \
+      hipLaunchKernelGGL((k_toeplitz_fu<T, T, T, PP, kE / 2, 2>), grid, block, 0, st, a, o, g1,  \
+                         g2, p3, h3, q3, twp, B, L, N, nblocks, b1, ca);                       \
+    else                                                                                       \
+      hipLaunchKernelGGL((k_toeplitz_fu<T, T, T, PP, kE, 2>), grid, block, 0, st, a, o, g1, g2,  \
+                         p3, h3, q3, twp, B, L, N, nblocks, b1, ca);                           \
+    return hipGetLastError();                                                                  \
+  }
+    CASE(256) CASE(512) CASE(1024) CASE(2048) CASE(4096) CASE(8192) CASE(16384)
 #undef CASE
     default:
       break;

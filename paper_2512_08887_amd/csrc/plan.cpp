@@ -661,6 +661,17 @@ fbst_status resolve_params(int M, int N, int B, const fbst_geometry* geom, const
       return FBST_E_UNSUPPORTED;
     }
   }
+  if (p.flags & FBST_FLAG_STAGE2_REFINE) {
+    if (p.prec == FBST_PREC_FP64 || p.prec == FBST_PREC_FP64_STAGE2) {
+      *msg = "FBST_FLAG_STAGE2_REFINE refines a float32 stage 2 (not FBST_PREC_FP64 or "
+             "FBST_PREC_FP64_STAGE2)";
+      return FBST_E_UNSUPPORTED;
+    }
+    if (p.flags & FBST_FLAG_PRECOMPUTE) {
+      *msg = "FBST_FLAG_STAGE2_REFINE and FBST_FLAG_PRECOMPUTE exclude each other";
+      return FBST_E_UNSUPPORTED;
+    }
+  }
   if (p.flags & FBST_FLAG_PRECOMPUTE) {
     if (p.prec == FBST_PREC_FP64) {
       *msg = "the precomputed stage 2 takes complex64 data (any precision but FBST_PREC_FP64)";
@@ -741,6 +752,17 @@ void finish_beam(const Params& p, int b, const zd* col, std::vector<zd>* xv, boo
   for (int i = 1; i < L; ++i) buf[i] = std::conj(x[L - i]);
   fft64(buf.data(), P3, -1);
   for (int i = 0; i < P3; ++i) t->G2[static_cast<size_t>(b) * P3 + i] = buf[i] * scale;
+  if (p.flags & FBST_FLAG_STAGE2_REFINE) {
+    // A_b as a circulant of P3 points: first column c_0 .. c_{L-1}, zeros, then
+    // conj(c_{L-1}) .. conj(c_1) (A_b Hermitian), so A_b v = first L of the
+    // circular convolution with v zero-padded; spectrum divided by P3 for the
+    // unscaled inverse transform of the kernel
+    std::fill(buf.begin(), buf.end(), zd());
+    for (int i = 0; i < L; ++i) buf[i] = col[i];
+    for (int i = 1; i < L; ++i) buf[P3 - i] = std::conj(col[i]);
+    fft64(buf.data(), P3, -1);
+    for (int i = 0; i < P3; ++i) t->CA[static_cast<size_t>(b) * P3 + i] = buf[i] / static_cast<double>(P3);
+  }
 }
 
 }  // namespace
@@ -823,6 +845,7 @@ fbst_status build_tables(const Params& p, bool keep_gram_gen, HostTables* t, std
   const int P3 = p.p3;
   t->G1.assign(static_cast<size_t>(B) * P3, zd());
   t->G2.assign(static_cast<size_t>(B) * P3, zd());
+  if (p.flags & FBST_FLAG_STAGE2_REFINE) t->CA.assign(static_cast<size_t>(B) * P3, zd());
   if (keep_gram_gen) {
     t->gram.assign(static_cast<size_t>(B) * L, zd());
     t->gen.assign(static_cast<size_t>(B) * L, zd());

@@ -27,6 +27,8 @@ struct HostTables {
   std::vector<zd> H1a, H1b;               // split-output stage 1a: [P1s] per output half
   AxisTables ax, ay;                      // stage 1b (ay unused for a line)
   std::vector<zd> G1, G2;                 // stage 2: [B][P3] spectra of x_b and y~_b
+  std::vector<zd> CA;                     // FBST_FLAG_STAGE2_REFINE: [B][P3] spectrum of the
+                                          // circulant embedding of A_b, divided by P3
   std::vector<zd> pre3, H3, post3;        // F_u chirp-z: [L], [P3], [N]
   std::vector<double> u, v;               // beam direction cosines [B]
   std::vector<zd> gram, gen;              // [B][L] (kept on request)
@@ -215,6 +217,7 @@ struct fbst_plan {
   const void *axp = nullptr, *axH = nullptr, *axq = nullptr;
   const void *ayp = nullptr, *ayH = nullptr, *ayq = nullptr;
   const void *G1 = nullptr, *G2 = nullptr, *pre3 = nullptr, *H3 = nullptr, *post3 = nullptr;
+  const void* CA = nullptr;        // FBST_FLAG_STAGE2_REFINE only
   // non-uniform stage 1b (arbitrary positions)
   const void *nu_pre = nullptr, *nu_posx = nullptr, *nu_posy = nullptr, *nu_cx = nullptr,
              *nu_cy = nullptr;

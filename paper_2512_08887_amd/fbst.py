@@ -24,6 +24,7 @@ FBST_PREC_FP32, FBST_PREC_FP64_STAGE2, FBST_PREC_FP64, FBST_PREC_BF16_SPLIT, FBS
 FBST_FLAG_HOST_ONLY, FBST_FLAG_KEEP_HOST_TABLES, FBST_FLAG_NO_SPLIT, FBST_FLAG_PRECOMPUTE = 1, 2, 4, 8
 FBST_FLAG_NU_UNFUSED = 16
 FBST_FLAG_DEVICE_GENERATORS = 32
+FBST_FLAG_STAGE2_REFINE = 64
 FBST_TABLE_BEAM_U, FBST_TABLE_BEAM_V, FBST_TABLE_GRAM, FBST_TABLE_GENERATOR = 0, 1, 2, 3
 MAX_LAUNCH_BLOCKS = 256  # FBST_MAX_LAUNCH_BLOCKS: blocks per kernel launch (pointers in the kernel arguments)
 

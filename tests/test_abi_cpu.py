@@ -421,3 +421,29 @@ def test_null_options_default_is_float64():
             F.fbst_destroy(hnd)
     else:
         assert st == F.FBST_E_DEVICE, (st, F.fbst_last_error())
+
+
+def test_stage2_refine_flag():
+    """FBST_FLAG_STAGE2_REFINE: accepted with a float32 stage 2 (its workspace
+    grows by beta_1, B L complex64 per block); refused with a float64 stage 2
+    and with the precomputed stage 2."""
+    band = F.make_band(2.0, 0.5, 1.0)
+    M, N, B = 16, 64, 12
+    delta = 0.1 * 2 * N
+    host = F.FBST_FLAG_HOST_ONLY
+    base = F.fbst_plan_create(M, N, B, None, band, None, F.make_options(delta, flags=host))
+    ref = F.fbst_plan_create(M, N, B, None, band, None,
+                             F.make_options(delta, flags=host | F.FBST_FLAG_STAGE2_REFINE))
+    try:
+        w0 = F.fbst_plan_info(base).workspace_per_block
+        w1 = F.fbst_plan_info(ref).workspace_per_block
+        assert w1 - w0 == B * 2 * N * 8, (w0, w1)
+    finally:
+        F.fbst_destroy(base)
+        F.fbst_destroy(ref)
+    for prec, extra in (("fp64_stage2", 0), ("fp64", 0), ("fp32", F.FBST_FLAG_PRECOMPUTE)):
+        st, h = F.fbst_plan_create_status(M, N, B, None, band, None,
+                                          F.make_options(delta, precision=prec,
+                                                         flags=host | extra | F.FBST_FLAG_STAGE2_REFINE))
+        assert st == F.FBST_E_UNSUPPORTED and h is None, (prec, st)
+        assert "REFINE" in F.fbst_last_error()

@@ -247,3 +247,30 @@ def test_split_stage1a_fp64():
     e = rel(yhat[0].cpu().numpy(), od.stage1a(y, p))
     print(f"fp64 split stage 1a rel err {e:.2e}")
     assert e < 1e-12
+
+
+@pytest.mark.parametrize("shape", [(16, 256, 16), (12, 100, 9), (7, 64, 20)])
+def test_refined_stage2_small(shape):
+    """FBST_FLAG_STAGE2_REFINE on small lines (ragged sizes, odd B, B > M)
+    against the oracle of record, also through fbst_execute_stage, batched
+    over three blocks in two launches and bit-identical to one block alone."""
+    need_gpu()
+    M, N, B = shape
+    delta = 0.1 * 2 * N
+    plan = F.Plan(M, N, B, band=F.make_band(2.0, 0.5, 1.0),
+                  options=F.make_options(delta, flags=F.FBST_FLAG_STAGE2_REFINE))
+    p = od.line_problem(M, N, B, fc=2.0, delta=delta)
+    rng = np.random.default_rng(70 + M)
+    y = (rng.standard_normal((3, M, N)) + 1j * rng.standard_normal((3, M, N))).astype(np.complex64)
+    x = torch.from_numpy(y).cuda()
+    out = plan.execute_batched(x, max_chunk=2).cpu().numpy()
+    one = plan.execute(x[1]).cpu().numpy()
+    ws = plan.workspace(3)
+    st2 = plan.stage(2, plan.stage(1, plan.stage(0, x, nblocks=3), nblocks=3), nblocks=3,
+                     workspace=ws).cpu().numpy()
+    e = max(rel(out[k], od.beams(y[k].astype(np.complex128), p)) for k in range(3))
+    print(f"refined stage 2 {shape}: rel err {e:.2e}")
+    assert e < 1e-5
+    assert np.array_equal(out[1], one)
+    assert np.array_equal(st2, out)
+    plan.close()
