@@ -264,7 +264,8 @@ def sq_summary(pmc_dirs, kernels=("k_toeplitz_fu", "k_time_czt", "k_axis_czt")):
 
 
 # Sources whose change invalidates stored HBM counter readings of the kernels.
-KERNEL_SOURCES = ["cx.h", "fft_lds.h", "kernels.h", "kernels.hip", "mfma_czt.hip", "precompute.hip"]
+KERNEL_SOURCES = ["cx.h", "fft_lds.h", "kernel_common.h", "kernels.h", "kernels.hip", "stage2.hip",
+                  "mfma_czt.hip", "precompute.hip"]
 COUNTERS_JSON = os.path.join(ROOT, "profiles", "hbm_counters_ula256.json")
 
 
@@ -760,13 +761,27 @@ def main():
 
     x = torch.from_numpy(ys).to(torch.complex64).cuda()
     beams = torch.empty((nblk, cfg.B, cfg.N), dtype=torch.complex64, device="cuda")
-    tuned_chunk = tuned_ms = None
+    tuned_chunk = tuned_ms = tuned_var = None
+    untuned = None
     if args.chunk < 0:
         tune_ws = plan.workspace(min(nblk, F.MAX_LAUNCH_BLOCKS))
-        tuned_chunk, tuned_ms = plan.autotune(x, beams=beams, workspace=tune_ws)
+        # the untuned configuration for comparison: the plan's default stage-2
+        # variant at 16 blocks per launch
+        u_var, u_chunk = plan.variant, min(16, nblk)
+        plan.execute_batched(x, beams=beams, workspace=tune_ws, max_chunk=u_chunk)
+        ua, ub = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ua.record()
+        for _ in range(5):
+            plan.execute_batched(x, beams=beams, workspace=tune_ws, max_chunk=u_chunk)
+        ub.record()
+        torch.cuda.synchronize()
+        untuned = {"blocks_per_launch": u_chunk, "k3_variant": u_var,
+                   "ms_per_step": ua.elapsed_time(ub) / 5}
+        tuned_chunk, tuned_var, tuned_ms = plan.autotune_ex(x, beams=beams, workspace=tune_ws)
         del tune_ws
         chunk = tuned_chunk
-        print(f"[bench] autotuned blocks per launch: {chunk} ({tuned_ms:.3f} ms per 64 blocks)",
+        print(f"[bench] autotuned: {chunk} blocks per launch, stage-2 variant {tuned_var} "
+              f"({tuned_ms:.3f} ms per 64 blocks; untuned {untuned['ms_per_step']:.3f} ms)",
               file=sys.stderr, flush=True)
     else:
         chunk = nblk if args.chunk == 0 else min(args.chunk, nblk)
@@ -860,7 +875,9 @@ def main():
     gall.close()
     if tuned_chunk is None:
         tune_ws = plan.workspace(min(nblk, F.MAX_LAUNCH_BLOCKS))
-        tuned_chunk, tuned_ms = plan.autotune(x, beams=gb, workspace=tune_ws)
+        fixed_var = plan.variant
+        tuned_chunk, tuned_var, tuned_ms = plan.autotune_ex(x, beams=gb, workspace=tune_ws)
+        plan.variant = fixed_var       # the timed run above used the plan's own variant
         del tune_ws
     del gb
     print(f"[bench] graph step {graph_ms:.3f} ms; autotune chunk {tuned_chunk} ({tuned_ms:.3f} ms)",
@@ -890,14 +907,21 @@ def main():
         "graph": {"latency_ms": {"p50": float(np.percentile(glat, 50)), "p99": float(np.percentile(glat, 99))},
                   "ms_per_step": graph_ms,
                   "what": "the single block and the 64-block step replayed from captured HIP graphs"},
-        "autotune": {"blocks_per_launch": tuned_chunk, "ms_per_step": tuned_ms},
+        "autotune": {"blocks_per_launch": tuned_chunk, "k3_variant": tuned_var,
+                     "ms_per_step": tuned_ms, "untuned": untuned,
+                     "gain": (untuned["ms_per_step"] / tuned_ms) if untuned else None,
+                     "what": "fbst_autotune_ex over blocks per launch x stage-2 kernel variant "
+                             "(bit 0 single-buffer form, bit 1 persistent grid, 4 three waves per "
+                             "SIMD); untuned = the plan's default variant at 16 blocks per launch"},
         "stage_gflop_per_block": [s0 / 1e9, s1 / 1e9, s2 / 1e9],
         "path_tflops": (s0 + s1 + s2) * nblk / (ms_step / 1e3) / 1e12,
         "roofline": {"kernel": "k_toeplitz_fu (stage 2: Gohberg-Semencul apply + F_u chirp-z)",
                      "bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32,
-                     "traffic": stored_traffic("k_toeplitz_fu<float, float, float, 4096, 4>",
-                                               chunk * cfg.B * 256),
+                     "traffic": stored_traffic(
+                         f"k_toeplitz_fu<float, float, float, 4096, 4, 0, {plan.variant}>",
+                         chunk * cfg.B * 256),
+                     "k3_variant": plan.variant,
                      "avg_launch_ms": k3_ms,
                      "flops_per_launch": k3_flops_launch},
     }

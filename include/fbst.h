@@ -283,6 +283,44 @@ fbst_status fbst_autotune(const fbst_plan* plan, int nblocks, const void* x, voi
                           void* workspace, void* hip_stream, int force, int* best_chunk,
                           float* best_ms);
 
+/* Compiled instances of the stage-2 kernel a plan can launch (variant bits).
+ * FBST_VARIANT_K3_PERSISTENT leaves the beams bit-identical;
+ * FBST_VARIANT_K3_SINGLE changes them at the level of float32 rounding (the
+ * two branches' products are combined in another rounding order):
+ *   FBST_VARIANT_K3_SINGLE      the two Gohberg-Semencul branches in sequence in
+ *                               one LDS buffer, instead of as one dual transform
+ *                               in two buffers;
+ *   FBST_VARIANT_K3_PERSISTENT  a persistent grid: as many workgroups as are
+ *                               resident at once, each working through a
+ *                               contiguous range of (block, beam) rows, instead
+ *                               of one workgroup per row group.
+ * Variants 1, 2, 3 and 5 exist for a float32 stage 2 (FBST_PREC_FP32 and the
+ * split precisions) at P3 >= 1024, without FBST_FLAG_PRECOMPUTE or
+ * FBST_FLAG_STAGE2_REFINE; such plans start with FBST_VARIANT_K3_SINGLE, the
+ * others with 0. */
+#define FBST_VARIANT_K3_SINGLE 1
+#define FBST_VARIANT_K3_PERSISTENT 2
+#define FBST_VARIANT_K3_WAVES3 4   /* with FBST_VARIANT_K3_SINGLE only: registers
+                                      allocated for 3 waves per SIMD (spills)    */
+
+/* As fbst_autotune, also over the stage-2 variants this plan can launch
+ * (chunk x variant), and leaves the fastest variant set on the plan (the only
+ * state a plan changes after creation; results stay within float32 rounding
+ * of the untuned plan's).  The
+ * cache key is (device architecture, M, N, B, L, geometry and beam-grid
+ * shape, precision, flags, nblocks).  best_variant may be NULL. */
+fbst_status fbst_autotune_ex(const fbst_plan* plan, int nblocks, const void* x, void* beams,
+                             void* workspace, void* hip_stream, int force, int* best_chunk,
+                             int* best_variant, float* best_ms);
+
+/* Select the stage-2 variant (FBST_E_UNSUPPORTED when it is not compiled
+ * for this plan); takes effect for launches issued afterwards.  Not to be
+ * called while another thread issues launches of the plan. */
+fbst_status fbst_plan_set_variant(const fbst_plan* plan, int variant);
+
+/* The plan's stage-2 variant (-1 on a NULL plan). */
+int fbst_plan_variant(const fbst_plan* plan);
+
 /* ---- Beamspace interference nulling (Sec. VIII, eq. interfer_beam_space) -- */
 typedef struct fbst_nulls fbst_nulls;
 

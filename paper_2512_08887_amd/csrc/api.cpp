@@ -39,6 +39,10 @@ bool stage2_double(const fbst::Params& p) {
   return p.prec == FBST_PREC_FP64 || p.prec == FBST_PREC_FP64_STAGE2;
 }
 size_t s1_elem(const fbst::Params& p) { return stage1_double(p) ? 16 : 8; }
+bool fp32_stage2(const fbst::Params& p) {
+  return p.prec == FBST_PREC_FP32 || p.prec == FBST_PREC_BF16_SPLIT ||
+         p.prec == FBST_PREC_FP16_SPLIT;
+}
 size_t s2_elem(const fbst::Params& p) { return stage2_double(p) ? 16 : 8; }
 
 // Elements per block of stage 1b's scratch z: a grid's x-axis output
@@ -280,7 +284,8 @@ hipError_t run_stage2(const fbst_plan* pl, int nb, const void* w, const fbst::Ou
     default:
       return fbst::launch_toeplitz_fu<float, float, float>(p.p3, w, outs, pl->G1, pl->G2,
                                                            pl->pre3, pl->H3, pl->post3, pl->tw2,
-                                                           p.B, p.L, p.N, nb, st);
+                                                           p.B, p.L, p.N, nb, st,
+                                                           pl->k3_variant.load(std::memory_order_relaxed));
   }
 }
 
@@ -653,6 +658,12 @@ fbst_status fbst_plan_create(int M, int N, int B, const fbst_geometry* geometry,
   pl->host_only = (p.flags & FBST_FLAG_HOST_ONLY) != 0;
   pl->kept = pl->host_only || (p.flags & FBST_FLAG_KEEP_HOST_TABLES) != 0;
   pl->ws_bytes_per_block = ws_per_block(p);
+  // stage 2 in the single-buffer form where it is compiled: at the same two
+  // waves per SIMD it needs fewer registers than the dual form and runs
+  // faster (fbst_autotune_ex measures all instances)
+  if (!(p.flags & (FBST_FLAG_PRECOMPUTE | FBST_FLAG_STAGE2_REFINE)) &&
+      fbst::k3_variant_available(p.p3, fp32_stage2(p), 1))
+    pl->k3_variant.store(1);
   try {
     st = fbst::build_tables(p, pl->kept, &pl->host, &msg);
   } catch (const std::bad_alloc&) {
@@ -870,24 +881,71 @@ void fbst_graph_destroy(fbst_graph* graph) {
   delete graph;
 }
 
-fbst_status fbst_autotune(const fbst_plan* plan, int nblocks, const void* x, void* beams,
-                          void* workspace, void* hip_stream, int force, int* best_chunk,
-                          float* best_ms) {
+}  // extern "C"
+
+namespace {
+
+std::string device_arch(int device) {
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return "unknown";
+  return prop.gcnArchName;
+}
+
+// Stage-2 variants the plan can launch (the refined and precomputed forms
+// have one instance each).
+std::vector<int> plan_variants(const fbst_plan* plan) {
+  std::vector<int> v{0};
+  const fbst::Params& p = plan->p;
+  if (plan->K || plan->CA) return v;
+  for (int var = 1; var <= 7; ++var)
+    if (fbst::k3_variant_available(p.p3, fp32_stage2(p), var)) v.push_back(var);
+  return v;
+}
+
+}  // namespace
+
+extern "C" {
+
+fbst_status fbst_plan_set_variant(const fbst_plan* plan, int variant) {
+  fbst_status s = check_exec(plan);
+  if (s != FBST_OK) return s;
+  const std::vector<int> ok = plan_variants(plan);
+  if (std::find(ok.begin(), ok.end(), variant) == ok.end())
+    return fail(FBST_E_UNSUPPORTED, "stage-2 variant " + std::to_string(variant) +
+                                        " is not compiled for this plan");
+  const_cast<fbst_plan*>(plan)->k3_variant.store(variant);
+  return FBST_OK;
+}
+
+int fbst_plan_variant(const fbst_plan* plan) { return plan ? plan->k3_variant.load() : -1; }
+
+fbst_status fbst_autotune_ex(const fbst_plan* plan, int nblocks, const void* x, void* beams,
+                             void* workspace, void* hip_stream, int force, int* best_chunk,
+                             int* best_variant, float* best_ms) {
   fbst_status s = check_exec(plan);
   if (s != FBST_OK) return s;
   if (nblocks < 1 || !x || !beams || !workspace || !best_chunk)
     return fail(FBST_E_INVALID, "nblocks >= 1, x, beams, workspace and best_chunk are required");
   const fbst::Params& p = plan->p;
-  const auto key = std::make_tuple(p.M, p.N, p.B, p.L, p.mx * 65536 + p.my, p.bu * 65536 + p.bv,
-                                   static_cast<int>(p.prec), nblocks);
+  const auto key = std::make_tuple(device_arch(plan->device), p.M, p.N, p.B, p.L,
+                                   p.mx * 65536 + p.my, p.bu * 65536 + p.bv,
+                                   static_cast<int>(p.prec), static_cast<int>(p.flags), nblocks,
+                                   static_cast<int>(p.kind));
+  struct Tuned {
+    int chunk, variant;
+    float ms;
+  };
   static std::mutex mu;
-  static std::map<decltype(key), std::pair<int, float>> cache;
+  static std::map<decltype(key), Tuned> cache;
+  fbst_plan* pl = const_cast<fbst_plan*>(plan);
   if (!force) {
     std::lock_guard<std::mutex> lk(mu);
     auto it = cache.find(key);
     if (it != cache.end()) {
-      *best_chunk = it->second.first;
-      if (best_ms) *best_ms = it->second.second;
+      pl->k3_variant.store(it->second.variant);
+      *best_chunk = it->second.chunk;
+      if (best_variant) *best_variant = it->second.variant;
+      if (best_ms) *best_ms = it->second.ms;
       return FBST_OK;
     }
   }
@@ -895,36 +953,49 @@ fbst_status fbst_autotune(const fbst_plan* plan, int nblocks, const void* x, voi
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
-  int best = 0;
-  float bms = 0.0f;
-  for (int chunk = 1; e == hipSuccess && chunk <= std::min(nblocks, fbst::MAX_LAUNCH_BLOCKS); chunk *= 2) {
-    e = fbst::run_contiguous(plan, nblocks, chunk, x, beams, workspace, st);   // warm-up
-    float acc = 0.0f;
-    for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
-      e = hipEventRecord(e0, st);
-      if (e == hipSuccess) e = fbst::run_contiguous(plan, nblocks, chunk, x, beams, workspace, st);
-      if (e == hipSuccess) e = hipEventRecord(e1, st);
-      if (e == hipSuccess) e = hipEventSynchronize(e1);
-      float ms = 0.0f;
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-      acc += ms;
-    }
-    const float ms = acc / 3.0f;
-    if (e == hipSuccess && (best == 0 || ms < bms)) {
-      best = chunk;
-      bms = ms;
+  const int before = pl->k3_variant.load();
+  Tuned best{0, 0, 0.0f};
+  for (int var : plan_variants(plan)) {
+    pl->k3_variant.store(var);
+    for (int chunk = 1; e == hipSuccess && chunk <= std::min(nblocks, fbst::MAX_LAUNCH_BLOCKS);
+         chunk *= 2) {
+      e = fbst::run_contiguous(plan, nblocks, chunk, x, beams, workspace, st);   // warm-up
+      float acc = 0.0f;
+      for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+        e = hipEventRecord(e0, st);
+        if (e == hipSuccess) e = fbst::run_contiguous(plan, nblocks, chunk, x, beams, workspace, st);
+        if (e == hipSuccess) e = hipEventRecord(e1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        acc += ms;
+      }
+      const float ms = acc / 3.0f;
+      if (e == hipSuccess && (best.chunk == 0 || ms < best.ms)) best = {chunk, var, ms};
     }
   }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
-  if (e != hipSuccess) return hip_fail(e, "fbst_autotune");
+  if (e != hipSuccess) {
+    pl->k3_variant.store(before);
+    return hip_fail(e, "fbst_autotune");
+  }
+  pl->k3_variant.store(best.variant);
   {
     std::lock_guard<std::mutex> lk(mu);
-    cache[key] = {best, bms};
+    cache[key] = best;
   }
-  *best_chunk = best;
-  if (best_ms) *best_ms = bms;
+  *best_chunk = best.chunk;
+  if (best_variant) *best_variant = best.variant;
+  if (best_ms) *best_ms = best.ms;
   return FBST_OK;
+}
+
+fbst_status fbst_autotune(const fbst_plan* plan, int nblocks, const void* x, void* beams,
+                          void* workspace, void* hip_stream, int force, int* best_chunk,
+                          float* best_ms) {
+  return fbst_autotune_ex(plan, nblocks, x, beams, workspace, hip_stream, force, best_chunk,
+                          nullptr, best_ms);
 }
 
 fbst_status fbst_nulls_create(const fbst_plan* plan, int n_interferers, const int* beams,
@@ -970,6 +1041,8 @@ fbst_status fbst_nulls_create_interp(const fbst_plan* plan, int n_interferers, c
       return fail(FBST_E_INVALID, "interferer directions must be finite");
   return make_nulls(plan, n_interferers, nullptr, u, v, true, out);
 }
+
+}  // extern "C"
 
 namespace {
 
@@ -1036,6 +1109,8 @@ fbst_status make_directions(const fbst_plan* plan, int n_directions, const doubl
 }
 
 }  // namespace
+
+extern "C" {
 
 fbst_status fbst_directions_create(const fbst_plan* plan, int n_directions, const double* u,
                                    const double* v, fbst_directions** out) {

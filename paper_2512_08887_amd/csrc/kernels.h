@@ -82,10 +82,19 @@ hipError_t launch_axis_dft(int P, const void* in, void* out, const void* corr, c
                            int a_out, int pre_n, int post_n, int L, int nblocks, hipStream_t st);
 
 // Stage 2: beams_blk[b][n] from w[blk][b][0..L-1], blk < nblocks; needs 2L <= P.
+// var selects a compiled instance (bit 0: the two Gohberg-Semencul branches in
+// sequence in one LDS buffer instead of as one dual transform; bit 1: a
+// persistent grid of the resident workgroups, each taking a contiguous range
+// of rows); bit 1 leaves the beams bit-identical, bit 0 changes them at the
+// level of float32 rounding.  Variants other than 0
+// exist for a float32 stage 2 at P >= 1024 (k3_variant_available), else
+// hipErrorInvalidValue.
 template <typename T, typename TIN, typename TOUT>
 hipError_t launch_toeplitz_fu(int P, const void* w, const OutPtrs& outs, const void* G1,
                               const void* G2, const void* pre3, const void* H3, const void* post3,
-                              const void* tw, int B, int L, int N, int nblocks, hipStream_t st);
+                              const void* tw, int B, int L, int N, int nblocks, hipStream_t st,
+                              int var = 0);
+bool k3_variant_available(int P, bool fp32_stage2, int var);
 
 // Stage 2 in float32 with one step of iterative refinement: beta_1 = A^{-1} w
 // by Gohberg-Semencul (stored to bt [nblocks][B][L]), then beta = beta_1 +

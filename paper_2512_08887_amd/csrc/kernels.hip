@@ -1,8 +1,9 @@
-// HIP kernels of the FBST hot path for gfx950.
+// HIP kernels of stage 1 of the FBST hot path for gfx950 (stage 2, K3, is in
+// stage2.hip).
 //
 //   K1 stage 1a  time chirp-z per sensor          (Sec. IV, sum over n of eq. DFT_1)
 //   K2 stage 1b  space chirp-z per frequency l     (Sec. IV, sum over m; App. B per axis)
-//   K3 stage 2   Gohberg-Semencul Toeplitz apply + F_u chirp-z per beam (Sec. V)
+//   non-uniform stage 1b (Sec. IX): spread, fused spread + FFT, per-axis DFT
 //
 // Every chirp-z is a Bluestein convolution held entirely in one workgroup:
 // chirp premultiply while loading, forward FFT in LDS, product with the
@@ -16,115 +17,11 @@
 // Workgroups are remapped so that each XCD (each L2) receives a contiguous
 // range of the logical work: per-frequency tables of K2 and per-beam spectra
 // of K3 are then fetched into one L2 and reused there.
-#include <hip/hip_runtime.h>
-
-#include "fft_lds.h"
-#include "kernels.h"
-
-#ifndef FBST_K3_DUAL
-#define FBST_K3_DUAL 1            // run the two Gohberg-Semencul branches as one dual FFT
-#endif
-#ifndef FBST_K3_WAVES
-#define FBST_K3_WAVES 2           // minimum waves per SIMD the register allocation must allow
-#endif
-// Twiddle modes of the transforms (TwiddleMode in fft_lds.h), per kernel.
-#ifndef FBST_K12_TW
-#define FBST_K12_TW 1             // stages 1a and 1b: prefetched across barriers
-#endif
-#ifndef FBST_K3_TW
-#define FBST_K3_TW 1              // stage 2, single transforms
-#endif
-#ifndef FBST_K3_TW_DUAL
-#define FBST_K3_TW_DUAL 0         // stage 2, dual transforms
-#endif
-#ifndef FBST_K12_WAVES
-#define FBST_K12_WAVES 0
-#endif
-#if FBST_K3_WAVES > 0
-#define FBST_K3_ATTR __attribute__((amdgpu_waves_per_eu(FBST_K3_WAVES)))
-#else
-#define FBST_K3_ATTR
-#endif
-#if FBST_K12_WAVES > 0
-#define FBST_K12_ATTR __attribute__((amdgpu_waves_per_eu(FBST_K12_WAVES)))
-#else
-#define FBST_K12_ATTR
-#endif
+#include "kernel_common.h"
 
 namespace fbst {
 
 namespace {
-
-constexpr int kE = FFT_E;
-constexpr int kXCD = 8;          // XCDs of an MI355X; workgroups are dealt round-robin
-
-template <int P, int WG = 256>
-struct Shape {
-  static constexpr int TT = P / kE;                        // threads per transform
-  static constexpr int G = (TT >= WG) ? 1 : WG / TT;       // transforms per workgroup
-  static constexpr int THREADS = TT * G;
-  static constexpr int S = lds_stride(P);                  // LDS elements per transform
-};
-
-#ifndef FBST_K2_THREADS
-#define FBST_K2_THREADS 512       // workgroup size of the space chirp-z (frequencies per tile x TT)
-#endif
-template <int P>
-using ShapeK2 = Shape<P, FBST_K2_THREADS>;
-
-// Logical index of this workgroup such that the workgroups the hardware
-// sends to one XCD (blockIdx % 8) form a contiguous logical range.
-__device__ __forceinline__ int xcd_linear(int nwg) {
-  const int b = blockIdx.x;
-  const int x = b % kXCD, i = b / kXCD;
-  const int q = nwg / kXCD, r = nwg % kXCD;
-  return (x < r) ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
-}
-
-template <typename T>
-__device__ __forceinline__ cx<T> ldg(const cx<T>* p) { return *p; }
-
-#ifndef FBST_BATCH
-#define FBST_BATCH 1              // issue each group of independent table/data loads together
-#endif
-
-// Loads above this point are issued before anything below it (an empty asm
-// statement with a memory clobber).  The register-pressure-driven scheduler
-// otherwise places each table load right before its use, one L2 round trip
-// after another; batched, their latencies overlap.
-template <bool ON = FBST_BATCH>
-__device__ __forceinline__ void issue_fence() {
-  if constexpr (ON) asm volatile("" ::: "memory");
-}
-
-#ifndef FBST_K3_GB
-#define FBST_K3_GB 16             // stage-2 spectrum loads issued this many at a time (0: as used)
-#endif
-
-// use(s, a[s], b[s]) for s < N, where a[s] = A[s * TT] and b[s] = B[s * TT]
-// (B may be null: then b[s] is unused), loading GB slots at a time.
-template <int GB, int N, int TT, typename T, typename Use>
-__device__ __forceinline__ void with_tables(const cx<T>* __restrict__ A, const cx<T>* __restrict__ B,
-                                            Use&& use) {
-  if constexpr (GB <= 0) {
-#pragma unroll
-    for (int s = 0; s < N; ++s) use(s, ldg(A + s * TT), B ? ldg(B + s * TT) : cx<T>{0, 0});
-  } else {
-    static_assert(N % GB == 0, "group size must divide the slot count");
-#pragma unroll
-    for (int s0 = 0; s0 < N; s0 += GB) {
-      cx<T> a[GB], b[GB];
-#pragma unroll
-      for (int i = 0; i < GB; ++i) {
-        a[i] = ldg(A + (s0 + i) * TT);
-        if (B) b[i] = ldg(B + (s0 + i) * TT);
-      }
-      issue_fence<true>();
-#pragma unroll
-      for (int i = 0; i < GB; ++i) use(s0 + i, a[i], b[i]);
-    }
-  }
-}
 
 // ---------------------------------------------------------------------------
 // K1: Yhat[row][i] = post[i] * IFFT(FFT(x[row][n] * pre[n]) * H)[i],  i < L.
@@ -799,176 +696,11 @@ __global__ __launch_bounds__(ShapeK2<P>::THREADS) FBST_K12_ATTR void k_axis_dft(
   }
 }
 
-// ---------------------------------------------------------------------------
-// K3: per beam, beta = A_b^{-1} w_b by the Gohberg-Semencul form
-//   A^{-1} = (1/x0) [L(x) L(x)^H - L(y~) L(y~)^H],  y~ = (0, conj x_{L-1}, ..., conj x_1)
-// with each triangular Toeplitz product done by circulant embedding in P
-// points (G1 = FFT(x) and G2 = FFT(y~), both scaled by 1 / (P sqrt(x0))), then
-// b = F_u beta as a Bluestein chirp-z in the same P points:
-//   V = FFT(w);  u_k = conj(G_k) V;  p_k = IFFT(u_k)[0:L]
-//   Z = G1 FFT(p_1) - G2 FFT(p_2);  beta = IFFT(Z)[0:L]
-//   b = post3 * IFFT(FFT(beta * pre3) * H3)[0:N]
-// Eight P-point transforms, all in LDS/registers.  L <= P/2 always (P >= 2L - 1),
-// so every L-long operand fills the first P/2 slots (SL = E/2); SN >= ceil(N / TT).
-// Both products with V are formed at once so V is dead before the branches.
-// Logical order: beam outermost, so the spectra of one beam are reused by the
-// workgroups of all blocks on one XCD.
-// ---------------------------------------------------------------------------
-// Dual-branch stage 2 when two transforms of P points fit the LDS of a CU.
-template <typename T, int P>
-constexpr bool k3_dual() {
-  return FBST_K3_DUAL && sizeof(T) * 2 * lds_stride(P) * 2 * Shape<P>::G <= 160 * 1024;
-}
-
-// Stage 2 with one step of iterative refinement (MODE 1 then MODE 2, two
-// launches): the float32 Gohberg-Semencul apply loses accuracy where its two
-// terms, each much larger than beta, cancel; a second apply to the residual
-// r = w - A beta_1 (A by circulant embedding of its first column, CA =
-// FFT(c_0 .. c_{L-1}, 0 .., conj c_{L-1} .. conj c_1) / P) recovers it:
-//   MODE 0  beta = GS(w); beams = F_u beta                       (8 transforms)
-//   MODE 1  beta_1 = GS(w) stored to bt [rows][L]                (6 transforms)
-//   MODE 2  r = w - A beta_1; beta = beta_1 + GS(r); beams = F_u beta (10 transforms)
-template <typename T, typename TIN, typename TOUT, int P, int SN, int MODE = 0>
-__global__ __launch_bounds__(Shape<P>::THREADS) FBST_K3_ATTR void k_toeplitz_fu(
-    const cx<TIN>* __restrict__ w, const OutPtrs outs, const cx<T>* __restrict__ G1,
-    const cx<T>* __restrict__ G2, const cx<T>* __restrict__ pre3, const cx<T>* __restrict__ H3,
-    const cx<T>* __restrict__ post3, const cx<T>* __restrict__ tw, int B, int L, int N,
-    int nblocks, cx<T>* __restrict__ bt = nullptr, const cx<T>* __restrict__ CA = nullptr) {
-  using SH = Shape<P>;
-  constexpr int SL = kE / 2;
-  constexpr bool DUAL = k3_dual<T, P>();
-  constexpr int NBUF = DUAL ? 2 : 1;
-  __shared__ cx<T> lds[SH::G * NBUF * SH::S];
-  const int g = threadIdx.x / SH::TT;
-  const int t = threadIdx.x % SH::TT;
-  const int rows = nblocks * B;
-  const int lw = xcd_linear(gridDim.x) * SH::G + g;     // beam-major logical row
-  const bool active = lw < rows;
-  const int b = active ? lw / nblocks : 0;
-  const int blk = active ? lw % nblocks : 0;
-  const size_t row = static_cast<size_t>(blk) * B + b;
-  cx<T>* buf = lds + g * NBUF * SH::S;
-  const cx<T>* g1 = G1 + static_cast<size_t>(b) * P;
-  const cx<T>* g2 = G2 + static_cast<size_t>(b) * P;
-
-  cx<T> u1[kE], u2[kE];
-  const cx<TIN>* src = w + row * L;                   // row of block 0, beam 0 when inactive
-  cx<T>* brow = bt + row * L;
-  if constexpr (MODE == 2) {
-    // r = w - A beta_1, A beta_1 = IFFT(CA FFT(beta_1)) (circulant embedding)
-#pragma unroll
-    for (int s = 0; s < kE; ++s) {
-      const int i = t + s * SH::TT;
-      u1[s] = (s < SL && active && i < L) ? brow[i] : cx<T>{0, 0};
-    }
-    fft<T, P, kE, -1, SL, FBST_K3_TW>(u1, buf, tw, t);
-    with_tables<FBST_K3_GB, kE, SH::TT>(CA + static_cast<size_t>(b) * P + t,
-                                        static_cast<const cx<T>*>(nullptr),
-                                        [&](int s, cx<T> a, cx<T>) { u1[s] = cmul(u1[s], a); });
-    fft<T, P, kE, +1, kE, FBST_K3_TW>(u1, buf, tw, t);
-#pragma unroll
-    for (int s = 0; s < kE; ++s) {
-      const int i = t + s * SH::TT;
-      u1[s] = (s < SL && active && i < L) ? cvt<T>(src[i]) - u1[s] : cx<T>{0, 0};
-    }
-  } else {
-#pragma unroll
-    for (int s = 0; s < kE; ++s) {
-      const int i = t + s * SH::TT;
-      u1[s] = (s < SL && active && i < L) ? cvt<T>(src[i]) : cx<T>{0, 0};
-    }
-  }
-  fft<T, P, kE, -1, SL, FBST_K3_TW>(u1, buf, tw, t);
-  with_tables<FBST_K3_GB, kE, SH::TT>(g1 + t, g2 + t, [&](int s, cx<T> a, cx<T> c) {
-    const cx<T> V = u1[s];
-    u1[s] = cmulc(V, a);
-    u2[s] = cmulc(V, c);
-  });
-  if constexpr (DUAL) {
-    // both branches: u_k <- FFT(trunc_L(IFFT(u_k)))
-    fft2<T, P, kE, +1, kE, FBST_K3_TW_DUAL>(u1, u2, buf, buf + SH::S, tw, t);
-#pragma unroll
-    for (int s = 0; s < kE; ++s)
-      if (s >= SL || t + s * SH::TT >= L) {
-        u1[s] = cx<T>{0, 0};
-        u2[s] = cx<T>{0, 0};
-      }
-    fft2<T, P, kE, -1, SL, FBST_K3_TW_DUAL>(u1, u2, buf, buf + SH::S, tw, t);
-    with_tables<FBST_K3_GB, kE, SH::TT>(g1 + t, g2 + t, [&](int s, cx<T> a, cx<T> c) {
-      u1[s] = cmul(u1[s], a) - cmul(u2[s], c);
-    });
-  } else {
-    // branch 1: u1 <- G1 * FFT(trunc_L(IFFT(u1)))
-    fft<T, P, kE, +1, kE, FBST_K3_TW>(u1, buf, tw, t);
-#pragma unroll
-    for (int s = 0; s < kE; ++s)
-      if (s >= SL || t + s * SH::TT >= L) u1[s] = cx<T>{0, 0};
-    fft<T, P, kE, -1, SL, FBST_K3_TW>(u1, buf, tw, t);
-#pragma unroll
-    for (int s = 0; s < kE; ++s) u1[s] = cmul(u1[s], ldg(g1 + t + s * SH::TT));
-    // branch 2: u1 -= G2 * FFT(trunc_L(IFFT(u2)))
-    fft<T, P, kE, +1, kE, FBST_K3_TW>(u2, buf, tw, t);
-#pragma unroll
-    for (int s = 0; s < kE; ++s)
-      if (s >= SL || t + s * SH::TT >= L) u2[s] = cx<T>{0, 0};
-    fft<T, P, kE, -1, SL, FBST_K3_TW>(u2, buf, tw, t);
-#pragma unroll
-    for (int s = 0; s < kE; ++s) u1[s] = u1[s] - cmul(u2[s], ldg(g2 + t + s * SH::TT));
-  }
-  // beta = trunc_L(IFFT(Z)), then the F_u chirp-z
-  fft<T, P, kE, +1, kE, FBST_K3_TW>(u1, buf, tw, t);
-  if constexpr (MODE == 1) {
-#pragma unroll
-    for (int s = 0; s < SL; ++s) {
-      const int i = t + s * SH::TT;
-      if (active && i < L) brow[i] = u1[s];
-    }
-    return;
-  }
-  if constexpr (MODE == 2) {
-#pragma unroll
-    for (int s = 0; s < SL; ++s) {
-      const int i = t + s * SH::TT;
-      if (i < L) u1[s] = u1[s] + brow[active ? i : 0];
-    }
-  }
-#pragma unroll
-  for (int s = 0; s < kE; ++s) {
-    const int i = t + s * SH::TT;
-    u1[s] = (s < SL && i < L) ? cmul(u1[s], ldg(pre3 + i)) : cx<T>{0, 0};
-  }
-  fft<T, P, kE, -1, SL, FBST_K3_TW>(u1, buf, tw, t);
-  with_tables<FBST_K3_GB, kE, SH::TT>(H3 + t, static_cast<const cx<T>*>(nullptr),
-                                      [&](int s, cx<T> a, cx<T>) { u1[s] = cmul(u1[s], a); });
-  fft<T, P, kE, +1, kE, FBST_K3_TW>(u1, buf, tw, t);
-  cx<TOUT>* dst = static_cast<cx<TOUT>*>(outs.p[blk]) + static_cast<size_t>(b) * N;
-#pragma unroll
-  for (int s = 0; s < SN; ++s) {
-    const int n = t + s * SH::TT;
-    if (active && n < N) dst[n] = cvt<TOUT>(cmul(u1[s], ldg(post3 + n)));
-  }
-}
-
-template <int P>
-int grid_for(int rows) { return (rows + Shape<P>::G - 1) / Shape<P>::G; }
-
-// smallest of {E/4, E/2, E} slots covering n elements of a P-point transform
-template <int P>
-int slots_for(int n) {
-  const int tt = Shape<P>::TT;
-  const int s = (n + tt - 1) / tt;
-  return s <= kE / 4 ? kE / 4 : (s <= kE / 2 ? kE / 2 : kE);
-}
-
-template <typename T, int P, int NBUF = 1>
-constexpr bool fits_lds() { return sizeof(T) * 2 * lds_stride(P) * NBUF * Shape<P>::G <= 160 * 1024; }
-
 }  // namespace
 
 // ---------------------------------------------------------------------------
 // Launchers: dispatch the runtime FFT size and slot counts to compiled instances.
 // ---------------------------------------------------------------------------
-#define FBST_FOR_EACH_P(X) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096) X(8192) X(16384)
 
 template <typename T>
 hipError_t launch_time_czt(int P, const InPtrs& xs, int nblocks, void* yhat, const void* pre,
@@ -1244,87 +976,6 @@ hipError_t launch_axis_dft(int P, const void* in, void* out, const void* corr, c
   return hipErrorInvalidValue;
 }
 
-// Stage 2 with one refinement step (float32): MODE 1 (beta_1 to bt) then
-// MODE 2 (residual, correction, F_u), both of one launch shape.
-hipError_t launch_toeplitz_fu_refined(int P, const void* w, const OutPtrs& outs, const void* G1,
-                                      const void* G2, const void* pre3, const void* H3,
-                                      const void* post3, const void* tw, const void* CA, void* bt,
-                                      int B, int L, int N, int nblocks, hipStream_t st) {
-  if (nblocks < 1 || nblocks > MAX_LAUNCH_BLOCKS || !CA || !bt) return hipErrorInvalidValue;
-  using T = float;
-  switch (P) {
-#define CASE(PP)                                                                               \
-  case PP: {                                                                                   \
-    if (2 * L > PP) return hipErrorInvalidValue;                                               \
-    const dim3 grid(grid_for<PP>(nblocks * B)), block(Shape<PP>::THREADS);                     \
-    const int sn = slots_for<PP>(N);                                                           \
-    const auto a = (const cx<T>*)w;                                                            \
-    const auto& o = outs;                                                                      \
-    const auto g1 = (const cx<T>*)G1, g2 = (const cx<T>*)G2, p3 = (const cx<T>*)pre3;          \
-    const auto h3 = (const cx<T>*)H3, q3 = (const cx<T>*)post3, twp = (const cx<T>*)tw;        \
-    const auto ca = (const cx<T>*)CA;                                                          \
-    const auto b1 = (cx<T>*)bt;                                                                \
-    hipLaunchKernelGGL((k_toeplitz_fu<T, T, T, PP, kE / 4, 1>), grid, block, 0, st, a, o, g1, g2, \
-                       p3, h3, q3, twp, B, L, N, nblocks, b1, ca);                             \
-    if (sn <= kE / 4)                                                                          \
-      hipLaunchKernelGGL((k_toeplitz_fu<T, T, T, PP, kE / 4, 2>), grid, block, 0, st, a, o, g1,  \
-                         g2, p3, h3, q3, twp, B, L, N, nblocks, b1, ca);                       \
-    else if (sn <= kE / 2)                                                                     \
-      hipLaunchKernelGGL((k_toeplitz_fu<T, T, T, PP, kE / 2, 2>), grid, block, 0, st, a, o, g1,  \
-                         g2, p3, h3, q3, twp, B, L, N, nblocks, b1, ca);                       \
-    else                                                                                       \
-      hipLaunchKernelGGL((k_toeplitz_fu<T, T, T, PP, kE, 2>), grid, block, 0, st, a, o, g1, g2,  \
-                         p3, h3, q3, twp, B, L, N, nblocks, b1, ca);                           \
-    return hipGetLastError();                                                                  \
-  }
-    CASE(256) CASE(512) CASE(1024) CASE(2048) CASE(4096) CASE(8192) CASE(16384)
-#undef CASE
-    default:
-      break;
-  }
-  return hipErrorInvalidValue;
-}
-
-template <typename T, typename TIN, typename TOUT>
-hipError_t launch_toeplitz_fu(int P, const void* w, const OutPtrs& outs, const void* G1,
-                              const void* G2, const void* pre3, const void* H3, const void* post3,
-                              const void* tw, int B, int L, int N, int nblocks, hipStream_t st) {
-  if (nblocks < 1 || nblocks > MAX_LAUNCH_BLOCKS) return hipErrorInvalidValue;
-  switch (P) {
-#define CASE(PP)                                                                               \
-  case PP:                                                                                     \
-    if constexpr (fits_lds<T, PP>()) {                                                         \
-      if (2 * L > PP) return hipErrorInvalidValue;                                             \
-      const dim3 grid(grid_for<PP>(nblocks * B)), block(Shape<PP>::THREADS);                   \
-      const int sn = slots_for<PP>(N);                                                         \
-      const auto a = (const cx<TIN>*)w;                                                        \
-      const auto& o = outs;                                                                    \
-      if (sn <= kE / 4)                                                                        \
-        hipLaunchKernelGGL((k_toeplitz_fu<T, TIN, TOUT, PP, kE / 4>), grid, block, 0, st, a, o, \
-                           (const cx<T>*)G1, (const cx<T>*)G2, (const cx<T>*)pre3,              \
-                           (const cx<T>*)H3, (const cx<T>*)post3, (const cx<T>*)tw, B, L, N,    \
-                           nblocks);                                                           \
-      else if (sn <= kE / 2)                                                                   \
-        hipLaunchKernelGGL((k_toeplitz_fu<T, TIN, TOUT, PP, kE / 2>), grid, block, 0, st, a, o, \
-                           (const cx<T>*)G1, (const cx<T>*)G2, (const cx<T>*)pre3,              \
-                           (const cx<T>*)H3, (const cx<T>*)post3, (const cx<T>*)tw, B, L, N,    \
-                           nblocks);                                                           \
-      else                                                                                     \
-        hipLaunchKernelGGL((k_toeplitz_fu<T, TIN, TOUT, PP, kE>), grid, block, 0, st, a, o,     \
-                           (const cx<T>*)G1, (const cx<T>*)G2, (const cx<T>*)pre3,              \
-                           (const cx<T>*)H3, (const cx<T>*)post3, (const cx<T>*)tw, B, L, N,    \
-                           nblocks);                                                           \
-      return hipGetLastError();                                                                \
-    }                                                                                          \
-    break;
-    FBST_FOR_EACH_P(CASE)
-#undef CASE
-    default:
-      break;
-  }
-  return hipErrorInvalidValue;
-}
-
 template hipError_t launch_time_czt<float>(int, const InPtrs&, int, void*, const void*, const void*,
                                            const void*, const void*, int, int, int, hipStream_t);
 template hipError_t launch_time_czt<double>(int, const InPtrs&, int, void*, const void*, const void*,
@@ -1365,14 +1016,4 @@ template hipError_t launch_axis_dft<float>(int, const void*, void*, const void*,
                                            int, int, int, int, hipStream_t);
 template hipError_t launch_axis_dft<double>(int, const void*, void*, const void*, const void*, int,
                                             int, int, int, int, hipStream_t);
-template hipError_t launch_toeplitz_fu<float, float, float>(
-    int, const void*, const OutPtrs&, const void*, const void*, const void*, const void*, const void*,
-    const void*, int, int, int, int, hipStream_t);
-template hipError_t launch_toeplitz_fu<double, float, float>(
-    int, const void*, const OutPtrs&, const void*, const void*, const void*, const void*, const void*,
-    const void*, int, int, int, int, hipStream_t);
-template hipError_t launch_toeplitz_fu<double, double, double>(
-    int, const void*, const OutPtrs&, const void*, const void*, const void*, const void*, const void*,
-    const void*, int, int, int, int, hipStream_t);
-
 }  // namespace fbst

@@ -976,7 +976,6 @@ fbst_status build_direction_tables(const Params& p, const std::vector<double>& u
   const int PG = next_pow2(2LL * L);
   const double lp0 = 1.0 - 0.5 * L;
   const double kap = 2.0 * kPi * p.eps / L;
-  const double dxs = p.dx / p.ts, dys = p.dy / p.ts;
   auto a_of = [&](int l) { return 2.0 * kPi * p.fc * p.ts + kap * (l + lp0); };
   K->assign(static_cast<size_t>(L) * D * N, zd());
   if (E) E->assign(static_cast<size_t>(D) * M * L, zd());
@@ -1027,7 +1026,6 @@ fbst_status build_null_tables(const Params& p, const std::vector<double>& uq,
   const int PG = next_pow2(2LL * L);
   const double lp0 = 1.0 - 0.5 * L;
   const double kap = 2.0 * kPi * p.eps / L;                     // rad per sample per unit l'
-  const double dxs = p.dx / p.ts, dys = p.dy / p.ts;
   auto beam_u = [&](int b) { return p.u0 + (b / p.bv) * p.du; };
   auto beam_v = [&](int b) { return p.kind != FBST_LINE ? p.v0 + (b % p.bv) * p.dv : 0.0; };
   // time factor sum_n exp(-j kappa d n), d = l - k in (-L, L)

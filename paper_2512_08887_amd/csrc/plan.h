@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <complex>
 #include <cstddef>
 #include <string>
@@ -227,6 +228,10 @@ struct fbst_plan {
   void* K = nullptr;
   size_t K_bytes = 0;
   int device = 0;
+  // kernel instance of stage 2 (variant bits of fbst::launch_toeplitz_fu),
+  // chosen by fbst_autotune or fbst_plan_set_variant; the instances agree to
+  // float32 rounding (the persistent bit changes nothing at all)
+  std::atomic<int> k3_variant{0};
 };
 
 namespace fbst {

@@ -25,6 +25,7 @@ FBST_FLAG_HOST_ONLY, FBST_FLAG_KEEP_HOST_TABLES, FBST_FLAG_NO_SPLIT, FBST_FLAG_P
 FBST_FLAG_NU_UNFUSED = 16
 FBST_FLAG_DEVICE_GENERATORS = 32
 FBST_FLAG_STAGE2_REFINE = 64
+FBST_VARIANT_K3_SINGLE, FBST_VARIANT_K3_PERSISTENT, FBST_VARIANT_K3_WAVES3 = 1, 2, 4
 FBST_TABLE_BEAM_U, FBST_TABLE_BEAM_V, FBST_TABLE_GRAM, FBST_TABLE_GENERATOR = 0, 1, 2, 3
 MAX_LAUNCH_BLOCKS = 256  # FBST_MAX_LAUNCH_BLOCKS: blocks per kernel launch (pointers in the kernel arguments)
 
@@ -122,6 +123,13 @@ def load_library(path: str = LIB_PATH):
     L.fbst_autotune.argtypes = [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_int,
                                 POINTER(c_int), POINTER(ctypes.c_float)]
     L.fbst_autotune.restype = c_int
+    L.fbst_autotune_ex.argtypes = [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_int,
+                                   POINTER(c_int), POINTER(c_int), POINTER(ctypes.c_float)]
+    L.fbst_autotune_ex.restype = c_int
+    L.fbst_plan_set_variant.argtypes = [c_void_p, c_int]
+    L.fbst_plan_set_variant.restype = c_int
+    L.fbst_plan_variant.argtypes = [c_void_p]
+    L.fbst_plan_variant.restype = c_int
     L.fbst_execute_stream.argtypes = [c_void_p, ctypes.c_longlong, c_int, c_void_p, c_void_p, c_void_p,
                                       c_int, c_void_p]
     L.fbst_execute_stream.restype = c_int
@@ -292,6 +300,21 @@ def fbst_autotune(plan, nblocks, x, beams, workspace, stream=0, force=False):
     _check(lib().fbst_autotune(plan, nblocks, x, beams, workspace, stream or None, int(force),
                                byref(c), byref(ms)))
     return c.value, ms.value
+
+
+def fbst_autotune_ex(plan, nblocks, x, beams, workspace, stream=0, force=False):
+    chunk, var, ms = c_int(0), c_int(0), ctypes.c_float(0.0)
+    _check(lib().fbst_autotune_ex(plan, nblocks, x, beams, workspace, stream or None, int(force),
+                                  byref(chunk), byref(var), byref(ms)))
+    return chunk.value, var.value, ms.value
+
+
+def fbst_plan_set_variant(plan, variant):
+    _check(lib().fbst_plan_set_variant(plan, int(variant)))
+
+
+def fbst_plan_variant(plan) -> int:
+    return int(lib().fbst_plan_variant(plan))
 
 
 def fbst_execute_stream(plan, T, hop, x, beams, workspace=0, max_chunk=0, stream=0):
@@ -569,6 +592,27 @@ class Plan:
             workspace = self.workspace(min(nb, MAX_LAUNCH_BLOCKS))
         return fbst_autotune(self.handle, nb, x.data_ptr(), beams.data_ptr(), workspace.data_ptr(),
                              self._stream(), force)
+
+    def autotune_ex(self, x, beams=None, workspace=None, force=False):
+        """Fastest (blocks per launch, stage-2 variant) for x [nblocks, M, N];
+        leaves that variant set on the plan; returns (chunk, variant, ms)."""
+        import torch
+        self._check_in(x, (self.M, self.N))
+        nb = x.shape[0]
+        if beams is None:
+            beams = torch.empty((nb, self.B, self.N), dtype=self.complex_dtype, device=x.device)
+        if workspace is None:
+            workspace = self.workspace(min(nb, MAX_LAUNCH_BLOCKS))
+        return fbst_autotune_ex(self.handle, nb, x.data_ptr(), beams.data_ptr(),
+                                workspace.data_ptr(), self._stream(), force)
+
+    @property
+    def variant(self):
+        return fbst_plan_variant(self.handle)
+
+    @variant.setter
+    def variant(self, v):
+        fbst_plan_set_variant(self.handle, v)
 
     def graph(self, x, beams, workspace=None, max_chunk=0):
         """Capture execute_batched(x -> beams) as a replayable graph bound to these tensors."""
