@@ -130,6 +130,16 @@ typedef struct {
                                          plan rebuilds when the beam set changes; the
                                          columns, refinement and spectra stay on the
                                          host.  Not with FBST_FLAG_HOST_ONLY. */
+#define FBST_FLAG_SUPERFAST_GENERATORS 128u /* the generators x_b = A_b^{-1} e_0 by the
+                                         superfast doubling Schur algorithm (Ammar and
+                                         Gragg), O(L log^2 L) per beam with FFT
+                                         polynomial products in float64, instead of
+                                         Levinson's O(L^2); on the host, or with
+                                         FBST_FLAG_DEVICE_GENERATORS on the GPU (one
+                                         workgroup per beam, L <= 4096).  Its forward
+                                         error grows faster with cond(A_b) than
+                                         Levinson's; the plan's refinement (cond > 1e6)
+                                         applies as for Levinson                       */
 #define FBST_FLAG_STAGE2_REFINE 64u /* float32 stage 2 with one step of iterative
                                          refinement (Sec. V system A_b beta = w_b):
                                          beta_1 by the Gohberg-Semencul apply, then
@@ -193,6 +203,9 @@ typedef struct {
                         frequency (1..16, chosen by the plan); else 0          */
   double cond_bound; /* upper bound on cond(F_b^H F_b + delta I) over the beams:
                         1 + M lambda_max(T) / delta, T the time Gram (Sec. V) */
+  double generator_ms; /* FBST_FLAG_DEVICE_GENERATORS: GPU time of the generator
+                          solve at plan creation (Levinson, or superfast with
+                          FBST_FLAG_SUPERFAST_GENERATORS), milliseconds; else 0 */
 } fbst_info;
 
 typedef struct fbst_plan fbst_plan;

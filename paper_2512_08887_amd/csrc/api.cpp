@@ -625,10 +625,36 @@ fbst_status solve_generators_on_device(fbst_plan* pl) {
   }
   std::vector<fbst::zd> x(n);
   std::vector<int> status(p.B, 1);
+  const bool superfast = (p.flags & FBST_FLAG_SUPERFAST_GENERATORS) != 0;
+  void *sscr = nullptr, *stw = nullptr;
+  size_t sbytes = 0;
+  hipEvent_t t0 = nullptr, t1 = nullptr;
   hipError_t e = hipMemcpy(dc, pl->host.cols.data(), n * 16, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = fbst::launch_levinson(dc, dx, static_cast<int*>(ds), p.B, p.L, nullptr);
+  if (e == hipSuccess && superfast) {
+    const std::vector<fbst::zd> tw = fbst::superfast_twiddles(p.L);
+    sbytes = fbst::superfast_scratch_bytes(p.B, p.L, nullptr);
+    e = hipMalloc(&sscr, sbytes);
+    if (e == hipSuccess) e = hipMalloc(&stw, tw.size() * 16);
+    if (e == hipSuccess) e = hipMemcpy(stw, tw.data(), tw.size() * 16, hipMemcpyHostToDevice);
+  }
+  if (e == hipSuccess) e = hipEventCreate(&t0);
+  if (e == hipSuccess) e = hipEventCreate(&t1);
+  if (e == hipSuccess) e = hipEventRecord(t0, nullptr);
+  if (e == hipSuccess)
+    e = superfast ? fbst::launch_superfast(dc, dx, static_cast<int*>(ds), p.B, p.L, sscr, sbytes,
+                                           stw, nullptr)
+                  : fbst::launch_levinson(dc, dx, static_cast<int*>(ds), p.B, p.L, nullptr);
+  if (e == hipSuccess) e = hipEventRecord(t1, nullptr);
+  if (e == hipSuccess) e = hipEventSynchronize(t1);
+  float ms = 0.0f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+  pl->generator_ms = ms;
+  if (t0) (void)hipEventDestroy(t0);
+  if (t1) (void)hipEventDestroy(t1);
   if (e == hipSuccess) e = hipMemcpy(x.data(), dx, n * 16, hipMemcpyDeviceToHost);
   if (e == hipSuccess) e = hipMemcpy(status.data(), ds, sizeof(int) * p.B, hipMemcpyDeviceToHost);
+  if (sscr) (void)hipFree(sscr);
+  if (stw) (void)hipFree(stw);
   release();
   if (e != hipSuccess) return hip_fail(e, "device generator solve");
   for (int b = 0; b < p.B; ++b)
@@ -1316,6 +1342,7 @@ fbst_status fbst_plan_info(const fbst_plan* plan, fbst_info* info) {
   info->io_elem_bytes = (p.prec == FBST_PREC_FP64) ? 16 : 8;
   info->device_bytes = plan->dev_bytes;
   info->workspace_per_block = plan->ws_bytes_per_block;
+  info->generator_ms = plan->generator_ms;
   info->p1_split = p.p1s;
   info->stage2_precomputed = plan->K ? 1 : 0;
   info->nu_width = p.nuw;

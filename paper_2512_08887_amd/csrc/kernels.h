@@ -143,6 +143,14 @@ hipError_t launch_project_dirs(const void* yhat, const void* E, void* out, int M
 // L <= 8192; status [B] (device ints): 0, or 1 if a pivot is not positive.
 hipError_t launch_levinson(const void* cols, void* x, int* status, int B, int L, hipStream_t st);
 
+// The same x [B][L] by the superfast doubling Schur algorithm (superfast.h),
+// float64, one workgroup per system, L <= 4096.  scratch: device memory of at
+// least superfast_scratch_bytes(B, L) bytes (grid: the workgroups launched);
+// tw: superfast_twiddles(L) (complex128, max_fft(L) / 2 entries).
+size_t superfast_scratch_bytes(int B, int L, int* grid);
+hipError_t launch_superfast(const void* cols, void* x, int* status, int B, int L, void* scratch,
+                            size_t scratch_bytes, const void* tw, hipStream_t st);
+
 // out[blk][d][n] = sum_{i<8, j<TV} wu[d][i] wv[d][j] beams[blk][(a0 + i) bv + c0 + j][n]
 // with (a0, c0) = first[d] and (wu, wv) = w[d] (TV = 8 if bv > 1, else 1);
 // complex64, or complex128 when fp64; beams [nb][B][N], out [nb][D][N];

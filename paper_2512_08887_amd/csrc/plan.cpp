@@ -1,6 +1,7 @@
 // FP64 host plan builder: validation, chirp tables, chirp-kernel spectra,
 // Toeplitz generators and Gohberg-Semencul spectra.
 #include "plan.h"
+#include "superfast.h"
 
 #include <sched.h>
 
@@ -660,6 +661,11 @@ fbst_status resolve_params(int M, int N, int B, const fbst_geometry* geom, const
       *msg = "the device generator solve holds L <= 8192 coefficients in LDS";
       return FBST_E_UNSUPPORTED;
     }
+    if ((p.flags & FBST_FLAG_SUPERFAST_GENERATORS) && p.L > 4096) {
+      *msg = "the device superfast generator solve holds transforms of 2L <= 8192 points in LDS "
+             "(L <= 4096)";
+      return FBST_E_UNSUPPORTED;
+    }
   }
   if (p.flags & FBST_FLAG_STAGE2_REFINE) {
     if (p.prec == FBST_PREC_FP64 || p.prec == FBST_PREC_FP64_STAGE2) {
@@ -740,7 +746,12 @@ void finish_beam(const Params& p, int b, const zd* col, std::vector<zd>* xv, boo
   // forward error visible (above ~1e6)
   const bool refine = 2.0 * p.M * p.N / p.delta > 1e6;
   if (keep_gram_gen) std::copy(col, col + L, t->gram.begin() + static_cast<size_t>(b) * L);
-  if (refine) refine_generator(col, L, P3, &x);
+  if (refine) {
+    // the superfast solve's forward error grows faster with cond(A) than
+    // Levinson's: up to three steps instead of one
+    const int steps = (p.flags & FBST_FLAG_SUPERFAST_GENERATORS) ? 3 : 1;
+    for (int s = 0; s < steps; ++s) refine_generator(col, L, P3, &x);
+  }
   if (keep_gram_gen) std::copy(x.begin(), x.end(), t->gen.begin() + static_cast<size_t>(b) * L);
   const double scale = 1.0 / (P3 * std::sqrt(x[0].real()));
   std::fill(buf.begin(), buf.end(), zd());
@@ -766,6 +777,31 @@ void finish_beam(const Params& p, int b, const zd* col, std::vector<zd>* xv, boo
 }
 
 }  // namespace
+
+namespace {
+
+struct HostSync {
+  void operator()() const {}
+};
+
+}  // namespace
+
+std::vector<zd> superfast_twiddles(int L) {
+  const int PM = superfast::max_fft(L);
+  std::vector<zd> tw(PM / 2);
+  for (int k = 0; k < PM / 2; ++k) tw[k] = cis(-2.0 * kPi * k / PM);
+  return tw;
+}
+
+bool superfast_first_column(const zd* col, int L, zd* x) {
+  const std::vector<zd> tw = superfast_twiddles(L);
+  std::vector<zd> scratch(superfast::scratch_elems(L)), lds(superfast::lds_elems(L));
+  using Z = superfast::z;
+  const superfast::Ctx c{0, 1, reinterpret_cast<const Z*>(tw.data()), superfast::max_fft(L)};
+  return superfast::generator(reinterpret_cast<const Z*>(col), reinterpret_cast<Z*>(x), L,
+                              reinterpret_cast<Z*>(scratch.data()), reinterpret_cast<Z*>(lds.data()),
+                              c, HostSync{});
+}
 
 fbst_status finish_generators(const Params& p, const std::vector<zd>& x, bool keep_gram_gen,
                               HostTables* t) {
@@ -888,6 +924,7 @@ fbst_status build_tables(const Params& p, bool keep_gram_gen, HostTables* t, std
   // generators solved on the device (FBST_FLAG_DEVICE_GENERATORS): keep the
   // columns only; finish_generators completes the tables
   const bool device = (p.flags & FBST_FLAG_DEVICE_GENERATORS) != 0;
+  const bool superfast = (p.flags & FBST_FLAG_SUPERFAST_GENERATORS) != 0;
   if (device) t->cols.assign(static_cast<size_t>(B) * L, zd());
   std::vector<std::vector<double>> rcol(K), xr(K);
   std::atomic<bool> ok{true};
@@ -907,7 +944,15 @@ fbst_status build_tables(const Params& p, bool keep_gram_gen, HostTables* t, std
       r[0] += p.delta;
       if (device) continue;
       xr[k].resize(L);
-      if (!levinson_real(r.data(), L, xr[k].data())) {
+      bool solved;
+      if (superfast) {
+        std::vector<zd> cz(r.begin(), r.end()), xz(L);
+        solved = superfast_first_column(cz.data(), L, xz.data());
+        for (int d = 0; d < L; ++d) xr[k][d] = xz[d].real();
+      } else {
+        solved = levinson_real(r.data(), L, xr[k].data());
+      }
+      if (!solved) {
         std::lock_guard<std::mutex> lk(fail_mu);
         ok = false;
         fail = "Toeplitz system not positive definite in float64 (delta too small?)";
@@ -925,7 +970,8 @@ fbst_status build_tables(const Params& p, bool keep_gram_gen, HostTables* t, std
           col[d] = geometric_sum(N, 0.0, -kd) * sensor_sum(p, kd * ub, kd * vb);
         }
         col[0] = zd(col[0].real() + p.delta, 0.0);
-        if (!device && !levinson_first_column(col.data(), L, x.data())) {
+        if (!device && !(superfast ? superfast_first_column(col.data(), L, x.data())
+                                   : levinson_first_column(col.data(), L, x.data()))) {
           std::lock_guard<std::mutex> lk(fail_mu);
           ok = false;
           fail = "Toeplitz system not positive definite in float64 (delta too small?)";

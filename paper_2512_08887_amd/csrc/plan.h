@@ -127,6 +127,13 @@ fbst_status build_null_tables(const Params& p, const std::vector<double>& uq,
                               const std::vector<double>& vq, std::vector<zd>* G,
                               std::vector<zd>* E, std::string* msg);
 
+// The same x by the superfast doubling Schur algorithm (superfast.h), O(L log^2 L),
+// run on the host by one thread.  false if a pivot is not positive.
+bool superfast_first_column(const zd* col, int L, zd* x);
+// exp(-2 pi j k / PM), k < PM / 2, PM = superfast::max_fft(L): the transform
+// table of the superfast solve for L coefficients.
+std::vector<zd> superfast_twiddles(int L);
+
 // Levinson recursion for a Hermitian positive definite Toeplitz matrix with
 // first column col: returns x = A^{-1} e_0.  false if a pivot is not positive.
 bool levinson_first_column(const zd* col, int L, zd* x);
@@ -232,6 +239,7 @@ struct fbst_plan {
   // chosen by fbst_autotune or fbst_plan_set_variant; the instances agree to
   // float32 rounding (the persistent bit changes nothing at all)
   std::atomic<int> k3_variant{0};
+  double generator_ms = 0.0;       // device generator solve (FBST_FLAG_DEVICE_GENERATORS), ms
 };
 
 namespace fbst {

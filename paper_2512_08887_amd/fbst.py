@@ -25,6 +25,7 @@ FBST_FLAG_HOST_ONLY, FBST_FLAG_KEEP_HOST_TABLES, FBST_FLAG_NO_SPLIT, FBST_FLAG_P
 FBST_FLAG_NU_UNFUSED = 16
 FBST_FLAG_DEVICE_GENERATORS = 32
 FBST_FLAG_STAGE2_REFINE = 64
+FBST_FLAG_SUPERFAST_GENERATORS = 128
 FBST_VARIANT_K3_SINGLE, FBST_VARIANT_K3_PERSISTENT, FBST_VARIANT_K3_WAVES3 = 1, 2, 4
 FBST_TABLE_BEAM_U, FBST_TABLE_BEAM_V, FBST_TABLE_GRAM, FBST_TABLE_GENERATOR = 0, 1, 2, 3
 MAX_LAUNCH_BLOCKS = 256  # FBST_MAX_LAUNCH_BLOCKS: blocks per kernel launch (pointers in the kernel arguments)
@@ -59,7 +60,7 @@ class fbst_info(ctypes.Structure):
                 ("p3", c_int), ("precision", c_int), ("io_elem_bytes", c_size_t),
                 ("device_bytes", c_size_t), ("workspace_per_block", c_size_t), ("p1_split", c_int),
                 ("stage2_precomputed", c_int), ("nu_width", c_int),
-                ("nu_lanes", c_int), ("cond_bound", c_double)]
+                ("nu_lanes", c_int), ("cond_bound", c_double), ("generator_ms", c_double)]
 
 
 class fbst_server_options(ctypes.Structure):

@@ -447,3 +447,52 @@ def test_stage2_refine_flag():
                                                          flags=host | extra | F.FBST_FLAG_STAGE2_REFINE))
         assert st == F.FBST_E_UNSUPPORTED and h is None, (prec, st)
         assert "REFINE" in F.fbst_last_error()
+
+
+@pytest.mark.parametrize("shape", ["line", "ragged", "grid", "arbitrary", "paper_delta"])
+def test_superfast_generators_host(shape):
+    """FBST_FLAG_SUPERFAST_GENERATORS on a host-only plan: the generators
+    x_b = A_b^{-1} e_0 by the doubling Schur algorithm against the oracle's
+    Cholesky solve of the same Toeplitz matrix (Sec. V), to Levinson's bound
+    L cond(A) u at a noise-level delta; at the paper's delta = 1e-5 the plan's
+    refinement brings it back within that bound.  Bar: 10 L cond(A) u (the
+    doubling algorithm is weakly stable: its error carries a larger constant
+    than Levinson's, 4e-11 against a Levinson bound of 1e-11 on the ragged
+    line)."""
+    band = F.make_band(2.0, 0.5, 1.0)
+    geom = grid = None
+    if shape == "line":
+        M, N, B, delta = 16, 256, 16, 51.2
+        p = od.line_problem(M, N, B, fc=2.0, delta=delta)
+    elif shape == "ragged":
+        M, N, B, delta = 13, 100, 9, 20.0
+        p = od.line_problem(M, N, B, fc=2.0, delta=delta)
+    elif shape == "grid":
+        M, N, B, delta = 12, 128, 20, 25.6
+        geom, grid = F.make_grid_geometry(4, 3), F.make_beam_grid(5, 4)
+        p = od.grid_problem(4, 3, 5, 4, N, fc=2.0, delta=delta)
+    elif shape == "arbitrary":
+        M, N, B, delta = 10, 96, 8, 19.2
+        rng = np.random.default_rng(5)
+        px = (np.arange(M) + rng.uniform(-0.25, 0.25, M)) / (2 * 2.5)
+        geom = F.make_arbitrary(px)
+        p = od.make_problem(N=N, L=2 * N, eps=1.01, delta=delta, fc=2.0, omega=0.5, ts=1.0, px=px,
+                            u=od.beam_grid(B))
+    else:
+        M, N, B, delta = 16, 128, 6, 1e-5
+        p = od.line_problem(M, N, B, fc=2.0, delta=delta)
+    flags = F.FBST_FLAG_HOST_ONLY | F.FBST_FLAG_KEEP_HOST_TABLES | F.FBST_FLAG_SUPERFAST_GENERATORS
+    h = F.fbst_plan_create(M, N, B, geom, band, grid,
+                           F.make_options(delta, precision="fp64", flags=flags))
+    try:
+        L = p.L
+        gen = np.empty((B, L), dtype=np.complex128)
+        F.fbst_plan_table(h, F.FBST_TABLE_GENERATOR, gen)
+    finally:
+        F.fbst_destroy(h)
+    for b in range(B):
+        A = od.toeplitz_system(p, b)
+        ref = od.generator(p, b)
+        cond = np.linalg.cond(A)
+        e = np.linalg.norm(gen[b] - ref) / np.linalg.norm(ref)
+        assert e < 10 * L * cond * 2.0 ** -52, (b, e, cond)

@@ -106,3 +106,58 @@ def test_device_generators_largest_L():
     print(f"ula1024: device vs host generators {d:.2e} (cond ~ {cond:.1e}); plan build "
           f"{t1 - t0:.2f} s host, {t2 - t1:.2f} s with device generators")
     assert d < dev.L * cond * np.finfo(np.float64).eps
+
+
+@pytest.mark.parametrize("name", ["ula16", "grid", "perturbed", "ula256", "ura32"])
+def test_superfast_device_generators(name):
+    """FBST_FLAG_SUPERFAST_GENERATORS with FBST_FLAG_DEVICE_GENERATORS: the
+    doubling Schur algorithm on the GPU (O(L log^2 L) per beam, float64).
+    Against the oracle's Cholesky generator (sampled beams) within 10 L cond u,
+    against the host's superfast solve within the same bound (the host solves
+    the real, centred form of a uniform array's matrix, the device the complex
+    one; on the perturbed line both solve the same complex matrix and agree to
+    1e-13), residual at float64 rounding, beams against the oracle; its GPU
+    time beside the O(L^2) device Levinson's."""
+    need_gpu()
+    cfg = {"ula16": synth.config("ula16"), "grid": grid_cfg(4, 6, 5, 4, 64),
+           "perturbed": perturbed_cfg("ula", 48, 128, 40, index=102),
+           "ula256": synth.config("ula256"), "ura32": synth.config("ura32")}[name]
+    keep = F.FBST_FLAG_KEEP_HOST_TABLES
+    sf = F.FBST_FLAG_SUPERFAST_GENERATORS
+    dev = F.plan_for_config(cfg, flags=keep | F.FBST_FLAG_DEVICE_GENERATORS | sf)
+    lev = F.plan_for_config(cfg, flags=keep | F.FBST_FLAG_DEVICE_GENERATORS)
+    t0 = time.perf_counter()
+    host = F.plan_for_config(cfg, flags=keep | sf)
+    host_s = time.perf_counter() - t0
+    gd, gh = generators(dev), generators(host)
+    p = oracle_problem(cfg, cfg.delta_noise)
+    L = dev.L
+    cond = 2.0 * cfg.M * cfg.N / cfg.delta_noise
+    sample = sorted(set([0, cfg.B // 3, cfg.B // 2, cfg.B - 1]))
+    err = max(rel(gd[b], od.generator(p, b)) for b in sample)
+    same = max(rel(gd[b], gh[b]) for b in range(cfg.B))
+    gram = F.fbst_plan_table(dev.handle, F.FBST_TABLE_GRAM, np.zeros((cfg.B, L), complex))
+    res = max(residual(gram[b], gd[b]) for b in sample)
+    y = cfg.scene().block(0)
+    x = torch.from_numpy(y).to(torch.complex64).cuda()
+    out = dev.execute(x).cpu().numpy()
+    idx = sample
+    e = rel(out[idx], od.beams(x.cpu().numpy().astype(np.complex128), p, idx))
+    print(f"{name} (L = {L}, B = {cfg.B}): superfast device vs Cholesky {err:.2e} "
+          f"(10 L cond u = {10 * L * cond * 2.0 ** -52:.1e}); device vs host superfast {same:.1e}; "
+          f"residual {res:.1e}; beams {e:.2e}; GPU solve {dev.info.generator_ms:.2f} ms superfast, "
+          f"{lev.info.generator_ms:.2f} ms Levinson; host superfast plan {host_s:.2f} s")
+    assert err < 10 * L * cond * 2.0 ** -52
+    assert same < 10 * L * cond * 2.0 ** -52
+    assert res < 10 * L * np.finfo(np.float64).eps
+    assert e < TOL32
+    for h in (dev, lev, host):
+        h.close()
+
+
+def test_superfast_device_limits():
+    need_gpu()
+    cfg = synth.config("ula1024")                           # L = 8192 > 4096
+    with pytest.raises(F.FbstError) as e:
+        F.plan_for_config(cfg, flags=F.FBST_FLAG_DEVICE_GENERATORS | F.FBST_FLAG_SUPERFAST_GENERATORS)
+    assert e.value.status == F.FBST_E_UNSUPPORTED
