@@ -7,7 +7,6 @@
 #include "fft_lds.h"
 #include "kernels.h"
 
-#include "kernels.h"
 
 #ifndef FBST_K3_DUAL
 #define FBST_K3_DUAL 1            // run the two Gohberg-Semencul branches as one dual FFT
