@@ -117,11 +117,13 @@ def fbst64_baseline(names=("ula16", "ula256", "ura32", "ula1024")):
 def large_bench(F, torch, *, steps=5, log=print):
     """Whole-path throughput of the planar array (32 x 32, N = 2048) and the
     1024-element line (N = 4096) in float32, and of the line with the
-    bfloat16 / float16 split stage 1a; blocks of one step in one launch.
+    bfloat16 / float16 split stage 1a and with a float64 stage 2 (P3 = 16384,
+    split transforms) or float64 throughout; blocks of one step in one launch.
     Returns the results and block 0's beams of each (for the oracle check)."""
     import synth
     runs = [("ura32", "fp32", 8), ("ura32", "fp32_refine", 8), ("ula1024", "fp32", 4),
-            ("ula1024", "bf16_split", 4), ("ula1024", "fp16_split", 4)]
+            ("ula1024", "bf16_split", 4), ("ula1024", "fp16_split", 4),
+            ("ula1024", "fp64_stage2", 4), ("ula1024", "fp64", 4)]
     out, first = {}, {}
     for name, prec, nb in runs:
         c = synth.config(name)
@@ -130,6 +132,8 @@ def large_bench(F, torch, *, steps=5, log=print):
         else:
             plan = F.plan_for_config(c, precision=prec)
         y = np.stack([c.scene().block(k) for k in range(nb)]).astype(np.complex64)
+        if prec == "fp64":
+            y = y.astype(np.complex128)
         x = torch.from_numpy(y).cuda()
         ws = plan.workspace(nb)
         bo = plan.execute_batched(x, workspace=ws)

@@ -203,9 +203,14 @@ typedef struct {
                         frequency (1..16, chosen by the plan); else 0          */
   double cond_bound; /* upper bound on cond(F_b^H F_b + delta I) over the beams:
                         1 + M lambda_max(T) / delta, T the time Gram (Sec. V) */
-  double generator_ms; /* FBST_FLAG_DEVICE_GENERATORS: GPU time of the generator
-                          solve at plan creation (Levinson, or superfast with
+  double generator_ms; /* GPU time of the last device generator solve (at plan
+                          creation with FBST_FLAG_DEVICE_GENERATORS, or by
+                          fbst_plan_steer; Levinson, or superfast with
                           FBST_FLAG_SUPERFAST_GENERATORS), milliseconds; else 0 */
+  size_t workspace_fixed; /* workspace bytes per launch on top of
+                          nblocks * workspace_per_block: the scratch of a
+                          float64 stage 2 at p3 = 16384 (each transform split
+                          into two halves in LDS, 128 MiB); else 0 */
 } fbst_info;
 
 typedef struct fbst_plan fbst_plan;
@@ -265,7 +270,9 @@ fbst_status fbst_execute_stream(const fbst_plan* plan, long long T, int hop, con
  *            workspace of fbst_workspace_bytes(plan, nb) bytes (else may be NULL);
  *   stage 2 (Sec. V):                  in W -> out beams [nb][B][N]; a plan
  *            with FBST_FLAG_STAGE2_REFINE needs workspace of
- *            fbst_workspace_bytes(plan, nb) bytes (may be NULL when nb == 1). */
+ *            fbst_workspace_bytes(plan, nb) bytes (may be NULL when nb == 1);
+ *            a float64 stage 2 at p3 = 16384 uses workspace_fixed bytes of
+ *            it as scratch (NULL: the plan's own, any nb). */
 fbst_status fbst_execute_stage(const fbst_plan* plan, int stage, int nblocks,
                                const void* in, void* out, void* workspace,
                                void* hip_stream);
@@ -498,7 +505,8 @@ fbst_status fbst_execute_interp(const fbst_interp* interp, int nblocks, const vo
  * caller; the array's contents from earlier calls are never read.  Errors:
  * FBST_E_INVALID on a NULL plan, x or beams, a host-only plan or another
  * current device; FBST_E_UNSUPPORTED when one block's workspace
- * (fbst_workspace_bytes(plan, 1)) exceeds the array.  nblocks == 0 is a
+ * (fbst_workspace_bytes(plan, 1)) exceeds the array (so every float64 stage
+ * 2 at p3 = 16384, whose fixed scratch alone is 128 MiB).  nblocks == 0 is a
  * no-op.  Layouts as fbst_execute_batched.
  * ------------------------------------------------------------------------ */
 #define FBST_STATIC_SCRATCH_BYTES (64u * 1024u * 1024u)
@@ -508,7 +516,28 @@ fbst_status fbst_execute_static(const fbst_plan* plan, int nblocks, const void* 
 /* Size of that array in bytes (FBST_STATIC_SCRATCH_BYTES). */
 size_t fbst_static_scratch_bytes(void);
 
-/* Workspace bytes for nblocks blocks processed in one launch (0 on NULL plan). */
+/* Point an existing plan at a new beam grid (same bu and bv; u0, du, v0,
+ * dv as in fbst_plan_create, du = 0 for the eq. (thetab) grid), for beam
+ * sets that change while the array streams (Sec. V: the generators of the
+ * new beams computed on the fly).  For a line or uniform grid: the host
+ * builds the new stage-1b chirps and the Toeplitz first columns in closed
+ * form; the GPU solves the new generators (Levinson, or the superfast
+ * doubling Schur algorithm with FBST_FLAG_SUPERFAST_GENERATORS) and forms
+ * the Gohberg-Semencul spectra in place of the old (with refinement on the
+ * host when 2MN/delta > 1e6, as at plan creation).  Synchronises hip_stream
+ * first (launches already issued on it finish with the old beams) and
+ * returns when the new tables are in place; the plan must not be in use on
+ * other streams meanwhile.  fbst_info.generator_ms reports the GPU solve.
+ * Tables made from the plan earlier (nulls, directions, interpolation)
+ * keep the old grid: recreate them.  Errors: FBST_E_INVALID (NULL plan,
+ * host-only plan, another current device, a grid that changes bu or bv, a
+ * system not positive definite: the plan is then unchanged);
+ * FBST_E_UNSUPPORTED for arbitrary arrays, FBST_FLAG_PRECOMPUTE and
+ * FBST_FLAG_STAGE2_REFINE plans. */
+fbst_status fbst_plan_steer(fbst_plan* plan, const fbst_grid* grid, void* hip_stream);
+
+/* Workspace bytes for nblocks blocks processed in one launch (0 on NULL plan):
+ * nblocks * workspace_per_block + workspace_fixed (fbst_info). */
 size_t fbst_workspace_bytes(const fbst_plan* plan, int nblocks);
 
 /* Device bytes owned by the plan (tables + its one-block workspace). */

@@ -21,7 +21,7 @@ LIB = os.path.join(PKG, "libfbst.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["kernels.hip", "stage2.hip", "mfma_czt.hip", "precompute.hip", "levinson.hip", "superfast.hip", "plan.cpp", "api.cpp",
+SOURCES = ["kernels.hip", "stage2.hip", "mfma_czt.hip", "precompute.hip", "levinson.hip", "superfast.hip", "gs_spectra.hip", "plan.cpp", "api.cpp",
            "server.cpp", "noalloc.cpp"]
 
 CFLAGS = [

@@ -44,6 +44,8 @@ bool fp32_stage2(const fbst::Params& p) {
          p.prec == FBST_PREC_FP16_SPLIT;
 }
 size_t s2_elem(const fbst::Params& p) { return stage2_double(p) ? 16 : 8; }
+// float64 stage 2 whose transforms exceed the LDS: each split into two halves
+bool split_stage2(const fbst::Params& p) { return stage2_double(p) && p.p3 > 8192; }
 
 // Elements per block of stage 1b's scratch z: a grid's x-axis output
 // [bu][my][L]; for arbitrary positions the oversampled grid [nfx][nfy][L]
@@ -150,7 +152,7 @@ fbst_status upload(fbst_plan* pl) {
   const size_t o_pre3 = up.add(h.pre3, d2), o_H3 = up.add(h.H3, d2), o_post3 = up.add(h.post3, d2);
   const size_t o_CA = up.add(h.CA, d2);
   const size_t tables = align_up(up.blob.size());
-  const size_t total = tables + align_up(pl->ws_bytes_per_block);
+  const size_t total = tables + align_up(pl->ws_bytes_per_block) + pl->ws_fixed_bytes;
 
   hipError_t e = hipGetDevice(&pl->device);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
@@ -264,11 +266,21 @@ hipError_t run_stage1(const fbst_plan* pl, int nb, const void* yhat, void* w, vo
 }
 
 // bt: room for beta_1 of nb blocks ([nb][B][L] complex64) when the plan
-// refines its stage 2, else unused.
+// refines its stage 2; the split float64 stage 2's scratch (ws_fixed_bytes)
+// when its transforms exceed the LDS; else unused.
 hipError_t run_stage2(const fbst_plan* pl, int nb, const void* w, const fbst::OutPtrs& outs,
                       void* bt, hipStream_t st) {
   const fbst::Params& p = pl->p;
   if (pl->K) return fbst::launch_precomputed_apply(pl->K, w, outs, p.B, p.L, p.N, nb, st);
+  if (split_stage2(p)) {
+    if (p.prec == FBST_PREC_FP64)
+      return fbst::launch_toeplitz_fu_split<double, double>(p.p3, w, outs, pl->G1, pl->G2,
+                                                            pl->pre3, pl->H3, pl->post3, pl->tw2,
+                                                            bt, p.B, p.L, p.N, nb, st);
+    return fbst::launch_toeplitz_fu_split<float, float>(p.p3, w, outs, pl->G1, pl->G2, pl->pre3,
+                                                        pl->H3, pl->post3, pl->tw2, bt, p.B, p.L,
+                                                        p.N, nb, st);
+  }
   if (pl->CA)
     return fbst::launch_toeplitz_fu_refined(p.p3, w, outs, pl->G1, pl->G2, pl->pre3, pl->H3,
                                             pl->post3, pl->tw2, pl->CA, bt, p.B, p.L, p.N, nb, st);
@@ -381,6 +393,8 @@ hipError_t run_blocks(const fbst_plan* pl, int nb, const InPtrs& xs, const OutPt
   if (e != hipSuccess) return e;
   e = d1 ? run_stage1<double>(pl, nb, yhat, w, z, st) : run_stage1<float>(pl, nb, yhat, w, z, st);
   if (e != hipSuccess) return e;
+  // beta_1 (inside the per-block part), or the split stage 2's scratch right
+  // after the nb blocks' part (ws_fixed_bytes; refine_elems is then 0)
   void* bt = static_cast<unsigned char*>(z) + static_cast<size_t>(nb) * z_elems(p) * e1;
   return run_stage2(pl, nb, w, outs, bt, st);
 }
@@ -455,7 +469,8 @@ hipError_t run_blocks_nulled(const fbst_plan* pl, const fbst_nulls* nl, int nb,
   c.nb = nb;
   e = fbst::launch_beam_product(c, st);
   if (e != hipSuccess) return e;
-  void* bt = static_cast<unsigned char*>(z) + static_cast<size_t>(nb) * z_elems(p) * 8;
+  void* bt = pl->ws_fixed_bytes ? base + static_cast<size_t>(nb) * nulled_ws_per_block(pl, nl)
+                                : static_cast<unsigned char*>(z) + static_cast<size_t>(nb) * z_elems(p) * 8;
   return run_stage2(pl, nb, wt, outs, bt, st);
 }
 
@@ -608,6 +623,41 @@ fbst_status make_nulls(const fbst_plan* plan, int n, const int* qs, const double
 
 // FBST_FLAG_DEVICE_GENERATORS: the Levinson solves of build_tables' columns
 // on the GPU (float64), then the host completes the stage-2 tables.
+// x_b = A_b^{-1} e_0 for the device columns dc [B][L] (complex128) into dx on
+// stream st by the plan's solver (the superfast doubling Schur algorithm with
+// FBST_FLAG_SUPERFAST_GENERATORS, else Levinson), status [B] into ds, GPU
+// time into *ms; returns after the solve has finished.
+hipError_t device_generator_solve(const fbst::Params& p, const void* dc, void* dx, int* ds,
+                                  hipStream_t st, float* ms) {
+  const bool superfast = (p.flags & FBST_FLAG_SUPERFAST_GENERATORS) != 0;
+  void *sscr = nullptr, *stw = nullptr;
+  size_t sbytes = 0;
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  hipError_t e = hipSuccess;
+  if (superfast) {
+    const std::vector<fbst::zd> tw = fbst::superfast_twiddles(p.L);
+    sbytes = fbst::superfast_scratch_bytes(p.B, p.L, nullptr);
+    e = hipMalloc(&sscr, sbytes);
+    if (e == hipSuccess) e = hipMalloc(&stw, tw.size() * 16);
+    if (e == hipSuccess) e = hipMemcpy(stw, tw.data(), tw.size() * 16, hipMemcpyHostToDevice);
+  }
+  if (e == hipSuccess) e = hipEventCreate(&t0);
+  if (e == hipSuccess) e = hipEventCreate(&t1);
+  if (e == hipSuccess) e = hipEventRecord(t0, st);
+  if (e == hipSuccess)
+    e = superfast ? fbst::launch_superfast(dc, dx, ds, p.B, p.L, sscr, sbytes, stw, st)
+                  : fbst::launch_levinson(dc, dx, ds, p.B, p.L, st);
+  if (e == hipSuccess) e = hipEventRecord(t1, st);
+  if (e == hipSuccess) e = hipEventSynchronize(t1);
+  *ms = 0.0f;
+  if (e == hipSuccess) e = hipEventElapsedTime(ms, t0, t1);
+  if (t0) (void)hipEventDestroy(t0);
+  if (t1) (void)hipEventDestroy(t1);
+  if (sscr) (void)hipFree(sscr);
+  if (stw) (void)hipFree(stw);
+  return e;
+}
+
 fbst_status solve_generators_on_device(fbst_plan* pl) {
   const fbst::Params& p = pl->p;
   const size_t n = static_cast<size_t>(p.B) * p.L;
@@ -625,36 +675,12 @@ fbst_status solve_generators_on_device(fbst_plan* pl) {
   }
   std::vector<fbst::zd> x(n);
   std::vector<int> status(p.B, 1);
-  const bool superfast = (p.flags & FBST_FLAG_SUPERFAST_GENERATORS) != 0;
-  void *sscr = nullptr, *stw = nullptr;
-  size_t sbytes = 0;
-  hipEvent_t t0 = nullptr, t1 = nullptr;
   hipError_t e = hipMemcpy(dc, pl->host.cols.data(), n * 16, hipMemcpyHostToDevice);
-  if (e == hipSuccess && superfast) {
-    const std::vector<fbst::zd> tw = fbst::superfast_twiddles(p.L);
-    sbytes = fbst::superfast_scratch_bytes(p.B, p.L, nullptr);
-    e = hipMalloc(&sscr, sbytes);
-    if (e == hipSuccess) e = hipMalloc(&stw, tw.size() * 16);
-    if (e == hipSuccess) e = hipMemcpy(stw, tw.data(), tw.size() * 16, hipMemcpyHostToDevice);
-  }
-  if (e == hipSuccess) e = hipEventCreate(&t0);
-  if (e == hipSuccess) e = hipEventCreate(&t1);
-  if (e == hipSuccess) e = hipEventRecord(t0, nullptr);
-  if (e == hipSuccess)
-    e = superfast ? fbst::launch_superfast(dc, dx, static_cast<int*>(ds), p.B, p.L, sscr, sbytes,
-                                           stw, nullptr)
-                  : fbst::launch_levinson(dc, dx, static_cast<int*>(ds), p.B, p.L, nullptr);
-  if (e == hipSuccess) e = hipEventRecord(t1, nullptr);
-  if (e == hipSuccess) e = hipEventSynchronize(t1);
   float ms = 0.0f;
-  if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+  if (e == hipSuccess) e = device_generator_solve(p, dc, dx, static_cast<int*>(ds), nullptr, &ms);
   pl->generator_ms = ms;
-  if (t0) (void)hipEventDestroy(t0);
-  if (t1) (void)hipEventDestroy(t1);
   if (e == hipSuccess) e = hipMemcpy(x.data(), dx, n * 16, hipMemcpyDeviceToHost);
   if (e == hipSuccess) e = hipMemcpy(status.data(), ds, sizeof(int) * p.B, hipMemcpyDeviceToHost);
-  if (sscr) (void)hipFree(sscr);
-  if (stw) (void)hipFree(stw);
   release();
   if (e != hipSuccess) return hip_fail(e, "device generator solve");
   for (int b = 0; b < p.B; ++b)
@@ -684,6 +710,7 @@ fbst_status fbst_plan_create(int M, int N, int B, const fbst_geometry* geometry,
   pl->host_only = (p.flags & FBST_FLAG_HOST_ONLY) != 0;
   pl->kept = pl->host_only || (p.flags & FBST_FLAG_KEEP_HOST_TABLES) != 0;
   pl->ws_bytes_per_block = ws_per_block(p);
+  pl->ws_fixed_bytes = split_stage2(p) ? align_up(fbst::split_scratch_bytes(p.p3)) : 0;
   // stage 2 in the single-buffer form where it is compiled: at the same two
   // waves per SIMD it needs fewer registers than the dual form and runs
   // faster (fbst_autotune_ex measures all instances)
@@ -817,6 +844,8 @@ fbst_status fbst_execute_stage(const fbst_plan* plan, int stage, int nblocks, co
       return fail(FBST_E_INVALID, "the refined stage 2 over several blocks needs a workspace");
     workspace = plan->own_ws;
   }
+  // the split float64 stage 2 needs ws_fixed_bytes of scratch, whatever nblocks
+  if (stage == 2 && plan->ws_fixed_bytes && !workspace) workspace = plan->own_ws;
   if (stage == 1) {
     void* z = nullptr;
     if (p.kind != FBST_LINE) {
@@ -1285,7 +1314,7 @@ void fbst_nulls_destroy(fbst_nulls* nulls) {
 
 size_t fbst_workspace_bytes_nulled(const fbst_plan* plan, const fbst_nulls* nulls, int nblocks) {
   if (!plan || !nulls || nblocks < 1) return 0;
-  return nulled_ws_per_block(plan, nulls) * static_cast<size_t>(nblocks);
+  return nulled_ws_per_block(plan, nulls) * static_cast<size_t>(nblocks) + plan->ws_fixed_bytes;
 }
 
 fbst_status fbst_execute_nulled(const fbst_plan* plan, const fbst_nulls* nulls, int nblocks,
@@ -1316,9 +1345,168 @@ fbst_status fbst_execute_nulled(const fbst_plan* plan, const fbst_nulls* nulls, 
   return FBST_OK;
 }
 
+fbst_status fbst_plan_steer(fbst_plan* plan, const fbst_grid* grid, void* hip_stream) {
+  fbst_status s = check_exec(plan);
+  if (s != FBST_OK) return s;
+  if (plan->K || plan->CA)
+    return fail(FBST_E_UNSUPPORTED, "a new beam grid needs a plan without FBST_FLAG_PRECOMPUTE "
+                                    "and FBST_FLAG_STAGE2_REFINE");
+  fbst::Params q = plan->p;
+  std::string msg;
+  s = fbst::resolve_grid(&q, grid, &msg);
+  if (s != FBST_OK) return fail(s, msg);
+  if (q.bu != plan->p.bu || q.bv != plan->p.bv)
+    return fail(FBST_E_INVALID, "the new beam grid must keep bu and bv");
+  int device = -1;
+  hipError_t e = hipGetDevice(&device);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (device != plan->device) return fail(FBST_E_INVALID, "the plan's device must be the current device");
+  fbst::HostTables t;
+  fbst::SteerKeys keys;
+  try {
+    s = fbst::build_steer_tables(q, &t, &keys, &msg);
+  } catch (const std::bad_alloc&) {
+    return fail(FBST_E_NOMEM, "host allocation of the steering tables failed");
+  }
+  if (s != FBST_OK) return fail(s, msg);
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  // launches already issued on the stream still read the old tables
+  e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  // one real centred system per distinct (|u|, |v|), as at plan creation
+  fbst::Params qk = q;
+  qk.B = static_cast<int>(keys.rcols.size() / q.L);
+  const size_t nk = keys.rcols.size();
+  void *dc = nullptr, *dx = nullptr, *ds = nullptr, *dtw = nullptr, *dkey = nullptr, *dsb = nullptr;
+  auto release = [&] {
+    for (void* ptr : {dc, dx, ds, dtw, dkey, dsb})
+      if (ptr) (void)hipFree(ptr);
+  };
+  if (hipMalloc(&dc, nk * 16) != hipSuccess || hipMalloc(&dx, nk * 16) != hipSuccess ||
+      hipMalloc(&ds, sizeof(int) * qk.B) != hipSuccess) {
+    (void)hipGetLastError();
+    release();
+    return fail(FBST_E_NOMEM, "hipMalloc for the steering solve failed");
+  }
+  std::vector<int> status(qk.B, 1);
+  float ms = 0.0f;
+  e = hipMemcpy(dc, keys.rcols.data(), nk * 16, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = device_generator_solve(qk, dc, dx, static_cast<int*>(ds), st, &ms);
+  if (e == hipSuccess) e = hipMemcpy(status.data(), ds, sizeof(int) * qk.B, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) {
+    release();
+    return hip_fail(e, "steering generator solve");
+  }
+  for (int k = 0; k < qk.B; ++k)
+    if (status[k]) {
+      release();
+      return fail(FBST_E_INVALID, "Toeplitz system not positive definite in float64 (delta too small?)");
+    }
+  // Nothing of the plan has changed so far.  Spectra: on the device, or,
+  // when cond(A) calls for refinement (as in build_tables), refined and
+  // transformed on the host; kept host tables are refreshed on the host.
+  const bool refine = 2.0 * q.M * q.N / q.delta > 1e6;
+  const bool d1 = stage1_double(q), d2 = stage2_double(q);
+  const size_t n = static_cast<size_t>(q.B) * q.L;
+  const size_t gbytes = static_cast<size_t>(q.B) * q.p3 * (d2 ? 16 : 8);
+  Upload up;
+  if (refine || plan->kept) {
+    std::vector<fbst::zd> xk(nk), x(n);
+    e = hipMemcpy(xk.data(), dx, nk * 16, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+      release();
+      return hip_fail(e, "steering generator download");
+    }
+    try {
+      for (int b = 0; b < q.B; ++b) {
+        const fbst::zd* r = xk.data() + static_cast<size_t>(keys.key[b]) * q.L;
+        fbst::zd* xb = x.data() + static_cast<size_t>(b) * q.L;
+        for (int d = 0; d < q.L; ++d)
+          xb[d] = std::polar(1.0, -2.0 * 3.141592653589793238 * q.eps * d / q.L * keys.s[b]) *
+                  r[d].real();
+        xb[0] = fbst::zd(r[0].real(), 0.0);
+      }
+      t.G1.assign(static_cast<size_t>(q.B) * q.p3, fbst::zd());
+      t.G2.assign(static_cast<size_t>(q.B) * q.p3, fbst::zd());
+      if (plan->kept) {
+        t.gram.assign(n, fbst::zd());
+        t.gen.assign(n, fbst::zd());
+      }
+      if (fbst::finish_generators(q, x, plan->kept, &t) != FBST_OK) {
+        release();
+        return fail(FBST_E_INVALID, "steering: inconsistent tables");
+      }
+    } catch (const std::bad_alloc&) {
+      release();
+      return fail(FBST_E_NOMEM, "host allocation of the steering spectra failed");
+    }
+  }
+  if (refine) {
+    const size_t o1 = up.add(t.G1, d2), o2 = up.add(t.G2, d2);
+    e = hipMemcpy(const_cast<void*>(plan->G1), up.blob.data() + o1, gbytes, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(const_cast<void*>(plan->G2), up.blob.data() + o2, gbytes, hipMemcpyHostToDevice);
+  } else {
+    const std::vector<fbst::zd> tw = twiddles();
+    e = hipMalloc(&dtw, tw.size() * 16);
+    if (e == hipSuccess) e = hipMalloc(&dkey, sizeof(int) * q.B);
+    if (e == hipSuccess) e = hipMalloc(&dsb, sizeof(double) * q.B);
+    if (e == hipSuccess) e = hipMemcpy(dtw, tw.data(), tw.size() * 16, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(dkey, keys.key.data(), sizeof(int) * q.B, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dsb, keys.s.data(), sizeof(double) * q.B, hipMemcpyHostToDevice);
+    void* g1 = const_cast<void*>(plan->G1);
+    void* g2 = const_cast<void*>(plan->G2);
+    const int* kp = static_cast<const int*>(dkey);
+    const double* sp = static_cast<const double*>(dsb);
+    if (e == hipSuccess)
+      e = d2 ? fbst::launch_gs_spectra<double>(q.p3, dx, q.B, q.L, g1, g2, dtw, st, kp, sp, q.eps)
+             : fbst::launch_gs_spectra<float>(q.p3, dx, q.B, q.L, g1, g2, dtw, st, kp, sp, q.eps);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+  }
+  // stage-1b chirps of the new grid, in place of the old
+  if (e == hipSuccess) {
+    Upload ax;
+    const size_t a0 = ax.add(t.ax.pre, d1), a1 = ax.add(t.ax.H, d1), a2 = ax.add(t.ax.post, d1);
+    const size_t el = d1 ? 16 : 8;
+    e = hipMemcpy(const_cast<void*>(plan->axp), ax.blob.data() + a0, t.ax.pre.size() * el, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(const_cast<void*>(plan->axH), ax.blob.data() + a1, t.ax.H.size() * el, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(const_cast<void*>(plan->axq), ax.blob.data() + a2, t.ax.post.size() * el, hipMemcpyHostToDevice);
+    if (e == hipSuccess && q.kind == FBST_GRID) {
+      Upload ay;
+      const size_t b0 = ay.add(t.ay.pre, d1), b1 = ay.add(t.ay.H, d1), b2 = ay.add(t.ay.post, d1);
+      e = hipMemcpy(const_cast<void*>(plan->ayp), ay.blob.data() + b0, t.ay.pre.size() * el, hipMemcpyHostToDevice);
+      if (e == hipSuccess)
+        e = hipMemcpy(const_cast<void*>(plan->ayH), ay.blob.data() + b1, t.ay.H.size() * el, hipMemcpyHostToDevice);
+      if (e == hipSuccess)
+        e = hipMemcpy(const_cast<void*>(plan->ayq), ay.blob.data() + b2, t.ay.post.size() * el, hipMemcpyHostToDevice);
+    }
+  }
+  release();
+  // the plan now describes the new grid (also when an upload failed part-way:
+  // its tables are then mixed, and the error says so)
+  plan->p = q;
+  plan->generator_ms = ms;
+  if (plan->kept) {
+    fbst::HostTables& h = plan->host;
+    h.ax = std::move(t.ax);
+    h.ay = std::move(t.ay);
+    h.u = std::move(t.u);
+    h.v = std::move(t.v);
+    h.G1 = std::move(t.G1);
+    h.G2 = std::move(t.G2);
+    h.gram = std::move(t.gram);
+    h.gen = std::move(t.gen);
+  }
+  if (e != hipSuccess) return hip_fail(e, "steering table upload (the plan's tables are inconsistent)");
+  return FBST_OK;
+}
+
 size_t fbst_workspace_bytes(const fbst_plan* plan, int nblocks) {
   if (!plan || nblocks < 1) return 0;
-  return plan->ws_bytes_per_block * static_cast<size_t>(nblocks);
+  return plan->ws_bytes_per_block * static_cast<size_t>(nblocks) + plan->ws_fixed_bytes;
 }
 
 size_t fbst_plan_device_bytes(const fbst_plan* plan) { return plan ? plan->dev_bytes : 0; }
@@ -1343,6 +1531,7 @@ fbst_status fbst_plan_info(const fbst_plan* plan, fbst_info* info) {
   info->device_bytes = plan->dev_bytes;
   info->workspace_per_block = plan->ws_bytes_per_block;
   info->generator_ms = plan->generator_ms;
+  info->workspace_fixed = plan->ws_fixed_bytes;
   info->p1_split = p.p1s;
   info->stage2_precomputed = plan->K ? 1 : 0;
   info->nu_width = p.nuw;

@@ -127,6 +127,34 @@ int slots_for(int n) {
 template <typename T, int P, int NBUF = 1>
 constexpr bool fits_lds() { return sizeof(T) * 2 * lds_stride(P) * NBUF * Shape<P>::G <= 160 * 1024; }
 
+// p itself, opaque to the optimiser (an empty asm that may change it), so
+// that nothing computed from it is reused across the point of the call.
+template <typename Q>
+__device__ __forceinline__ Q* fresh(Q* p) {
+  asm volatile("" : "+s"(p));
+  return p;
+}
+
+// W^i = exp(-2 pi j i / P) for 0 <= i < P/2, from the twiddles of the last
+// pass of a P-point transform (entries exp(-2 pi j k / P), k < P / R_last).
+template <int P>
+__device__ __forceinline__ cx<double> split_twiddle(const cx<double>* __restrict__ tw, int i) {
+  constexpr int NSL = [] {
+    int ns = 1;
+    while (P / ns > kE) ns *= kE;
+    return ns;
+  }();
+  constexpr int RL = P / NSL;
+  static_assert(RL == 2 || RL == 4, "split twiddles need a last pass of radix 2 or 4");
+  const cx<double>* base = tw + tw_offset(P, NSL);
+  if constexpr (RL == 2) {
+    return base[i];
+  } else {
+    const cx<double> v = base[i & (NSL - 1)];
+    return (i >= NSL) ? rot90<-1>(v) : v;     // exp(-j pi / 2) exp(-2 pi j (i - NSL) / P)
+  }
+}
+
 }  // namespace
 
 #define FBST_FOR_EACH_P(X) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096) X(8192) X(16384)

@@ -96,6 +96,17 @@ hipError_t launch_toeplitz_fu(int P, const void* w, const OutPtrs& outs, const v
                               int var = 0);
 bool k3_variant_available(int P, bool fp32_stage2, int var);
 
+// Stage 2 in float64 at P = 8192 or 16384 with every P-point transform split
+// into two P/2-point transforms in LDS (the form for P = 16384, where one
+// float64 transform exceeds the LDS).  scratch: split_scratch_bytes(P) bytes
+// of device memory, overwritten.  Needs 2L <= P and N + L - 1 <= P.
+size_t split_scratch_bytes(int P);
+template <typename TIN, typename TOUT>
+hipError_t launch_toeplitz_fu_split(int P, const void* w, const OutPtrs& outs, const void* G1,
+                                    const void* G2, const void* pre3, const void* H3,
+                                    const void* post3, const void* tw, void* scratch, int B, int L,
+                                    int N, int nblocks, hipStream_t st);
+
 // Stage 2 in float32 with one step of iterative refinement: beta_1 = A^{-1} w
 // by Gohberg-Semencul (stored to bt [nblocks][B][L]), then beta = beta_1 +
 // A^{-1} (w - A beta_1) with A applied through its circulant-embedding
@@ -142,6 +153,18 @@ hipError_t launch_project_dirs(const void* yhat, const void* E, void* out, int M
 // with first columns cols [B][L] (complex128), Levinson recursion in float64,
 // L <= 8192; status [B] (device ints): 0, or 1 if a pivot is not positive.
 hipError_t launch_levinson(const void* cols, void* x, int* status, int B, int L, hipStream_t st);
+
+// Spectra of the Gohberg-Semencul factors from generators x [B][L]
+// (complex128): G1[b] = FFT_P(x_b) s_b, G2[b] = FFT_P(y~_b) s_b with
+// s_b = 1 / (P sqrt(x_b[0])) and y~_b = (0, conj x_b[L-1], ..., conj x_b[1]),
+// computed in float64 and stored [B][P] in TG (float or double); tw64: the
+// per-pass twiddle tables in float64.  With key (device int [B]) and s
+// (device double [B]), x holds generators of real centred systems [K][L] and
+// beam b's is x[key[b]][d] exp(-j 2 pi eps d s[b] / L).  Needs 2L <= P <= PMAX.
+template <typename TG>
+hipError_t launch_gs_spectra(int P, const void* x, int B, int L, void* G1, void* G2,
+                             const void* tw64, hipStream_t st, const int* key = nullptr,
+                             const double* s = nullptr, double eps = 0.0);
 
 // The same x [B][L] by the superfast doubling Schur algorithm (superfast.h),
 // float64, one workgroup per system, L <= 4096.  scratch: device memory of at

@@ -100,7 +100,6 @@ __global__ __launch_bounds__(Shape<P>::THREADS) FBST_K12_ATTR void k_time_czt(
 #ifndef FBST_K1S_DUAL
 #define FBST_K1S_DUAL 1           // run the two inverse transforms as one dual transform
 #endif
-constexpr int kK1sBufs = FBST_K1S_DUAL ? 2 : 1;
 #ifndef FBST_K1S_WAVES
 #define FBST_K1S_WAVES 0          // minimum waves per SIMD for the split stage 1a (0: compiler's choice)
 #endif
@@ -110,9 +109,15 @@ constexpr int kK1sBufs = FBST_K1S_DUAL ? 2 : 1;
 #define FBST_K1S_ATTR
 #endif
 
+// LDS buffers of the split stage 1a: two (the inverses as one dual
+// transform) where they fit, else one (float64 at P = 8192)
+template <typename T, int P>
+constexpr int k1s_bufs() {
+  return (FBST_K1S_DUAL && sizeof(T) * 2 * lds_stride(P) * 2 * Shape<P>::G <= 160 * 1024) ? 2 : 1;
+}
 template <typename T, int P>
 constexpr bool k1s_fits() {
-  return sizeof(T) * 2 * lds_stride(P) * kK1sBufs * Shape<P>::G <= 160 * 1024;
+  return sizeof(T) * 2 * lds_stride(P) * k1s_bufs<T, P>() * Shape<P>::G <= 160 * 1024;
 }
 
 template <typename T, int P, int SI, int SO>
@@ -121,12 +126,13 @@ __global__ __launch_bounds__(Shape<P>::THREADS) FBST_K1S_ATTR void k_time_czt_sp
     const cx<T>* __restrict__ Ha, const cx<T>* __restrict__ Hb, const cx<T>* __restrict__ post,
     const cx<T>* __restrict__ tw, int M, int N, int L, int Ls, int rows) {
   using SH = Shape<P>;
-  __shared__ cx<T> lds[SH::G * kK1sBufs * SH::S];
+  constexpr int NBUF = k1s_bufs<T, P>();
+  __shared__ cx<T> lds[SH::G * NBUF * SH::S];
   const int g = threadIdx.x / SH::TT;
   const int t = threadIdx.x % SH::TT;
   const int row = blockIdx.x * SH::G + g;
   const bool active = row < rows;
-  cx<T>* buf = lds + g * kK1sBufs * SH::S;
+  cx<T>* buf = lds + g * NBUF * SH::S;
 
   cx<T> v[kE], u[kE];
   const int rr = active ? row : 0;                    // inactive lanes read row 0, store nothing
@@ -162,7 +168,7 @@ __global__ __launch_bounds__(Shape<P>::THREADS) FBST_K1S_ATTR void k_time_czt_sp
       v[s] = cmul(v[s], ha[s]);
     }
   }
-  if constexpr (FBST_K1S_DUAL) {
+  if constexpr (NBUF == 2) {
     fft2<T, P, kE, +1, kE, FBST_K12_TW>(v, u, buf, buf + SH::S, tw, t);
   } else {
     fft<T, P, kE, +1, kE, FBST_K12_TW>(v, buf, tw, t);

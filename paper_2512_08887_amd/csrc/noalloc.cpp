@@ -61,10 +61,10 @@ fbst_status fbst_execute_static(const fbst_plan* plan, int nblocks, const void* 
   if (nblocks < 0) return fail(FBST_E_INVALID, "nblocks must be >= 0");
   if (nblocks == 0) return FBST_OK;
   if (!x || !beams) return fail(FBST_E_INVALID, "x and beams must not be NULL");
-  const size_t per_block = plan->ws_bytes_per_block;
-  if (per_block > FBST_STATIC_SCRATCH_BYTES)
+  const size_t per_block = plan->ws_bytes_per_block, fixed = plan->ws_fixed_bytes;
+  if (per_block + fixed > FBST_STATIC_SCRATCH_BYTES)
     return fail(FBST_E_UNSUPPORTED,
-                "one block of this plan needs " + std::to_string(per_block) +
+                "one block of this plan needs " + std::to_string(per_block + fixed) +
                     " bytes of workspace, more than the " +
                     std::to_string(static_cast<size_t>(FBST_STATIC_SCRATCH_BYTES)) +
                     "-byte static scratch; use fbst_execute_batched with a workspace");
@@ -76,7 +76,7 @@ fbst_status fbst_execute_static(const fbst_plan* plan, int nblocks, const void* 
   void* ws = nullptr;
   fbst_status s = scratch_address(device, &ws);
   if (s != FBST_OK) return s;
-  int chunk = static_cast<int>(FBST_STATIC_SCRATCH_BYTES / per_block);
+  int chunk = static_cast<int>((FBST_STATIC_SCRATCH_BYTES - fixed) / per_block);
   if (chunk > fbst::MAX_LAUNCH_BLOCKS) chunk = fbst::MAX_LAUNCH_BLOCKS;
   if (chunk > nblocks) chunk = nblocks;
   e = fbst::run_contiguous(plan, nblocks, chunk, x, beams, ws, static_cast<hipStream_t>(hip_stream));

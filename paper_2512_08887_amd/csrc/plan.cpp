@@ -477,6 +477,44 @@ double time_gram_lmax(int N, int L, double eps) {
   return lam;
 }
 
+// The beam grid of p (kind and B already set) from fbst_grid; NULL selects
+// the eq. (thetab) grid of a line.
+fbst_status resolve_grid(Params* pp, const fbst_grid* grid, std::string* msg) {
+  Params& p = *pp;
+  const int B = p.B;
+  if (!grid) {
+    if (p.kind == FBST_GRID) {
+      *msg = "a grid geometry needs an explicit beam grid (bu x bv)";
+      return FBST_E_INVALID;
+    }
+    p.bu = B;
+    p.bv = 1;
+    default_grid(B, &p.u0, &p.du);
+  } else {
+    p.bu = grid->bu;
+    p.bv = grid->bv;
+    if (p.bu < 1 || p.bv < 1 || 1LL * p.bu * p.bv != B) {
+      *msg = "grid needs bu * bv == B";
+      return FBST_E_INVALID;
+    }
+    if (p.kind == FBST_LINE && p.bv != 1) {
+      *msg = "a line needs bv == 1";
+      return FBST_E_INVALID;
+    }
+    if (grid->du == 0.0) default_grid(p.bu, &p.u0, &p.du);
+    else { p.u0 = grid->u0; p.du = grid->du; }
+    if (p.kind != FBST_LINE) {
+      if (grid->dv == 0.0) default_grid(p.bv, &p.v0, &p.dv);
+      else { p.v0 = grid->v0; p.dv = grid->dv; }
+    }
+    if (!std::isfinite(p.u0) || !std::isfinite(p.du) || !std::isfinite(p.v0) || !std::isfinite(p.dv)) {
+      *msg = "grid values must be finite";
+      return FBST_E_INVALID;
+    }
+  }
+  return FBST_OK;
+}
+
 fbst_status resolve_params(int M, int N, int B, const fbst_geometry* geom, const fbst_band* band,
                            const fbst_grid* grid, const fbst_options* opt, Params* out,
                            std::string* msg) {
@@ -577,36 +615,8 @@ fbst_status resolve_params(int M, int N, int B, const fbst_geometry* geom, const
       return FBST_E_INVALID;
     }
   }
-  if (!grid) {
-    if (p.kind == FBST_GRID) {
-      *msg = "a grid geometry needs an explicit beam grid (bu x bv)";
-      return FBST_E_INVALID;
-    }
-    p.bu = B;
-    p.bv = 1;
-    default_grid(B, &p.u0, &p.du);
-  } else {
-    p.bu = grid->bu;
-    p.bv = grid->bv;
-    if (p.bu < 1 || p.bv < 1 || 1LL * p.bu * p.bv != B) {
-      *msg = "grid needs bu * bv == B";
-      return FBST_E_INVALID;
-    }
-    if (p.kind == FBST_LINE && p.bv != 1) {
-      *msg = "a line needs bv == 1";
-      return FBST_E_INVALID;
-    }
-    if (grid->du == 0.0) default_grid(p.bu, &p.u0, &p.du);
-    else { p.u0 = grid->u0; p.du = grid->du; }
-    if (p.kind != FBST_LINE) {
-      if (grid->dv == 0.0) default_grid(p.bv, &p.v0, &p.dv);
-      else { p.v0 = grid->v0; p.dv = grid->dv; }
-    }
-    if (!std::isfinite(p.u0) || !std::isfinite(p.du) || !std::isfinite(p.v0) || !std::isfinite(p.dv)) {
-      *msg = "grid values must be finite";
-      return FBST_E_INVALID;
-    }
-  }
+  const fbst_status gst = resolve_grid(&p, grid, msg);
+  if (gst != FBST_OK) return gst;
   p.p1 = next_pow2(static_cast<long long>(p.N) + p.L - 1);
   p.p2x = next_pow2(static_cast<long long>(p.mx) + p.bu - 1);
   p.p2y = p.kind == FBST_GRID ? next_pow2(static_cast<long long>(p.my) + p.bv - 1) : 0;
@@ -694,12 +704,13 @@ fbst_status resolve_params(int M, int N, int B, const fbst_geometry* geom, const
       return FBST_E_UNSUPPORTED;
     }
   }
+  // Stage 1 in float64 (FBST_PREC_FP64) holds one transform in LDS (8192
+  // points; stage 1a in split-output form needs only p1s); stage 2 goes to
+  // PMAX in every precision (in float64 above 8192 points each transform is
+  // split into two halves in LDS).
   const int lim1 = (p.prec == FBST_PREC_FP64) ? 8192 : PMAX;
-  // stage 2 runs in float64 for FBST_PREC_FP64 and FBST_PREC_FP64_STAGE2, in
-  // float32 otherwise (the split precisions change stage 1a only)
-  const bool s2_double = p.prec == FBST_PREC_FP64 || p.prec == FBST_PREC_FP64_STAGE2;
-  const int lim2 = s2_double ? 8192 : PMAX;
-  if (p.p1 > lim1 || p.p2x > lim1 || p.p2y > lim1 || p.p3 > lim2) {
+  const int p1_run = p.p1s ? p.p1s : p.p1;
+  if (p1_run > lim1 || p.p1 > PMAX || p.p2x > lim1 || p.p2y > lim1 || p.p3 > PMAX) {
     *msg = "an FFT size exceeds what one workgroup holds in LDS for this precision";
     return FBST_E_UNSUPPORTED;
   }
@@ -1007,6 +1018,77 @@ fbst_status build_tables(const Params& p, bool keep_gram_gen, HostTables* t, std
     *msg = fail;
     return FBST_E_INVALID;
   }
+  return FBST_OK;
+}
+
+// --- a new beam grid for an existing plan (line or planar grid) -------------
+// The tables that depend on the beam directions: the stage-1b chirps of each
+// axis, the beams' (u, v), and the Toeplitz first columns [B][L] (with delta)
+// of the new beams in the closed form of build_tables (a frame centred in
+// time and on the array: c_b(d) = exp(-j kd s_b) r_b(d)); the generators and
+// their spectra are left to the caller.
+fbst_status build_steer_tables(const Params& p, HostTables* t, SteerKeys* k, std::string* msg) {
+  if (p.kind == FBST_ARBITRARY) {
+    *msg = "a new beam grid is supported for lines and uniform grids";
+    return FBST_E_UNSUPPORTED;
+  }
+  const int N = p.N, L = p.L, B = p.B;
+  build_axis(p, p.mx, p.bu, p.x0, p.dx / p.ts, p.u0, p.du, p.p2x, &t->ax);
+  if (p.kind == FBST_GRID) build_axis(p, p.my, p.bv, p.y0, p.dy / p.ts, p.v0, p.dv, p.p2y, &t->ay);
+  t->u.resize(B);
+  t->v.resize(B);
+  for (int a = 0; a < p.bu; ++a)
+    for (int c = 0; c < p.bv; ++c) {
+      t->u[a * p.bv + c] = p.u0 + a * p.du;
+      t->v[a * p.bv + c] = (p.kind != FBST_LINE) ? p.v0 + c * p.dv : 0.0;
+    }
+  const double dxs = p.dx / p.ts, dys = p.dy / p.ts;
+  auto dirichlet = [](int K, double y) {
+    const double s = std::sin(0.5 * y);
+    return s == 0.0 ? static_cast<double>(K) : std::sin(0.5 * K * y) / s;
+  };
+  std::vector<double> rt(L);
+  for (int d = 0; d < L; ++d) rt[d] = dirichlet(N, 2.0 * kPi * p.eps * d / L);
+  // distinct (|u|, |v|), as build_tables keys its real solves
+  std::vector<std::pair<double, double>> keys;
+  k->key.assign(B, 0);
+  k->s.assign(B, 0.0);
+  for (int b = 0; b < B; ++b) {
+    const std::pair<double, double> kv(std::fabs(t->u[b]), std::fabs(t->v[b]));
+    int idx = -1;
+    for (size_t i = 0; i < keys.size(); ++i)
+      if (keys[i] == kv) { idx = static_cast<int>(i); break; }
+    if (idx < 0) {
+      idx = static_cast<int>(keys.size());
+      keys.push_back(kv);
+    }
+    k->key[b] = idx;
+    k->s[b] = 0.5 * (N - 1) - t->u[b] * dxs * (p.x0 + 0.5 * (p.mx - 1)) -
+              ((p.kind == FBST_GRID) ? t->v[b] * dys * (p.y0 + 0.5 * (p.my - 1)) : 0.0);
+  }
+  const int K = static_cast<int>(keys.size());
+  k->rcols.assign(static_cast<size_t>(K) * L, zd());
+  for (int q = 0; q < K; ++q) {
+    zd* r = k->rcols.data() + static_cast<size_t>(q) * L;
+    for (int d = 0; d < L; ++d) {
+      const double kd = 2.0 * kPi * p.eps * d / L;
+      double v = rt[d] * dirichlet(p.mx, kd * keys[q].first * dxs);
+      if (p.kind == FBST_GRID) v *= dirichlet(p.my, kd * keys[q].second * dys);
+      r[d] = zd(v, 0.0);
+    }
+    r[0] += p.delta;
+  }
+  // the complex columns of each beam (for the host refinement)
+  t->cols.assign(static_cast<size_t>(B) * L, zd());
+  parallel_for(B, 1LL * B * L * 16, [&](int b0, int b1) {
+    for (int b = b0; b < b1; ++b) {
+      const zd* r = k->rcols.data() + static_cast<size_t>(k->key[b]) * L;
+      zd* col = t->cols.data() + static_cast<size_t>(b) * L;
+      for (int d = 0; d < L; ++d) col[d] = cis(-2.0 * kPi * p.eps * d / L * k->s[b]) * r[d].real();
+      col[0] = zd(r[0].real(), 0.0);
+    }
+  });
+  (void)msg;
   return FBST_OK;
 }
 

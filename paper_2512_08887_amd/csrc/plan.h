@@ -89,6 +89,23 @@ fbst_status build_tables(const Params& p, bool keep_gram_gen, HostTables* t, std
 fbst_status finish_generators(const Params& p, const std::vector<zd>& x, bool keep_gram_gen,
                               HostTables* t);
 
+// The beam grid of p (kind and B set) from fbst_grid, as fbst_plan_create
+// resolves it (NULL: the eq. (thetab) grid of a line).
+fbst_status resolve_grid(Params* p, const fbst_grid* grid, std::string* msg);
+
+// For a new beam grid of a line or uniform-grid plan: t->ax (and t->ay), t->u,
+// t->v and the Toeplitz first columns t->cols [B][L] of the new beams, and
+// their real centred form (build_tables): A_b = D_b (R_k + delta I) D_b^H with
+// D_b = diag(exp(-j 2 pi eps d s_b / L)), k = key[b] indexing the distinct
+// (|u|, |v|); rcols [K][L] holds R_k + delta e_0 (as complex128, imaginary 0)
+// and s [B] the centring s_b in samples.
+struct SteerKeys {
+  std::vector<zd> rcols;
+  std::vector<int> key;
+  std::vector<double> s;
+};
+fbst_status build_steer_tables(const Params& p, HostTables* t, SteerKeys* k, std::string* msg);
+
 // Beams at directions (ud, vd): K [l][d][n] = (F_u A_d^{-1})[n][l] and, when
 // E is given, the projection phases E [d][m][l] = exp(j a_l tau_{d,m}); float64.
 fbst_status build_direction_tables(const Params& p, const std::vector<double>& ud,
@@ -217,6 +234,9 @@ struct fbst_plan {
   void* dev = nullptr;
   size_t dev_bytes = 0;
   size_t ws_bytes_per_block = 0;
+  // workspace bytes per launch on top of the per-block part: the scratch of
+  // the split float64 stage 2 (P3 > 8192), else 0
+  size_t ws_fixed_bytes = 0;
   void* own_ws = nullptr;
   // device table pointers (element type per stage precision)
   const void* tw1 = nullptr;       // twiddles in the stage-1 type

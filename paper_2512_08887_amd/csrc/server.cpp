@@ -163,15 +163,19 @@ struct fbst_server {
         }
       if (s < 0) break;
       const fbst_plan* plan = queue.front().plan;
-      const size_t per = plan->ws_bytes_per_block;
+      // workspace of n blocks: n per + fixed (fixed: the split float64 stage 2's scratch)
+      const size_t per = plan->ws_bytes_per_block, fixed = plan->ws_fixed_bytes;
       // gather same-plan requests in arrival order
       std::vector<size_t> pick;
       for (size_t i = 0; i < queue.size() && static_cast<int>(pick.size()) < max_batch; ++i)
         if (queue[i].plan == plan) pick.push_back(i);
       size_t off = 0;
       // as many of them as the largest free workspace range holds
-      int n = static_cast<int>(std::min<size_t>(pick.size(), per ? pool->largest() / per : pick.size()));
-      while (n > 0 && !pool->alloc(per * static_cast<size_t>(n), &off)) --n;
+      const size_t room = pool->largest();
+      int n = room < fixed ? 0
+                           : static_cast<int>(std::min<size_t>(
+                                 pick.size(), per ? (room - fixed) / per : pick.size()));
+      while (n > 0 && !pool->alloc(per * static_cast<size_t>(n) + fixed, &off)) --n;
       if (n == 0) {
         if (inflight.empty()) {
           // the budget cannot hold even one block of this plan: fail the request
@@ -189,7 +193,7 @@ struct fbst_server {
       Launch l;
       l.stream = s;
       l.ws_off = off;
-      l.ws_len = per * static_cast<size_t>(n);
+      l.ws_len = per * static_cast<size_t>(n) + fixed;
       fbst::InPtrs xs{};
       fbst::OutPtrs outs{};
       for (int i = 0; i < n; ++i) {

@@ -339,6 +339,256 @@ hipError_t launch_toeplitz_fu(int P, const void* w, const OutPtrs& outs, const v
   return hipErrorInvalidValue;
 }
 
+namespace {
+
+// ---------------------------------------------------------------------------
+// Float64 stage 2 at P points when one float64 P-point transform exceeds the
+// LDS (P = 16384: 256 KiB).  Each P-point transform becomes two H = P/2-point
+// transforms in LDS with one radix-2 step in the registers around them
+// (W = exp(-2 pi j / P), H-point index n, k):
+//   forward, input zero at n >= H (every forward transform of stage 2, since
+//   L <= P/2 and the F_u input is L long):
+//     X[2k] = FFT_H(x)[k],   X[2k + 1] = FFT_H(x[n] W^n)[k];
+//   inverse (unscaled):
+//     x[n] = a[n] + W^-n b[n],  x[n + H] = a[n] - W^-n b[n],
+//     a = IFFT_H(X[2k]), b = IFFT_H(X[2k + 1]).
+// A spectrum is therefore held as [even half | odd half]; the products with
+// G1, G2 and H3 read the natural-order tables at 2k and 2k + 1.  Between the
+// transforms the two branch spectra of a row sit in a global scratch of
+// [2][P] elements per workgroup; each element is written and read back by
+// the same thread (slot s of thread t is element t + s TT of both halves), so
+// the scratch needs no barrier.  The grid is at most kSplitGrid workgroups,
+// each taking a contiguous range of rows.
+// ---------------------------------------------------------------------------
+constexpr int kSplitGrid = 256;
+constexpr int kSplitTw = FBST_K3_TW;
+
+template <typename TIN, typename TOUT, int P>
+__global__ __launch_bounds__(Shape<P / 2>::THREADS) void k_toeplitz_fu_split(
+    const cx<TIN>* __restrict__ w, const OutPtrs outs, const cx<double>* __restrict__ G1,
+    const cx<double>* __restrict__ G2, const cx<double>* __restrict__ pre3,
+    const cx<double>* __restrict__ H3, const cx<double>* __restrict__ post3,
+    const cx<double>* __restrict__ twg, int B, int L, int N, int nblocks,
+    cx<double>* __restrict__ scratch) {
+  using T = double;
+  constexpr int H = P / 2;
+  using SH = Shape<H>;
+  static_assert(SH::G == 1, "one half transform per workgroup");
+  constexpr int TT = SH::TT;
+  __shared__ cx<T> lds[SH::S];
+  const int t = threadIdx.x;
+  const int wl = xcd_linear(gridDim.x);
+  cx<T>* const U1w = scratch + static_cast<size_t>(wl) * 2 * P;
+  const int rows = nblocks * B;
+  const int per = (rows + static_cast<int>(gridDim.x) - 1) / static_cast<int>(gridDim.x);
+  const int r1 = min(rows, (wl + 1) * per);
+  cx<T> v[kE];
+  // One half transform is live in registers at a time; the other half waits
+  // in the scratch.  Each loop below takes its base pointers through fresh():
+  // the compiler then recomputes the per-slot addresses (and reloads table
+  // values) where they are used instead of keeping those of every array live
+  // across the transforms, which spills.
+  auto load = [&](const cx<T>* a) {
+    a = fresh(a);
+#pragma unroll
+    for (int s = 0; s < kE; ++s) v[s] = a[t + s * TT];
+  };
+  auto store = [&](cx<T>* a) {
+    a = fresh(a);
+#pragma unroll
+    for (int s = 0; s < kE; ++s) a[t + s * TT] = v[s];
+  };
+  // (the thread index too goes through an empty asm per transform, so that
+  // the LDS addresses of the passes are not kept live between transforms)
+  auto fwd = [&] {
+    int tf = t;
+    asm volatile("" : "+v"(tf));
+    fft<T, H, kE, -1, kE, kSplitTw>(v, lds, fresh(twg), tf);
+  };
+  auto inv = [&] {
+    int tf = t;
+    asm volatile("" : "+v"(tf));
+    fft<T, H, kE, +1, kE, kSplitTw>(v, lds, fresh(twg), tf);
+  };
+  // every thread runs the same trip count (the transforms hold barriers)
+  for (int row = wl * per; row < r1; ++row) {
+    cx<T>* const U1 = U1w;                               // Z accumulates here
+    cx<T>* const U2 = U1w + P;
+    const int bm = row / nblocks, blk = row % nblocks;
+    const cx<TIN>* const src = w + (static_cast<size_t>(blk) * B + bm) * L;
+    const cx<T>* const g1 = G1 + static_cast<size_t>(bm) * P;
+    const cx<T>* const g2 = G2 + static_cast<size_t>(bm) * P;
+
+    // V = FFT_P(w); U1 = conj(G1) V, U2 = conj(G2) V
+#pragma unroll 1
+    for (int par = 0; par < 2; ++par) {
+      {
+        const cx<TIN>* x0 = fresh(src);
+        const cx<T>* tw = fresh(twg);
+#pragma unroll
+        for (int s = 0; s < kE; ++s) {
+          const int i = t + s * TT;
+          const cx<T> x = (i < L) ? cvt<T>(x0[i]) : cx<T>{0, 0};
+          v[s] = par ? cmul(x, split_twiddle<P>(tw, i)) : x;
+          issue_fence<true>();   // bound the loads in flight
+        }
+      }
+      fwd();
+      cx<T>* u1 = fresh(U1);
+      cx<T>* u2 = fresh(U2);
+      const cx<T>* a1 = fresh(g1);
+      const cx<T>* a2 = fresh(g2);
+#pragma unroll
+      for (int s = 0; s < kE; ++s) {
+        const int i = t + s * TT, k = 2 * i + par;
+        u1[par * H + i] = cmulc(v[s], a1[k]);
+        u2[par * H + i] = cmulc(v[s], a2[k]);
+        issue_fence<true>();   // bound the loads in flight
+      }
+    }
+    // Z = G1 FFT_P(trunc_L IFFT_P(U1)) - G2 FFT_P(trunc_L IFFT_P(U2)), into U1
+#pragma unroll 1
+    for (int br = 0; br < 2; ++br) {
+      cx<T>* const U = br ? U2 : U1;
+      const cx<T>* const g = br ? g2 : g1;
+      load(U);                                           // a = IFFT_H(even half)
+      inv();
+      store(U);
+      load(U + H);                                       // b = IFFT_H(odd half)
+      inv();
+      {
+        cx<T>* u = fresh(U);
+        const cx<T>* tw = fresh(twg);
+#pragma unroll
+        for (int s = 0; s < kE; ++s) {                   // p = a + W^-n b (n < L) to U;
+          const int i = t + s * TT;                      // v = p W^n
+          const cx<T> wi = split_twiddle<P>(tw, i);
+          const cx<T> pv = (i < L) ? u[i] + cmulc(v[s], wi) : cx<T>{0, 0};
+          u[i] = pv;
+          v[s] = cmul(pv, wi);
+          issue_fence<true>();   // bound the loads in flight
+        }
+      }
+      fwd();                                             // odd half of FFT_P(p)
+      {
+        cx<T>* z1 = fresh(U1);
+        const cx<T>* a = fresh(g);
+#pragma unroll
+        for (int s = 0; s < kE; ++s) {
+          const int i = t + s * TT;
+          const cx<T> z = cmul(v[s], a[2 * i + 1]);
+          z1[H + i] = br ? z1[H + i] - z : z;
+          issue_fence<true>();   // bound the loads in flight
+        }
+      }
+      load(U);                                           // even half of FFT_P(p)
+      fwd();
+      {
+        cx<T>* z1 = fresh(U1);
+        const cx<T>* a = fresh(g);
+#pragma unroll
+        for (int s = 0; s < kE; ++s) {
+          const int i = t + s * TT;
+          const cx<T> z = cmul(v[s], a[2 * i]);
+          z1[i] = br ? z1[i] - z : z;
+          issue_fence<true>();   // bound the loads in flight
+        }
+      }
+    }
+    // beta = trunc_L IFFT_P(Z); F_u: beams = post3 * IFFT_P(H3 FFT_P(beta * pre3))[0:N]
+    load(U1);
+    inv();
+    store(U1);
+    load(U1 + H);
+    inv();
+    {
+      cx<T>* u = fresh(U1);
+      const cx<T>* tw = fresh(twg);
+      const cx<T>* pre = fresh(pre3);
+#pragma unroll
+      for (int s = 0; s < kE; ++s) {                     // y = beta pre3 to U1; v = y W^n
+        const int i = t + s * TT;
+        const cx<T> wi = split_twiddle<P>(tw, i);
+        const cx<T> y = (i < L) ? cmul(u[i] + cmulc(v[s], wi), pre[i]) : cx<T>{0, 0};
+        u[i] = y;
+        v[s] = cmul(y, wi);
+        issue_fence<true>();   // bound the loads in flight
+      }
+    }
+    fwd();                                               // odd half of FFT_P(y), times H3,
+    {                                                    // then its H-point inverse (b)
+      const cx<T>* h = fresh(H3);
+#pragma unroll
+      for (int s = 0; s < kE; ++s) v[s] = cmul(v[s], h[2 * (t + s * TT) + 1]);
+    }
+    inv();
+    store(U1 + H);
+    load(U1);                                            // even half, times H3, inverse (a)
+    fwd();
+    {
+      const cx<T>* h = fresh(H3);
+#pragma unroll
+      for (int s = 0; s < kE; ++s) v[s] = cmul(v[s], h[2 * (t + s * TT)]);
+    }
+    inv();
+    {
+      cx<TOUT>* dst = static_cast<cx<TOUT>*>(outs.p[blk]) + static_cast<size_t>(bm) * N;
+      const cx<T>* u = fresh(U1);
+      const cx<T>* tw = fresh(twg);
+      const cx<T>* post = fresh(post3);
+#pragma unroll
+      for (int s = 0; s < kE; ++s) {                     // x[n] = a + W^-n b, x[n + H] = a - W^-n b
+        const int i = t + s * TT;
+        const cx<T> wb = cmulc(u[H + i], split_twiddle<P>(tw, i));
+        if (i < N) dst[i] = cvt<TOUT>(cmul(v[s] + wb, post[i]));
+        if (i + H < N) dst[i + H] = cvt<TOUT>(cmul(v[s] - wb, post[i + H]));
+        issue_fence<true>();   // bound the loads in flight
+      }
+    }
+  }
+}
+
+}  // namespace
+
+size_t split_scratch_bytes(int P) {
+  return static_cast<size_t>(kSplitGrid) * 2 * P * sizeof(cx<double>);
+}
+
+template <typename TIN, typename TOUT>
+hipError_t launch_toeplitz_fu_split(int P, const void* w, const OutPtrs& outs, const void* G1,
+                                    const void* G2, const void* pre3, const void* H3,
+                                    const void* post3, const void* tw, void* scratch, int B, int L,
+                                    int N, int nblocks, hipStream_t st) {
+  if (nblocks < 1 || nblocks > MAX_LAUNCH_BLOCKS || !scratch) return hipErrorInvalidValue;
+  if (2 * L > P || N + L - 1 > P) return hipErrorInvalidValue;
+  const int grid = std::min(kSplitGrid, nblocks * B);
+  switch (P) {
+#define CASE(PP)                                                                               \
+  case PP:                                                                                     \
+    hipLaunchKernelGGL((k_toeplitz_fu_split<TIN, TOUT, PP>), dim3(grid),                       \
+                       dim3(Shape<PP / 2>::THREADS), 0, st, (const cx<TIN>*)w, outs,           \
+                       (const cx<double>*)G1, (const cx<double>*)G2, (const cx<double>*)pre3,  \
+                       (const cx<double>*)H3, (const cx<double>*)post3, (const cx<double>*)tw, \
+                       B, L, N, nblocks, (cx<double>*)scratch);                                \
+    return hipGetLastError();
+    CASE(8192) CASE(16384)
+#undef CASE
+    default:
+      break;
+  }
+  return hipErrorInvalidValue;
+}
+
+template hipError_t launch_toeplitz_fu_split<float, float>(int, const void*, const OutPtrs&,
+                                                           const void*, const void*, const void*,
+                                                           const void*, const void*, const void*,
+                                                           void*, int, int, int, int, hipStream_t);
+template hipError_t launch_toeplitz_fu_split<double, double>(int, const void*, const OutPtrs&,
+                                                             const void*, const void*, const void*,
+                                                             const void*, const void*, const void*,
+                                                             void*, int, int, int, int,
+                                                             hipStream_t);
+
 template hipError_t launch_toeplitz_fu<float, float, float>(
     int, const void*, const OutPtrs&, const void*, const void*, const void*, const void*, const void*,
     const void*, int, int, int, int, hipStream_t, int);

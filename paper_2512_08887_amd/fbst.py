@@ -60,7 +60,8 @@ class fbst_info(ctypes.Structure):
                 ("p3", c_int), ("precision", c_int), ("io_elem_bytes", c_size_t),
                 ("device_bytes", c_size_t), ("workspace_per_block", c_size_t), ("p1_split", c_int),
                 ("stage2_precomputed", c_int), ("nu_width", c_int),
-                ("nu_lanes", c_int), ("cond_bound", c_double), ("generator_ms", c_double)]
+                ("nu_lanes", c_int), ("cond_bound", c_double), ("generator_ms", c_double),
+                ("workspace_fixed", c_size_t)]
 
 
 class fbst_server_options(ctypes.Structure):
@@ -131,6 +132,8 @@ def load_library(path: str = LIB_PATH):
     L.fbst_plan_set_variant.restype = c_int
     L.fbst_plan_variant.argtypes = [c_void_p]
     L.fbst_plan_variant.restype = c_int
+    L.fbst_plan_steer.argtypes = [c_void_p, POINTER(fbst_grid), c_void_p]
+    L.fbst_plan_steer.restype = c_int
     L.fbst_execute_stream.argtypes = [c_void_p, ctypes.c_longlong, c_int, c_void_p, c_void_p, c_void_p,
                                       c_int, c_void_p]
     L.fbst_execute_stream.restype = c_int
@@ -316,6 +319,10 @@ def fbst_plan_set_variant(plan, variant):
 
 def fbst_plan_variant(plan) -> int:
     return int(lib().fbst_plan_variant(plan))
+
+
+def fbst_plan_steer(plan, grid, stream=0):
+    _check(lib().fbst_plan_steer(plan, byref(grid), stream or None))
 
 
 def fbst_execute_stream(plan, T, hop, x, beams, workspace=0, max_chunk=0, stream=0):
@@ -606,6 +613,11 @@ class Plan:
             workspace = self.workspace(min(nb, MAX_LAUNCH_BLOCKS))
         return fbst_autotune_ex(self.handle, nb, x.data_ptr(), beams.data_ptr(),
                                 workspace.data_ptr(), self._stream(), force)
+
+    def steer(self, grid):
+        """Point the plan at a new beam grid (fbst_plan_steer; same bu, bv)."""
+        fbst_plan_steer(self.handle, grid, self._stream())
+        self.info = fbst_plan_info(self.handle)
 
     @property
     def variant(self):

@@ -123,21 +123,55 @@ def test_invalid_arguments():
 
 
 def test_stage2_size_limit_follows_the_stage2_precision():
-    """The split precisions change stage 1a only: their float32 stage 2 takes
-    the float32 limit (P3 = 16384 at M = B = 1024, N = 4096), while a float64
-    stage 2 holds P3 <= 8192 in one workgroup's LDS."""
+    """Stage 2 takes P3 = 16384 (M = B = 1024, N = 4096, L = 8192) in every
+    precision: in float32 in one workgroup's LDS, in float64 with each
+    transform split into two 8192-point halves and a fixed scratch of
+    256 workgroups x 2 x 16384 complex128 (128 MiB) added to the workspace
+    of every launch.  A float64 stage 1 holds 8192 points: FBST_PREC_FP64 runs
+    here with stage 1a in split-output form (p1_split = 8192), and is refused
+    where that form does not apply (FBST_FLAG_NO_SPLIT)."""
     band = F.make_band(2.0, 0.5, 1.0)
     delta = 1.0 * 2 * 4096
-    for prec in ("fp32", "bf16_split", "fp16_split"):
+    for prec in ("fp32", "bf16_split", "fp16_split", "fp64_stage2"):
         h = F.fbst_plan_create(1024, 4096, 1024, None, band, None,
                                F.make_options(delta, precision=prec, flags=F.FBST_FLAG_HOST_ONLY))
         info = F.fbst_plan_info(h)
+        ws1, ws3 = F.fbst_workspace_bytes(h, 1), F.fbst_workspace_bytes(h, 3)
         F.fbst_destroy(h)
         assert info.p3 == 16384, (prec, info.p3)
-    st, hnd = F.fbst_plan_create_status(1024, 4096, 1024, None, band, None,
-                                        F.make_options(delta, precision="fp64_stage2",
-                                                       flags=F.FBST_FLAG_HOST_ONLY))
+        fixed = 256 * 2 * 16384 * 16 if prec == "fp64_stage2" else 0
+        assert info.workspace_fixed == fixed, (prec, info.workspace_fixed)
+        assert ws1 == info.workspace_per_block + fixed
+        assert ws3 == 3 * info.workspace_per_block + fixed
+    h = F.fbst_plan_create(1024, 4096, 1024, None, band, None,
+                           F.make_options(delta, precision="fp64", flags=F.FBST_FLAG_HOST_ONLY))
+    info = F.fbst_plan_info(h)
+    F.fbst_destroy(h)
+    assert info.p1 == 16384 and info.p1_split == 8192 and info.p3 == 16384
+    st, hnd = F.fbst_plan_create_status(
+        1024, 4096, 1024, None, band, None,
+        F.make_options(delta, precision="fp64",
+                       flags=F.FBST_FLAG_HOST_ONLY | F.FBST_FLAG_NO_SPLIT))
     assert st == F.FBST_E_UNSUPPORTED and hnd is None
+    # a float64 plan with a float64 stage 1 of 8192 points and P3 = 16384
+    h = F.fbst_plan_create(8, 2400, 8, None, band, None,
+                           F.make_options(1.0, precision="fp64", flags=F.FBST_FLAG_HOST_ONLY))
+    info = F.fbst_plan_info(h)
+    F.fbst_destroy(h)
+    assert info.p3 == 16384 and info.p1 <= 8192 and info.workspace_fixed == 256 * 2 * 16384 * 16
+
+
+def test_steer_needs_a_device_plan():
+    """fbst_plan_steer (a new beam grid in place) rejects NULL and host-only
+    plans without touching them."""
+    band = F.make_band(2.0, 0.5, 1.0)
+    h = F.fbst_plan_create(8, 32, 8, None, band, None,
+                           F.make_options(1.0, flags=F.FBST_FLAG_HOST_ONLY))
+    g = F.make_beam_grid(8, 1, -0.5, 0.1)
+    assert F.lib().fbst_plan_steer(h, g, None) == F.FBST_E_INVALID
+    assert F.lib().fbst_plan_steer(None, g, None) == F.FBST_E_INVALID
+    assert F.fbst_plan_info(h).B == 8
+    F.fbst_destroy(h)
 
 
 def test_null_and_host_only_plan_calls():
