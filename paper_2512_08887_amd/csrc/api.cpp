@@ -274,13 +274,14 @@ hipError_t run_stage2(const fbst_plan* pl, int nb, const void* w, const fbst::Ou
   if (pl->K) return fbst::launch_precomputed_apply(pl->K, w, outs, p.B, p.L, p.N, nb, st);
   if (split_stage2(p)) {
     if (p.prec == FBST_PREC_FP64)
-      return fbst::launch_toeplitz_fu_split<double, double>(p.p3, w, outs, pl->G1, pl->G2,
-                                                            pl->pre3, pl->H3, pl->post3, pl->tw2,
-                                                            bt, p.B, p.L, p.N, nb, st);
-    return fbst::launch_toeplitz_fu_split<float, float>(p.p3, w, outs, pl->G1, pl->G2, pl->pre3,
-                                                        pl->H3, pl->post3, pl->tw2, bt, p.B, p.L,
-                                                        p.N, nb, st);
+      return fbst::launch_toeplitz_fu_split<double, double, double>(
+          p.p3, w, outs, pl->G1, pl->G2, pl->pre3, pl->H3, pl->post3, pl->tw2, bt, p.B, p.L, p.N,
+          nb, st);
+    return fbst::launch_toeplitz_fu_split<double, float, float>(
+        p.p3, w, outs, pl->G1, pl->G2, pl->pre3, pl->H3, pl->post3, pl->tw2, bt, p.B, p.L, p.N,
+        nb, st);
   }
+  const int var = pl->k3_variant.load(std::memory_order_relaxed);
   if (pl->CA)
     return fbst::launch_toeplitz_fu_refined(p.p3, w, outs, pl->G1, pl->G2, pl->pre3, pl->H3,
                                             pl->post3, pl->tw2, pl->CA, bt, p.B, p.L, p.N, nb, st);
@@ -296,8 +297,7 @@ hipError_t run_stage2(const fbst_plan* pl, int nb, const void* w, const fbst::Ou
     default:
       return fbst::launch_toeplitz_fu<float, float, float>(p.p3, w, outs, pl->G1, pl->G2,
                                                            pl->pre3, pl->H3, pl->post3, pl->tw2,
-                                                           p.B, p.L, p.N, nb, st,
-                                                           pl->k3_variant.load(std::memory_order_relaxed));
+                                                           p.B, p.L, p.N, nb, st, var);
   }
 }
 
@@ -710,7 +710,7 @@ fbst_status fbst_plan_create(int M, int N, int B, const fbst_geometry* geometry,
   pl->host_only = (p.flags & FBST_FLAG_HOST_ONLY) != 0;
   pl->kept = pl->host_only || (p.flags & FBST_FLAG_KEEP_HOST_TABLES) != 0;
   pl->ws_bytes_per_block = ws_per_block(p);
-  pl->ws_fixed_bytes = split_stage2(p) ? align_up(fbst::split_scratch_bytes(p.p3)) : 0;
+  pl->ws_fixed_bytes = split_stage2(p) ? align_up(fbst::split_scratch_bytes(p.p3, true)) : 0;
   // stage 2 in the single-buffer form where it is compiled: at the same two
   // waves per SIMD it needs fewer registers than the dual form and runs
   // faster (fbst_autotune_ex measures all instances)

@@ -137,8 +137,8 @@ __device__ __forceinline__ Q* fresh(Q* p) {
 
 // W^i = exp(-2 pi j i / P) for 0 <= i < P/2, from the twiddles of the last
 // pass of a P-point transform (entries exp(-2 pi j k / P), k < P / R_last).
-template <int P>
-__device__ __forceinline__ cx<double> split_twiddle(const cx<double>* __restrict__ tw, int i) {
+template <int P, typename T>
+__device__ __forceinline__ cx<T> split_twiddle(const cx<T>* __restrict__ tw, int i) {
   constexpr int NSL = [] {
     int ns = 1;
     while (P / ns > kE) ns *= kE;
@@ -146,11 +146,11 @@ __device__ __forceinline__ cx<double> split_twiddle(const cx<double>* __restrict
   }();
   constexpr int RL = P / NSL;
   static_assert(RL == 2 || RL == 4, "split twiddles need a last pass of radix 2 or 4");
-  const cx<double>* base = tw + tw_offset(P, NSL);
+  const cx<T>* base = tw + tw_offset(P, NSL);
   if constexpr (RL == 2) {
     return base[i];
   } else {
-    const cx<double> v = base[i & (NSL - 1)];
+    const cx<T> v = base[i & (NSL - 1)];
     return (i >= NSL) ? rot90<-1>(v) : v;     // exp(-j pi / 2) exp(-2 pi j (i - NSL) / P)
   }
 }

@@ -100,8 +100,8 @@ bool k3_variant_available(int P, bool fp32_stage2, int var);
 // into two P/2-point transforms in LDS (the form for P = 16384, where one
 // float64 transform exceeds the LDS).  scratch: split_scratch_bytes(P) bytes
 // of device memory, overwritten.  Needs 2L <= P and N + L - 1 <= P.
-size_t split_scratch_bytes(int P);
-template <typename TIN, typename TOUT>
+size_t split_scratch_bytes(int P, bool dbl);   // dbl: float64 stage 2
+template <typename T, typename TIN, typename TOUT>
 hipError_t launch_toeplitz_fu_split(int P, const void* w, const OutPtrs& outs, const void* G1,
                                     const void* G2, const void* pre3, const void* H3,
                                     const void* post3, const void* tw, void* scratch, int B, int L,

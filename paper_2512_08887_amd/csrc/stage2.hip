@@ -360,17 +360,20 @@ namespace {
 // the scratch needs no barrier.  The grid is at most kSplitGrid workgroups,
 // each taking a contiguous range of rows.
 // ---------------------------------------------------------------------------
-constexpr int kSplitGrid = 256;
+// at most this many workgroups: one per CU (float64: 139 KiB of LDS)
+template <typename T>
+constexpr int split_grid() {
+  return 256;
+}
 constexpr int kSplitTw = FBST_K3_TW;
 
-template <typename TIN, typename TOUT, int P>
+template <typename T, typename TIN, typename TOUT, int P>
 __global__ __launch_bounds__(Shape<P / 2>::THREADS) void k_toeplitz_fu_split(
-    const cx<TIN>* __restrict__ w, const OutPtrs outs, const cx<double>* __restrict__ G1,
-    const cx<double>* __restrict__ G2, const cx<double>* __restrict__ pre3,
-    const cx<double>* __restrict__ H3, const cx<double>* __restrict__ post3,
-    const cx<double>* __restrict__ twg, int B, int L, int N, int nblocks,
-    cx<double>* __restrict__ scratch) {
-  using T = double;
+    const cx<TIN>* __restrict__ w, const OutPtrs outs, const cx<T>* __restrict__ G1,
+    const cx<T>* __restrict__ G2, const cx<T>* __restrict__ pre3,
+    const cx<T>* __restrict__ H3, const cx<T>* __restrict__ post3,
+    const cx<T>* __restrict__ twg, int B, int L, int N, int nblocks,
+    cx<T>* __restrict__ scratch) {
   constexpr int H = P / 2;
   using SH = Shape<H>;
   static_assert(SH::G == 1, "one half transform per workgroup");
@@ -550,26 +553,27 @@ __global__ __launch_bounds__(Shape<P / 2>::THREADS) void k_toeplitz_fu_split(
 
 }  // namespace
 
-size_t split_scratch_bytes(int P) {
-  return static_cast<size_t>(kSplitGrid) * 2 * P * sizeof(cx<double>);
+size_t split_scratch_bytes(int P, bool dbl) {
+  return dbl ? static_cast<size_t>(split_grid<double>()) * 2 * P * sizeof(cx<double>)
+             : static_cast<size_t>(split_grid<float>()) * 2 * P * sizeof(cx<float>);
 }
 
-template <typename TIN, typename TOUT>
+template <typename T, typename TIN, typename TOUT>
 hipError_t launch_toeplitz_fu_split(int P, const void* w, const OutPtrs& outs, const void* G1,
                                     const void* G2, const void* pre3, const void* H3,
                                     const void* post3, const void* tw, void* scratch, int B, int L,
                                     int N, int nblocks, hipStream_t st) {
   if (nblocks < 1 || nblocks > MAX_LAUNCH_BLOCKS || !scratch) return hipErrorInvalidValue;
   if (2 * L > P || N + L - 1 > P) return hipErrorInvalidValue;
-  const int grid = std::min(kSplitGrid, nblocks * B);
+  const int grid = std::min(split_grid<T>(), nblocks * B);
   switch (P) {
 #define CASE(PP)                                                                               \
   case PP:                                                                                     \
-    hipLaunchKernelGGL((k_toeplitz_fu_split<TIN, TOUT, PP>), dim3(grid),                       \
+    hipLaunchKernelGGL((k_toeplitz_fu_split<T, TIN, TOUT, PP>), dim3(grid),                    \
                        dim3(Shape<PP / 2>::THREADS), 0, st, (const cx<TIN>*)w, outs,           \
-                       (const cx<double>*)G1, (const cx<double>*)G2, (const cx<double>*)pre3,  \
-                       (const cx<double>*)H3, (const cx<double>*)post3, (const cx<double>*)tw, \
-                       B, L, N, nblocks, (cx<double>*)scratch);                                \
+                       (const cx<T>*)G1, (const cx<T>*)G2, (const cx<T>*)pre3,                 \
+                       (const cx<T>*)H3, (const cx<T>*)post3, (const cx<T>*)tw,                \
+                       B, L, N, nblocks, (cx<T>*)scratch);                                     \
     return hipGetLastError();
     CASE(8192) CASE(16384)
 #undef CASE
@@ -579,15 +583,13 @@ hipError_t launch_toeplitz_fu_split(int P, const void* w, const OutPtrs& outs, c
   return hipErrorInvalidValue;
 }
 
-template hipError_t launch_toeplitz_fu_split<float, float>(int, const void*, const OutPtrs&,
-                                                           const void*, const void*, const void*,
-                                                           const void*, const void*, const void*,
-                                                           void*, int, int, int, int, hipStream_t);
-template hipError_t launch_toeplitz_fu_split<double, double>(int, const void*, const OutPtrs&,
-                                                             const void*, const void*, const void*,
-                                                             const void*, const void*, const void*,
-                                                             void*, int, int, int, int,
-                                                             hipStream_t);
+#define FBST_SPLIT_INST(T, TIN, TOUT)                                                          \
+  template hipError_t launch_toeplitz_fu_split<T, TIN, TOUT>(                                  \
+      int, const void*, const OutPtrs&, const void*, const void*, const void*, const void*,    \
+      const void*, const void*, void*, int, int, int, int, hipStream_t);
+FBST_SPLIT_INST(double, float, float)
+FBST_SPLIT_INST(double, double, double)
+#undef FBST_SPLIT_INST
 
 template hipError_t launch_toeplitz_fu<float, float, float>(
     int, const void*, const OutPtrs&, const void*, const void*, const void*, const void*, const void*,
