@@ -78,6 +78,30 @@ std::vector<zd> kernel_spectrum_int(int P, long long kmin, long long kmax, long 
   return h;
 }
 
+// Run fn(i0, i1) over [0, n) on the hardware threads when the work is large.
+int cpu_threads() {
+  cpu_set_t set;
+  if (sched_getaffinity(0, sizeof(set), &set) == 0) return std::max(1, CPU_COUNT(&set));
+  return std::max(1, static_cast<int>(std::thread::hardware_concurrency()));
+}
+
+template <typename F>
+void parallel_for(int n, long long cost, F&& fn) {
+  const int hw = cpu_threads();
+  const int nthreads = std::min({hw, n, 64});
+  if (nthreads <= 1 || cost < 4'000'000LL) {
+    fn(0, n);
+    return;
+  }
+  std::vector<std::thread> th;
+  const int per = (n + nthreads - 1) / nthreads;
+  for (int i = 0; i < nthreads; ++i) {
+    const int a = i * per, b = std::min(n, a + per);
+    if (a < b) th.emplace_back([&fn, a, b] { fn(a, b); });
+  }
+  for (auto& x : th) x.join();
+}
+
 void build_axis(const Params& p, int a_in, int a_out, double pos0, double d_samples, double u0,
                 double du, int P, AxisTables* ax) {
   const int L = p.L;
@@ -88,8 +112,10 @@ void build_axis(const Params& p, int a_in, int a_out, double pos0, double d_samp
   ax->H.assign(static_cast<size_t>(P) * L, zd());
   ax->post.assign(static_cast<size_t>(a_out) * L, zd());
   const double lp0 = 1.0 - 0.5 * L;
+  // frequencies are independent: split them over the host threads
+  parallel_for(L, 1LL * L * P * 16, [&](int l0, int l1) {
   std::vector<zd> h(P);
-  for (int l = 0; l < L; ++l) {
+  for (int l = l0; l < l1; ++l) {
     const double lp = l + lp0;
     const double rho = 2.0 * kPi * (p.fc * p.ts + p.eps * lp / L);   // rad per (sample of delay)
     const double theta = rho * d_samples * du;
@@ -110,6 +136,7 @@ void build_axis(const Params& p, int a_in, int a_out, double pos0, double d_samp
           cis(rho * d_samples * pos0 * (u0 + da * du) + 0.5 * theta * da * da);
     }
   }
+  });
 }
 
 // beta = A^{-1} r through the Gohberg-Semencul form with generator x
@@ -165,30 +192,6 @@ void refine_generator(const zd* col, int L, int P, std::vector<zd>* x) {
   gs_apply(*x, r, L, P, &dx);
   for (int i = 0; i < L; ++i) (*x)[i] += dx[i];
   (*x)[0] = zd((*x)[0].real(), 0.0);
-}
-
-// Run fn(i0, i1) over [0, n) on the hardware threads when the work is large.
-int cpu_threads() {
-  cpu_set_t set;
-  if (sched_getaffinity(0, sizeof(set), &set) == 0) return std::max(1, CPU_COUNT(&set));
-  return std::max(1, static_cast<int>(std::thread::hardware_concurrency()));
-}
-
-template <typename F>
-void parallel_for(int n, long long cost, F&& fn) {
-  const int hw = cpu_threads();
-  const int nthreads = std::min({hw, n, 64});
-  if (nthreads <= 1 || cost < 4'000'000LL) {
-    fn(0, n);
-    return;
-  }
-  std::vector<std::thread> th;
-  const int per = (n + nthreads - 1) / nthreads;
-  for (int i = 0; i < nthreads; ++i) {
-    const int a = i * per, b = std::min(n, a + per);
-    if (a < b) th.emplace_back([&fn, a, b] { fn(a, b); });
-  }
-  for (auto& x : th) x.join();
 }
 
 // sum_m exp(j (ax xs_m + ay ys_m)) over the elements, positions in samples of
