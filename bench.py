@@ -772,16 +772,26 @@ def main():
         # the untuned configuration for comparison: the plan's default stage-2
         # variant at 16 blocks per launch
         u_var, u_chunk = plan.variant, min(16, nblk)
-        plan.execute_batched(x, beams=beams, workspace=tune_ws, max_chunk=u_chunk)
-        ua, ub = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        ua.record()
-        for _ in range(5):
-            plan.execute_batched(x, beams=beams, workspace=tune_ws, max_chunk=u_chunk)
-        ub.record()
-        torch.cuda.synchronize()
-        untuned = {"blocks_per_launch": u_chunk, "k3_variant": u_var,
-                   "ms_per_step": ua.elapsed_time(ub) / 5}
         tuned_chunk, tuned_var, tuned_ms = plan.autotune_ex(x, beams=beams, workspace=tune_ws)
+
+        def step_ms(var, ch):
+            # both configurations timed alike, after the autotuner's sweep has
+            # warmed the GPU: 3 untimed, 10 timed steps
+            plan.variant = var
+            for _ in range(3):
+                plan.execute_batched(x, beams=beams, workspace=tune_ws, max_chunk=ch)
+            ua, ub = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ua.record()
+            for _ in range(10):
+                plan.execute_batched(x, beams=beams, workspace=tune_ws, max_chunk=ch)
+            ub.record()
+            torch.cuda.synchronize()
+            return ua.elapsed_time(ub) / 10
+
+        untuned = {"blocks_per_launch": u_chunk, "k3_variant": u_var,
+                   "ms_per_step": step_ms(u_var, u_chunk)}
+        tuned_ms = step_ms(tuned_var, tuned_chunk)
+        plan.variant = tuned_var
         del tune_ws
         chunk = tuned_chunk
         print(f"[bench] autotuned: {chunk} blocks per launch, stage-2 variant {tuned_var} "

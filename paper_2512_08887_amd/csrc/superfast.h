@@ -80,20 +80,28 @@ __host__ __device__ inline int depth_caps(int L, int* cap) {
   return d + 1;
 }
 
+// FFT size of the window advance at a node of n steps (n1 = n / 2 of them
+// first): the windows of n coefficients convolved with Theta_1 (degree n1).
+__host__ __device__ inline int advance_size(int n) { return pow2_at_least(n / 2 + n); }
+
 // Scratch (complex128 elements) one solve of L coefficients needs: per depth
-// the windows (2 cap), Theta_1 and the result Theta (4 (cap + 1) each), plus 8
-// spectra of the largest FFT size (a window advance uses 5 of size <= max_fft,
-// a Theta product 9 of size <= max_fft / 2).
+// the windows (2 cap), Theta_1 and the result Theta (4 (cap + 1) each) and the
+// spectra of Theta_1 at the advance size (4 advance_size(cap)), kept for the
+// product Theta_2 Theta_1; plus 12 spectra of the largest FFT size (a window
+// advance uses 8 of size <= max_fft, a Theta product 8 of size <= max_fft / 2).
 __host__ __device__ inline size_t scratch_elems(int L) {
   int cap[kMaxDepth];
   const int D = depth_caps(L, cap);
   size_t n = 0;
-  for (int d = 0; d < D; ++d) n += 2 * static_cast<size_t>(cap[d]) + 8 * (static_cast<size_t>(cap[d]) + 1);
+  for (int d = 0; d < D; ++d)
+    n += 2 * static_cast<size_t>(cap[d]) + 8 * (static_cast<size_t>(cap[d]) + 1) +
+         4 * static_cast<size_t>(advance_size(cap[d]));
   return n + 8 * static_cast<size_t>(max_fft(L));
 }
 
-// LDS (or host buffer) elements: one FFT of the largest size, plus the base
-// case's windows and Theta in two copies.
+// LDS (or host buffer) elements: the transforms' buffer (max_fft points: one
+// transform of the largest size, or several smaller ones at once), plus the
+// base case's windows and Theta in two copies.
 __host__ __device__ inline int lds_elems(int L) {
   return max_fft(L) + 2 * (2 * kBase + 4 * (kBase + 1));
 }
@@ -104,48 +112,78 @@ struct Ctx {
   int PM;
 };
 
-// In-place radix-2 transform of P points held in bit-reversed order in buf,
-// result in natural order; dir = -1 forward, +1 inverse (unscaled).
+// One transform of a batch: dst[i] = s X[off + i] for i < ndst, X the P-point
+// DFT (dir -1) or unscaled inverse (dir +1, s = 1 / P; else s = 1) of src
+// zero-padded from nsrc points.
+struct Xf {
+  const z* src;
+  int nsrc;
+  z* dst;
+  int off, ndst;
+};
+
+// exp(dir 2 pi j k / Q) from the table, Q a power of two <= PM, k < Q / 2
+__host__ __device__ inline z twid(const Ctx& c, int k, int Q, int dir) {
+  z w = c.tw[k * (c.PM / Q)];
+  if (dir > 0) w.im = -w.im;
+  return w;
+}
+
+// cnt transforms of P points (P a power of two), as many at a time as buf
+// (cap elements) holds: bit-reversed load, radix-4 decimation-in-time passes
+// (a radix-2 pass first when log2 P is odd), store.  Transforms of one group
+// share every barrier.
 template <class Sync>
-__host__ __device__ void fft_inplace(z* buf, int P, int dir, const Ctx& cx_, Sync sync) {
-  for (int half = 1; half < P; half <<= 1) {
-    const int stride = cx_.PM / (2 * half);
-    for (int q = cx_.tid; q < P / 2; q += cx_.nth) {
-      const int k = q % half;
-      const int i = (q / half) * 2 * half + k;
-      z w = cx_.tw[k * stride];
-      if (dir > 0) w.im = -w.im;
-      const z a = buf[i], b = cmul(buf[i + half], w);
-      buf[i] = a + b;
-      buf[i + half] = a - b;
+__host__ __device__ void xforms(const Xf* jobs, int cnt, int P, int dir, z* buf, int cap,
+                                const Ctx& c, Sync sync) {
+  const int bits = ilog2(P);
+  const int per = cap / P > 0 ? cap / P : 1;
+  const double s = dir > 0 ? 1.0 / P : 1.0;
+  for (int j0 = 0; j0 < cnt; j0 += per) {
+    const int g = (cnt - j0 < per) ? cnt - j0 : per;
+    for (int i = c.tid; i < g * P; i += c.nth) {
+      const int t = i / P, ii = i - t * P;
+      const Xf& jb = jobs[j0 + t];
+      buf[t * P + bitrev(ii, bits)] = (ii < jb.nsrc) ? jb.src[ii] : z{0.0, 0.0};
+    }
+    sync();
+    int h = 1;
+    if (bits & 1) {                       // radix-2: pairs (i, i + 1)
+      for (int q = c.tid; q < g * P / 2; q += c.nth) {
+        z* b = buf + 2 * q;
+        const z a0 = b[0], a1 = b[1];
+        b[0] = a0 + a1;
+        b[1] = a0 - a1;
+      }
+      sync();
+      h = 2;
+    }
+    for (; h < P; h <<= 2) {              // radix-4: the stages of spans h and 2h at once
+      const int quarter = P / 4;
+      for (int q = c.tid; q < g * quarter; q += c.nth) {
+        const int t = q / quarter, qq = q - t * quarter;
+        const int k = qq % h;
+        z* b = buf + t * P + (qq / h) * 4 * h + k;
+        const z w2 = twid(c, k, 2 * h, dir), w4 = twid(c, k, 4 * h, dir);
+        const z a0 = b[0], a1 = cmul(b[h], w2), a2 = b[2 * h], a3 = cmul(b[3 * h], w2);
+        const z b0 = a0 + a1, b1 = a0 - a1, b2 = a2 + a3, b3 = a2 - a3;
+        const z u2 = cmul(b2, w4);
+        z u3 = cmul(b3, w4);
+        u3 = dir < 0 ? z{u3.im, -u3.re} : z{-u3.im, u3.re};   // times exp(dir j pi / 2)
+        b[0] = b0 + u2;
+        b[2 * h] = b0 - u2;
+        b[h] = b1 + u3;
+        b[3 * h] = b1 - u3;
+      }
+      sync();
+    }
+    for (int i = c.tid; i < g * P; i += c.nth) {
+      const int t = i / P, ii = i - t * P;
+      const Xf& jb = jobs[j0 + t];
+      if (ii < jb.ndst) jb.dst[ii] = buf[t * P + jb.off + ii] * s;
     }
     sync();
   }
-}
-
-// spec = FFT_P(a zero-padded), a of length na <= P.
-template <class Sync>
-__host__ __device__ void forward(const z* a, int na, z* spec, z* buf, int P, const Ctx& c,
-                                 Sync sync) {
-  const int bits = ilog2(P);
-  for (int i = c.tid; i < P; i += c.nth) buf[bitrev(i, bits)] = (i < na) ? a[i] : z{0.0, 0.0};
-  sync();
-  fft_inplace(buf, P, -1, c, sync);
-  for (int i = c.tid; i < P; i += c.nth) spec[i] = buf[i];
-  sync();
-}
-
-// out[i] = IFFT_P(spec)[off + i] for i < n (scaled by 1 / P).
-template <class Sync>
-__host__ __device__ void inverse(const z* spec, z* out, int off, int n, z* buf, int P, const Ctx& c,
-                                 Sync sync) {
-  const int bits = ilog2(P);
-  for (int i = c.tid; i < P; i += c.nth) buf[bitrev(i, bits)] = spec[i];
-  sync();
-  fft_inplace(buf, P, +1, c, sync);
-  const double s = 1.0 / P;
-  for (int i = c.tid; i < n; i += c.nth) out[i] = buf[off + i] * s;
-  sync();
 }
 
 // n <= kBase Schur steps on windows f, g (length >= n): Theta (4 arrays of
@@ -197,77 +235,94 @@ __host__ __device__ void base_case(const z* f, const z* g, int n, z* th, z* lds,
 
 // New windows (nout each, [f | g] to wout) after the m steps of Theta_1 (th1,
 // m + 1 coefficients per entry) from windows f, g of length nin = m + nout.
+// The spectra of Theta_1's entries at P = pow2(m + nin) go to ts (4 P), for
+// the product Theta_2 Theta_1 when it has the same size.
 template <class Sync>
 __host__ __device__ void advance(const z* th1, int m, const z* f, const z* g, int nin, int nout,
-                                 z* wout, z* spec, z* lds, const Ctx& c, Sync sync) {
+                                 z* wout, z* ts, z* spec, z* lds, int cap, const Ctx& c,
+                                 Sync sync) {
   const int P = pow2_at_least(m + nin);
   z* Ff = spec;
   z* Fg = spec + P;
-  z* S = spec + 2 * P;
-  z* Af = spec + 3 * P;
-  z* Ag = spec + 4 * P;
+  z* Af = spec + 2 * P;
+  z* Ag = spec + 3 * P;
+  const Xf fw[6] = {{f, nin, Ff, 0, P},
+                    {g, nin, Fg, 0, P},
+                    {th1, m + 1, ts, 0, P},
+                    {th1 + (m + 1), m + 1, ts + P, 0, P},
+                    {th1 + 2 * (m + 1), m + 1, ts + 2 * P, 0, P},
+                    {th1 + 3 * (m + 1), m + 1, ts + 3 * P, 0, P}};
+  xforms(fw, 6, P, -1, lds, cap, c, sync);
+  // Af = T11 Ff + T12 Fg e^{+2 pi j k / P};  Ag = T21 Ff e^{-2 pi j k / P} + T22 Fg
   const int stride = c.PM / P;
-  forward(f, nin, Ff, lds, P, c, sync);
-  forward(g, nin, Fg, lds, P, c, sync);
-  for (int e = 0; e < 4; ++e) {
-    forward(th1 + e * (m + 1), m + 1, S, lds, P, c, sync);
-    // Af = T11 Ff + T12 Fg e^{+2 pi j k / P};  Ag = T21 Ff e^{-2 pi j k / P} + T22 Fg
-    for (int k = c.tid; k < P; k += c.nth) {
-      // e^{-2 pi j k / P} from the table (k < P; tw holds half a turn)
-      const int kk = (k % P) * stride;
-      z w = (kk < c.PM / 2) ? c.tw[kk] : z{-c.tw[kk - c.PM / 2].re, -c.tw[kk - c.PM / 2].im};
-      z v;
-      if (e == 0) v = cmul(S[k], Ff[k]);
-      else if (e == 1) v = cmul(cmul(S[k], Fg[k]), conjg(w));
-      else if (e == 2) v = cmul(cmul(S[k], Ff[k]), w);
-      else v = cmul(S[k], Fg[k]);
-      if (e < 2) Af[k] = (e == 0) ? v : Af[k] + v;
-      else Ag[k] = (e == 2) ? v : Ag[k] + v;
-    }
-    sync();
+  for (int k = c.tid; k < P; k += c.nth) {
+    const int kk = k * stride;   // e^{-2 pi j k / P} from the table (half a turn)
+    const z w = (kk < c.PM / 2) ? c.tw[kk] : z{-c.tw[kk - c.PM / 2].re, -c.tw[kk - c.PM / 2].im};
+    const z ff = Ff[k], fg = Fg[k];
+    Af[k] = cmul(ts[k], ff) + cmul(cmul(ts[P + k], fg), conjg(w));
+    Ag[k] = cmul(cmul(ts[2 * P + k], ff), w) + cmul(ts[3 * P + k], fg);
   }
-  inverse(Af, wout, m, nout, lds, P, c, sync);
-  inverse(Ag, wout + nout, m, nout, lds, P, c, sync);
+  sync();
+  const Xf iv[2] = {{Af, P, wout, m, nout}, {Ag, P, wout + nout, m, nout}};
+  xforms(iv, 2, P, +1, lds, cap, c, sync);
 }
 
 // Theta = Theta_2 Theta_1 (entries of n2 + 1 and n1 + 1 coefficients) to th,
-// n + 1 coefficients per entry (n = n1 + n2).
+// n + 1 coefficients per entry (n = n1 + n2).  ts: Theta_1's spectra at size
+// pts (from advance), used when pts is this product's size.
 template <class Sync>
-__host__ __device__ void combine(const z* th2, int n2, const z* th1, int n1, z* th, z* spec,
-                                 z* lds, const Ctx& c, Sync sync) {
+__host__ __device__ void combine(const z* th2, int n2, const z* th1, int n1, const z* ts, int pts,
+                                 z* th, z* spec, z* lds, int cap, const Ctx& c, Sync sync) {
   const int n = n1 + n2;
   const int P = pow2_at_least(n + 1);
-  z* A = spec;              // spectra of Theta_1's entries, 4 P
+  z* T = spec;              // spectra of Theta_2's entries, 4 P
   z* R = spec + 4 * P;      // products, 4 P
-  for (int e = 0; e < 4; ++e) forward(th1 + e * (n1 + 1), n1 + 1, A + e * P, lds, P, c, sync);
-  for (int e = 0; e < 4; ++e) {
-    // spectrum of Theta_2 entry e (row r = e / 2, column q = e % 2) into a
-    // temporary, then R_{r,s} += T2_{r,q} T1_{q,s}
-    z* T = R + 4 * P;      // the fifth scratch spectrum
-    forward(th2 + e * (n2 + 1), n2 + 1, T, lds, P, c, sync);
-    const int r = e / 2, q = e % 2;
-    for (int k = c.tid; k < P; k += c.nth)
-      for (int s = 0; s < 2; ++s) {
-        const z v = cmul(T[k], A[(2 * q + s) * P + k]);
-        z* dst = R + (2 * r + s) * P;
-        dst[k] = (q == 0) ? v : dst[k] + v;
-      }
-    sync();
+  z* A1 = spec + 8 * P;     // Theta_1's spectra when they must be recomputed
+  const z* A = ts;
+  if (pts != P) {
+    const Xf fa[4] = {{th1, n1 + 1, A1, 0, P},
+                      {th1 + (n1 + 1), n1 + 1, A1 + P, 0, P},
+                      {th1 + 2 * (n1 + 1), n1 + 1, A1 + 2 * P, 0, P},
+                      {th1 + 3 * (n1 + 1), n1 + 1, A1 + 3 * P, 0, P}};
+    xforms(fa, 4, P, -1, lds, cap, c, sync);
+    A = A1;
   }
-  for (int e = 0; e < 4; ++e) inverse(R + e * P, th + e * (n + 1), 0, n + 1, lds, P, c, sync);
+  const Xf fb[4] = {{th2, n2 + 1, T, 0, P},
+                    {th2 + (n2 + 1), n2 + 1, T + P, 0, P},
+                    {th2 + 2 * (n2 + 1), n2 + 1, T + 2 * P, 0, P},
+                    {th2 + 3 * (n2 + 1), n2 + 1, T + 3 * P, 0, P}};
+  xforms(fb, 4, P, -1, lds, cap, c, sync);
+  // R_{r,s} = sum_q T_{r,q} A_{q,s}  (entry e = 2 r + s)
+  for (int k = c.tid; k < P; k += c.nth) {
+    const z t11 = T[k], t12 = T[P + k], t21 = T[2 * P + k], t22 = T[3 * P + k];
+    const z a11 = A[k], a12 = A[P + k], a21 = A[2 * P + k], a22 = A[3 * P + k];
+    R[k] = cmul(t11, a11) + cmul(t12, a21);
+    R[P + k] = cmul(t11, a12) + cmul(t12, a22);
+    R[2 * P + k] = cmul(t21, a11) + cmul(t22, a21);
+    R[3 * P + k] = cmul(t21, a12) + cmul(t22, a22);
+  }
+  sync();
+  const Xf iv[4] = {{R, P, th, 0, n + 1},
+                    {R + P, P, th + (n + 1), 0, n + 1},
+                    {R + 2 * P, P, th + 2 * (n + 1), 0, n + 1},
+                    {R + 3 * P, P, th + 3 * (n + 1), 0, n + 1}};
+  xforms(iv, 4, P, +1, lds, cap, c, sync);
 }
 
 // x = A^{-1} e_0 for the first column col (L coefficients, L >= 2).
 // scratch: scratch_elems(L); lds: lds_elems(L).  Returns false when a pivot
 // eps_k is not positive (then x is unspecified).
-template <class Sync>
+// base(f, g, n, th, buf) runs base_case on windows f, g (buf: its LDS area)
+// and returns once th is visible to the whole group.
+template <class Sync, class Base>
 __host__ __device__ bool generator(const z* col, z* x, int L, z* scratch, z* lds, const Ctx& c,
-                                   Sync sync) {
+                                   Sync sync, Base base) {
   int cap[kMaxDepth];
   const int D = depth_caps(L, cap);
   z* win[kMaxDepth];
   z* t1[kMaxDepth];
   z* res[kMaxDepth];
+  z* ts[kMaxDepth];
   z* p = scratch;
   for (int d = 0; d < D; ++d) {
     win[d] = p;
@@ -276,8 +331,11 @@ __host__ __device__ bool generator(const z* col, z* x, int L, z* scratch, z* lds
     p += 4 * (static_cast<size_t>(cap[d]) + 1);
     res[d] = p;
     p += 4 * (static_cast<size_t>(cap[d]) + 1);
+    ts[d] = p;
+    p += 4 * static_cast<size_t>(advance_size(cap[d]));
   }
   z* spec = p;
+  const int xcap = max_fft(L);    // transform buffer at the start of lds
   struct Frame {
     int n, n1, state;
     const z* f;
@@ -291,7 +349,7 @@ __host__ __device__ bool generator(const z* col, z* x, int L, z* scratch, z* lds
     const int d = top;
     if (fr.state == 0) {
       if (fr.n <= kBase) {
-        base_case(fr.f, fr.g, fr.n, res[d], lds + max_fft(L), c, sync);
+        base(fr.f, fr.g, fr.n, res[d], lds + max_fft(L));
         --top;
         continue;
       }
@@ -303,13 +361,14 @@ __host__ __device__ bool generator(const z* col, z* x, int L, z* scratch, z* lds
       const int n1 = fr.n1, n2 = fr.n - fr.n1;
       for (int i = c.tid; i < 4 * (n1 + 1); i += c.nth) t1[d][i] = res[d + 1][i];
       sync();
-      advance(t1[d], n1, fr.f, fr.g, fr.n, n2, win[d + 1], spec, lds, c, sync);
+      advance(t1[d], n1, fr.f, fr.g, fr.n, n2, win[d + 1], ts[d], spec, lds, xcap, c, sync);
       fr.state = 2;
       st[top + 1] = Frame{n2, 0, 0, win[d + 1], win[d + 1] + n2};
       ++top;
     } else {
       const int n1 = fr.n1, n2 = fr.n - fr.n1;
-      combine(res[d + 1], n2, t1[d], n1, res[d], spec, lds, c, sync);
+      combine(res[d + 1], n2, t1[d], n1, ts[d], pow2_at_least(n1 + fr.n), res[d], spec, lds, xcap,
+              c, sync);
       --top;
     }
   }
@@ -325,6 +384,16 @@ __host__ __device__ bool generator(const z* col, z* x, int L, z* scratch, z* lds
   for (int i = c.tid; i < L; i += c.nth) x[i] = zdiv(x[i], eps);
   sync();
   return true;
+}
+
+// The same with the base cases run by the whole group.
+template <class Sync>
+__host__ __device__ bool generator(const z* col, z* x, int L, z* scratch, z* lds, const Ctx& c,
+                                   Sync sync) {
+  return generator(col, x, L, scratch, lds, c, sync,
+                   [&](const z* f, const z* g, int n, z* th, z* buf) {
+                     base_case(f, g, n, th, buf, c, sync);
+                   });
 }
 
 }  // namespace superfast

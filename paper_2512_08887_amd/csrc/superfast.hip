@@ -24,6 +24,18 @@ struct DevSync {
   __device__ void operator()() const { __syncthreads(); }
 };
 
+// Ordering among the lanes of one wave: the wave's LDS operations complete in
+// issue order, so a fence at wavefront scope (which keeps the compiler from
+// moving memory operations across it) is all a base case run by one wave
+// needs between its steps.
+struct WaveSync {
+  __device__ void operator()() const {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+};
+
 __global__ __launch_bounds__(kSfThreads) void k_superfast(const cx<double>* __restrict__ cols,
                                                           cx<double>* __restrict__ x,
                                                           int* __restrict__ status, int B, int L,
@@ -36,7 +48,17 @@ __global__ __launch_bounds__(kSfThreads) void k_superfast(const cx<double>* __re
   cx<double>* sc = scratch + static_cast<size_t>(blockIdx.x) * per_wg;
   for (int b = blockIdx.x; b < B; b += gridDim.x) {
     const size_t off = static_cast<size_t>(b) * L;
-    const bool ok = superfast::generator(cols + off, x + off, L, sc, lds, c, DevSync{});
+    // base cases (at most 32 steps on windows of at most 32 coefficients) on
+    // the first wave alone, without workgroup barriers between their steps
+    auto base = [&](const cx<double>* f, const cx<double>* g, int n, cx<double>* th,
+                    cx<double>* buf) {
+      if (threadIdx.x < 64) {
+        const superfast::Ctx cw{static_cast<int>(threadIdx.x), 64, tw, PM};
+        superfast::base_case(f, g, n, th, buf, cw, WaveSync{});
+      }
+      __syncthreads();
+    };
+    const bool ok = superfast::generator(cols + off, x + off, L, sc, lds, c, DevSync{}, base);
     if (threadIdx.x == 0) status[b] = ok ? 0 : 1;
     __syncthreads();
   }
