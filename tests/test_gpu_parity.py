@@ -274,3 +274,17 @@ def test_refined_stage2_small(shape):
     assert np.array_equal(out[1], one)
     assert np.array_equal(st2, out)
     plan.close()
+
+
+def test_zero_blocks_is_a_no_op():
+    """nblocks = 0 launches nothing and leaves the outputs as they were."""
+    need_gpu()
+    plan = F.Plan(8, 64, 8, band=F.make_band(2.0, 0.5, 1.0), options=F.make_options(0.1 * 2 * 64))
+    x = torch.zeros((0, 8, 64), dtype=torch.complex64, device="cuda")
+    beams = torch.full((1, 8, 64), 7.0 + 0j, dtype=torch.complex64, device="cuda")
+    F.fbst_execute_batched(plan.handle, 0, 0, beams.data_ptr(), beams.data_ptr())
+    F.fbst_execute_static(plan.handle, 0, beams.data_ptr(), beams.data_ptr())
+    torch.cuda.synchronize()
+    assert torch.all(beams == 7.0)
+    assert x.numel() == 0
+    plan.close()

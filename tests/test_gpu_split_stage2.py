@@ -152,3 +152,44 @@ def test_split_stage2_ula1024_paper_conditioning():
         print(f"ula1024 fp64 delta {delta:.3g} (cond bound {cond:.2e}) beam {b}: {e:.2e} "
               f"(bar {bar:.1e})", flush=True)
         assert e < bar, (b, e)
+
+
+def test_split_stage2_served_and_static():
+    """The fixed scratch of the split stage 2 goes with every launch: the
+    server reserves nblocks * per-block + fixed bytes (batches of 2 and 3
+    blocks and a single one equal fbst_execute bit for bit; a budget below
+    one block plus the scratch fails the request cleanly), and the
+    allocation-free entry point, whose array is smaller than the scratch,
+    refuses the plan."""
+    need_gpu()
+    cfg = line_cfg(16, 2800, 16, index=143)
+    plan = F.plan_for_config(cfg, precision="fp64_stage2")
+    info = plan.info
+    ys = np.stack([cfg.scene().block(k) for k in range(5)]).astype(np.complex64)
+    xs = [torch.from_numpy(y).cuda() for y in ys]
+    outs = [torch.empty((cfg.B, cfg.N), dtype=torch.complex64, device="cuda") for _ in xs]
+    torch.cuda.synchronize()
+    budget = 3 * info.workspace_per_block + info.workspace_fixed + (1 << 20)
+    srv = F.Server(workspace_bytes=budget, streams=2, max_batch=3)
+    for tag, (x, o) in enumerate(zip(xs, outs)):
+        srv.submit(plan, x, o, tag)
+    srv.drain(timeout_s=60)
+    comps = srv.poll(16)
+    srv.close()
+    assert sorted(c.tag for c in comps) == list(range(len(xs)))
+    assert all(c.status == F.FBST_OK for c in comps)
+    for x, o in zip(xs, outs):
+        alone = plan.execute(x)
+        torch.cuda.synchronize()
+        assert torch.equal(alone, o)
+    small = F.Server(workspace_bytes=info.workspace_per_block + info.workspace_fixed // 2,
+                     streams=1, max_batch=1)
+    small.submit(plan, xs[0], outs[0], 99)
+    small.drain(timeout_s=30)
+    c = small.poll(4)
+    small.close()
+    assert len(c) == 1 and c[0].status == F.FBST_E_NOMEM
+    with pytest.raises(F.FbstError) as e:
+        plan.execute_static(xs[0][None], outs[0][None])
+    assert e.value.status == F.FBST_E_UNSUPPORTED
+    plan.close()
