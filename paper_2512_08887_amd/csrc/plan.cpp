@@ -796,6 +796,7 @@ namespace {
 
 struct HostSync {
   void operator()() const {}
+  void wave() const {}
 };
 
 }  // namespace

@@ -38,7 +38,10 @@ namespace superfast {
 
 using z = cx<double>;
 
-constexpr int kBase = 32;       // steps done directly (Schur) below this many
+#ifndef FBST_SF_BASE
+#define FBST_SF_BASE 64
+#endif
+constexpr int kBase = FBST_SF_BASE;   // steps done directly (Schur) below this many
 constexpr int kMaxDepth = 24;
 
 __host__ __device__ inline int pow2_at_least(int n) {
@@ -129,16 +132,77 @@ __host__ __device__ inline z twid(const Ctx& c, int k, int Q, int dir) {
   return w;
 }
 
-// cnt transforms of P points (P a power of two), as many at a time as buf
-// (cap elements) holds: bit-reversed load, radix-4 decimation-in-time passes
-// (a radix-2 pass first when log2 P is odd), store.  Transforms of one group
-// share every barrier.
+// Radix-2 / radix-4 decimation-in-time passes over g transforms of P points
+// at b (bit-reversed order in, natural order out), by lanes lane, lane + W, ...
+// of W, with step() between passes.
+template <class Step>
+__host__ __device__ void dit_passes(z* b, int g, int P, int dir, int lane, int W, const Ctx& c,
+                                    Step step) {
+  const int bits = ilog2(P);
+  int h = 1;
+  if (bits & 1) {                         // radix-2: pairs (i, i + 1)
+    for (int q = lane; q < g * P / 2; q += W) {
+      z* e = b + 2 * q;
+      const z a0 = e[0], a1 = e[1];
+      e[0] = a0 + a1;
+      e[1] = a0 - a1;
+    }
+    step();
+    h = 2;
+  }
+  for (; h < P; h <<= 2) {                // radix-4: the stages of spans h and 2h at once
+    const int quarter = P / 4;
+    for (int q = lane; q < g * quarter; q += W) {
+      const int t = q / quarter, qq = q - t * quarter;
+      const int k = qq % h;
+      z* e = b + t * P + (qq / h) * 4 * h + k;
+      const z w2 = twid(c, k, 2 * h, dir), w4 = twid(c, k, 4 * h, dir);
+      const z a0 = e[0], a1 = cmul(e[h], w2), a2 = e[2 * h], a3 = cmul(e[3 * h], w2);
+      const z b0 = a0 + a1, b1 = a0 - a1, b2 = a2 + a3, b3 = a2 - a3;
+      const z u2 = cmul(b2, w4);
+      z u3 = cmul(b3, w4);
+      u3 = dir < 0 ? z{u3.im, -u3.re} : z{-u3.im, u3.re};   // times exp(dir j pi / 2)
+      e[0] = b0 + u2;
+      e[2 * h] = b0 - u2;
+      e[h] = b1 + u3;
+      e[3 * h] = b1 - u3;
+    }
+    step();
+  }
+}
+
+// Transforms up to this size run one per wave (ordering among the wave's
+// lanes only) when the group has several waves.
+constexpr int kWaveP = 512;
+
+// cnt transforms of P points (P a power of two): bit-reversed load, radix-4
+// decimation-in-time passes (a radix-2 pass first when log2 P is odd), store.
+// Small transforms: each wave of the group takes whole transforms in turn
+// in its own part of buf, with only sync.wave() between its steps.  Larger
+// ones: as many at a time as buf (cap elements) holds, the whole group on
+// each, sharing every barrier.
 template <class Sync>
 __host__ __device__ void xforms(const Xf* jobs, int cnt, int P, int dir, z* buf, int cap,
                                 const Ctx& c, Sync sync) {
   const int bits = ilog2(P);
   const int per = cap / P > 0 ? cap / P : 1;
   const double s = dir > 0 ? 1.0 / P : 1.0;
+  const int W = c.nth < 64 ? c.nth : 64;
+  const int nw = c.nth / W;
+  if (nw > 1 && P <= kWaveP && nw * P <= cap) {
+    const int lane = c.tid % W, wave = c.tid / W;
+    z* b = buf + wave * P;
+    for (int j = wave; j < cnt; j += nw) {
+      const Xf& jb = jobs[j];
+      for (int i = lane; i < P; i += W) b[bitrev(i, bits)] = (i < jb.nsrc) ? jb.src[i] : z{0.0, 0.0};
+      sync.wave();
+      dit_passes(b, 1, P, dir, lane, W, c, [&] { sync.wave(); });
+      for (int i = lane; i < jb.ndst; i += W) jb.dst[i] = b[jb.off + i] * s;
+      sync.wave();
+    }
+    sync();
+    return;
+  }
   for (int j0 = 0; j0 < cnt; j0 += per) {
     const int g = (cnt - j0 < per) ? cnt - j0 : per;
     for (int i = c.tid; i < g * P; i += c.nth) {
@@ -147,36 +211,7 @@ __host__ __device__ void xforms(const Xf* jobs, int cnt, int P, int dir, z* buf,
       buf[t * P + bitrev(ii, bits)] = (ii < jb.nsrc) ? jb.src[ii] : z{0.0, 0.0};
     }
     sync();
-    int h = 1;
-    if (bits & 1) {                       // radix-2: pairs (i, i + 1)
-      for (int q = c.tid; q < g * P / 2; q += c.nth) {
-        z* b = buf + 2 * q;
-        const z a0 = b[0], a1 = b[1];
-        b[0] = a0 + a1;
-        b[1] = a0 - a1;
-      }
-      sync();
-      h = 2;
-    }
-    for (; h < P; h <<= 2) {              // radix-4: the stages of spans h and 2h at once
-      const int quarter = P / 4;
-      for (int q = c.tid; q < g * quarter; q += c.nth) {
-        const int t = q / quarter, qq = q - t * quarter;
-        const int k = qq % h;
-        z* b = buf + t * P + (qq / h) * 4 * h + k;
-        const z w2 = twid(c, k, 2 * h, dir), w4 = twid(c, k, 4 * h, dir);
-        const z a0 = b[0], a1 = cmul(b[h], w2), a2 = b[2 * h], a3 = cmul(b[3 * h], w2);
-        const z b0 = a0 + a1, b1 = a0 - a1, b2 = a2 + a3, b3 = a2 - a3;
-        const z u2 = cmul(b2, w4);
-        z u3 = cmul(b3, w4);
-        u3 = dir < 0 ? z{u3.im, -u3.re} : z{-u3.im, u3.re};   // times exp(dir j pi / 2)
-        b[0] = b0 + u2;
-        b[2 * h] = b0 - u2;
-        b[h] = b1 + u3;
-        b[3 * h] = b1 - u3;
-      }
-      sync();
-    }
+    dit_passes(buf, g, P, dir, c.tid, c.nth, c, sync);
     for (int i = c.tid; i < g * P; i += c.nth) {
       const int t = i / P, ii = i - t * P;
       const Xf& jb = jobs[j0 + t];

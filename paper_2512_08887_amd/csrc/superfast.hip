@@ -20,20 +20,24 @@ constexpr int kSfLMax = 4096;
 // LDS elements for L <= kSfLMax: superfast::lds_elems(kSfLMax)
 constexpr int kSfLds = 2 * kSfLMax + 2 * (2 * superfast::kBase + 4 * (superfast::kBase + 1));
 
-struct DevSync {
-  __device__ void operator()() const { __syncthreads(); }
-};
-
 // Ordering among the lanes of one wave: the wave's LDS operations complete in
 // issue order, so a fence at wavefront scope (which keeps the compiler from
-// moving memory operations across it) is all a base case run by one wave
+// moving memory operations across it) is all that work done by one wave
 // needs between its steps.
+__device__ __forceinline__ void wave_order() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+struct DevSync {
+  __device__ void operator()() const { __syncthreads(); }
+  __device__ void wave() const { wave_order(); }
+};
+
 struct WaveSync {
-  __device__ void operator()() const {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  }
+  __device__ void operator()() const { wave_order(); }
+  __device__ void wave() const { wave_order(); }
 };
 
 __global__ __launch_bounds__(kSfThreads) void k_superfast(const cx<double>* __restrict__ cols,
@@ -48,7 +52,7 @@ __global__ __launch_bounds__(kSfThreads) void k_superfast(const cx<double>* __re
   cx<double>* sc = scratch + static_cast<size_t>(blockIdx.x) * per_wg;
   for (int b = blockIdx.x; b < B; b += gridDim.x) {
     const size_t off = static_cast<size_t>(b) * L;
-    // base cases (at most 32 steps on windows of at most 32 coefficients) on
+    // base cases (at most kBase steps on windows of at most kBase coefficients) on
     // the first wave alone, without workgroup barriers between their steps
     auto base = [&](const cx<double>* f, const cx<double>* g, int n, cx<double>* th,
                     cx<double>* buf) {
