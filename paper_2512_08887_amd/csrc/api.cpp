@@ -1364,7 +1364,8 @@ fbst_status fbst_plan_steer(fbst_plan* plan, const fbst_grid* grid, void* hip_st
   fbst::HostTables t;
   fbst::SteerKeys keys;
   try {
-    s = fbst::build_steer_tables(q, &t, &keys, &msg);
+    const bool refine_host = 2.0 * q.M * q.N / q.delta > 1e6;
+    s = fbst::build_steer_tables(q, &t, &keys, refine_host || plan->kept, &msg);
   } catch (const std::bad_alloc&) {
     return fail(FBST_E_NOMEM, "host allocation of the steering tables failed");
   }

@@ -1031,7 +1031,8 @@ fbst_status build_tables(const Params& p, bool keep_gram_gen, HostTables* t, std
 // of the new beams in the closed form of build_tables (a frame centred in
 // time and on the array: c_b(d) = exp(-j kd s_b) r_b(d)); the generators and
 // their spectra are left to the caller.
-fbst_status build_steer_tables(const Params& p, HostTables* t, SteerKeys* k, std::string* msg) {
+fbst_status build_steer_tables(const Params& p, HostTables* t, SteerKeys* k, bool cols,
+                               std::string* msg) {
   if (p.kind == FBST_ARBITRARY) {
     *msg = "a new beam grid is supported for lines and uniform grids";
     return FBST_E_UNSUPPORTED;
@@ -1072,15 +1073,21 @@ fbst_status build_steer_tables(const Params& p, HostTables* t, SteerKeys* k, std
   }
   const int K = static_cast<int>(keys.size());
   k->rcols.assign(static_cast<size_t>(K) * L, zd());
-  for (int q = 0; q < K; ++q) {
-    zd* r = k->rcols.data() + static_cast<size_t>(q) * L;
-    for (int d = 0; d < L; ++d) {
-      const double kd = 2.0 * kPi * p.eps * d / L;
-      double v = rt[d] * dirichlet(p.mx, kd * keys[q].first * dxs);
-      if (p.kind == FBST_GRID) v *= dirichlet(p.my, kd * keys[q].second * dys);
-      r[d] = zd(v, 0.0);
+  parallel_for(K, 1LL * K * L * 64, [&](int q0, int q1) {
+    for (int q = q0; q < q1; ++q) {
+      zd* r = k->rcols.data() + static_cast<size_t>(q) * L;
+      for (int d = 0; d < L; ++d) {
+        const double kd = 2.0 * kPi * p.eps * d / L;
+        double v = rt[d] * dirichlet(p.mx, kd * keys[q].first * dxs);
+        if (p.kind == FBST_GRID) v *= dirichlet(p.my, kd * keys[q].second * dys);
+        r[d] = zd(v, 0.0);
+      }
+      r[0] += p.delta;
     }
-    r[0] += p.delta;
+  });
+  if (!cols) {
+    t->cols.clear();
+    return FBST_OK;
   }
   // the complex columns of each beam (for the host refinement)
   t->cols.assign(static_cast<size_t>(B) * L, zd());

@@ -104,7 +104,9 @@ struct SteerKeys {
   std::vector<int> key;
   std::vector<double> s;
 };
-fbst_status build_steer_tables(const Params& p, HostTables* t, SteerKeys* k, std::string* msg);
+// cols: also the complex columns t->cols (needed by a host refinement).
+fbst_status build_steer_tables(const Params& p, HostTables* t, SteerKeys* k, bool cols,
+                               std::string* msg);
 
 // Beams at directions (ud, vd): K [l][d][n] = (F_u A_d^{-1})[n][l] and, when
 // E is given, the projection phases E [d][m][l] = exp(j a_l tau_{d,m}); float64.
