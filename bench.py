@@ -926,16 +926,18 @@ def main():
                      "gain": (untuned["ms_per_step"] / tuned_ms) if untuned else None,
                      "what": "fbst_autotune_ex over blocks per launch x stage-2 kernel variant "
                              "(bit 0 single-buffer form, bit 1 persistent grid, 4 three waves per "
-                             "SIMD); untuned = the plan's default variant at 16 blocks per launch"},
+                             "SIMD), then the stage-1b workgroup size (16 half, 32 twice the "
+                             "frequencies per workgroup); untuned = the plan's default variant at "
+                             "16 blocks per launch"},
         "stage_gflop_per_block": [s0 / 1e9, s1 / 1e9, s2 / 1e9],
         "path_tflops": (s0 + s1 + s2) * nblk / (ms_step / 1e3) / 1e12,
         "roofline": {"kernel": "k_toeplitz_fu (stage 2: Gohberg-Semencul apply + F_u chirp-z)",
                      "bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32,
                      "traffic": stored_traffic(
-                         f"k_toeplitz_fu<float, float, float, 4096, 4, 0, {plan.variant}>",
+                         f"k_toeplitz_fu<float, float, float, 4096, 4, 0, {plan.variant & 15}>",
                          chunk * cfg.B * 256),
-                     "k3_variant": plan.variant,
+                     "k3_variant": plan.variant & 15,
                      "avg_launch_ms": k3_ms,
                      "flops_per_launch": k3_flops_launch},
     }

@@ -322,6 +322,12 @@ fbst_status fbst_autotune(const fbst_plan* plan, int nblocks, const void* x, voi
 #define FBST_VARIANT_K3_PERSISTENT 2
 #define FBST_VARIANT_K3_WAVES3 4   /* with FBST_VARIANT_K3_SINGLE only: registers
                                       allocated for 3 waves per SIMD (spills)    */
+/* Stage-1b instances (bits 4-5, combined with any stage-2 variant): the
+ * space chirp-z's workgroup holds half (FBST_VARIANT_K2_TILE_HALF) or twice
+ * (FBST_VARIANT_K2_TILE_DOUBLE) the default number of frequencies; beams are
+ * bit-identical.  For lines and uniform grids with a float32 stage 1. */
+#define FBST_VARIANT_K2_TILE_HALF 16
+#define FBST_VARIANT_K2_TILE_DOUBLE 32
 
 /* As fbst_autotune, also over the stage-2 variants this plan can launch
  * (chunk x variant), and leaves the fastest variant set on the plan (the only

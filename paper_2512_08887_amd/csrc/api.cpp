@@ -227,9 +227,10 @@ template <typename T1>
 hipError_t run_stage1(const fbst_plan* pl, int nb, const void* yhat, void* w, void* z,
                       hipStream_t st) {
   const fbst::Params& p = pl->p;
+  const int tile = (pl->k3_variant.load(std::memory_order_relaxed) >> 4) & 3;
   if (p.kind == FBST_LINE) {
     return fbst::launch_axis_czt<T1>(p.p2x, yhat, w, pl->axp, pl->axH, pl->axq, pl->tw1, p.M, p.B,
-                                     1, 1, p.L, nb, st);
+                                     1, 1, p.L, nb, st, tile);
   }
   if (p.kind == FBST_ARBITRARY) {
     // spread yhat onto the oversampled grid z [nb][nfx][nfy][L]; 1-D: the x
@@ -259,10 +260,10 @@ hipError_t run_stage1(const fbst_plan* pl, int nb, const void* yhat, void* w, vo
   // grid: x axis on [nb][1][mx][my][L] -> z [nb][1][bu][my][L], then the
   // y axis on [nb][bu][my][1][L] -> w [nb][bu][bv][1][L]
   hipError_t e = fbst::launch_axis_czt<T1>(p.p2x, yhat, z, pl->axp, pl->axH, pl->axq, pl->tw1,
-                                           p.mx, p.bu, 1, p.my, p.L, nb, st);
+                                           p.mx, p.bu, 1, p.my, p.L, nb, st, tile);
   if (e != hipSuccess) return e;
   return fbst::launch_axis_czt<T1>(p.p2y, z, w, pl->ayp, pl->ayH, pl->ayq, pl->tw1, p.my, p.bv,
-                                   p.bu, 1, p.L, nb, st);
+                                   p.bu, 1, p.L, nb, st, tile);
 }
 
 // bt: room for beta_1 of nb blocks ([nb][B][L] complex64) when the plan
@@ -281,7 +282,7 @@ hipError_t run_stage2(const fbst_plan* pl, int nb, const void* w, const fbst::Ou
         p.p3, w, outs, pl->G1, pl->G2, pl->pre3, pl->H3, pl->post3, pl->tw2, bt, p.B, p.L, p.N,
         nb, st);
   }
-  const int var = pl->k3_variant.load(std::memory_order_relaxed);
+  const int var = pl->k3_variant.load(std::memory_order_relaxed) & 15;
   if (pl->CA)
     return fbst::launch_toeplitz_fu_refined(p.p3, w, outs, pl->G1, pl->G2, pl->pre3, pl->H3,
                                             pl->post3, pl->tw2, pl->CA, bt, p.B, p.L, p.N, nb, st);
@@ -957,6 +958,22 @@ std::vector<int> plan_variants(const fbst_plan* plan) {
   return v;
 }
 
+// Stage-1b workgroup sizes (variant bits 4-5) the plan can launch: the
+// chirp-z of lines and grids in float32 has three.
+std::vector<int> plan_tiles(const fbst_plan* plan) {
+  const fbst::Params& p = plan->p;
+  if (p.kind == FBST_ARBITRARY || stage1_double(p)) return {0};
+  return {0, 1 << 4, 2 << 4};
+}
+
+// Every variant the plan accepts: a stage-2 variant with a stage-1b tile.
+std::vector<int> plan_all_variants(const fbst_plan* plan) {
+  std::vector<int> all;
+  for (int t : plan_tiles(plan))
+    for (int v : plan_variants(plan)) all.push_back(v | t);
+  return all;
+}
+
 }  // namespace
 
 extern "C" {
@@ -964,7 +981,7 @@ extern "C" {
 fbst_status fbst_plan_set_variant(const fbst_plan* plan, int variant) {
   fbst_status s = check_exec(plan);
   if (s != FBST_OK) return s;
-  const std::vector<int> ok = plan_variants(plan);
+  const std::vector<int> ok = plan_all_variants(plan);
   if (std::find(ok.begin(), ok.end(), variant) == ok.end())
     return fail(FBST_E_UNSUPPORTED, "stage-2 variant " + std::to_string(variant) +
                                         " is not compiled for this plan");
@@ -1028,6 +1045,25 @@ fbst_status fbst_autotune_ex(const fbst_plan* plan, int nblocks, const void* x, 
       const float ms = acc / 3.0f;
       if (e == hipSuccess && (best.chunk == 0 || ms < best.ms)) best = {chunk, var, ms};
     }
+  }
+  // then the stage-1b workgroup size at the chosen chunk and stage-2 variant
+  const int chosen = best.variant;
+  for (int t : plan_tiles(plan)) {
+    if (t == 0 || e != hipSuccess) continue;
+    pl->k3_variant.store(chosen | t);
+    e = fbst::run_contiguous(plan, nblocks, best.chunk, x, beams, workspace, st);   // warm-up
+    float acc = 0.0f;
+    for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+      e = hipEventRecord(e0, st);
+      if (e == hipSuccess) e = fbst::run_contiguous(plan, nblocks, best.chunk, x, beams, workspace, st);
+      if (e == hipSuccess) e = hipEventRecord(e1, st);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      acc += ms;
+    }
+    const float ms = acc / 3.0f;
+    if (e == hipSuccess && ms < best.ms) best = {best.chunk, chosen | t, ms};
   }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);

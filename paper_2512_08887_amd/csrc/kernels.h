@@ -46,10 +46,12 @@ hipError_t launch_time_czt_mfma(int P, bool fp16, const InPtrs& xs, int nblocks,
                                 int M, int N, int L, hipStream_t st);
 
 // Stage 1b, one axis: layout [nb][pre_n][A][post_n][L], A = a_in -> a_out.
+// tile: workgroup size of the instance (frequencies per workgroup): 0 the
+// default, 1 half, 2 twice (float32 only; else hipErrorInvalidValue).
 template <typename T>
 hipError_t launch_axis_czt(int P, const void* in, void* out, const void* pre, const void* H,
                            const void* post, const void* tw, int a_in, int a_out, int pre_n,
-                           int post_n, int L, int nblocks, hipStream_t st);
+                           int post_n, int L, int nblocks, hipStream_t st, int tile = 0);
 
 // Stage 1b for arbitrary positions (type-1 non-uniform FFT per frequency):
 // spread yhat [nb][M][L] onto the oversampled grid out [nb][nfx][nfy][L]

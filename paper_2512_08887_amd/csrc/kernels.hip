@@ -19,6 +19,8 @@
 // of K3 are then fetched into one L2 and reused there.
 #include "kernel_common.h"
 
+#include <type_traits>
+
 namespace fbst {
 
 namespace {
@@ -200,12 +202,12 @@ __global__ __launch_bounds__(Shape<P>::THREADS) FBST_K1S_ATTR void k_time_czt_sp
 // workgroups of one XCD share the tables of a few tiles.
 // SI >= ceil(a_in / TT), SO >= ceil(a_out / TT).
 // ---------------------------------------------------------------------------
-template <typename T, int P, int SI, int SO>
-__global__ __launch_bounds__(ShapeK2<P>::THREADS) FBST_K12_ATTR void k_axis_czt(
+template <typename T, int P, int SI, int SO, int WG = FBST_K2_THREADS>
+__global__ __launch_bounds__((Shape<P, WG>::THREADS)) FBST_K12_ATTR void k_axis_czt(
     const cx<T>* __restrict__ in, cx<T>* __restrict__ out, const cx<T>* __restrict__ pre,
     const cx<T>* __restrict__ H, const cx<T>* __restrict__ post, const cx<T>* __restrict__ tw,
     int a_in, int a_out, int pre_n, int post_n, int L, int nblocks, int n_tiles) {
-  using SH = ShapeK2<P>;
+  using SH = Shape<P, WG>;
   __shared__ cx<T> lds[SH::G * SH::S];
   const int g = threadIdx.x % SH::G;
   const int t = threadIdx.x / SH::G;
@@ -781,29 +783,48 @@ hipError_t launch_time_czt_split(int P, const InPtrs& xs, int nblocks, void* yha
 template <typename T>
 hipError_t launch_axis_czt(int P, const void* in, void* out, const void* pre, const void* H,
                            const void* post, const void* tw, int a_in, int a_out, int pre_n,
-                           int post_n, int L, int nblocks, hipStream_t st) {
+                           int post_n, int L, int nblocks, hipStream_t st, int tile) {
+  if (tile < 0 || tile > 2) return hipErrorInvalidValue;
+  // one instance per workgroup size: tile 0 the default, 1 half as many
+  // frequencies per workgroup, 2 twice as many (float32 only)
+  auto go = [&](auto wg_tag, auto p_tag) -> hipError_t {
+    constexpr int WG = decltype(wg_tag)::value, PP = decltype(p_tag)::value;
+    using SH = Shape<PP, WG>;
+    if constexpr (sizeof(T) * 2 * lds_stride(PP) * SH::G <= 160 * 1024) {
+      const int n_tiles = (L + SH::G - 1) / SH::G;
+      const long long ng = 1LL * nblocks * pre_n * post_n * n_tiles;
+      if (ng <= 0 || ng > 0x7fffffffLL) return hipErrorInvalidValue;
+      const dim3 grid((unsigned)ng), block(SH::THREADS);
+      const bool half = slots_for<PP>(a_in) <= kE / 2 && slots_for<PP>(a_out) <= kE / 2;
+      if (half)
+        hipLaunchKernelGGL((k_axis_czt<T, PP, kE / 2, kE / 2, WG>), grid, block, 0, st,
+                           (const cx<T>*)in, (cx<T>*)out, (const cx<T>*)pre, (const cx<T>*)H,
+                           (const cx<T>*)post, (const cx<T>*)tw, a_in, a_out, pre_n, post_n, L,
+                           nblocks, n_tiles);
+      else
+        hipLaunchKernelGGL((k_axis_czt<T, PP, kE, kE, WG>), grid, block, 0, st,
+                           (const cx<T>*)in, (cx<T>*)out, (const cx<T>*)pre, (const cx<T>*)H,
+                           (const cx<T>*)post, (const cx<T>*)tw, a_in, a_out, pre_n, post_n, L,
+                           nblocks, n_tiles);
+      return hipGetLastError();
+    }
+    return hipErrorInvalidValue;
+  };
+  using W0 = std::integral_constant<int, FBST_K2_THREADS>;
+  using W1 = std::integral_constant<int, FBST_K2_THREADS / 2>;
+  using W2 = std::integral_constant<int, FBST_K2_THREADS * 2>;
+  if (tile != 0 && sizeof(T) != 4) return hipErrorInvalidValue;
   switch (P) {
 #define CASE(PP)                                                                               \
-  case PP:                                                                                     \
-    if constexpr ((sizeof(T) * 2 * lds_stride(PP) * ShapeK2<PP>::G <= 160 * 1024)) {                                                         \
-      const int n_tiles = (L + ShapeK2<PP>::G - 1) / ShapeK2<PP>::G;                               \
-      const long long ng = 1LL * nblocks * pre_n * post_n * n_tiles;                           \
-      if (ng <= 0 || ng > 0x7fffffffLL) return hipErrorInvalidValue;                          \
-      const dim3 grid((unsigned)ng), block(ShapeK2<PP>::THREADS);                                \
-      const bool half = slots_for<PP>(a_in) <= kE / 2 && slots_for<PP>(a_out) <= kE / 2;      \
-      if (half)                                                                                \
-        hipLaunchKernelGGL((k_axis_czt<T, PP, kE / 2, kE / 2>), grid, block, 0, st,            \
-                           (const cx<T>*)in, (cx<T>*)out, (const cx<T>*)pre, (const cx<T>*)H,  \
-                           (const cx<T>*)post, (const cx<T>*)tw, a_in, a_out, pre_n, post_n,   \
-                           L, nblocks, n_tiles);                                               \
-      else                                                                                     \
-        hipLaunchKernelGGL((k_axis_czt<T, PP, kE, kE>), grid, block, 0, st,                    \
-                           (const cx<T>*)in, (cx<T>*)out, (const cx<T>*)pre, (const cx<T>*)H,  \
-                           (const cx<T>*)post, (const cx<T>*)tw, a_in, a_out, pre_n, post_n,   \
-                           L, nblocks, n_tiles);                                               \
-      return hipGetLastError();                                                                \
+  case PP: {                                                                                   \
+    using PT = std::integral_constant<int, PP>;                                                \
+    if (tile == 0) return go(W0{}, PT{});                                                      \
+    if constexpr (sizeof(T) == 4) {                                                            \
+      if (tile == 1) return go(W1{}, PT{});                                                    \
+      return go(W2{}, PT{});                                                                   \
     }                                                                                          \
-    break;
+    return hipErrorInvalidValue;                                                               \
+  }
     FBST_FOR_EACH_P(CASE)
 #undef CASE
     default:
@@ -994,10 +1015,10 @@ template hipError_t launch_time_czt_split<double>(int, const InPtrs&, int, void*
                                                   const void*, int, int, int, int, hipStream_t);
 template hipError_t launch_axis_czt<float>(int, const void*, void*, const void*, const void*,
                                            const void*, const void*, int, int, int, int, int, int,
-                                           hipStream_t);
+                                           hipStream_t, int);
 template hipError_t launch_axis_czt<double>(int, const void*, void*, const void*, const void*,
                                             const void*, const void*, int, int, int, int, int, int,
-                                            hipStream_t);
+                                            hipStream_t, int);
 template hipError_t launch_nu_spread<float>(int, const void*, void*, const void*, const void*,
                                             const void*, const int*, int, int, int, int, double,
                                             int, int, hipStream_t);

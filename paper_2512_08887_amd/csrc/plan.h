@@ -257,9 +257,11 @@ struct fbst_plan {
   void* K = nullptr;
   size_t K_bytes = 0;
   int device = 0;
-  // kernel instance of stage 2 (variant bits of fbst::launch_toeplitz_fu),
-  // chosen by fbst_autotune or fbst_plan_set_variant; the instances agree to
-  // float32 rounding (the persistent bit changes nothing at all)
+  // kernel instances: bits 0-3 stage 2 (variant bits of
+  // fbst::launch_toeplitz_fu), bits 4-5 the stage-1b workgroup size (tile of
+  // fbst::launch_axis_czt); chosen by fbst_autotune_ex or
+  // fbst_plan_set_variant; the stage-2 instances agree to float32 rounding
+  // (the persistent bit changes nothing at all), the stage-1b ones exactly
   std::atomic<int> k3_variant{0};
   double generator_ms = 0.0;       // device generator solve (FBST_FLAG_DEVICE_GENERATORS), ms
 };

@@ -27,6 +27,7 @@ FBST_FLAG_DEVICE_GENERATORS = 32
 FBST_FLAG_STAGE2_REFINE = 64
 FBST_FLAG_SUPERFAST_GENERATORS = 128
 FBST_VARIANT_K3_SINGLE, FBST_VARIANT_K3_PERSISTENT, FBST_VARIANT_K3_WAVES3 = 1, 2, 4
+FBST_VARIANT_K2_TILE_HALF, FBST_VARIANT_K2_TILE_DOUBLE = 16, 32
 FBST_TABLE_BEAM_U, FBST_TABLE_BEAM_V, FBST_TABLE_GRAM, FBST_TABLE_GENERATOR = 0, 1, 2, 3
 MAX_LAUNCH_BLOCKS = 256  # FBST_MAX_LAUNCH_BLOCKS: blocks per kernel launch (pointers in the kernel arguments)
 

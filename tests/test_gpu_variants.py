@@ -88,6 +88,42 @@ def test_variant_rules():
         p.close()
 
 
+def test_stage1b_tiles_bit_identical():
+    """The stage-1b instances with half and twice the frequencies per
+    workgroup give the same beams bit for bit (each transform is the same
+    arithmetic), on a line and a planar grid, combined with the stage-2
+    variants; a float64 stage 1 and an arbitrary array have one instance."""
+    need_gpu()
+    rng = np.random.default_rng(81)
+    band = F.make_band(2.0, 0.5, 1.0)
+    line = F.Plan(64, 512, 48, band=band, options=F.make_options(102.4))
+    grid = F.Plan(64, 256, 36, band=band, geometry=F.make_grid_geometry(8, 8),
+                  grid=F.make_beam_grid(6, 6), options=F.make_options(51.2))
+    for name, plan in (("line", line), ("grid", grid)):
+        x = torch.from_numpy(crandn(rng, 3, plan.M, plan.N)).to(torch.complex64).cuda()
+        ws = plan.workspace(3)
+        base = plan.variant
+        ref = plan.execute_batched(x, workspace=ws)
+        for tile in (F.FBST_VARIANT_K2_TILE_HALF, F.FBST_VARIANT_K2_TILE_DOUBLE):
+            plan.variant = base | tile
+            assert plan.variant == base | tile
+            out = plan.execute_batched(x, workspace=ws)
+            torch.cuda.synchronize()
+            assert torch.equal(out, ref), (name, tile)
+        plan.variant = base
+        plan.close()
+    fp64 = F.Plan(16, 512, 16, band=band, options=F.make_options(1e-2, precision="fp64"))
+    px = (np.arange(16) + 0.2 * np.sin(np.arange(16))) / 5.0
+    arb = F.Plan(16, 256, 16, band=band, geometry=F.make_arbitrary(px),
+                 options=F.make_options(51.2))
+    for p in (fp64, arb):
+        for tile in (F.FBST_VARIANT_K2_TILE_HALF, F.FBST_VARIANT_K2_TILE_DOUBLE):
+            with pytest.raises(F.FbstError) as e:
+                p.variant = p.variant | tile
+            assert e.value.status == F.FBST_E_UNSUPPORTED
+        p.close()
+
+
 def test_tuned_variant_graph_and_oracle():
     """fbst_autotune_ex over chunk x variant on ula256 (64 blocks): the chosen
     variant is set on the plan and cached; each variant captured in a graph
@@ -100,7 +136,8 @@ def test_tuned_variant_graph_and_oracle():
     x = torch.from_numpy(y).cuda()
     chunk, var, ms = plan.autotune_ex(x, force=True)
     print(f"ula256 tuned: {chunk} blocks per launch, variant {var}, {ms:.3f} ms")
-    assert chunk in (1, 2, 4, 8, 16, 32, 64) and var in VARIANTS and ms > 0
+    assert chunk in (1, 2, 4, 8, 16, 32, 64) and (var & 15) in VARIANTS and ms > 0
+    assert (var & ~15) in (0, F.FBST_VARIANT_K2_TILE_HALF, F.FBST_VARIANT_K2_TILE_DOUBLE)
     assert plan.variant == var
     assert plan.autotune_ex(x)[:2] == (chunk, var)       # cached
     ws = plan.workspace(chunk)
