@@ -690,8 +690,12 @@ def serve_accuracy(checks, n_beams=6):
 
 def main():
     if len(sys.argv) > 1 and sys.argv[1] == "--sq-summary":
-        # bench.py --sq-summary PMC_DIR[,PMC_DIR...]: per-wave SQ counters of the hot kernels
-        print(sq_summary(sys.argv[2].split(",")))
+        # bench.py --sq-summary PMC_DIR[,PMC_DIR...] [KERNEL_PREFIX,...]: per-wave SQ counters
+        # of the hot kernels (default: the three stages of the path)
+        if len(sys.argv) > 3:
+            print(sq_summary(sys.argv[2].split(","), tuple(sys.argv[3].split(","))))
+        else:
+            print(sq_summary(sys.argv[2].split(",")))
         return
     if len(sys.argv) > 1 and sys.argv[1] == "--rocprof-summary":
         # bench.py --rocprof-summary KT_DIR PMC_DIR[,PMC_DIR] COPY_DIR[,COPY_DIR] [COUNTERS_JSON]
