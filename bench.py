@@ -855,17 +855,21 @@ def main():
     lat = []
     one = x[0].contiguous()
     out1 = torch.empty((cfg.B, cfg.N), dtype=torch.complex64, device="cuda")
-    ws1 = plan.workspace(1)
+    # single blocks on a plan of their own, its kernel instances tuned for one
+    # block per launch (the step's plan keeps the ones tuned for 64)
+    lplan = F.plan_for_config(cfg, precision="fp32")
+    ws1 = lplan.workspace(1)
+    lat_var = lplan.autotune_ex(one.unsqueeze(0), workspace=ws1)[1] if args.chunk < 0 else lplan.variant
     for i in range(args.latency_reps + 5):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        F.fbst_execute(plan.handle, one.data_ptr(), out1.data_ptr(), ws1.data_ptr(), sptr)
+        F.fbst_execute(lplan.handle, one.data_ptr(), out1.data_ptr(), ws1.data_ptr(), sptr)
         stream.synchronize()
         if i >= 5:
             lat.append((time.perf_counter() - t0) * 1e3)
     lat = np.array(lat)
     # the same single block replayed from a captured graph (one launch call)
-    g1 = plan.graph(one.unsqueeze(0), out1.unsqueeze(0), workspace=ws1)
+    g1 = lplan.graph(one.unsqueeze(0), out1.unsqueeze(0), workspace=ws1)
     glat = []
     for i in range(args.latency_reps + 5):
         torch.cuda.synchronize()
@@ -876,6 +880,7 @@ def main():
             glat.append((time.perf_counter() - t0) * 1e3)
     glat = np.array(glat)
     g1.close()
+    lplan.close()
     # the whole 64-block step as one graph, and the autotuned blocks per launch
     gb = torch.empty_like(beams)
     gall = plan.graph(x, gb, workspace=ws, max_chunk=chunk)
@@ -921,7 +926,9 @@ def main():
                                "8 sources over 30 dB, 10 dB SNR, delta=sigma^2 L=204.8, 64 blocks per step",
                    "blocks_per_step": nblk, "blocks_per_launch": chunk, "precision": "fp32"},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                       "what": "one block alone: execute + stream sync, host clock"},
+                       "variant": lat_var,
+                       "what": "one block alone: execute + stream sync, host clock; kernel "
+                               "instances tuned by fbst_autotune_ex for one block per launch"},
         "graph": {"latency_ms": {"p50": float(np.percentile(glat, 50)), "p99": float(np.percentile(glat, 99))},
                   "ms_per_step": graph_ms,
                   "what": "the single block and the 64-block step replayed from captured HIP graphs"},
