@@ -106,10 +106,21 @@ struct Upload {
 };
 
 // Per-pass twiddle tables of every transform size (layout in fft_lds.h):
-// entry tw_offset(P, NS) + (r - 1) NS + k = exp(-2 pi j r k / (NS R)).
+// entry tw_offset(P, NS) + (r - 1) NS + k = exp(-2 pi j r k / (NS R)); for
+// the radix-16 passes after the first, entry TW_MERGED + tw_offset(P, NS) +
+// i NS + k holds the i-th merged factor f of k as (Re f, Im f / Re f).
 std::vector<fbst::zd> twiddles() {
-  std::vector<fbst::zd> tw(fbst::TW_ENTRIES, fbst::zd(0.0, 0.0));
+  std::vector<fbst::zd> tw(fbst::TW_TABLE, fbst::zd(0.0, 0.0));
   const double pi = 3.141592653589793238462643383279502884;
+  // exp(-2 pi j m / D) as (c, t), |c| held at least 2^-40
+  auto merged = [&](long long m, long long D) {
+    const double a = 2.0 * pi * static_cast<double>(((m % D) + D) % D) / static_cast<double>(D);
+    double c = std::cos(a);
+    const double s = -std::sin(a);
+    const double cmin = std::ldexp(1.0, -40);
+    if (std::fabs(c) < cmin) c = std::signbit(c) ? -cmin : cmin;
+    return fbst::zd(c, s / c);
+  };
   for (int P = 32; P <= fbst::PMAX; P *= 2) {
     for (int NS = 1; NS < P;) {
       const int R = std::min(fbst::FFT_E, P / NS);
@@ -121,6 +132,23 @@ std::vector<fbst::zd> twiddles() {
             const double a = 2.0 * pi * static_cast<double>((1LL * r * k) % NR) / static_cast<double>(NR);
             tw[off + (r - 1) * NS + k] = fbst::zd(std::cos(a), -std::sin(a));
           }
+        if (R == 16) {
+          // angles in units of 2 pi / (16 NS): psi = w^{4k}, om = w^k w_16^{k1},
+          // i^-1 = 4 NS units
+          const long long D = 16LL * NS, q = 4LL * NS;
+          fbst::zd* m = tw.data() + fbst::TW_MERGED + off;
+          for (int k = 0; k < NS; ++k) {
+            m[0 * NS + k] = merged(8LL * k, D);
+            m[1 * NS + k] = merged(4LL * k, D);
+            m[2 * NS + k] = merged(4LL * k + q, D);
+            for (int k1 = 0; k1 < 4; ++k1) {
+              const long long o = k + 1LL * NS * k1;
+              m[(3 + 3 * k1) * NS + k] = merged(2 * o, D);
+              m[(4 + 3 * k1) * NS + k] = merged(o, D);
+              m[(5 + 3 * k1) * NS + k] = merged(o + q, D);
+            }
+          }
+        }
       }
       NS *= R;
     }

@@ -30,6 +30,9 @@ template <typename T>
 __host__ __device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
   return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
 }
+// a * b + c with one rounding
+__host__ __device__ __forceinline__ float fmx(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__host__ __device__ __forceinline__ double fmx(double a, double b, double c) { return __builtin_fma(a, b, c); }
 // a * conj(b)
 template <typename T>
 __host__ __device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b) {

@@ -32,6 +32,25 @@
 // NS starts NS - E entries into it (the pass tables tile the range exactly,
 // since (R - 1) NS = NS_next - NS).  Values are computed in float64 on the
 // host and rounded once.
+//
+// Merged twiddles (float32 radix-16 passes after the first, FBST_TW_MERGED):
+// the pass's DFT_16 of x_r w^{r k} is taken as 4 x 4 (r = 4 n1 + n2,
+// output k' = k1 + 4 k2).  The outer twiddles fold into the two stages:
+//   Y[n2][k1]     = sum_n1 x_{4 n1 + n2} psi^{n1} i^{DIR n1 k1},   psi = w^{4 k}
+//   X[k1 + 4 k2]  = sum_n2 Y[n2][k1] om^{n2} i^{DIR n2 k2},         om  = w^k w_16^{k1}
+// and a 4-point DFT with twiddle om, z_n -> sum_n z_n om^n i^{DIR n k2}, is
+// four butterflies x +- c y of the form x +- om^2 y, x +- om y and
+// x +- (i^DIR om) y.  With each factor held as (c, t) = (Re f, Im f / Re f),
+// x + f y = x + c (y.re - t y.im, y.im + t y.re): two fused multiply-adds for
+// the bracket and one per output component, 6 instructions per butterfly in
+// place of a complex product (4) and a complex add and subtract (4).  A pass
+// therefore takes 192 instead of 220 instructions per radix-16 butterfly (the
+// linear-algebra idea is the cosine-scaled twiddle of Linzer and Feig).
+// The 15 factors of each k are psi^2, psi, i^-1 psi, then om^2, om, i^-1 om
+// for k1 = 0..3 (forward sign), in the [factor][k] layout of the plain
+// tables, in entries [TW_MERGED, TW_TABLE) of the same array at the same
+// offsets.  |Re f| is held at least 2^-40 so that t stays finite; that moves
+// f by less than 1e-12.
 #pragma once
 
 #include "cx.h"
@@ -41,6 +60,16 @@ namespace fbst {
 constexpr int PMAX = 16384;      // largest supported transform size
 constexpr int FFT_E = 16;        // elements per thread (radix of the full passes)
 constexpr int TW_ENTRIES = 2 * PMAX;
+constexpr int TW_MERGED = TW_ENTRIES;        // first entry of the merged tables
+constexpr int TW_TABLE = 2 * TW_ENTRIES;     // entries of the whole twiddle array
+#ifndef FBST_TW_MERGED
+#define FBST_TW_MERGED 1
+#endif
+// passes that use the merged tables: float32, radix 16, not the first
+template <typename T, int R, int NS>
+__host__ __device__ constexpr bool merged_pass() {
+  return FBST_TW_MERGED && sizeof(T) == 4 && R == 16 && NS > 1;
+}
 
 #ifndef FBST_LDS_PAD_SHIFT
 #define FBST_LDS_PAD_SHIFT 4
@@ -217,6 +246,54 @@ __device__ __forceinline__ void dft(cx<T> (&v)[R]) {
   }
 }
 
+// x <- x + f y, y <- x - f y with f = c (1 + j t) given as {c, t} (forward
+// sign; DIR > 0 applies conj(f))
+template <int DIR, typename T>
+__host__ __device__ __forceinline__ void bfly_m(cx<T>& x, cx<T>& y, cx<T> f) {
+  const T t = DIR < 0 ? f.im : -f.im;
+  const T u = fmx(-t, y.im, y.re);
+  const T v = fmx(t, y.re, y.im);
+  const cx<T> a{fmx(f.re, u, x.re), fmx(f.re, v, x.im)};
+  const cx<T> b{fmx(-f.re, u, x.re), fmx(-f.re, v, x.im)};
+  x = a;
+  y = b;
+}
+
+// z_n -> Z[k2] = sum_n z_n om^n i^{DIR n k2}, given om^2, om, i^-1 om (forward
+// sign); on return z0..z3 hold Z[0], Z[2], Z[1], Z[3]
+template <int DIR, typename T>
+__host__ __device__ __forceinline__ void dft4_m(cx<T>& z0, cx<T>& z1, cx<T>& z2, cx<T>& z3,
+                                                cx<T> f2, cx<T> f1, cx<T> f3) {
+  bfly_m<DIR>(z0, z2, f2);    // z0 + om^2 z2, z0 - om^2 z2
+  bfly_m<DIR>(z1, z3, f2);    // z1 + om^2 z3, z1 - om^2 z3
+  bfly_m<DIR>(z0, z1, f1);    // Z[0], Z[2]
+  bfly_m<DIR>(z2, z3, f3);    // Z[1], Z[3]
+}
+
+// DFT_16 of x_r w^{r k} (natural order in and out) from the 15 merged
+// factors of k
+template <int DIR, typename T, typename F>
+__host__ __device__ __forceinline__ void dft16_m(cx<T> (&v)[16], F&& f) {
+  // first stage, over n1 for each n2: Y[n2][k1] lands in v[4 br(k1) + n2],
+  // br = (0, 2, 1, 3)
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) dft4_m<DIR>(v[n2], v[4 + n2], v[8 + n2], v[12 + n2], f(0), f(1), f(2));
+  // second stage, over n2 for each k1: X[k1 + 4 k2] for k2 = 0, 2, 1, 3
+  constexpr int br[4] = {0, 2, 1, 3};
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    const int b = 4 * br[k1];
+    dft4_m<DIR>(v[b], v[b + 1], v[b + 2], v[b + 3], f(3 + 3 * k1), f(4 + 3 * k1), f(5 + 3 * k1));
+  }
+  cx<T> o[16];
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) o[k1 + 4 * br[j]] = v[4 * br[k1] + j];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) v[i] = o[i];
+}
+
 // ---------------------------------------------------------------------------
 // How a pass obtains its twiddles (global loads, L2/L1 latency):
 //   TW_LAZY      each one loaded where it is used (fewest live registers; the
@@ -243,6 +320,12 @@ struct PassTw {
   cx<T> w[N];
 };
 
+// first entry of the table (plain or merged) read by the pass with span NS
+template <typename T, int P, int R, int NS>
+__device__ __forceinline__ const cx<T>* pass_table(const cx<T>* __restrict__ tw) {
+  return tw + (merged_pass<T, R, NS>() ? TW_MERGED : 0) + tw_offset(P, NS);
+}
+
 template <typename T, int P, int E, int NS>
 __device__ __forceinline__ void load_tw(PassTw<T, P, E, NS>& pt, const cx<T>* __restrict__ tw,
                                         int t) {
@@ -252,7 +335,7 @@ __device__ __forceinline__ void load_tw(PassTw<T, P, E, NS>& pt, const cx<T>* __
 #pragma unroll
     for (int q = 0; q < PT::NB; ++q) {
       const int k = (t + q * TT) & (NS - 1);
-      const cx<T>* twp = tw + tw_offset(P, NS) + k;
+      const cx<T>* twp = pass_table<T, P, PT::R, NS>(tw) + k;
 #pragma unroll
       for (int r = 1; r < PT::R; ++r) pt.w[q * (PT::R - 1) + r - 1] = twp[(r - 1) * NS];
     }
@@ -284,18 +367,23 @@ __device__ __forceinline__ void stockham_pass(cx<T> (&v)[E], cx<T>* __restrict__
       else b[q][r] = buf[read_slot<P, R>(j, r)];
     }
     if constexpr (NS > 1) {
-      const cx<T>* twp = tw + tw_offset(P, NS) + (j & (NS - 1));
+      const cx<T>* twp = pass_table<T, P, R, NS>(tw) + (j & (NS - 1));
       cx<T> wb[R - 1];
       if constexpr (TWM == TW_BATCH) {
 #pragma unroll
         for (int r = 1; r < R; ++r) wb[r - 1] = twp[(r - 1) * NS];
         asm volatile("" ::: "memory");   // issue the loads together (see TW_BATCH)
       }
+      auto factor = [&](int i) {
+        return TWM == TW_PREFETCH ? cur.w[q * (R - 1) + i] : TWM == TW_BATCH ? wb[i] : twp[i * NS];
+      };
+      if constexpr (merged_pass<T, R, NS>()) {
+        dft16_m<DIR>(b[q], factor);
+        continue;
+      } else {
 #pragma unroll
-      for (int r = 1; r < R; ++r)
-        b[q][r] = cmul_dir<DIR>(b[q][r], TWM == TW_PREFETCH ? cur.w[q * (R - 1) + r - 1]
-                                         : TWM == TW_BATCH  ? wb[r - 1]
-                                                            : twp[(r - 1) * NS]);
+        for (int r = 1; r < R; ++r) b[q][r] = cmul_dir<DIR>(b[q][r], factor(r - 1));
+      }
     }
     if constexpr (FIRST && NB == 1) {
       dft<R, DIR, NZ_IN>(b[q]);
@@ -351,20 +439,27 @@ __device__ __forceinline__ void stockham_pass2(cx<T> (&v1)[E], cx<T> (&v2)[E],
       }
     }
     if constexpr (NS > 1) {
-      const cx<T>* twp = tw + tw_offset(P, NS) + (j & (NS - 1));
+      const cx<T>* twp = pass_table<T, P, R, NS>(tw) + (j & (NS - 1));
       cx<T> wb[R - 1];
       if constexpr (TWM == TW_BATCH) {
 #pragma unroll
         for (int r = 1; r < R; ++r) wb[r - 1] = twp[(r - 1) * NS];
         asm volatile("" ::: "memory");
       }
+      auto factor = [&](int i) {
+        return TWM == TW_PREFETCH ? cur.w[q * (R - 1) + i] : TWM == TW_BATCH ? wb[i] : twp[i * NS];
+      };
+      if constexpr (merged_pass<T, R, NS>()) {
+        dft16_m<DIR>(a[q], factor);
+        dft16_m<DIR>(b[q], factor);
+        continue;
+      } else {
 #pragma unroll
-      for (int r = 1; r < R; ++r) {
-        const cx<T> w = TWM == TW_PREFETCH ? cur.w[q * (R - 1) + r - 1]
-                        : TWM == TW_BATCH  ? wb[r - 1]
-                                           : twp[(r - 1) * NS];
-        a[q][r] = cmul_dir<DIR>(a[q][r], w);
-        b[q][r] = cmul_dir<DIR>(b[q][r], w);
+        for (int r = 1; r < R; ++r) {
+          const cx<T> w = factor(r - 1);
+          a[q][r] = cmul_dir<DIR>(a[q][r], w);
+          b[q][r] = cmul_dir<DIR>(b[q][r], w);
+        }
       }
     }
     if constexpr (FIRST && NB == 1) {

@@ -1,7 +1,7 @@
 // Host-side launchers of the FBST kernels (kernels.hip).  Pointers are device
 // pointers to interleaved complex arrays of the template element type; P is
 // the FFT size of the launch (power of two, 32..16384; 8192 at most for
-// double); tw is the twiddle array of fft_lds.h (TW_ENTRIES entries).  All
+// double); tw is the twiddle array of fft_lds.h (TW_TABLE entries).  All
 // return the HIP error of the launch.
 #pragma once
 
