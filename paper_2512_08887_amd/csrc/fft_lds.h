@@ -347,9 +347,14 @@ __device__ __forceinline__ void load_tw(PassTw<T, P, E, NS>& pt, const cx<T>* __
 // called once the butterflies are computed and before the first barrier (the
 // hook that issues the next pass's twiddle loads).
 // ---------------------------------------------------------------------------
+// The pass reads its operands from bin (unless FIRST) and writes its results
+// to bout (unless LAST); PRE adds the barrier that keeps the writes behind
+// every thread's reads of bout's previous contents (needed whenever bout may
+// still be read, in particular when bin == bout).
 template <typename T, int P, int E, int R, int NS, int DIR, bool FIRST, bool LAST, int NZ_IN,
-          int TWM, typename Hook>
-__device__ __forceinline__ void stockham_pass(cx<T> (&v)[E], cx<T>* __restrict__ buf,
+          int TWM, bool PRE = true, typename Hook>
+__device__ __forceinline__ void stockham_pass(cx<T> (&v)[E], const cx<T>* __restrict__ bin,
+                                              cx<T>* __restrict__ bout,
                                               const PassTw<T, P, E, NS>& cur,
                                               const cx<T>* __restrict__ tw, int t,
                                               Hook&& before_barrier) {
@@ -364,7 +369,7 @@ __device__ __forceinline__ void stockham_pass(cx<T> (&v)[E], cx<T>* __restrict__
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       if constexpr (FIRST) b[q][r] = v[q + r * NB];
-      else b[q][r] = buf[read_slot<P, R>(j, r)];
+      else b[q][r] = bin[read_slot<P, R>(j, r)];
     }
     if constexpr (NS > 1) {
       const cx<T>* twp = pass_table<T, P, R, NS>(tw) + (j & (NS - 1));
@@ -398,14 +403,14 @@ __device__ __forceinline__ void stockham_pass(cx<T> (&v)[E], cx<T>* __restrict__
       for (int r = 0; r < R; ++r) v[q + r * NB] = b[q][r];
   } else {
     before_barrier();
-    __syncthreads();   // every thread has finished reading the previous contents
+    if constexpr (PRE) __syncthreads();   // every thread has finished reading the previous contents
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
       const int j = t + q * TT;
       const int k = j & (NS - 1);
       const int base = (j - k) * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[write_slot<R, NS>(base, r)] = b[q][r];
+      for (int r = 0; r < R; ++r) bout[write_slot<R, NS>(base, r)] = b[q][r];
     }
     __syncthreads();   // the new contents are visible to every thread
   }
@@ -496,22 +501,42 @@ __device__ __forceinline__ void stockham_pass2(cx<T> (&v1)[E], cx<T> (&v2)[E],
   }
 }
 
+// LDS exchanges of a P-point transform (its passes less one)
+template <int P, int E>
+__host__ __device__ constexpr int fft_exchanges() {
+  int n = 0;
+  for (int NS = 1; NS < P; NS *= (P / NS >= E ? E : P / NS)) ++n;
+  return n - 1;
+}
+
 // Pass drivers.  TWM selects how a pass gets its twiddles (TwiddleMode).
-template <typename T, int P, int E, int DIR, int NS, int NZ_IN, int TWM>
+// PING: the exchanges alternate between buf and buf + lds_stride(P) (pass XI
+// writes buffer XI mod 2), so a pass's writes cannot meet another thread's
+// reads of the same pass and need no barrier before them; the first exchange
+// keeps it when the transform's last exchange also lands in the first buffer
+// (an odd number of exchanges), so that back-to-back transforms stay ordered.
+template <typename T, int P, int E, int DIR, int NS, int NZ_IN, int TWM, bool PING = false,
+          int XI = 0>
 __device__ __forceinline__ void fft_passes(cx<T> (&v)[E], cx<T>* buf, const cx<T>* tw, int t,
                                            PassTw<T, P, E, NS>& cur) {
   constexpr int REM = P / NS;
   constexpr int R = (REM >= E) ? E : REM;
   constexpr bool FIRST = (NS == 1);
   constexpr bool LAST = (REM == R);
+  constexpr int S = lds_stride(P);
+  const cx<T>* bin = PING ? buf + ((XI + 1) & 1) * S : buf;    // written by pass XI - 1
+  cx<T>* bout = PING ? buf + (XI & 1) * S : buf;
+  constexpr bool PRE = !PING || (XI == 0 && (fft_exchanges<P, E>() & 1));
   if constexpr (LAST) {
-    stockham_pass<T, P, E, R, NS, DIR, FIRST, true, NZ_IN, TWM>(v, buf, cur, tw, t, [] {});
+    stockham_pass<T, P, E, R, NS, DIR, FIRST, true, NZ_IN, TWM, PRE>(v, bin, bout, cur, tw, t,
+                                                                     [] {});
   } else {
     PassTw<T, P, E, NS * R> nxt;
-    stockham_pass<T, P, E, R, NS, DIR, FIRST, false, NZ_IN, TWM>(v, buf, cur, tw, t, [&] {
+    stockham_pass<T, P, E, R, NS, DIR, FIRST, false, NZ_IN, TWM, PRE>(v, bin, bout, cur, tw, t,
+                                                                      [&] {
       if constexpr (TWM == TW_PREFETCH) load_tw(nxt, tw, t);
     });
-    fft_passes<T, P, E, DIR, NS * R, NZ_IN, TWM>(v, buf, tw, t, nxt);
+    fft_passes<T, P, E, DIR, NS * R, NZ_IN, TWM, PING, XI + 1>(v, buf, tw, t, nxt);
   }
 }
 
@@ -541,12 +566,17 @@ __device__ __forceinline__ void fft2_passes(cx<T> (&v1)[E], cx<T> (&v2)[E], cx<T
 // lds_stride(P) elements).  v[s] for s >= NZ_IN must be zero on entry.
 // Must be reached by every thread of the workgroup (it contains workgroup
 // barriers).
-template <typename T, int P, int E, int DIR, int NZ_IN = E, int TWM = TW_PREFETCH>
+// PING: buf holds two transform buffers (2 lds_stride(P) elements) used in
+// alternation (fft_passes), one barrier per exchange instead of two; every
+// use of them between two such transforms must be a PING transform of the
+// same size or be followed by a workgroup barrier.
+template <typename T, int P, int E, int DIR, int NZ_IN = E, int TWM = TW_PREFETCH,
+          bool PING = false>
 __device__ __forceinline__ void fft(cx<T> (&v)[E], cx<T>* buf, const cx<T>* tw, int t) {
   static_assert((P & (P - 1)) == 0 && P >= E && P <= PMAX, "P must be a power of two in [E, PMAX]");
   static_assert(E == FFT_E, "twiddle tables are laid out for FFT_E elements per thread");
   PassTw<T, P, E, 1> none;
-  fft_passes<T, P, E, DIR, 1, NZ_IN, TWM>(v, buf, tw, t, none);
+  fft_passes<T, P, E, DIR, 1, NZ_IN, TWM, PING>(v, buf, tw, t, none);
 }
 
 // Two independent transforms of the same size and direction at once (their

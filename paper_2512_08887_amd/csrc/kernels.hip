@@ -155,7 +155,10 @@ __global__ __launch_bounds__(Shape<P>::THREADS) FBST_K1S_ATTR void k_time_czt_sp
   }
 #pragma unroll
   for (int s = SI; s < kE; ++s) v[s] = cx<T>{0, 0};
-  fft<T, P, kE, -1, SI, FBST_K12_TW>(v, buf, tw, t);
+  // the forward transform alternates between the two buffers of the dual
+  // inverse where there are two (the dual transform's first exchange keeps
+  // its barrier before the writes)
+  fft<T, P, kE, -1, SI, FBST_K12_TW, NBUF == 2>(v, buf, tw, t);
   {
     cx<T> ha[kE], hb[kE];
 #pragma unroll

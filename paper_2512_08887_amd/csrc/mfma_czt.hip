@@ -151,8 +151,8 @@ __device__ __forceinline__ void mfma_passes(c32* buf, const c32* tw, const DftA<
     // remainder radix (P = 16^a * REM): one float32 Stockham pass through LDS
     c32 unused[FFT_E];
     PassTw<float, P, FFT_E, NS> none;
-    stockham_pass<float, P, FFT_E, REM, NS, DIR, false, false, FFT_E, TW_LAZY>(unused, buf, none, tw,
-                                                                            t, [] {});
+    stockham_pass<float, P, FFT_E, REM, NS, DIR, false, false, FFT_E, TW_LAZY>(unused, buf, buf, none,
+                                                                            tw, t, [] {});
   }
 }
 

@@ -26,9 +26,16 @@ namespace {
 // ---------------------------------------------------------------------------
 // Dual-branch stage 2 when two transforms of P points fit the LDS of a CU.
 template <typename T, int P>
-constexpr bool k3_dual() {
-  return FBST_K3_DUAL && sizeof(T) * 2 * lds_stride(P) * 2 * Shape<P>::G <= 160 * 1024;
+constexpr bool k3_two_buffers() {
+  return sizeof(T) * 2 * lds_stride(P) * 2 * Shape<P>::G <= 160 * 1024;
 }
+template <typename T, int P>
+constexpr bool k3_dual() {
+  return FBST_K3_DUAL && k3_two_buffers<T, P>();
+}
+#ifndef FBST_K3_PING
+#define FBST_K3_PING 1
+#endif
 
 // Stage 2 with one step of iterative refinement (MODE 1 then MODE 2, two
 // launches): the float32 Gohberg-Semencul apply loses accuracy where its two
@@ -60,7 +67,10 @@ __device__ __forceinline__ void k3_row(
     int B, int L, int N, int nblocks, cx<T>* __restrict__ bt, const cx<T>* __restrict__ CA) {
   using SH = Shape<P>;
   constexpr int SL = kE / 2;
-  constexpr int NBUF = DUAL ? 2 : 1;
+  // the single form alternates its transforms' exchanges between two buffers
+  // where they fit (one barrier per exchange)
+  constexpr bool PING = FBST_K3_PING && !DUAL && k3_two_buffers<T, P>();
+  constexpr int NBUF = (DUAL || PING) ? 2 : 1;
   const int g = threadIdx.x / SH::TT;
   const int t = threadIdx.x % SH::TT;
   const int rows = nblocks * B;
@@ -82,11 +92,11 @@ __device__ __forceinline__ void k3_row(
       const int i = t + s * SH::TT;
       u1[s] = (s < SL && active && i < L) ? brow[i] : cx<T>{0, 0};
     }
-    fft<T, P, kE, -1, SL, FBST_K3_TW>(u1, buf, tw, t);
+    fft<T, P, kE, -1, SL, FBST_K3_TW, PING>(u1, buf, tw, t);
     with_tables<FBST_K3_GB, kE, SH::TT>(CA + static_cast<size_t>(b) * P + t,
                                         static_cast<const cx<T>*>(nullptr),
                                         [&](int s, cx<T> a, cx<T>) { u1[s] = cmul(u1[s], a); });
-    fft<T, P, kE, +1, kE, FBST_K3_TW>(u1, buf, tw, t);
+    fft<T, P, kE, +1, kE, FBST_K3_TW, PING>(u1, buf, tw, t);
 #pragma unroll
     for (int s = 0; s < kE; ++s) {
       const int i = t + s * SH::TT;
@@ -99,7 +109,7 @@ __device__ __forceinline__ void k3_row(
       u1[s] = (s < SL && active && i < L) ? cvt<T>(src[i]) : cx<T>{0, 0};
     }
   }
-  fft<T, P, kE, -1, SL, FBST_K3_TW>(u1, buf, tw, t);
+  fft<T, P, kE, -1, SL, FBST_K3_TW, PING>(u1, buf, tw, t);
   with_tables<FBST_K3_GB, kE, SH::TT>(g1 + t, g2 + t, [&](int s, cx<T> a, cx<T> c) {
     const cx<T> V = u1[s];
     u1[s] = cmulc(V, a);
@@ -120,24 +130,24 @@ __device__ __forceinline__ void k3_row(
     });
   } else {
     // branch 1: u1 <- G1 * FFT(trunc_L(IFFT(u1)))
-    fft<T, P, kE, +1, kE, FBST_K3_TW>(u1, buf, tw, t);
+    fft<T, P, kE, +1, kE, FBST_K3_TW, PING>(u1, buf, tw, t);
 #pragma unroll
     for (int s = 0; s < kE; ++s)
       if (s >= SL || t + s * SH::TT >= L) u1[s] = cx<T>{0, 0};
-    fft<T, P, kE, -1, SL, FBST_K3_TW>(u1, buf, tw, t);
+    fft<T, P, kE, -1, SL, FBST_K3_TW, PING>(u1, buf, tw, t);
 #pragma unroll
     for (int s = 0; s < kE; ++s) u1[s] = cmul(u1[s], ldg(g1 + t + s * SH::TT));
     // branch 2: u1 -= G2 * FFT(trunc_L(IFFT(u2)))
-    fft<T, P, kE, +1, kE, FBST_K3_TW>(u2, buf, tw, t);
+    fft<T, P, kE, +1, kE, FBST_K3_TW, PING>(u2, buf, tw, t);
 #pragma unroll
     for (int s = 0; s < kE; ++s)
       if (s >= SL || t + s * SH::TT >= L) u2[s] = cx<T>{0, 0};
-    fft<T, P, kE, -1, SL, FBST_K3_TW>(u2, buf, tw, t);
+    fft<T, P, kE, -1, SL, FBST_K3_TW, PING>(u2, buf, tw, t);
 #pragma unroll
     for (int s = 0; s < kE; ++s) u1[s] = u1[s] - cmul(u2[s], ldg(g2 + t + s * SH::TT));
   }
   // beta = trunc_L(IFFT(Z)), then the F_u chirp-z
-  fft<T, P, kE, +1, kE, FBST_K3_TW>(u1, buf, tw, t);
+  fft<T, P, kE, +1, kE, FBST_K3_TW, PING>(u1, buf, tw, t);
   if constexpr (MODE == 1) {
 #pragma unroll
     for (int s = 0; s < SL; ++s) {
@@ -158,10 +168,10 @@ __device__ __forceinline__ void k3_row(
     const int i = t + s * SH::TT;
     u1[s] = (s < SL && i < L) ? cmul(u1[s], ldg(pre3 + i)) : cx<T>{0, 0};
   }
-  fft<T, P, kE, -1, SL, FBST_K3_TW>(u1, buf, tw, t);
+  fft<T, P, kE, -1, SL, FBST_K3_TW, PING>(u1, buf, tw, t);
   with_tables<FBST_K3_GB, kE, SH::TT>(H3 + t, static_cast<const cx<T>*>(nullptr),
                                       [&](int s, cx<T> a, cx<T>) { u1[s] = cmul(u1[s], a); });
-  fft<T, P, kE, +1, kE, FBST_K3_TW>(u1, buf, tw, t);
+  fft<T, P, kE, +1, kE, FBST_K3_TW, PING>(u1, buf, tw, t);
   cx<TOUT>* dst = static_cast<cx<TOUT>*>(outs.p[blk]) + static_cast<size_t>(b) * N;
 #pragma unroll
   for (int s = 0; s < SN; ++s) {
@@ -179,7 +189,8 @@ __attribute__((amdgpu_waves_per_eu((VAR & K3_WAVES3) ? 3 : FBST_K3_WAVES))) void
     int nblocks, cx<T>* __restrict__ bt = nullptr, const cx<T>* __restrict__ CA = nullptr) {
   using SH = Shape<P>;
   constexpr bool DUAL = !(VAR & K3_SINGLE) && k3_dual<T, P>();
-  __shared__ cx<T> lds[SH::G * (DUAL ? 2 : 1) * SH::S];
+  constexpr bool TWO = DUAL || (FBST_K3_PING && k3_two_buffers<T, P>());
+  __shared__ cx<T> lds[SH::G * (TWO ? 2 : 1) * SH::S];
   const int g = threadIdx.x / SH::TT;
   const int wl = xcd_linear(gridDim.x);                 // contiguous logical range per XCD
   if constexpr (VAR & K3_PERSISTENT) {
