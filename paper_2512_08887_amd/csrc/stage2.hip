@@ -46,9 +46,10 @@ constexpr bool k3_dual() {
 //   MODE 1  beta_1 = GS(w) stored to bt [rows][L]                (6 transforms)
 //   MODE 2  r = w - A beta_1; beta = beta_1 + GS(r); beams = F_u beta (10 transforms)
 // Instance variants, chosen at run time (fbst_autotune):
-//   K3_SINGLE      the two Gohberg-Semencul branches one after the other in one
-//                  LDS buffer (default: as one dual transform in two buffers,
-//                  where they fit);
+//   K3_SINGLE      the two Gohberg-Semencul branches one after the other, each
+//                  transform alternating its exchanges between two buffers
+//                  (default: the branches as one dual transform in two
+//                  buffers, where they fit);
 //   K3_PERSISTENT  a grid of at most the resident workgroups, each taking a
 //                  contiguous range of rows (default: one workgroup per row
 //                  group).
@@ -57,9 +58,9 @@ constexpr bool k3_dual() {
 // combination of the two branches in another order (float32 rounding level).
 constexpr int K3_SINGLE = 1;
 constexpr int K3_PERSISTENT = 2;
-constexpr int K3_WAVES3 = 4;     // register allocation for 3 waves per SIMD (single form)
+constexpr int K3_WAVES3 = 4;     // registers for 3 waves per SIMD (single form, one buffer)
 
-template <typename T, typename TIN, typename TOUT, int P, int SN, int MODE, bool DUAL>
+template <typename T, typename TIN, typename TOUT, int P, int SN, int MODE, bool DUAL, bool PING>
 __device__ __forceinline__ void k3_row(
     int lw, cx<T>* __restrict__ lds, const cx<TIN>* __restrict__ w, const OutPtrs& outs,
     const cx<T>* __restrict__ G1, const cx<T>* __restrict__ G2, const cx<T>* __restrict__ pre3,
@@ -67,9 +68,8 @@ __device__ __forceinline__ void k3_row(
     int B, int L, int N, int nblocks, cx<T>* __restrict__ bt, const cx<T>* __restrict__ CA) {
   using SH = Shape<P>;
   constexpr int SL = kE / 2;
-  // the single form alternates its transforms' exchanges between two buffers
-  // where they fit (one barrier per exchange)
-  constexpr bool PING = FBST_K3_PING && !DUAL && k3_two_buffers<T, P>();
+  // PING: the single form alternates its transforms' exchanges between two
+  // buffers (one barrier per exchange)
   constexpr int NBUF = (DUAL || PING) ? 2 : 1;
   const int g = threadIdx.x / SH::TT;
   const int t = threadIdx.x % SH::TT;
@@ -189,8 +189,11 @@ __attribute__((amdgpu_waves_per_eu((VAR & K3_WAVES3) ? 3 : FBST_K3_WAVES))) void
     int nblocks, cx<T>* __restrict__ bt = nullptr, const cx<T>* __restrict__ CA = nullptr) {
   using SH = Shape<P>;
   constexpr bool DUAL = !(VAR & K3_SINGLE) && k3_dual<T, P>();
-  constexpr bool TWO = DUAL || (FBST_K3_PING && k3_two_buffers<T, P>());
-  __shared__ cx<T> lds[SH::G * (TWO ? 2 : 1) * SH::S];
+  // the single form takes two alternating buffers where they fit, except in
+  // the instance that keeps its registers for 3 waves per SIMD (the second
+  // buffer would leave room for two workgroups only)
+  constexpr bool PING = FBST_K3_PING && !DUAL && !(VAR & K3_WAVES3) && k3_two_buffers<T, P>();
+  __shared__ cx<T> lds[SH::G * ((DUAL || PING) ? 2 : 1) * SH::S];
   const int g = threadIdx.x / SH::TT;
   const int wl = xcd_linear(gridDim.x);                 // contiguous logical range per XCD
   if constexpr (VAR & K3_PERSISTENT) {
@@ -200,10 +203,10 @@ __attribute__((amdgpu_waves_per_eu((VAR & K3_WAVES3) ? 3 : FBST_K3_WAVES))) void
     const int per = (groups + static_cast<int>(gridDim.x) - 1) / static_cast<int>(gridDim.x);
     const int q1 = min(groups, (wl + 1) * per);
     for (int q = wl * per; q < q1; ++q)
-      k3_row<T, TIN, TOUT, P, SN, MODE, DUAL>(q * SH::G + g, lds, w, outs, G1, G2, pre3, H3, post3,
+      k3_row<T, TIN, TOUT, P, SN, MODE, DUAL, PING>(q * SH::G + g, lds, w, outs, G1, G2, pre3, H3, post3,
                                               tw, B, L, N, nblocks, bt, CA);
   } else {
-    k3_row<T, TIN, TOUT, P, SN, MODE, DUAL>(wl * SH::G + g, lds, w, outs, G1, G2, pre3, H3, post3,
+    k3_row<T, TIN, TOUT, P, SN, MODE, DUAL, PING>(wl * SH::G + g, lds, w, outs, G1, G2, pre3, H3, post3,
                                             tw, B, L, N, nblocks, bt, CA);
   }
 }
