@@ -33,6 +33,10 @@ def _plans():
         ("line 100x300x70", F.Plan(100, 300, 70, band=band, options=F.make_options(0.1 * 2 * 300)), 5),
         ("grid 6x5", F.Plan(30, 512, 42, band=band, geometry=F.make_grid_geometry(6, 5),
                             grid=F.make_beam_grid(7, 6), options=F.make_options(0.1 * 2 * 512)), 3),
+        # P3 = 8192: three LDS exchanges per transform, so the single form's
+        # alternating buffers keep the barrier ahead of each transform's first
+        # exchange
+        ("line 16x2048x16", F.Plan(16, 2048, 16, band=band, options=F.make_options(0.1 * 2 * 2048)), 2),
     ]
 
 
