@@ -54,7 +54,7 @@ extern "C" {
 typedef enum {
   FBST_OK = 0,
   FBST_E_INVALID = -1,     /* an argument is null, out of range or inconsistent  */
-  FBST_E_UNSUPPORTED = -2, /* valid, but outside what this build implements      */
+  FBST_E_UNSUPPORTED = -2, /* valid, but outside what the library implements    */
   FBST_E_NOMEM = -3,       /* host or device allocation failed                    */
   FBST_E_DEVICE = -4       /* HIP runtime error (no device, launch or copy error) */
 } fbst_status;
